@@ -1,0 +1,337 @@
+"""FP64 CPU oracle of the SBS diffusion-reaction method -- TEST INFRASTRUCTURE.
+
+Only tests/, the smoke check and the CPU-baseline leg of bench.py may import
+this package.  The HIP engine never imports, links or calls it; the two share
+no code.  The arithmetic lives in gsbs_oracle.c (plain C, FP64); this module
+only marshals arguments through ctypes.  See gsbs_oracle.c for the passages of
+arXiv 2509.03313 each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsbs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+MAX_SPECIES = 16
+MAX_REACT = 32
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE arithmetic, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Chem(C.Structure):
+    _fields_ = [
+        ("ns", C.c_int32), ("nr", C.c_int32),
+        ("D", C.c_double * MAX_SPECIES),
+        ("ra", C.c_int32 * MAX_REACT), ("rb", C.c_int32 * MAX_REACT),
+        ("k_in", C.c_double * MAX_REACT),
+        ("nprod", C.c_int32 * MAX_REACT),
+        ("prod", (C.c_int32 * 3) * MAX_REACT),
+        ("keep_b", C.c_int32 * MAX_REACT),
+        ("c_cut", C.c_double),
+        ("rounds", C.c_int32), ("contact_only", C.c_int32), ("brute", C.c_int32),
+    ]
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            L = C.CDLL(_LIB)
+            d, i32, i64, u64, f32 = C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_float
+            P = C.POINTER
+            vp = C.c_void_p
+            sig = {
+                "orc_philox4x64_10": (None, [P(u64), P(u64), P(u64)]),
+                "orc_u24": (d, [u64]),
+                "orc_gauss3": (None, [P(u64), P(d)]),
+                "orc_wrap": (d, [d, d]),
+                "orc_minimg": (d, [d, d]),
+                "orc_radius": (d, [d, d]),
+                "orc_cutoff": (d, [d, d, d, d]),
+                "orc_bridge": (d, [d, d, d, d]),
+                "orc_dt_max": (d, [P(Chem), d]),
+                "orc_schedule": (i64, [d, d, i32, P(d), i32, P(d), d, d, d, P(d), i64]),
+                "orc_new": (vp, [d, u64, u64]),
+                "orc_free": (None, [vp]),
+                "orc_get_n": (i64, [vp]),
+                "orc_get_step": (i64, [vp]),
+                "orc_get_time": (d, [vp]),
+                "orc_get_edep": (d, [vp]),
+                "orc_get_diag": (None, [vp, P(i64)]),
+                "orc_inject": (None, [vp, i64, P(d), P(i32), d]),
+                "orc_set_state": (None, [vp, i64, P(d), P(d), P(i32), P(u64), i64, u64]),
+                "orc_get_state": (None, [vp, P(d), P(d), P(i32), P(u64)]),
+                "orc_counts": (None, [vp, i32, P(i64)]),
+                "orc_set_log": (None, [vp, i32]),
+                "orc_log_size": (i64, [vp]),
+                "orc_get_log": (None, [vp, P(u64), P(d), P(C.c_uint32), P(i32), P(i32)]),
+                "orc_step": (i64, [vp, P(Chem), d]),
+                "orc_run": (i64, [vp, P(Chem), i32, P(d), P(i64), P(d), P(i32), P(d), i32, P(d),
+                                  d, d, d, d, P(i64), P(d), P(i64)]),
+                "orc_bin_f32": (None, [i64, P(f32), f32, i32, P(i32)]),
+                "orc_rc2_f32": (None, [P(Chem), d, P(f32)]),
+                "orc_cand_f32": (i64, [i64, P(f32), P(i32), f32, P(Chem), d, P(i64), i64]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ chemistry ---
+def make_chem(D, reactions, c_cut: float = 5.0, rounds: int = 4, contact_only: bool = False,
+              brute: bool = False) -> Chem:
+    """reactions: objects with a, b, k_in, products, keep_b (see workload.Reaction)."""
+    c = Chem()
+    c.ns = len(D)
+    c.nr = len(reactions)
+    for k, v in enumerate(D):
+        c.D[k] = float(v)
+    for r, rx in enumerate(reactions):
+        c.ra[r] = rx.a
+        c.rb[r] = rx.b
+        c.k_in[r] = rx.k_in
+        c.nprod[r] = len(rx.products)
+        for k, p in enumerate(rx.products):
+            c.prod[r][k] = p
+        c.keep_b[r] = 1 if getattr(rx, "keep_b", False) else 0
+    c.c_cut = c_cut
+    c.rounds = rounds
+    c.contact_only = 1 if contact_only else 0
+    c.brute = 1 if brute else 0
+    return c
+
+
+# ------------------------------------------------------------- scalars ---
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c, C.c_uint64), _p(k, C.c_uint64), _p(out, C.c_uint64))
+    return out
+
+
+def u24(w):
+    return lib().orc_u24(int(w))
+
+
+def gauss3(w):
+    w = np.asarray(w, dtype=np.uint64)
+    z = np.zeros(3)
+    lib().orc_gauss3(_p(w, C.c_uint64), _p(z, C.c_double))
+    return z
+
+
+def wrap(x, L):
+    return lib().orc_wrap(float(x), float(L))
+
+
+def minimg(d, L):
+    return lib().orc_minimg(float(d), float(L))
+
+
+def radius(k_in, Dab):
+    return lib().orc_radius(float(k_in), float(Dab))
+
+
+def cutoff(R, Dab, dt, c):
+    return lib().orc_cutoff(float(R), float(Dab), float(dt), float(c))
+
+
+def bridge(r0, r1, R, s):
+    return lib().orc_bridge(float(r0), float(r1), float(R), float(s))
+
+
+def dt_max(chem: Chem, L: float) -> float:
+    return lib().orc_dt_max(C.byref(chem), float(L))
+
+
+def schedule(t_start, t_end, anchors, events, dt0, ratio, dt_max_):
+    a = np.ascontiguousarray(anchors, dtype=np.float64)
+    e = np.ascontiguousarray(events, dtype=np.float64)
+    L = lib()
+    n = L.orc_schedule(t_start, t_end, len(a), _p(a, C.c_double), len(e), _p(e, C.c_double),
+                       dt0, ratio, dt_max_, None, 0)
+    out = np.zeros(max(n, 1))
+    L.orc_schedule(t_start, t_end, len(a), _p(a, C.c_double), len(e), _p(e, C.c_double),
+                   dt0, ratio, dt_max_, _p(out, C.c_double), n)
+    return out[:n]
+
+
+# ------------------------------------------------------------ instance ---
+class Instance:
+    """One periodic cube of edge L (nm), Philox key (seed, inst)."""
+
+    def __init__(self, L: float, seed: int, inst: int = 0):
+        self.L = float(L)
+        self._h = lib().orc_new(self.L, int(seed), int(inst))
+
+    def close(self):
+        if self._h:
+            lib().orc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return lib().orc_get_n(self._h)
+
+    @property
+    def step_index(self):
+        return lib().orc_get_step(self._h)
+
+    @property
+    def t(self):
+        return lib().orc_get_time(self._h)
+
+    @property
+    def edep(self):
+        return lib().orc_get_edep(self._h)
+
+    def inject(self, xyz, species, edep_ev: float = 0.0):
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        s = np.ascontiguousarray(species, dtype=np.int32)
+        lib().orc_inject(self._h, len(s), _p(x, C.c_double), _p(s, C.c_int32), float(edep_ev))
+
+    def set_state(self, xyz, species, uid, x0=None, step: int = 0, next_uid: int = None):
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, 3)
+        s = np.ascontiguousarray(species, dtype=np.int32)
+        u = np.ascontiguousarray(uid, dtype=np.uint64)
+        nu = int(u.max()) + 1 if next_uid is None and len(u) else (next_uid or 0)
+        lib().orc_set_state(self._h, len(s), _p(x, C.c_double),
+                            None if x0a is None else _p(x0a, C.c_double),
+                            _p(s, C.c_int32), _p(u, C.c_uint64), int(step), nu)
+
+    def state(self):
+        n = self.n
+        x = np.zeros((n, 3))
+        x0 = np.zeros((n, 3))
+        s = np.zeros(n, dtype=np.int32)
+        u = np.zeros(n, dtype=np.uint64)
+        lib().orc_get_state(self._h, _p(x, C.c_double), _p(x0, C.c_double), _p(s, C.c_int32),
+                            _p(u, C.c_uint64))
+        return x, x0, s, u
+
+    def counts(self, ns: int = 7):
+        out = np.zeros(ns, dtype=np.int64)
+        lib().orc_counts(self._h, ns, _p(out, C.c_int64))
+        return out
+
+    def set_log(self, mode: int):
+        lib().orc_set_log(self._h, int(mode))
+
+    def log(self):
+        n = lib().orc_log_size(self._h)
+        uid2 = np.zeros((n, 2), dtype=np.uint64)
+        P = np.zeros(n)
+        u = np.zeros(n, dtype=np.uint32)
+        f = np.zeros(n, dtype=np.int32)
+        rx = np.zeros(n, dtype=np.int32)
+        if n:
+            lib().orc_get_log(self._h, _p(uid2, C.c_uint64), _p(P, C.c_double),
+                              _p(u, C.c_uint32), _p(f, C.c_int32), _p(rx, C.c_int32))
+        return dict(uid=uid2, P=P, u24=u, flag=f, rx=rx)
+
+    def diag(self):
+        out = np.zeros(3, dtype=np.int64)
+        lib().orc_get_diag(self._h, _p(out, C.c_int64))
+        return dict(n_cand=int(out[0]), n_acc=int(out[1]), n_react=int(out[2]))
+
+    def step(self, chem: Chem, dt: float) -> int:
+        r = lib().orc_step(self._h, C.byref(chem), float(dt))
+        if r < 0:
+            raise RuntimeError("oracle: tied matching keys")
+        return r
+
+
+def run(workload, chem: Chem = None, inst: int = 0, dt0: float = None, ratio: float = None,
+        dtmax: float = None, t_end: float = None, c_cut: float = 5.0):
+    """Run a workload.Workload through the oracle.  Returns dict with counts
+    (n_records x n_species), edep (eV at each record) and stats."""
+    if chem is None:
+        chem = make_chem(workload.D, workload.reactions, c_cut=c_cut)
+    dt0 = workload.dt0 if dt0 is None else dt0
+    ratio = workload.ratio if ratio is None else ratio
+    t_end = workload.t_end if t_end is None else t_end
+    if dtmax is None:
+        dtmax = dt_max(chem, workload.L)
+    s = Instance(workload.L, workload.seed, inst)
+    injs = [i for i in workload.injections if i.t <= t_end]
+    n_inj = len(injs)
+    inj_t = np.array([i.t for i in injs], dtype=np.float64)
+    inj_n = np.array([len(i.species) for i in injs], dtype=np.int64)
+    inj_x = np.ascontiguousarray(np.concatenate([i.xyz for i in injs]).astype(np.float64))
+    inj_s = np.ascontiguousarray(np.concatenate([i.species for i in injs]).astype(np.int32))
+    inj_e = np.array([i.edep_ev for i in injs], dtype=np.float64)
+    rec = np.ascontiguousarray(workload.records[workload.records <= t_end], dtype=np.float64)
+    ns = chem.ns
+    counts = np.full((len(rec), ns), -1, dtype=np.int64)
+    edep = np.zeros(len(rec))
+    stats = np.zeros(4, dtype=np.int64)
+    lib().orc_run(s._h, C.byref(chem), n_inj, _p(inj_t, C.c_double), _p(inj_n, C.c_int64),
+                  _p(inj_x, C.c_double), _p(inj_s, C.c_int32), _p(inj_e, C.c_double),
+                  len(rec), _p(rec, C.c_double), float(t_end), float(dt0), float(ratio),
+                  float(dtmax), _p(counts, C.c_int64), _p(edep, C.c_double), _p(stats, C.c_int64))
+    out = dict(times=rec, counts=counts, edep=edep, n_steps=int(stats[0]),
+               molecule_steps=int(stats[1]), n_react=int(stats[2]), tie=bool(stats[3]),
+               final_n=s.n, final_t=s.t)
+    s.close()
+    return out
+
+
+# ------------------------------------------------------- FP32 emulation ---
+def bin_f32(xyz, L: float, nc: int):
+    x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    out = np.zeros(len(x), dtype=np.int32)
+    lib().orc_bin_f32(len(x), _p(x, C.c_float), np.float32(L), int(nc), _p(out, C.c_int32))
+    return out
+
+
+def rc2_f32(chem: Chem, dt: float):
+    out = np.zeros(MAX_REACT, dtype=np.float32)
+    lib().orc_rc2_f32(C.byref(chem), float(dt), _p(out, C.c_float))
+    return out[:chem.nr]
+
+
+def cand_f32(xyz, species, L: float, chem: Chem, dt: float, max_pairs: int = 10_000_000):
+    x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    s = np.ascontiguousarray(species, dtype=np.int32)
+    L_ = lib()
+    n = L_.orc_cand_f32(len(x), _p(x, C.c_float), _p(s, C.c_int32), np.float32(L), C.byref(chem),
+                        float(dt), None, 0)
+    out = np.zeros((max(n, 1), 2), dtype=np.int64)
+    L_.orc_cand_f32(len(x), _p(x, C.c_float), _p(s, C.c_int32), np.float32(L), C.byref(chem),
+                    float(dt), _p(out, C.c_int64), n)
+    return out[:n]

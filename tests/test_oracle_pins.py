@@ -1,0 +1,511 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Every check below compares the oracle with a library routine, a closed form,
+an invariant or a brute-force computation that does not reuse the oracle's
+code, so that a dropped term, a wrong sign or a swapped index in the oracle
+fails one of them.  CPU only.
+"""
+import json
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from paper_2509_03313_amd import workload as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_A = 6.02214076e23
+
+
+class Rx:
+    """A reaction record for test chemistries."""
+
+    def __init__(self, a, b, k_in, products=(), keep_b=False):
+        self.a, self.b, self.k_in, self.products, self.keep_b = a, b, k_in, tuple(products), keep_b
+
+
+def k_in_for_radius(R, Dab):
+    """Rate constant (1e10 L/mol/s) whose steady-state Smoluchowski radius is R.
+    Uses CODATA N_A via the physical definition k = 4 pi R D_AB, so it does not
+    reuse the oracle's unit constant."""
+    k_nm3_ns = 4.0 * math.pi * R * Dab                      # nm^3/ns per pair
+    k_m3_s = k_nm3_ns * 1e-27 / 1e-9                        # m^3/s per pair
+    return k_m3_s * N_A * 1e3 / 1e10                        # 1e10 L/mol/s
+
+
+# ------------------------------------------------------------- Philox ---
+def test_philox_matches_numpy(orc):
+    """Philox4x64-10 block at counter c equals numpy's Philox output after its
+    counter is set to c-1 (numpy increments before generating)."""
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        key = rng.integers(0, 2 ** 63, size=2, dtype=np.uint64)
+        ctr = rng.integers(1, 2 ** 63, size=4, dtype=np.uint64)
+        bg = np.random.Philox(key=key)
+        st = bg.state
+        c = ctr.copy()
+        c[0] -= np.uint64(1)
+        st["state"]["counter"] = c
+        st["buffer_pos"] = 4
+        bg.state = st
+        ref = bg.random_raw(4)
+        got = orc.philox(ctr, key)
+        assert np.array_equal(ref, got)
+
+
+def _numpy_philox(ctr, key):
+    bg = np.random.Philox(key=np.asarray(key, dtype=np.uint64))
+    st = bg.state
+    c = np.asarray(ctr, dtype=np.uint64).copy()
+    # numpy's counter is a 256-bit integer incremented before use: borrow on underflow
+    i = 0
+    while c[i] == 0:
+        c[i] = np.uint64(2 ** 64 - 1)
+        i += 1
+    c[i] -= np.uint64(1)
+    st["state"]["counter"] = c
+    st["buffer_pos"] = 4
+    bg.state = st
+    return bg.random_raw(4)
+
+
+def test_uniforms_exact_and_open(orc):
+    for w in [0, 1, 2 ** 40 - 1, 2 ** 64 - 1, 0x123456789ABCDEF0]:
+        u = orc.u24(w)
+        assert 0.0 < u < 1.0
+        k = w >> 40
+        assert u * 2 ** 25 == 2 * k + 1            # (k + 1/2) / 2^24 exactly
+    assert orc.u24(2 ** 64 - 1) == 1.0 - 2.0 ** -25 and orc.u24(0) == 2.0 ** -25
+
+
+def test_box_muller_is_standard_normal(orc):
+    rng = np.random.default_rng(3)
+    z = np.array([orc.gauss3(rng.integers(0, 2 ** 64, size=4, dtype=np.uint64)) for _ in range(6000)])
+    for a in range(3):
+        assert stats.kstest(z[:, a], "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 0.05
+
+
+# --------------------------------------------------------------- PBCs ---
+def test_wrap_eq1(orc):
+    L = 1000.0
+    assert orc.wrap(500.0, L) == -500.0          # x >= L/2 -> x - L
+    assert orc.wrap(-500.0, L) == -500.0         # lower face belongs to the cube
+    assert orc.wrap(-500.5, L) == 499.5          # x < -L/2 -> x + L
+    assert orc.wrap(499.9, L) == 499.9
+    rng = np.random.default_rng(1)
+    for x in rng.uniform(-3 * L, 3 * L, size=2000):
+        y = orc.wrap(x, L)
+        assert -L / 2 <= y < L / 2
+        k = round((x - y) / L)
+        assert abs(x - y - k * L) < 1e-9          # shifted by whole edges only
+
+
+def test_minimum_image_is_nearest_periodic_image(orc):
+    """Eq. (2) applied per axis equals the shortest of the 27 periodic images."""
+    L = 700.0
+    rng = np.random.default_rng(2)
+    a = rng.uniform(-L / 2, L / 2, size=(3000, 3))
+    b = rng.uniform(-L / 2, L / 2, size=(3000, 3))
+    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]) * L
+    for p, q in zip(a, b):
+        d = np.array([orc.minimg(q[k] - p[k], L) for k in range(3)])
+        brute = np.min(np.linalg.norm(q[None, :] + shifts - p[None, :], axis=1))
+        assert abs(np.linalg.norm(d) - brute) < 1e-9
+
+
+# ------------------------------------------------------ reaction radius ---
+def test_radius_from_rate_constant(orc):
+    """R = k / (4 pi D_AB N_A): invert with the test's own unit conversion."""
+    for R, Dab in [(0.3, 5.0), (1.0, 14.3), (0.1, 9.8)]:
+        assert orc.radius(k_in_for_radius(R, Dab), Dab) == pytest.approx(R, rel=1e-12)
+
+
+def test_paper_tables_are_the_inputs():
+    """The workload tables carry Table 1 and Table S2 of the paper."""
+    g = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))
+    for row, rx in zip(g["table1"], W.REACTIONS):
+        assert rx.name == row["name"]
+        assert rx.k_in == row["k"]
+        assert sorted(W.SPECIES[s] for s in (rx.a, rx.b)) == sorted(row["reactants"])
+        assert sorted(W.SPECIES[s] for s in rx.products) == sorted(row["products"])
+    for name, d in g["table_s2"].items():
+        assert W.D_PAPER[W.SPECIES.index(name)] == d
+
+
+# ------------------------------------------------------- bridge formula ---
+def _free_radial(r1, r0, s):
+    """Radial density of the relative separation after time t (D_AB t = s) in
+    free 3-D space: textbook propagator integrated over angles."""
+    return (r1 / r0) / math.sqrt(4 * math.pi * s) * (
+        math.exp(-(r1 - r0) ** 2 / (4 * s)) - math.exp(-(r1 + r0) ** 2 / (4 * s)))
+
+
+@pytest.mark.parametrize("r0,R,s", [(1.0, 0.3, 0.01), (1.0, 0.3, 0.3), (1.0, 0.3, 44.0),
+                                    (5.0, 1.0, 2.0), (0.6, 0.55, 0.001), (2.0, 0.2, 1e3)])
+def test_bridge_integrates_to_smoluchowski(orc, r0, R, s):
+    """Averaged over the free end-point density, the per-step contact
+    probability must give the Smoluchowski absorbed fraction
+    (R/r0) erfc((r0-R)/sqrt(4 D t)) -- the supplement's p(r,t) with its erfc
+    argument read as +(r-R)."""
+    f = lambda r1: _free_radial(r1, r0, s) * (1.0 if r1 <= R else orc.bridge(r0, r1, R, s))
+    hi = r0 + 40 * math.sqrt(s) + 10
+    pts = sorted({R, r0})
+    val = integrate.quad(f, 0.0, hi, points=pts, limit=400, epsabs=1e-12, epsrel=1e-10)[0]
+    ref = R / r0 * special.erfc((r0 - R) / math.sqrt(4 * s))
+    assert val == pytest.approx(ref, rel=2e-6, abs=1e-10)
+
+
+def test_bridge_limits(orc):
+    assert orc.bridge(0.5, 2.0, 0.5, 1.0) == 1.0          # started in contact
+    assert orc.bridge(2.0, 0.4, 0.5, 1.0) == 1.0          # ended inside R
+    # far from the sphere it is the planar bridge exp(-(r0-R)(r1-R)/s)
+    r0, r1, R, s = 50.0, 51.0, 1.0, 2.0
+    assert orc.bridge(r0, r1, R, s) == pytest.approx(math.exp(-(r0 - R) * (r1 - R) / s), rel=1e-12)
+    for r0, r1, R, s in [(1, 1, 0.3, 1e-4), (3, 7, 0.3, 1e5), (1.01, 1.02, 1.0, 1e-6)]:
+        p = orc.bridge(r0, r1, R, s)
+        assert 0.0 <= p <= 1.0
+
+
+# ------------------------------------------------------------ schedule ---
+def test_schedule_single_injection_log_lattice(orc):
+    """One injection at 0, end 1 us: the step end times are 1 ps * 10^(6j/1999)."""
+    t = orc.schedule(0.0, 1000.0, [0.0], [], 1e-3, 10 ** (6 / 1999), 1e9)
+    assert len(t) == 2000
+    ref = 1e-3 * 10.0 ** (6.0 * np.arange(2000) / 1999.0)
+    assert np.allclose(t, ref, rtol=1e-12)
+    assert t[-1] == 1000.0
+
+
+def test_schedule_events_and_cap(orc):
+    anchors = [0.0, 100.0]
+    events = [0.5, 100.0, 250.0]
+    t = orc.schedule(0.0, 400.0, anchors, events, 1e-2, 1.5, 20.0)
+    assert np.all(np.diff(t) > 0)
+    for e in events + [400.0]:
+        assert np.any(t == e)
+    assert np.max(np.diff(np.concatenate([[0.0], t]))) <= 20.0 + 1e-12
+    # the lattice restarts after the second injection
+    assert np.any(np.isclose(t, 100.0 + 1e-2, rtol=0, atol=1e-12))
+
+
+# ------------------------------------------------------------ diffusion ---
+def _inert_chem(orc, D):
+    return orc.make_chem(D, [])
+
+
+def test_one_step_matches_numpy_philox_jump(orc):
+    """Single step, no reactions: x' = wrap(x + sqrt(2 D dt) z) with z from
+    Box-Muller of the Philox block at (uid, step, 0, 0), key (seed, instance);
+    recomputed here with numpy's Philox."""
+    L, seed, inst, dt = 800.0, 11, 3, 0.37
+    D = [1.0, 4.0]
+    chem = _inert_chem(orc, D)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-L / 2, L / 2, size=(200, 3))
+    x[0] = [L / 2 - 1e-3, -L / 2, 0.0]
+    sp = rng.integers(0, 2, size=200)
+    uid = rng.integers(0, 2 ** 40, size=200).astype(np.uint64)
+    s = orc.Instance(L, seed, inst)
+    s.set_state(x, sp, uid, step=17)
+    s.step(chem, dt)
+    xn, x0, sp2, uid2 = s.state()
+    assert np.array_equal(uid2, uid) and np.array_equal(x0, x)
+    for i in range(200):
+        w = _numpy_philox([int(uid[i]), 17, 0, 0], [seed, inst])
+        u = (w >> np.uint64(40)).astype(np.float64)
+        u = (u + 0.5) / 2 ** 24
+        r_a, r_b = math.sqrt(-2 * math.log(u[0])), math.sqrt(-2 * math.log(u[2]))
+        z = np.array([r_a * math.cos(2 * math.pi * u[1]), r_a * math.sin(2 * math.pi * u[1]),
+                      r_b * math.cos(2 * math.pi * u[3])])
+        y = x[i] + math.sqrt(2 * D[sp[i]] * dt) * z
+        y = (y + L / 2) % L - L / 2
+        d = (xn[i] - y + L / 2) % L - L / 2
+        assert np.all(np.abs(d) < 1e-9)
+
+
+def test_msd_is_6Dt(orc):
+    """Mean squared displacement of free molecules grows as 6 D t per species."""
+    L, D = 2000.0, [0.5, 2.2, 9.0]
+    chem = _inert_chem(orc, D)
+    n_per = 3000
+    rng = np.random.default_rng(9)
+    sp = np.repeat(np.arange(3), n_per)
+    x = rng.uniform(-L / 2, L / 2, size=(len(sp), 3))
+    s = orc.Instance(L, 4, 0)
+    s.set_state(x, sp, np.arange(len(sp), dtype=np.uint64))
+    unwrapped = x.copy()
+    dts = [0.01] * 20 + [0.5] * 20 + [5.0] * 10
+    t = 0.0
+    for dt in dts:
+        s.step(chem, dt)
+        xn, x0, _, _ = s.state()
+        unwrapped += (xn - x0 + L / 2) % L - L / 2
+        t += dt
+    for k in range(3):
+        r2 = np.sum((unwrapped[sp == k] - x[sp == k]) ** 2, axis=1)
+        mean, se = r2.mean(), r2.std(ddof=1) / math.sqrt(n_per)
+        assert abs(mean - 6 * D[k] * t) < 3.5 * se, (k, mean, 6 * D[k] * t, se)
+    # per-axis displacement over the run is N(0, 2 D t)
+    z = (unwrapped[sp == 1, 0] - x[sp == 1, 0]) / math.sqrt(2 * D[1] * t)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+# ------------------------------------------------------- kinetics pins ---
+def _run_many(orc, fn, seeds):
+    with ThreadPoolExecutor(max_workers=min(8, len(seeds))) as ex:
+        return list(ex.map(fn, seeds))
+
+
+@pytest.mark.parametrize("schedule", ["fine", "coarse"])
+def test_isolated_pair_smoluchowski(orc, schedule):
+    """An isolated A-B pair started at r0 has reacted by time t with probability
+    (R/r0) erfc((r0-R)/sqrt(4 D_AB t)) (supplement, pair density p(r,t)); the
+    radial bridge makes this exact for any step schedule."""
+    DA, DB = 2.0, 3.0
+    Dab = DA + DB
+    R, r0 = 0.5, 1.0
+    chem = orc.make_chem([DA, DB], [Rx(0, 1, k_in_for_radius(R, Dab))])
+    spacing, m = 150.0, 16
+    L = spacing * m
+    g = (np.stack(np.meshgrid(*[np.arange(m)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) * spacing - L / 2
+    rec = np.array([0.01, 0.1, 1.0, 5.0])
+    if schedule == "fine":
+        dt0, ratio = 1e-4, 1.01
+    else:
+        dt0, ratio = 5e-3, 1.6
+
+    def one(seed):
+        rng = np.random.default_rng(seed)
+        u = rng.normal(size=(len(g), 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        xyz = np.concatenate([g, g + r0 * u])
+        sp = np.concatenate([np.zeros(len(g), int), np.ones(len(g), int)])
+        wl = W.Workload("pair", L, seed, [W.Injection(0.0, xyz, sp, 0.0)], rec, rec[-1],
+                        D=[DA, DB], reactions=[], dt0=dt0, ratio=ratio)
+        return orc.run(wl, chem=chem)["counts"][:, 0]
+
+    res = np.array(_run_many(orc, one, list(range(4))))
+    M = len(g) * res.shape[0]
+    reacted = (len(g) * res.shape[0] - res.sum(axis=0)) / M
+    ref = R / r0 * special.erfc((r0 - R) / np.sqrt(4 * Dab * rec))
+    se = np.sqrt(ref * (1 - ref) / M)
+    assert np.all(np.abs(reacted - ref) < 4 * se + 1e-3), (reacted, ref, se)
+
+
+def test_pseudo_first_order_transient_rate(orc):
+    """Static A among mobile B (sink A + B -> B, B in excess): the survival of A
+    is exp(-n_B * integral of k_diff(t)), k_diff(t) = 4 pi R D (1 + R/sqrt(pi D t))
+    (supplement, time-dependent rate); exact for independent B."""
+    DA, DB = 0.0, 5.0
+    R = 1.0
+    chem = orc.make_chem([DA, DB], [Rx(0, 1, k_in_for_radius(R, DA + DB), products=(), keep_b=True)])
+    L, nB, nA = 200.0, 1e-3, 1000
+    rec = np.array([1.0, 5.0, 20.0])
+
+    def one(seed):
+        rng = np.random.default_rng(100 + seed)
+        xb = rng.uniform(-L / 2, L / 2, size=(int(nB * L ** 3), 3))
+        xa = rng.uniform(-L / 2, L / 2, size=(nA, 3))
+        xyz = np.concatenate([xa, xb])
+        sp = np.concatenate([np.zeros(nA, int), np.ones(len(xb), int)])
+        wl = W.Workload("sink", L, seed, [W.Injection(0.0, xyz, sp, 0.0)], rec, rec[-1],
+                        D=[DA, DB], reactions=[], dt0=0.01, ratio=1.05)
+        return orc.run(wl, chem=chem)["counts"]
+
+    res = np.array(_run_many(orc, one, list(range(8))))
+    assert np.all(res[:, :, 1] == int(nB * L ** 3))        # B is never consumed
+    S = res[:, :, 0].sum(axis=0) / (nA * res.shape[0])
+    D = DB
+    ref = np.exp(-nB * 4 * math.pi * R * D * (rec + 2 * R * np.sqrt(rec / (math.pi * D))))
+    no_transient = np.exp(-nB * 4 * math.pi * R * D * rec)
+    se = np.sqrt(ref * (1 - ref) / (nA * res.shape[0]))
+    assert np.all(np.abs(S - ref) < 4 * se), (S, ref, se)
+    assert abs(S[1] - no_transient[1]) > 5 * se[1]            # the transient term is seen
+
+
+def test_self_recombination_uses_2k(orc):
+    """A + A at low density with R taken from the printed 2k: the mean-field law
+    -dn/dt = 2k(t) n^2, 2k(t) = 4 pi R D_AA (1 + R/sqrt(pi D_AA t)) (supplement,
+    self-recombination form) gives 1/n - 1/n0 = 4 pi R D_AA (t + 2R sqrt(t/(pi D_AA))).
+    The law is the low-density limit: at n0 = 2.5e-4 nm^-3 (R = 1 nm) the
+    many-body excess of the simulated decay is about 1.5% and independent of
+    the step schedule, so the bound is 3%."""
+    DA = 2.5
+    Daa = 2 * DA
+    R = 1.0
+    chem = orc.make_chem([DA], [Rx(0, 0, k_in_for_radius(R, Daa))])
+    L, n0 = 300.0, 2.5e-4
+    rec = np.array([8.0, 40.0, 160.0])
+
+    def one(seed):
+        rng = np.random.default_rng(200 + seed)
+        xyz = rng.uniform(-L / 2, L / 2, size=(int(n0 * L ** 3), 3))
+        wl = W.Workload("aa", L, seed, [W.Injection(0.0, xyz, np.zeros(len(xyz), int), 0.0)],
+                        rec, rec[-1], D=[DA], reactions=[], dt0=0.01, ratio=1.05)
+        return orc.run(wl, chem=chem)["counts"][:, 0]
+
+    res = np.array(_run_many(orc, one, list(range(8))))
+    n = res.mean(axis=0) / L ** 3
+    ref = 1.0 / (1.0 / n0 + 4 * math.pi * R * Daa * (rec + 2 * R * np.sqrt(rec / (math.pi * Daa))))
+    assert np.all(np.abs(n / ref - 1) < 0.03), (n, ref)
+    # taking the printed number as k instead of 2k would change the decay by far more
+    wrong = 1.0 / (1.0 / n0 + 2 * 4 * math.pi * R * Daa * rec)
+    assert np.all(np.abs(wrong / ref - 1)[1:] > 0.1)
+
+
+# ----------------------------------------------------------- reactions ---
+def test_products_placement_and_uids(orc):
+    """Two electrons in contact react (R1): products H2, OH-, OH- sit at the
+    D-weighted point of the end positions; uids: lower, higher, Philox|2^63."""
+    L, seed, inst, dt, step = 500.0, 21, 2, 1e-3, 5
+    D = W.D_CONFIG
+    chem = orc.make_chem(D, W.REACTIONS)
+    x = np.array([[10.0, 10.0, 10.0], [10.05, 10.0, 10.0]])
+    uid = np.array([7, 3], dtype=np.uint64)
+    s = orc.Instance(L, seed, inst)
+    s.set_state(x, [W.E_AQ, W.E_AQ], uid, step=step)
+    assert s.step(chem, dt) == 1
+    xn, _, sp, u = s.state()
+    assert sorted(sp.tolist()) == sorted([W.H2, W.OHM, W.OHM])
+    assert u[0] == 3 and sp[0] == W.H2 and u[1] == 7 and sp[1] == W.OHM
+    w = _numpy_philox([3, 7, step, 2], [seed, inst])
+    assert u[2] == (int(w[0]) | (1 << 63))
+    # end positions recomputed from numpy's Philox
+    ends = {}
+    for i in range(2):
+        ww = _numpy_philox([int(uid[i]), step, 0, 0], [seed, inst])
+        uu = ((ww >> np.uint64(40)).astype(np.float64) + 0.5) / 2 ** 24
+        ra, rb = math.sqrt(-2 * math.log(uu[0])), math.sqrt(-2 * math.log(uu[2]))
+        z = np.array([ra * math.cos(2 * math.pi * uu[1]), ra * math.sin(2 * math.pi * uu[1]),
+                      rb * math.cos(2 * math.pi * uu[3])])
+        ends[int(uid[i])] = x[i] + math.sqrt(2 * D[W.E_AQ] * dt) * z
+    xp = ends[3] + 0.5 * (ends[7] - ends[3])      # equal D: midpoint
+    assert np.allclose(xn, xp[None, :], atol=1e-9)
+
+
+def test_invariants_charge_and_redox(orc):
+    """Q = H3O+ - e_aq - OH- and W = OH + 2 H2O2 - e_aq - H - 2 H2 are conserved
+    by every reaction of Table 1."""
+    wl = W.single_pulse_small(0)
+    wl.records = wl.records[wl.records <= 3.0]
+    wl.t_end = 3.0
+    r = orc.run(wl)
+    c = r["counts"]
+    Q = c[:, W.H3O] - c[:, W.E_AQ] - c[:, W.OHM]
+    Wr = c[:, W.OH] + 2 * c[:, W.H2O2] - c[:, W.E_AQ] - c[:, W.H] - 2 * c[:, W.H2]
+    assert r["n_react"] > 50
+    assert np.all(Q == Q[0]) and np.all(Wr == Wr[0])
+
+
+def test_cell_list_equals_brute_force(orc):
+    """The bucket-grid candidate search and the all-pairs search give identical
+    trajectories (same candidates, same accepts, same products)."""
+    wl = W.single_pulse_small(4, n_tracks=1, track_nm=4000.0)
+    states = []
+    for brute in (False, True):
+        chem = orc.make_chem(wl.D, wl.reactions, brute=brute)
+        s = orc.Instance(wl.L, wl.seed, 0)
+        inj = wl.injections[0]
+        s.inject(inj.xyz.astype(np.float64), inj.species.astype(np.int32))
+        t = 0.0
+        for k, te in enumerate(orc.schedule(0.0, 50.0, [0.0], [], wl.dt0, wl.ratio, 1e9)):
+            if k % 7 == 0 or k > 900:
+                s.set_log(1)
+            s.step(chem, te - t)
+            t = te
+        x, _, sp, u = s.state()
+        o = np.argsort(u)
+        states.append((x[o], sp[o], u[o]))
+    assert np.array_equal(states[0][2], states[1][2])
+    assert np.array_equal(states[0][1], states[1][1])
+    assert np.array_equal(states[0][0], states[1][0])
+
+
+def test_candidates_match_brute_force_distances(orc):
+    """Per-step candidates (logged) are exactly the reactive pairs whose
+    minimum-image end separation is below R + 5 sqrt(2 D_AB dt)."""
+    L = 300.0
+    D = W.D_CONFIG
+    chem = orc.make_chem(D, W.REACTIONS)
+    rng = np.random.default_rng(8)
+    n = 600
+    x = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    sp = rng.integers(0, 7, size=n)
+    s = orc.Instance(L, 1, 0)
+    s.set_state(x, sp, np.arange(n, dtype=np.uint64))
+    s.set_log(2)
+    dt = 2.0
+    s.step(chem, dt)
+    lg = s.log()
+    got = set(map(tuple, lg["uid"].tolist()))
+    # rebuild end positions from the log-free path: run the same step with no reactions
+    s2 = orc.Instance(L, 1, 0)
+    s2.set_state(x, sp, np.arange(n, dtype=np.uint64))
+    s2.step(orc.make_chem(D, []), dt)
+    xe, _, _, ue = s2.state()
+    pos = xe[np.argsort(ue)]
+    rmap = {}
+    for r, rx in enumerate(W.REACTIONS):
+        rmap[(rx.a, rx.b)] = rmap[(rx.b, rx.a)] = r
+    ref = set()
+    for i in range(n):
+        for j in range(i + 1, n):
+            r = rmap.get((sp[i], sp[j]))
+            if r is None:
+                continue
+            rx = W.REACTIONS[r]
+            Dab = D[rx.a] + D[rx.b]
+            Rr = orc.radius(rx.k_in, Dab)
+            rc = Rr + 5 * math.sqrt(2 * Dab * dt)
+            d = pos[j] - pos[i]
+            d = (d + L / 2) % L - L / 2
+            if np.linalg.norm(d) < rc:
+                ref.add((i, j))
+    assert got == ref
+
+
+# ------------------------------------------------------ FP32 emulation ---
+def test_bin_f32_matches_numpy_float32(orc):
+    rng = np.random.default_rng(12)
+    L = np.float32(1000.0)
+    x = rng.uniform(-500, 500, size=(20000, 3)).astype(np.float32)
+    x[:5] = [[-500, -500, -500], [499.99997, 499.99997, 499.99997], [0, 0, 0],
+             [np.nextafter(np.float32(500), np.float32(0))] * 3, [-1e-7, 1e-7, 250.0]]
+    for nc in (3, 13, 46, 97):
+        got = orc.bin_f32(x, L, nc)
+        inv = np.float32(nc) / L
+        q = np.floor((x + np.float32(0.5) * L) * inv).astype(np.int64)
+        q = np.clip(q, 0, nc - 1)
+        ref = (q[:, 0] * nc + q[:, 1]) * nc + q[:, 2]
+        assert np.array_equal(got, ref)
+
+
+def test_cand_f32_matches_numpy_float32(orc):
+    rng = np.random.default_rng(13)
+    L = 400.0
+    n = 700
+    x = rng.uniform(-L / 2, L / 2, size=(n, 3)).astype(np.float32)
+    sp = rng.integers(0, 7, size=n)
+    chem = orc.make_chem(W.D_CONFIG, W.REACTIONS)
+    dt = 30.0
+    got = set(map(tuple, orc.cand_f32(x, sp, L, chem, dt).tolist()))
+    rc2 = orc.rc2_f32(chem, dt)
+    rmap = {}
+    for r, rx in enumerate(W.REACTIONS):
+        rmap[(rx.a, rx.b)] = rmap[(rx.b, rx.a)] = r
+    Lf, hL = np.float32(L), np.float32(L / 2)
+    ref = set()
+    for i in range(n):
+        d = x[i + 1:] - x[i]
+        d = np.where(d >= hL, d - Lf, np.where(d < -hL, d + Lf, d)).astype(np.float32)
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        for k in np.nonzero(d2 >= 0)[0]:
+            j = i + 1 + k
+            r = rmap.get((sp[i], sp[j]))
+            if r is not None and d2[k] < rc2[r]:
+                ref.add((i, j))
+    assert got == ref and len(ref) > 100
