@@ -1,0 +1,228 @@
+/*
+ * gsbs.h -- C ABI of the MI355X step-by-step (SBS) diffusion-reaction engine
+ * for water-radiolysis species in periodic cubes.
+ *
+ * The method (arXiv 2509.03313, "Advancements in Monte Carlo simulations with
+ * gMicroMC ..."): molecules of the chemical stage make Brownian jumps, re-enter
+ * the cube through the opposite face (PBC 1, Eq. 1), and react with a partner
+ * found through the minimum image (PBC 2, Eq. 2) when the pair comes within the
+ * reaction radius R derived from the rate constants of Table 1 (supplement,
+ * reaction-radius derivation; 2k for self-recombination).  Fresh molecules
+ * are injected at the times radiation events arrive (Sec. "Workflow of
+ * gMicroMC extension"); species counts give G-values (molecules per 100 eV).
+ *
+ * Units: nm, ns, nm^2/ns (= 1e-9 m^2/s), rate constants in 1e10 L/mol/s.
+ *
+ * Conventions
+ *   - Every function returns 0 (GSBS_OK) or a negative GSBS_E* code; the
+ *     message of the last failure on the calling thread is gsbs_last_error().
+ *   - Host arrays passed in are read during the call only; the caller keeps
+ *     ownership.  Device arrays passed in (flag device_ptrs) are read in
+ *     stream order on the context's stream and must stay valid until the
+ *     next synchronising call (gsbs_advance_to, gsbs_get_*, gsbs_sync).
+ *   - The context owns every device allocation it makes and frees them in
+ *     gsbs_destroy.  All work runs on the HIP stream given to gsbs_create.
+ *   - One context is used by one host thread at a time.
+ *   - Instances are independent periodic cubes simulated together: instance
+ *     i uses the Philox4x64-10 key (seed, i).
+ */
+#ifndef GSBS_H
+#define GSBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSBS_OK 0
+#define GSBS_EINVAL (-1)     /* bad argument */
+#define GSBS_ESTATE (-2)     /* call not valid now (e.g. time before the present) */
+#define GSBS_EMINIMAGE (-3)  /* reaction radius or cutoff too large for the cube */
+#define GSBS_ECAPACITY (-4)  /* molecule, pair or cell capacity exceeded */
+#define GSBS_EHIP (-5)       /* HIP runtime error */
+#define GSBS_ENOMEM (-6)     /* host or device allocation failed */
+
+#define GSBS_MAX_SPECIES 16
+#define GSBS_MAX_REACTIONS 32
+
+typedef struct gsbs_ctx gsbs_ctx;
+
+/* One periodic cube. */
+typedef struct {
+    double L_nm;          /* edge length; positions live in [-L/2, L/2)^3 */
+    int64_t capacity;     /* molecules this instance may hold at once (0: grow on demand) */
+} gsbs_box;
+
+/* One reaction of Table 1: a + b -> products. */
+typedef struct {
+    int32_t a, b;            /* reactant species indices */
+    double k_in;             /* rate constant as printed (for a == b the printed 2k) */
+    int32_t n_products;      /* 0..3 */
+    int32_t products[3];     /* species of the products */
+    int32_t keep_b;          /* 1: the reactant of species b survives unchanged (sink, tests) */
+} gsbs_reaction;
+
+/* Method and schedule parameters (gsbs_default_params fills the defaults). */
+typedef struct {
+    double c_cut;            /* candidate cutoff r_c = R + c_cut * sqrt(2 D_AB dt); 5 */
+    int32_t rounds;          /* mutual-best partner matching rounds per step; 4 */
+    int32_t contact_only;    /* 1: react only pairs within R at the start or end of a step */
+    double dt0_ns;           /* first step end after an injection; 1e-3 */
+    double ratio;            /* step end times after an injection: dt0 * ratio^j; 10^(6/1999) */
+    double dt_max_ns;        /* cap of a step; 0 = largest step keeping every r_c below L/2 */
+    double k_occ;            /* target molecules per cell of the search grid; 0 = autotuned */
+} gsbs_params;
+
+/* Counters since the context was created. */
+typedef struct {
+    int64_t steps;           /* global steps launched */
+    int64_t molecule_steps;  /* sum over active instances and steps of the live molecules */
+    int64_t reactions;       /* reactions performed */
+    int64_t pair_candidates; /* candidate pairs tested (end separation below r_c) */
+    int64_t max_live;        /* largest live count seen at a synchronisation point */
+} gsbs_stats;
+
+/* ---------------------------------------------------------------- setup --- */
+
+/* Fill p with the defaults listed above.  Host only. */
+int gsbs_default_params(gsbs_params* p);
+
+/* Create a context of n_instances cubes (boxes[i]) on `stream` (a hipStream_t,
+ * NULL for the null stream) of the current HIP device.  seed keys every Philox
+ * stream.  *out receives the context. */
+int gsbs_create(const gsbs_box* boxes, int32_t n_instances, uint64_t seed, void* stream,
+                gsbs_ctx** out);
+
+/* Free the context and all its device memory. NULL is accepted. */
+int gsbs_destroy(gsbs_ctx* ctx);
+
+/* Message of the last failure on this thread (never NULL). */
+const char* gsbs_last_error(void);
+
+/* Species diffusion coefficients D[0..n) in nm^2/ns (Table S2), n <= 16. Must be
+ * called before the first injection. */
+int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
+
+/* Reactions (Table 1), n <= 32, at most one reaction per unordered species pair.
+ * The engine derives each radius from the steady state of the supplement's
+ * k_diff(t): R = k_in / (4 pi (D_a + D_b) N_A).  Fails with GSBS_EMINIMAGE if
+ * 2R >= L for some cube (PBC 2). */
+int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
+
+/* Replace the method parameters (before the first advance). */
+int gsbs_set_params(gsbs_ctx* ctx, const gsbs_params* p);
+
+/* Reaction radii R[0..n_reactions) in nm. */
+int gsbs_get_radii(gsbs_ctx* ctx, double* R);
+
+/* Largest step of instance inst (ns) after the params' cap is applied. */
+int gsbs_get_dt_max(gsbs_ctx* ctx, int32_t inst, double* dt);
+
+/* ------------------------------------------------------------- injection --- */
+
+/* Queue n molecules for instance inst at time t_ns (>= the instance's time).
+ * xyz: n x 3 float32 positions inside [-L/2, L/2)^3; species: n uint8.  With
+ * device_ptrs = 1 both arrays are device pointers, else host pointers.  The
+ * molecules enter at the step boundary at t_ns (every injection time is a
+ * step boundary and restarts the step ramp), get uids in array order from the
+ * instance's counter, and add edep_eV to the deposited energy used by the
+ * G-values.  The arrays are copied before the call returns (device arrays in
+ * stream order). */
+int gsbs_inject(gsbs_ctx* ctx, int32_t inst, double t_ns, int64_t n, const float* xyz,
+                const uint8_t* species, double edep_eV, int32_t device_ptrs);
+
+/* Record times of instance inst (ns, ascending); counts are taken at each
+ * record time after that boundary's injection.  Replaces earlier records. */
+int gsbs_set_records(gsbs_ctx* ctx, int32_t inst, int32_t n, const double* t_ns);
+
+/* ---------------------------------------------------------------- advance --- */
+
+/* Advance every instance i to t_target[i] (>= its current time) by SBS steps:
+ * Brownian jump + PBC 1, cell binning, minimum-image candidate search, radial
+ * Brownian-bridge contact probability, mutual-best single-partner matching,
+ * products.  Returns after the device work has completed. */
+int gsbs_advance_to(gsbs_ctx* ctx, const double* t_target);
+
+/* Block until all queued work on the context's stream has finished. */
+int gsbs_sync(gsbs_ctx* ctx);
+
+/* -------------------------------------------------------------- results --- */
+
+/* Species counts of instance inst at its record times: out[n_records][n_species]
+ * (int64); records not reached yet hold -1. */
+int gsbs_get_counts(gsbs_ctx* ctx, int32_t inst, int64_t* out);
+
+/* G-values at the record times: out[n_records][n_species] in molecules per
+ * 100 eV of the energy deposited up to that record (NaN before any energy). */
+int gsbs_get_gvalues(gsbs_ctx* ctx, int32_t inst, double* out);
+
+/* Current species counts of instance inst: out[n_species]. */
+int gsbs_get_current_counts(gsbs_ctx* ctx, int32_t inst, int64_t* out);
+
+/* Current time (ns) and live molecule count of an instance. */
+int gsbs_get_time(gsbs_ctx* ctx, int32_t inst, double* t_ns);
+int gsbs_get_n(gsbs_ctx* ctx, int32_t inst, int64_t* n);
+
+int gsbs_get_stats(gsbs_ctx* ctx, gsbs_stats* out);
+
+/* Per-kernel timing with HIP events recorded around every step kernel on the
+ * context's stream (on = 1).  Profiling drains the stream after each step, so
+ * it is for measurement passes, not for production runs. */
+int gsbs_set_profiling(gsbs_ctx* ctx, int32_t on);
+
+/* Accumulated profile: for k < *n (at most max_k) the kernel name (NUL-padded
+ * in names[k*32 .. k*32+31]), total milliseconds and number of launches. */
+int gsbs_get_profile(gsbs_ctx* ctx, int32_t max_k, char* names, double* total_ms, int64_t* launches,
+                     int32_t* n);
+
+/* ------------------------------------------------- schedule (host only) --- */
+
+/* Step end times in (t_start, t_end] for ramp anchors (injection times) and
+ * events (records, injections; t_end is always one): after each anchor the
+ * lattice anchor + dt0 * ratio^j, j >= 0, up to the next anchor; lattice points
+ * within 1e-9 (relative) of an event are dropped; gaps above dt_max are cut in
+ * equal sub-steps.  Writes min(count, max_out) times to out (may be NULL) and
+ * returns the count in *n_out.  Needs no device. */
+int gsbs_plan_schedule(double t_start, double t_end, int32_t n_anchor, const double* anchors,
+                       int32_t n_events, const double* events, double dt0, double ratio,
+                       double dt_max, double* out, int64_t max_out, int64_t* n_out);
+
+/* ---------------------------------------------------------------- debug --- */
+
+/* Copy instance inst's live molecules out (host arrays of capacity max_n):
+ * positions xyz (n x 3), species, uids; *n receives the live count. */
+int gsbs_debug_get_state(gsbs_ctx* ctx, int32_t inst, int64_t max_n, float* xyz, uint8_t* species,
+                         uint64_t* uid, int64_t* n);
+
+/* Replace the whole state of a single-instance context: n molecules with
+ * positions xyz, species and uids (host arrays); `step` is the index the next
+ * step uses in its Philox counters; next_uid the next fresh uid. */
+int gsbs_debug_set_state(gsbs_ctx* ctx, int64_t n, const float* xyz, const uint8_t* species,
+                         const uint64_t* uid, int64_t step, uint64_t next_uid);
+
+/* One step of length dt_ns on a single-instance context.  flags bit 0: skip the
+ * Brownian jump and treat xyz0 (n x 3, host) as the start positions of the
+ * current state (pairs are then searched on fixed positions).  flags bit 1:
+ * log every candidate pair, not only accepted ones.  flags bit 2: stop after
+ * the pair search (no matching, no reactions, state unchanged).  nc_force > 0
+ * forces the search grid to nc_force^3 cells. */
+int gsbs_debug_step(gsbs_ctx* ctx, double dt_ns, int32_t flags, const float* xyz0, int32_t nc_force);
+
+/* Pair log of the last debug step (host arrays of capacity max_n): uid pairs
+ * (lower, higher), contact probability P (FP32), the pair uniform's 24-bit
+ * integer, reaction index, flags (bit0 accepted, bit1 reacted); *n the size. */
+int gsbs_debug_get_pairs(gsbs_ctx* ctx, int64_t max_n, uint64_t* uid2, float* P, uint32_t* u24,
+                         int32_t* rx, int32_t* flags, int64_t* n);
+
+/* Search grid of the last debug step: *nc cells per axis, and for every live
+ * molecule (same order as gsbs_debug_get_state after that step's sort) its
+ * cell index (ix*nc + iy)*nc + iz and uid. */
+int gsbs_debug_get_cells(gsbs_ctx* ctx, int64_t max_n, int32_t* cell, uint64_t* uid, int32_t* nc,
+                         int64_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSBS_H */

@@ -277,9 +277,10 @@ class Instance:
 
 
 def run(workload, chem: Chem = None, inst: int = 0, dt0: float = None, ratio: float = None,
-        dtmax: float = None, t_end: float = None, c_cut: float = 5.0):
-    """Run a workload.Workload through the oracle.  Returns dict with counts
-    (n_records x n_species), edep (eV at each record) and stats."""
+        dtmax: float = None, t_end: float = None, c_cut: float = 5.0, philox_seed: int = None):
+    """Run a workload.Workload through the oracle (Philox key (philox_seed or
+    workload.seed, inst)).  Returns dict with counts (n_records x n_species),
+    edep (eV at each record) and stats."""
     if chem is None:
         chem = make_chem(workload.D, workload.reactions, c_cut=c_cut)
     dt0 = workload.dt0 if dt0 is None else dt0
@@ -287,7 +288,7 @@ def run(workload, chem: Chem = None, inst: int = 0, dt0: float = None, ratio: fl
     t_end = workload.t_end if t_end is None else t_end
     if dtmax is None:
         dtmax = dt_max(chem, workload.L)
-    s = Instance(workload.L, workload.seed, inst)
+    s = Instance(workload.L, workload.seed if philox_seed is None else philox_seed, inst)
     injs = [i for i in workload.injections if i.t <= t_end]
     n_inj = len(injs)
     inj_t = np.array([i.t for i in injs], dtype=np.float64)

@@ -1,0 +1,1091 @@
+// api.cpp -- C ABI (include/gsbs.h) and host scheduler of the SBS engine.
+//
+// The host decides, for every instance, the step end times (ramp after each
+// injection, events, cap), builds the per-step parameter rows (sigma per
+// species, cutoff, radius, search grid) in pinned memory, uploads them in
+// chunks and launches the step kernels on the context's stream.  Injections
+// and record copies are issued at the step boundaries they belong to.  No
+// device result is needed on the host while stepping, so the stream is never
+// drained inside gsbs_advance_to except at its end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "gsbs.h"
+
+using namespace gsbs;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(GSBS_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+constexpr int kChunk = 64;  // global steps per uploaded parameter chunk
+
+// 1e10 L/mol/s expressed per pair in nm^3/ns: 1e10 * 1e24 nm^3 / (N_A * 1e9 ns)
+double rate_to_nm3_per_ns(double k_in) { return k_in * (1e25 / 6.02214076e23); }
+
+// Steady-state Smoluchowski radius (supplement: k = 4 pi R D_AB N_A).
+double smol_radius(double k_in, double Dab) {
+    return rate_to_nm3_per_ns(k_in) / (4.0 * 3.14159265358979323846264338327950 * Dab);
+}
+
+double cutoff_of(double R, double Dab, double dt, double c) { return R + c * std::sqrt(2.0 * Dab * dt); }
+
+struct Pending {
+    double t;
+    int64_t n;
+    float* d_xyz;
+    uint8_t* d_sp;
+    double edep;
+};
+
+struct InstHost {
+    double L = 0;
+    int64_t cap_hint = 0;
+    double t = 0;
+    uint64_t step = 0;
+    uint64_t next_uid = 0;
+    double edep = 0;
+    int64_t n_est = 0;
+    std::vector<double> anchors;
+    std::vector<Pending> pending;
+    std::vector<double> rec_t;
+    std::vector<char> rec_done;
+    std::vector<double> rec_edep;
+    double dt_max = 0;
+};
+
+// The step schedule: lattice anchor + dt0 * ratio^j after every anchor up to the
+// next one, every event a step end, lattice points within 1e-9 (relative) of
+// an event dropped, gaps above dt_max split evenly.
+struct TP {
+    double t;
+    int ev;
+};
+
+void plan_steps(double t_start, double t_end, const double* anchors, int na, const double* events, int ne,
+                double dt0, double ratio, double dt_max, std::vector<double>& out) {
+    std::vector<TP> pts;
+    for (int k = 0; k < na; ++k) {
+        const double a = anchors[k];
+        const double nxt = (k + 1 < na) ? anchors[k + 1] : INFINITY;
+        for (int64_t j = 0;; ++j) {
+            const double p = a + dt0 * std::pow(ratio, (double)j);
+            if (p >= nxt || p > t_end) break;
+            if (p <= t_start) continue;
+            pts.push_back({p, 0});
+        }
+    }
+    for (int k = 0; k <= ne; ++k) {
+        const double e = (k < ne) ? events[k] : t_end;
+        if (!(e > t_start) || e > t_end) continue;
+        pts.push_back({e, 1});
+    }
+    std::sort(pts.begin(), pts.end(), [](const TP& x, const TP& y) {
+        if (x.t != y.t) return x.t < y.t;
+        return x.ev > y.ev;
+    });
+    std::vector<TP> kept;
+    kept.reserve(pts.size());
+    for (const TP& q : pts) {
+        const double prev = kept.empty() ? t_start : kept.back().t;
+        const int prev_ev = kept.empty() ? 1 : kept.back().ev;
+        if (q.t - prev <= 1e-9 * std::fabs(q.t)) {
+            if (!kept.empty() && q.ev && !prev_ev) {
+                kept.back() = q;
+                continue;
+            }
+            if (!q.ev) continue;
+            if (q.t == prev) continue;
+        }
+        kept.push_back(q);
+    }
+    out.clear();
+    double prev = t_start;
+    for (const TP& q : kept) {
+        const double g = q.t - prev;
+        if (g > dt_max) {
+            const int64_t ns = (int64_t)std::ceil(g / dt_max);
+            for (int64_t s = 1; s < ns; ++s) out.push_back(prev + g * (double)s / (double)ns);
+        }
+        out.push_back(q.t);
+        prev = q.t;
+    }
+}
+
+}  // namespace
+
+struct gsbs_ctx {
+    int n_inst = 0;
+    uint64_t seed = 0;
+    hipStream_t st = nullptr;
+    std::vector<InstHost> inst;
+    gsbs_params prm{};
+    int ns = 0;
+    std::vector<double> D;
+    std::vector<gsbs_reaction> rx;
+    std::vector<double> R;
+    bool chem_ready = false;
+    ChemDev chem_h{};
+    ChemDev* chem_d = nullptr;
+
+    int32_t cap = 0;
+    float4* pos[2] = {nullptr, nullptr};
+    uint64_t* uid[2] = {nullptr, nullptr};
+    int cur = 0;
+    float4* pos0 = nullptr;
+    uint2* cellrank = nullptr;
+    unsigned long long* claim = nullptr;
+    int32_t* mate = nullptr;
+    float4* x0_dbg = nullptr;
+    int32_t cell_cap = 0;
+    uint32_t* cell_count = nullptr;
+    uint32_t* cell_start = nullptr;
+    uint32_t* block_sums = nullptr;
+    PairRec* pairs = nullptr;
+    uint32_t pair_cap = 0;
+    long long* counts = nullptr;
+    unsigned long long* msteps = nullptr;
+    DevCounters* ctr = nullptr;
+    long long* rec = nullptr;
+    int32_t max_rec = 0;
+
+    InstStep* h_chunk[2] = {nullptr, nullptr};
+    InstStep* d_chunk[2] = {nullptr, nullptr};
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+    int chunk_buf = 0;
+
+    int64_t steps = 0;
+    int64_t max_live = 0;
+    // profiling
+    bool profiling = false;
+    hipEvent_t prof_ev[2 * kStepKernels] = {};
+    double prof_ms[kStepKernels] = {};
+    int64_t prof_n[kStepKernels] = {};
+    // last debug step
+    int32_t dbg_nc = 0;
+    int32_t dbg_cell_base = 0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T) + 16);
+    if (e != hipSuccess) return fail(GSBS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    *p = (T*)q;
+    return GSBS_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+#define CHK(x)                      \
+    do {                            \
+        int r_ = (x);               \
+        if (r_ != GSBS_OK) return r_; \
+    } while (0)
+
+int read_counters(gsbs_ctx* c, DevCounters* out) {
+    HIPCHK(hipMemcpyAsync(out, c->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GSBS_OK;
+}
+
+// Grow the molecule arrays to hold at least `need` molecules.
+int ensure_capacity(gsbs_ctx* c, int64_t need) {
+    if (need <= c->cap) return GSBS_OK;
+    int64_t nc = std::max<int64_t>({need, (int64_t)c->cap * 2, 4096});
+    if (nc > (int64_t)0x7FFFFFF0) return fail(GSBS_ECAPACITY, "molecule capacity beyond 2^31");
+    DevCounters h{};
+    int32_t n_in = 0;
+    if (c->ctr) {
+        CHK(read_counters(c, &h));
+        n_in = h.n_in;
+    }
+    float4* np[2];
+    uint64_t* nu[2];
+    for (int b = 0; b < 2; ++b) {
+        CHK(dalloc(&np[b], nc));
+        CHK(dalloc(&nu[b], nc));
+    }
+    if (n_in > 0) {
+        HIPCHK(hipMemcpyAsync(np[0], c->pos[c->cur], sizeof(float4) * n_in, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(nu[0], c->uid[c->cur], sizeof(uint64_t) * n_in, hipMemcpyDeviceToDevice, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int b = 0; b < 2; ++b) {
+        dfree(c->pos[b]);
+        dfree(c->uid[b]);
+        c->pos[b] = np[b];
+        c->uid[b] = nu[b];
+    }
+    c->cur = 0;
+    dfree(c->pos0);
+    dfree(c->cellrank);
+    dfree(c->claim);
+    dfree(c->mate);
+    dfree(c->x0_dbg);
+    CHK(dalloc(&c->pos0, nc));
+    CHK(dalloc(&c->cellrank, nc));
+    CHK(dalloc(&c->claim, nc));
+    CHK(dalloc(&c->mate, nc));
+    CHK(dalloc(&c->x0_dbg, nc));
+    HIPCHK(hipMemsetAsync(c->claim, 0xFF, sizeof(unsigned long long) * nc, c->st));
+    HIPCHK(hipMemsetAsync(c->mate, 0xFF, sizeof(int32_t) * nc, c->st));
+    c->cap = (int32_t)nc;
+    uint32_t want_pairs = (uint32_t)std::max<int64_t>(1 << 16, nc);
+    if (want_pairs > c->pair_cap) {
+        dfree(c->pairs);
+        CHK(dalloc(&c->pairs, want_pairs));
+        c->pair_cap = want_pairs;
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GSBS_OK;
+}
+
+int ensure_cells(gsbs_ctx* c, int64_t total) {
+    if (total <= c->cell_cap) return GSBS_OK;
+    int64_t nc = std::max<int64_t>(total, (int64_t)c->cell_cap * 2);
+    nc = std::max<int64_t>(nc, 4096);
+    HIPCHK(hipStreamSynchronize(c->st));
+    dfree(c->cell_count);
+    dfree(c->cell_start);
+    dfree(c->block_sums);
+    CHK(dalloc(&c->cell_count, nc + 1));
+    CHK(dalloc(&c->cell_start, nc + 1));
+    CHK(dalloc(&c->block_sums, nc / 4096 + 2));
+    HIPCHK(hipMemsetAsync(c->cell_count, 0, sizeof(uint32_t) * (nc + 1), c->st));
+    c->cell_cap = (int32_t)nc;
+    return GSBS_OK;
+}
+
+int ensure_pairs(gsbs_ctx* c, uint32_t want) {
+    if (want <= c->pair_cap) return GSBS_OK;
+    HIPCHK(hipStreamSynchronize(c->st));
+    dfree(c->pairs);
+    CHK(dalloc(&c->pairs, want));
+    c->pair_cap = want;
+    return GSBS_OK;
+}
+
+int build_chem(gsbs_ctx* c) {
+    ChemDev& h = c->chem_h;
+    std::memset(&h, 0, sizeof(h));
+    for (int a = 0; a < kMaxSpecies; ++a)
+        for (int b = 0; b < kMaxSpecies; ++b) h.rmap[a][b] = -1;
+    for (int s = 0; s < c->ns; ++s) h.D[s] = (float)c->D[s];
+    c->R.assign(c->rx.size(), 0.0);
+    uint32_t mask = 0;
+    for (size_t r = 0; r < c->rx.size(); ++r) {
+        const gsbs_reaction& q = c->rx[r];
+        h.rmap[q.a][q.b] = (int32_t)r;
+        h.rmap[q.b][q.a] = (int32_t)r;
+        h.nprod[r] = q.n_products;
+        for (int k = 0; k < 3; ++k) h.prod[r][k] = q.products[k];
+        h.keep_b[r] = q.keep_b;
+        h.rb[r] = q.b;
+        mask |= (1u << q.a) | (1u << q.b);
+        const double Dab = c->D[q.a] + c->D[q.b];
+        c->R[r] = Dab > 0 ? smol_radius(q.k_in, Dab) : 0.0;
+    }
+    h.reactive_mask = mask;
+    h.n_species = c->ns;
+    h.rounds = c->prm.rounds;
+    h.contact_only = c->prm.contact_only;
+    if (!c->chem_d) CHK(dalloc(&c->chem_d, 1));
+    HIPCHK(hipMemcpyAsync(c->chem_d, &h, sizeof(ChemDev), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    // largest step keeping every cutoff below L/2 (minimum image unique)
+    for (auto& in : c->inst) {
+        double best = INFINITY;
+        for (size_t r = 0; r < c->rx.size(); ++r) {
+            const double Dab = c->D[c->rx[r].a] + c->D[c->rx[r].b];
+            if (Dab <= 0) continue;
+            const double room = (0.5 * in.L - c->R[r]) / c->prm.c_cut;
+            if (room <= 0) return fail(GSBS_EMINIMAGE, "reaction radius reaches L/2");
+            best = std::min(best, room * room / (2.0 * Dab));
+        }
+        if (c->prm.dt_max_ns > 0) best = std::min(best, c->prm.dt_max_ns);
+        in.dt_max = best;
+    }
+    c->chem_ready = true;
+    return GSBS_OK;
+}
+
+// Per-instance parameters of one step.  Returns the cells of the grid.
+int32_t fill_step(const gsbs_ctx* c, double L, uint64_t step, int64_t n_est, int idx, double dt, bool active,
+                  int32_t cell_base, int32_t nc_force, InstStep& S) {
+    std::memset(&S, 0, sizeof(S));
+    S.L = (float)L;
+    S.halfL = 0.5f * S.L;
+    S.invL = 1.0f / S.L;
+    S.active = active ? 1 : 0;
+    S.step = step;
+    S.key0 = c->seed;
+    S.key1 = (uint64_t)idx;
+    S.cell_base = cell_base;
+    double rcmax = 0.0;
+    if (active) {
+        for (int s = 0; s < c->ns; ++s) S.sigma[s] = (float)std::sqrt(2.0 * c->D[s] * dt);
+        for (size_t r = 0; r < c->rx.size(); ++r) {
+            const double Dab = c->D[c->rx[r].a] + c->D[c->rx[r].b];
+            const double rc = cutoff_of(c->R[r], Dab, dt, c->prm.c_cut);
+            S.rc2[r] = (float)(rc * rc);
+            S.R[r] = (float)c->R[r];
+            S.inv_s[r] = (Dab * dt > 0) ? (float)(1.0 / (Dab * dt)) : 0.0f;
+            rcmax = std::max(rcmax, rc);
+        }
+    }
+    int64_t nc;
+    if (nc_force > 0) {
+        nc = nc_force;  // validated by the caller
+    } else {
+        // cells no smaller than the largest cutoff (with margin for FP32 binning)
+        nc = rcmax > 0 ? (int64_t)std::floor(L / (rcmax * (1.0 + 1e-5))) : 1024;
+        const double kocc = c->prm.k_occ > 0 ? c->prm.k_occ : 2.0;
+        const int64_t nocc = (int64_t)std::floor(std::cbrt((double)std::max<int64_t>(n_est, 1) / kocc));
+        nc = std::min<int64_t>(nc, std::max<int64_t>(nocc, 1));
+        nc = std::min<int64_t>(nc, 1024);
+        nc = std::max<int64_t>(nc, 1);
+    }
+    S.nc = (int32_t)nc;
+    S.inv_h = (float)S.nc / S.L;
+    return (int32_t)(nc * nc * nc);
+}
+
+StepBuffers buffers(gsbs_ctx* c) {
+    StepBuffers b{};
+    b.pos_in = c->pos[c->cur];
+    b.uid_in = c->uid[c->cur];
+    b.pos_out = c->pos[c->cur ^ 1];
+    b.uid_out = c->uid[c->cur ^ 1];
+    b.pos0_out = c->pos0;
+    b.cellrank = c->cellrank;
+    b.cell_count = c->cell_count;
+    b.cell_start = c->cell_start;
+    b.block_sums = c->block_sums;
+    b.pairs = c->pairs;
+    b.pair_cap = c->pair_cap;
+    b.claim = c->claim;
+    b.mate = c->mate;
+    b.counts = c->counts;
+    b.msteps = c->msteps;
+    b.ctr = c->ctr;
+    b.cap = c->cap;
+    b.x0_override = c->x0_dbg;
+    return b;
+}
+
+int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_inst, int32_t cells, int32_t grid,
+             int32_t flags) {
+    launch_step(c->st, bf, P, c->chem_d, n_inst, cells, grid, flags, c->profiling ? c->prof_ev : nullptr);
+    HIPCHK(hipGetLastError());
+    if (c->profiling) {
+        HIPCHK(hipEventSynchronize(c->prof_ev[2 * kStepKernels - 1]));
+        for (int k = 0; k < kStepKernels; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
+            c->prof_ms[k] += ms;
+            c->prof_n[k] += 1;
+        }
+    }
+    return GSBS_OK;
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    g = std::max<int64_t>(g, 1);
+    return (int)std::min<int64_t>(g, 16384);
+}
+
+int apply_injection(gsbs_ctx* c, int idx, const Pending& p) {
+    InstHost& in = c->inst[idx];
+    launch_inject(c->st, c->pos[c->cur], c->uid[c->cur], c->counts, c->ctr, p.d_xyz, p.d_sp, (int32_t)p.n, idx,
+                  in.next_uid, c->cap);
+    HIPCHK(hipGetLastError());
+    in.next_uid += (uint64_t)p.n;
+    in.edep += p.edep;
+    return GSBS_OK;
+}
+
+// Injections due at the instance's present time, then its records there.
+int boundary(gsbs_ctx* c, int idx, RecordList& rl) {
+    InstHost& in = c->inst[idx];
+    std::vector<Pending> keep;
+    for (const Pending& p : in.pending) {
+        if (p.t <= in.t) {
+            CHK(apply_injection(c, idx, p));
+            in.n_est += p.n;
+            HIPCHK(hipStreamSynchronize(c->st));
+            dfree(const_cast<Pending&>(p).d_xyz);
+            dfree(const_cast<Pending&>(p).d_sp);
+        } else {
+            keep.push_back(p);
+        }
+    }
+    in.pending.swap(keep);
+    for (size_t r = 0; r < in.rec_t.size(); ++r) {
+        if (!in.rec_done[r] && in.rec_t[r] == in.t) {
+            in.rec_done[r] = 1;
+            in.rec_edep[r] = in.edep;
+            if (rl.n == 32) {
+                launch_record(c->st, c->counts, c->rec, c->max_rec, rl);
+                rl.n = 0;
+            }
+            rl.inst[rl.n] = idx;
+            rl.rec[rl.n] = (int32_t)r;
+            rl.n++;
+        }
+    }
+    return GSBS_OK;
+}
+
+int check_device_errors(gsbs_ctx* c) {
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    if (h.err & kErrMolOverflow) return fail(GSBS_ECAPACITY, "molecule capacity exceeded on the device");
+    if (h.err & kErrPairOverflow) return fail(GSBS_ECAPACITY, "pair list capacity exceeded on the device");
+    if (h.err & kErrTie) return fail(GSBS_ESTATE, "two pairs with identical matching keys");
+    return GSBS_OK;
+}
+
+int refresh_estimates(gsbs_ctx* c) {
+    std::vector<long long> cnt((size_t)c->n_inst * kMaxSpecies);
+    HIPCHK(hipMemcpyAsync(cnt.data(), c->counts, sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    int64_t tot = 0;
+    for (int i = 0; i < c->n_inst; ++i) {
+        int64_t s = 0;
+        for (int k = 0; k < kMaxSpecies; ++k) s += cnt[(size_t)i * kMaxSpecies + k];
+        c->inst[i].n_est = s;
+        tot += s;
+    }
+    c->max_live = std::max<int64_t>(c->max_live, tot);
+    return GSBS_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char* gsbs_last_error(void) { return g_err.c_str(); }
+
+int gsbs_default_params(gsbs_params* p) {
+    if (!p) return fail(GSBS_EINVAL, "null params");
+    p->c_cut = 5.0;
+    p->rounds = 4;
+    p->contact_only = 0;
+    p->dt0_ns = 1e-3;
+    p->ratio = std::pow(10.0, 6.0 / 1999.0);
+    p->dt_max_ns = 0.0;
+    p->k_occ = 0.0;
+    return GSBS_OK;
+}
+
+int gsbs_create(const gsbs_box* boxes, int32_t n_instances, uint64_t seed, void* stream, gsbs_ctx** out) {
+    if (!boxes || !out || n_instances <= 0 || n_instances > (1 << 23)) return fail(GSBS_EINVAL, "bad instances");
+    for (int i = 0; i < n_instances; ++i)
+        if (!(boxes[i].L_nm > 0)) return fail(GSBS_EINVAL, "box edge must be positive");
+    gsbs_ctx* c = new gsbs_ctx();
+    c->n_inst = n_instances;
+    c->seed = seed;
+    c->st = (hipStream_t)stream;
+    gsbs_default_params(&c->prm);
+    c->inst.resize(n_instances);
+    int64_t cap = 0;
+    for (int i = 0; i < n_instances; ++i) {
+        c->inst[i].L = boxes[i].L_nm;
+        c->inst[i].cap_hint = boxes[i].capacity;
+        cap += std::max<int64_t>(boxes[i].capacity, 0);
+    }
+    int r = GSBS_OK;
+    if ((r = dalloc(&c->ctr, 1)) || (r = dalloc(&c->counts, (size_t)n_instances * kMaxSpecies)) ||
+        (r = dalloc(&c->msteps, (size_t)n_instances))) {
+        gsbs_destroy(c);
+        return r;
+    }
+    hipError_t e = hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->counts, 0, sizeof(long long) * n_instances * kMaxSpecies, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->msteps, 0, sizeof(unsigned long long) * n_instances, c->st);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipHostMalloc((void**)&c->h_chunk[b], sizeof(InstStep) * kChunk * n_instances);
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_chunk[b], sizeof(InstStep) * kChunk * n_instances);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunk_ev[b], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        gsbs_destroy(c);
+        return fail(GSBS_EHIP, std::string("create: ") + hipGetErrorString(e));
+    }
+    if ((r = ensure_capacity(c, std::max<int64_t>(cap, 4096))) != GSBS_OK || (r = ensure_cells(c, 4096))) {
+        gsbs_destroy(c);
+        return r;
+    }
+    *out = c;
+    return GSBS_OK;
+}
+
+int gsbs_destroy(gsbs_ctx* c) {
+    if (!c) return GSBS_OK;
+    if (c->st || true) (void)hipStreamSynchronize(c->st);
+    for (auto& in : c->inst)
+        for (auto& p : in.pending) {
+            dfree(p.d_xyz);
+            dfree(p.d_sp);
+        }
+    for (int b = 0; b < 2; ++b) {
+        dfree(c->pos[b]);
+        dfree(c->uid[b]);
+        if (c->h_chunk[b]) (void)hipHostFree(c->h_chunk[b]);
+        dfree(c->d_chunk[b]);
+        if (c->chunk_ev[b]) (void)hipEventDestroy(c->chunk_ev[b]);
+    }
+    dfree(c->pos0);
+    dfree(c->cellrank);
+    dfree(c->claim);
+    dfree(c->mate);
+    dfree(c->x0_dbg);
+    dfree(c->cell_count);
+    dfree(c->cell_start);
+    dfree(c->block_sums);
+    dfree(c->pairs);
+    dfree(c->counts);
+    dfree(c->msteps);
+    dfree(c->ctr);
+    dfree(c->rec);
+    dfree(c->chem_d);
+    for (auto& e : c->prof_ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return GSBS_OK;
+}
+
+int gsbs_set_species(gsbs_ctx* c, int32_t n, const double* D) {
+    if (!c || !D || n <= 0 || n > kMaxSpecies) return fail(GSBS_EINVAL, "species: 1..16 coefficients");
+    for (int i = 0; i < n; ++i)
+        if (!(D[i] >= 0)) return fail(GSBS_EINVAL, "negative diffusion coefficient");
+    c->ns = n;
+    c->D.assign(D, D + n);
+    c->chem_ready = false;
+    if (!c->rx.empty()) return build_chem(c);
+    return GSBS_OK;
+}
+
+int gsbs_set_reactions(gsbs_ctx* c, int32_t n, const gsbs_reaction* r) {
+    if (!c || n < 0 || n > kMaxReactions || (n > 0 && !r)) return fail(GSBS_EINVAL, "reactions: 0..32");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    std::vector<int> seen(kMaxSpecies * kMaxSpecies, 0);
+    for (int k = 0; k < n; ++k) {
+        const gsbs_reaction& q = r[k];
+        if (q.a < 0 || q.b < 0 || q.a >= c->ns || q.b >= c->ns) return fail(GSBS_EINVAL, "reactant species");
+        if (q.n_products < 0 || q.n_products > 3) return fail(GSBS_EINVAL, "0..3 products");
+        for (int p = 0; p < q.n_products; ++p)
+            if (q.products[p] < 0 || q.products[p] >= c->ns) return fail(GSBS_EINVAL, "product species");
+        if (!(q.k_in > 0)) return fail(GSBS_EINVAL, "rate constant must be positive");
+        if (q.keep_b && (q.a == q.b || q.n_products != 0)) return fail(GSBS_EINVAL, "keep_b needs a != b, no products");
+        if (seen[q.a * kMaxSpecies + q.b]++ || (q.a != q.b && seen[q.b * kMaxSpecies + q.a]++))
+            return fail(GSBS_EINVAL, "two reactions for one species pair");
+    }
+    c->rx.assign(r, r + n);
+    CHK(build_chem(c));
+    for (size_t k = 0; k < c->rx.size(); ++k)
+        for (auto& in : c->inst)
+            if (2.0 * c->R[k] >= in.L) return fail(GSBS_EMINIMAGE, "2R >= L");
+    return GSBS_OK;
+}
+
+int gsbs_set_params(gsbs_ctx* c, const gsbs_params* p) {
+    if (!c || !p) return fail(GSBS_EINVAL, "null");
+    if (!(p->c_cut > 0) || p->rounds < 1 || !(p->dt0_ns > 0) || !(p->ratio > 1.0) || p->dt_max_ns < 0 ||
+        p->k_occ < 0)
+        return fail(GSBS_EINVAL, "bad parameters");
+    c->prm = *p;
+    if (c->ns && !c->rx.empty()) return build_chem(c);
+    return GSBS_OK;
+}
+
+int gsbs_get_radii(gsbs_ctx* c, double* R) {
+    if (!c || !R) return fail(GSBS_EINVAL, "null");
+    for (size_t k = 0; k < c->R.size(); ++k) R[k] = c->R[k];
+    return GSBS_OK;
+}
+
+int gsbs_get_dt_max(gsbs_ctx* c, int32_t i, double* dt) {
+    if (!c || !dt || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    *dt = c->inst[i].dt_max;
+    return GSBS_OK;
+}
+
+int gsbs_inject(gsbs_ctx* c, int32_t i, double t, int64_t n, const float* xyz, const uint8_t* sp,
+                double edep, int32_t device_ptrs) {
+    if (!c || i < 0 || i >= c->n_inst || n < 0 || (n > 0 && (!xyz || !sp)))
+        return fail(GSBS_EINVAL, "bad injection");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    InstHost& in = c->inst[i];
+    if (t < in.t) return fail(GSBS_ESTATE, "injection before the instance's present time");
+    if (!device_ptrs) {
+        for (int64_t k = 0; k < n; ++k)
+            if (sp[k] >= c->ns) return fail(GSBS_EINVAL, "species index out of range");
+    }
+    int64_t total = 0;
+    for (auto& q : c->inst) {
+        int64_t pend = 0;
+        for (auto& p : q.pending) pend += p.n;
+        total += q.n_est + pend;
+    }
+    total += n;
+    // R1-like reactions add one molecule per two consumed: 1.5x covers the worst case
+    CHK(ensure_capacity(c, total + total / 2 + 1024));
+    Pending p{t, n, nullptr, nullptr, edep};
+    if (n > 0) {
+        CHK(dalloc(&p.d_xyz, (size_t)n * 3));
+        CHK(dalloc(&p.d_sp, (size_t)n));
+        const hipMemcpyKind k = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIPCHK(hipMemcpyAsync(p.d_xyz, xyz, sizeof(float) * 3 * n, k, c->st));
+        HIPCHK(hipMemcpyAsync(p.d_sp, sp, (size_t)n, k, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    in.pending.push_back(p);
+    std::stable_sort(in.pending.begin(), in.pending.end(), [](const Pending& x, const Pending& y) { return x.t < y.t; });
+    in.anchors.push_back(t);
+    std::sort(in.anchors.begin(), in.anchors.end());
+    in.anchors.erase(std::unique(in.anchors.begin(), in.anchors.end()), in.anchors.end());
+    return GSBS_OK;
+}
+
+int gsbs_set_records(gsbs_ctx* c, int32_t i, int32_t n, const double* t) {
+    if (!c || i < 0 || i >= c->n_inst || n < 0 || (n > 0 && !t)) return fail(GSBS_EINVAL, "bad records");
+    for (int k = 1; k < n; ++k)
+        if (!(t[k] > t[k - 1])) return fail(GSBS_EINVAL, "record times must increase");
+    if (n > c->max_rec) {
+        const int32_t nm = std::max(n, c->max_rec * 2);
+        long long* nr = nullptr;
+        CHK(dalloc(&nr, (size_t)c->n_inst * nm * kMaxSpecies));
+        std::vector<long long> fill((size_t)c->n_inst * nm * kMaxSpecies, -1);
+        if (c->rec) {
+            std::vector<long long> old((size_t)c->n_inst * c->max_rec * kMaxSpecies);
+            HIPCHK(hipMemcpyAsync(old.data(), c->rec, sizeof(long long) * old.size(), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            for (int q = 0; q < c->n_inst; ++q)
+                std::memcpy(&fill[(size_t)q * nm * kMaxSpecies], &old[(size_t)q * c->max_rec * kMaxSpecies],
+                            sizeof(long long) * c->max_rec * kMaxSpecies);
+        }
+        HIPCHK(hipMemcpyAsync(nr, fill.data(), sizeof(long long) * fill.size(), hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        dfree(c->rec);
+        c->rec = nr;
+        c->max_rec = nm;
+    }
+    std::vector<long long> neg((size_t)c->max_rec * kMaxSpecies, -1);
+    HIPCHK(hipMemcpyAsync(c->rec + (size_t)i * c->max_rec * kMaxSpecies, neg.data(), sizeof(long long) * neg.size(),
+                          hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    InstHost& in = c->inst[i];
+    in.rec_t.assign(t, t + n);
+    in.rec_done.assign(n, 0);
+    in.rec_edep.assign(n, 0.0);
+    return GSBS_OK;
+}
+
+int gsbs_advance_to(gsbs_ctx* c, const double* target) {
+    if (!c || !target) return fail(GSBS_EINVAL, "null");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (target[i] < c->inst[i].t) return fail(GSBS_ESTATE, "target time before the present");
+    // schedules
+    std::vector<std::vector<double>> sched(c->n_inst);
+    size_t G = 0;
+    for (int i = 0; i < c->n_inst; ++i) {
+        InstHost& in = c->inst[i];
+        std::vector<double> ev;
+        for (double r : in.rec_t)
+            if (r > in.t && r <= target[i]) ev.push_back(r);
+        for (auto& p : in.pending)
+            if (p.t > in.t && p.t <= target[i]) ev.push_back(p.t);
+        std::sort(ev.begin(), ev.end());
+        plan_steps(in.t, target[i], in.anchors.data(), (int)in.anchors.size(), ev.data(), (int)ev.size(),
+                   c->prm.dt0_ns, c->prm.ratio, in.dt_max, sched[i]);
+        G = std::max(G, sched[i].size());
+    }
+    std::vector<double> t0(c->n_inst);
+    std::vector<uint64_t> step0(c->n_inst);
+    for (int i = 0; i < c->n_inst; ++i) {
+        t0[i] = c->inst[i].t;
+        step0[i] = c->inst[i].step;
+    }
+    // boundary at the present time
+    RecordList rl{};
+    for (int i = 0; i < c->n_inst; ++i) CHK(boundary(c, i, rl));
+    launch_record(c->st, c->counts, c->rec, c->max_rec, rl);
+    rl.n = 0;
+
+    std::vector<int32_t> total_cells(kChunk);
+    for (size_t g0 = 0; g0 < G; g0 += kChunk) {
+        const int nstep = (int)std::min<size_t>(kChunk, G - g0);
+        const int b = c->chunk_buf;
+        HIPCHK(hipEventSynchronize(c->chunk_ev[b]));
+        InstStep* hrow = c->h_chunk[b];
+        // n_est evolves with the injections inside the chunk
+        std::vector<int64_t> nest(c->n_inst);
+        for (int i = 0; i < c->n_inst; ++i) nest[i] = c->inst[i].n_est;
+        int64_t n_total = 0;
+        for (int k = 0; k < nstep; ++k) {
+            int32_t base = 0;
+            for (int i = 0; i < c->n_inst; ++i) {
+                const size_t g = g0 + k;
+                const bool active = g < sched[i].size();
+                const double tprev = (g == 0) ? t0[i] : sched[i][g - 1];
+                const double dt = active ? sched[i][g] - tprev : 0.0;
+                const uint64_t stp = step0[i] + (uint64_t)std::min<size_t>(g, sched[i].size());
+                base += fill_step(c, c->inst[i].L, stp, nest[i], i, dt, active, base, 0,
+                                  hrow[(size_t)k * c->n_inst + i]);
+                if (active)
+                    for (auto& p : c->inst[i].pending)
+                        if (p.t == sched[i][g]) nest[i] += p.n;
+            }
+            total_cells[k] = base;
+        }
+        for (int i = 0; i < c->n_inst; ++i) n_total += std::max(nest[i], c->inst[i].n_est);
+        int32_t maxc = 0;
+        for (int k = 0; k < nstep; ++k) maxc = std::max(maxc, total_cells[k]);
+        CHK(ensure_cells(c, maxc));
+        HIPCHK(hipMemcpyAsync(c->d_chunk[b], hrow, sizeof(InstStep) * nstep * c->n_inst, hipMemcpyHostToDevice,
+                              c->st));
+        HIPCHK(hipEventRecord(c->chunk_ev[b], c->st));
+        c->chunk_buf ^= 1;
+        for (int k = 0; k < nstep; ++k) {
+            const size_t g = g0 + k;
+            StepBuffers bf = buffers(c);
+            CHK(run_step(c, bf, c->d_chunk[b] + (size_t)k * c->n_inst, c->n_inst, total_cells[k], grid_for(n_total),
+                         0));
+            c->cur ^= 1;
+            c->steps++;
+            for (int i = 0; i < c->n_inst; ++i) {
+                if (g >= sched[i].size()) continue;
+                c->inst[i].t = sched[i][g];
+                c->inst[i].step++;
+                CHK(boundary(c, i, rl));
+            }
+            if (rl.n) {
+                launch_record(c->st, c->counts, c->rec, c->max_rec, rl);
+                rl.n = 0;
+            }
+        }
+        for (int i = 0; i < c->n_inst; ++i) c->inst[i].n_est = nest[i];
+    }
+    for (int i = 0; i < c->n_inst; ++i) c->inst[i].t = target[i];
+    HIPCHK(hipStreamSynchronize(c->st));
+    CHK(check_device_errors(c));
+    return refresh_estimates(c);
+}
+
+int gsbs_sync(gsbs_ctx* c) {
+    if (!c) return fail(GSBS_EINVAL, "null");
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GSBS_OK;
+}
+
+int gsbs_get_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
+    if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    const InstHost& in = c->inst[i];
+    if (in.rec_t.empty()) return GSBS_OK;
+    std::vector<long long> buf((size_t)c->max_rec * kMaxSpecies);
+    HIPCHK(hipMemcpyAsync(buf.data(), c->rec + (size_t)i * c->max_rec * kMaxSpecies, sizeof(long long) * buf.size(),
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (size_t r = 0; r < in.rec_t.size(); ++r)
+        for (int s = 0; s < c->ns; ++s) out[r * c->ns + s] = buf[r * kMaxSpecies + s];
+    return GSBS_OK;
+}
+
+int gsbs_get_gvalues(gsbs_ctx* c, int32_t i, double* out) {
+    if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    const InstHost& in = c->inst[i];
+    std::vector<int64_t> cnt(in.rec_t.size() * (size_t)c->ns);
+    CHK(gsbs_get_counts(c, i, cnt.data()));
+    for (size_t r = 0; r < in.rec_t.size(); ++r)
+        for (int s = 0; s < c->ns; ++s) {
+            const double e = in.rec_edep[r];
+            const int64_t v = cnt[r * c->ns + s];
+            out[r * c->ns + s] = (in.rec_done[r] && e > 0 && v >= 0) ? (double)v / (e / 100.0) : NAN;
+        }
+    return GSBS_OK;
+}
+
+int gsbs_get_current_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
+    if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    std::vector<long long> buf(kMaxSpecies);
+    HIPCHK(hipMemcpyAsync(buf.data(), c->counts + (size_t)i * kMaxSpecies, sizeof(long long) * kMaxSpecies,
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int s = 0; s < c->ns; ++s) out[s] = buf[s];
+    return GSBS_OK;
+}
+
+int gsbs_get_time(gsbs_ctx* c, int32_t i, double* t) {
+    if (!c || !t || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    *t = c->inst[i].t;
+    return GSBS_OK;
+}
+
+int gsbs_get_n(gsbs_ctx* c, int32_t i, int64_t* n) {
+    if (!c || !n || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    std::vector<int64_t> cnt(c->ns);
+    CHK(gsbs_get_current_counts(c, i, cnt.data()));
+    int64_t s = 0;
+    for (auto v : cnt) s += v;
+    *n = s;
+    return GSBS_OK;
+}
+
+int gsbs_get_stats(gsbs_ctx* c, gsbs_stats* out) {
+    if (!c || !out) return fail(GSBS_EINVAL, "null");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    std::vector<unsigned long long> ms(c->n_inst);
+    HIPCHK(hipMemcpyAsync(ms.data(), c->msteps, sizeof(unsigned long long) * c->n_inst, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    out->steps = c->steps;
+    out->molecule_steps = 0;
+    for (auto v : ms) out->molecule_steps += (int64_t)v;
+    out->reactions = (int64_t)h.reactions;
+    out->pair_candidates = (int64_t)h.cand;
+    out->max_live = c->max_live;
+    return GSBS_OK;
+}
+
+int gsbs_set_profiling(gsbs_ctx* c, int32_t on) {
+    if (!c) return fail(GSBS_EINVAL, "null");
+    if (on && !c->prof_ev[0])
+        for (auto& e : c->prof_ev) HIPCHK(hipEventCreate(&e));
+    c->profiling = on != 0;
+    for (int k = 0; k < kStepKernels; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    return GSBS_OK;
+}
+
+int gsbs_get_profile(gsbs_ctx* c, int32_t max_k, char* names, double* total_ms, int64_t* launches, int32_t* n) {
+    if (!c || !n) return fail(GSBS_EINVAL, "null");
+    for (int k = 0; k < std::min(max_k, kStepKernels); ++k) {
+        if (names) {
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, kStepKernelNames[k], 31);
+        }
+        if (total_ms) total_ms[k] = c->prof_ms[k];
+        if (launches) launches[k] = c->prof_n[k];
+    }
+    *n = kStepKernels;
+    return GSBS_OK;
+}
+
+int gsbs_plan_schedule(double t_start, double t_end, int32_t n_anchor, const double* anchors, int32_t n_events,
+                       const double* events, double dt0, double ratio, double dt_max, double* out, int64_t max_out,
+                       int64_t* n_out) {
+    if (!n_out || n_anchor < 0 || n_events < 0 || (n_anchor && !anchors) || (n_events && !events) ||
+        !(dt0 > 0) || !(ratio > 1) || !(dt_max > 0) || t_end < t_start)
+        return fail(GSBS_EINVAL, "bad schedule arguments");
+    std::vector<double> s;
+    plan_steps(t_start, t_end, anchors, n_anchor, events, n_events, dt0, ratio, dt_max, s);
+    *n_out = (int64_t)s.size();
+    if (out)
+        for (int64_t k = 0; k < std::min<int64_t>(max_out, (int64_t)s.size()); ++k) out[k] = s[k];
+    return GSBS_OK;
+}
+
+// ---------------------------------------------------------------- debug ---
+
+int gsbs_debug_get_state(gsbs_ctx* c, int32_t i, int64_t max_n, float* xyz, uint8_t* sp, uint64_t* uid,
+                         int64_t* n) {
+    if (!c || !n || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    std::vector<float4> p(h.n_in);
+    std::vector<uint64_t> u(h.n_in);
+    if (h.n_in > 0) {
+        HIPCHK(hipMemcpyAsync(p.data(), c->pos[c->cur], sizeof(float4) * h.n_in, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(u.data(), c->uid[c->cur], sizeof(uint64_t) * h.n_in, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    int64_t k = 0;
+    for (int32_t q = 0; q < h.n_in; ++q) {
+        int meta;
+        std::memcpy(&meta, &p[q].w, 4);
+        if ((meta & 0xFF) == kDead || (meta >> 8) != i) continue;
+        if (k < max_n) {
+            if (xyz) {
+                xyz[3 * k] = p[q].x;
+                xyz[3 * k + 1] = p[q].y;
+                xyz[3 * k + 2] = p[q].z;
+            }
+            if (sp) sp[k] = (uint8_t)(meta & 0xFF);
+            if (uid) uid[k] = u[q];
+        }
+        ++k;
+    }
+    *n = k;
+    return GSBS_OK;
+}
+
+int gsbs_debug_set_state(gsbs_ctx* c, int64_t n, const float* xyz, const uint8_t* sp, const uint64_t* uid,
+                         int64_t step, uint64_t next_uid) {
+    if (!c || n < 0 || (n > 0 && (!xyz || !sp || !uid))) return fail(GSBS_EINVAL, "bad state");
+    if (c->n_inst != 1) return fail(GSBS_EINVAL, "debug state needs a single-instance context");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    CHK(ensure_capacity(c, n + n / 2 + 1024));
+    std::vector<float4> p(n);
+    std::vector<long long> cnt(kMaxSpecies, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        if (sp[k] >= c->ns) return fail(GSBS_EINVAL, "species index out of range");
+        int meta = sp[k];
+        float w;
+        std::memcpy(&w, &meta, 4);
+        p[k] = make_float4(xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], w);
+        cnt[sp[k]]++;
+    }
+    c->cur = 0;
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(c->pos[0], p.data(), sizeof(float4) * n, hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(c->uid[0], uid, sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->st));
+    }
+    HIPCHK(hipMemcpyAsync(c->counts, cnt.data(), sizeof(long long) * kMaxSpecies, hipMemcpyHostToDevice, c->st));
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    h.n_in = (int32_t)n;
+    h.n_live = (int32_t)n;
+    h.n_pairs = 0;
+    h.err = 0;
+    HIPCHK(hipMemcpyAsync(c->ctr, &h, sizeof(DevCounters), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    InstHost& in = c->inst[0];
+    in.step = (uint64_t)step;
+    in.next_uid = next_uid;
+    in.n_est = n;
+    return GSBS_OK;
+}
+
+int gsbs_debug_step(gsbs_ctx* c, double dt, int32_t flags, const float* xyz0, int32_t nc_force) {
+    if (!c || !(dt > 0)) return fail(GSBS_EINVAL, "bad step");
+    if (c->n_inst != 1) return fail(GSBS_EINVAL, "debug step needs a single-instance context");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    if ((flags & kStepFixed)) {
+        if (!xyz0) return fail(GSBS_EINVAL, "fixed-position step needs start positions");
+        std::vector<float4> p(h.n_in);
+        for (int32_t k = 0; k < h.n_in; ++k) p[k] = make_float4(xyz0[3 * k], xyz0[3 * k + 1], xyz0[3 * k + 2], 0.f);
+        if (h.n_in)
+            HIPCHK(hipMemcpyAsync(c->x0_dbg, p.data(), sizeof(float4) * h.n_in, hipMemcpyHostToDevice, c->st));
+    }
+    if (flags & kStepLogAll) CHK(ensure_pairs(c, 1u << 24));
+    InstHost& in = c->inst[0];
+    in.n_est = std::max<int64_t>(h.n_in, 1);
+    InstStep* S = c->h_chunk[c->chunk_buf];
+    HIPCHK(hipEventSynchronize(c->chunk_ev[c->chunk_buf]));
+    if (nc_force > 0) {
+        double rcmax = 0.0;
+        for (size_t r = 0; r < c->rx.size(); ++r) {
+            const double Dab = c->D[c->rx[r].a] + c->D[c->rx[r].b];
+            rcmax = std::max(rcmax, cutoff_of(c->R[r], Dab, dt, c->prm.c_cut));
+        }
+        if (rcmax > 0 && nc_force > (int64_t)std::floor(in.L / (rcmax * (1.0 + 1e-5))))
+            return fail(GSBS_EINVAL, "forced search grid has cells smaller than the cutoff");
+        if (nc_force > 1024) return fail(GSBS_EINVAL, "forced search grid too fine");
+    }
+    const int32_t cells = fill_step(c, in.L, in.step, in.n_est, 0, dt, true, 0, nc_force, S[0]);
+    CHK(ensure_cells(c, cells));
+    HIPCHK(hipMemcpyAsync(c->d_chunk[c->chunk_buf], S, sizeof(InstStep), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipEventRecord(c->chunk_ev[c->chunk_buf], c->st));
+    StepBuffers bf = buffers(c);
+    CHK(run_step(c, bf, c->d_chunk[c->chunk_buf], 1, cells, grid_for(h.n_in), flags));
+    c->chunk_buf ^= 1;
+    c->cur ^= 1;
+    c->dbg_nc = S[0].nc;
+    c->dbg_cell_base = 0;
+    if (!(flags & kStepSearchOnly)) {
+        in.step++;
+        in.t += dt;
+        c->steps++;
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    CHK(check_device_errors(c));
+    return refresh_estimates(c);
+}
+
+int gsbs_debug_get_pairs(gsbs_ctx* c, int64_t max_n, uint64_t* uid2, float* P, uint32_t* u24, int32_t* rx,
+                         int32_t* flags, int64_t* n) {
+    if (!c || !n) return fail(GSBS_EINVAL, "null");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    const int64_t np = std::min<int64_t>(h.n_pairs, c->pair_cap);
+    std::vector<PairRec> pr(np);
+    std::vector<uint64_t> u(std::max<int32_t>(h.n_live, 1));
+    if (np > 0) {
+        HIPCHK(hipMemcpyAsync(pr.data(), c->pairs, sizeof(PairRec) * np, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(u.data(), c->uid[c->cur], sizeof(uint64_t) * h.n_live, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    for (int64_t k = 0; k < std::min(np, max_n); ++k) {
+        const uint64_t a = u[pr[k].i], b = u[pr[k].j];
+        if (uid2) {
+            uid2[2 * k] = a < b ? a : b;
+            uid2[2 * k + 1] = a < b ? b : a;
+        }
+        if (P) P[k] = pr[k].P;
+        if (u24) u24[k] = pr[k].u24;
+        if (rx) rx[k] = pr[k].rx;
+        if (flags) flags[k] = pr[k].flags;
+    }
+    *n = np;
+    return GSBS_OK;
+}
+
+int gsbs_debug_get_cells(gsbs_ctx* c, int64_t max_n, int32_t* cell, uint64_t* uid, int32_t* nc, int64_t* n) {
+    if (!c || !n) return fail(GSBS_EINVAL, "null");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    std::vector<float4> p0(std::max<int32_t>(h.n_live, 1));
+    std::vector<uint64_t> u(std::max<int32_t>(h.n_live, 1));
+    if (h.n_live > 0) {
+        HIPCHK(hipMemcpyAsync(p0.data(), c->pos0, sizeof(float4) * h.n_live, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(u.data(), c->uid[c->cur], sizeof(uint64_t) * h.n_live, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    for (int64_t k = 0; k < std::min<int64_t>(h.n_live, max_n); ++k) {
+        uint32_t g;
+        std::memcpy(&g, &p0[k].w, 4);
+        if (cell) cell[k] = (int32_t)g - c->dbg_cell_base;
+        if (uid) uid[k] = u[k];
+    }
+    if (nc) *nc = c->dbg_nc;
+    *n = h.n_live;
+    return GSBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,399 @@
+"""Python binding of libgsbs.so (include/gsbs.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; all of
+the method runs in the HIP kernels of the library.  PyTorch is used only to
+own device buffers (tensors passed to gsbs_inject with device_ptrs=1) and to
+provide the HIP stream.  Importing this module fails loudly if the library has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime first so that the library binds to the same one
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is optional for host-only calls
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsbs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2509_03313_amd.build.build() "
+                      "(or __graft_entry__.build()); there is no fallback path")
+
+_lib = C.CDLL(LIB_PATH)
+
+GSBS_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ESTATE", -3: "EMINIMAGE", -4: "ECAPACITY", -5: "EHIP", -6: "ENOMEM"}
+MAX_SPECIES = 16
+MAX_REACTIONS = 32
+
+
+class GsbsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gsbs error {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gsbs_box(C.Structure):
+    _fields_ = [("L_nm", C.c_double), ("capacity", C.c_int64)]
+
+
+class gsbs_reaction(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("k_in", C.c_double), ("n_products", C.c_int32),
+                ("products", C.c_int32 * 3), ("keep_b", C.c_int32)]
+
+
+class gsbs_params(C.Structure):
+    _fields_ = [("c_cut", C.c_double), ("rounds", C.c_int32), ("contact_only", C.c_int32),
+                ("dt0_ns", C.c_double), ("ratio", C.c_double), ("dt_max_ns", C.c_double),
+                ("k_occ", C.c_double)]
+
+
+class gsbs_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("molecule_steps", C.c_int64), ("reactions", C.c_int64),
+                ("pair_candidates", C.c_int64), ("max_live", C.c_int64)]
+
+
+_P = C.POINTER
+_vp = C.c_void_p
+_i32, _i64, _u64, _d = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+_SIGS = {
+    "gsbs_default_params": [_P(gsbs_params)],
+    "gsbs_create": [_P(gsbs_box), _i32, _u64, _vp, _P(_vp)],
+    "gsbs_destroy": [_vp],
+    "gsbs_set_species": [_vp, _i32, _P(_d)],
+    "gsbs_set_reactions": [_vp, _i32, _P(gsbs_reaction)],
+    "gsbs_set_params": [_vp, _P(gsbs_params)],
+    "gsbs_get_radii": [_vp, _P(_d)],
+    "gsbs_get_dt_max": [_vp, _i32, _P(_d)],
+    "gsbs_inject": [_vp, _i32, _d, _i64, _vp, _vp, _d, _i32],
+    "gsbs_set_records": [_vp, _i32, _i32, _P(_d)],
+    "gsbs_advance_to": [_vp, _P(_d)],
+    "gsbs_sync": [_vp],
+    "gsbs_get_counts": [_vp, _i32, _P(_i64)],
+    "gsbs_get_gvalues": [_vp, _i32, _P(_d)],
+    "gsbs_get_current_counts": [_vp, _i32, _P(_i64)],
+    "gsbs_get_time": [_vp, _i32, _P(_d)],
+    "gsbs_get_n": [_vp, _i32, _P(_i64)],
+    "gsbs_get_stats": [_vp, _P(gsbs_stats)],
+    "gsbs_set_profiling": [_vp, _i32],
+    "gsbs_get_profile": [_vp, _i32, C.c_char_p, _P(_d), _P(_i64), _P(_i32)],
+    "gsbs_plan_schedule": [_d, _d, _i32, _P(_d), _i32, _P(_d), _d, _d, _d, _P(_d), _i64, _P(_i64)],
+    "gsbs_debug_get_state": [_vp, _i32, _i64, _P(C.c_float), _P(C.c_uint8), _P(_u64), _P(_i64)],
+    "gsbs_debug_set_state": [_vp, _i64, _P(C.c_float), _P(C.c_uint8), _P(_u64), _i64, _u64],
+    "gsbs_debug_step": [_vp, _d, _i32, _P(C.c_float), _i32],
+    "gsbs_debug_get_pairs": [_vp, _i64, _P(_u64), _P(C.c_float), _P(C.c_uint32), _P(_i32), _P(_i32),
+                             _P(_i64)],
+    "gsbs_debug_get_cells": [_vp, _i64, _P(_i32), _P(_u64), _P(_i32), _P(_i64)],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.gsbs_last_error.argtypes = []
+_lib.gsbs_last_error.restype = C.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["gsbs_last_error"])
+
+
+def _chk(code):
+    if code != GSBS_OK:
+        raise GsbsError(code, _lib.gsbs_last_error().decode())
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(_P(t))
+
+
+def gsbs_last_error() -> str:
+    return _lib.gsbs_last_error().decode()
+
+
+# ------------------------------------------------------ thin wrappers ---
+def gsbs_default_params() -> gsbs_params:
+    p = gsbs_params()
+    _chk(_lib.gsbs_default_params(C.byref(p)))
+    return p
+
+
+def gsbs_create(boxes, seed: int, stream=None):
+    arr = (gsbs_box * len(boxes))()
+    for k, (L, cap) in enumerate(boxes):
+        arr[k].L_nm = float(L)
+        arr[k].capacity = int(cap)
+    h = _vp()
+    _chk(_lib.gsbs_create(arr, len(boxes), int(seed), stream, C.byref(h)))
+    return h
+
+
+def gsbs_destroy(ctx):
+    _chk(_lib.gsbs_destroy(ctx))
+
+
+def gsbs_set_species(ctx, D):
+    d = np.ascontiguousarray(D, dtype=np.float64)
+    _chk(_lib.gsbs_set_species(ctx, len(d), _ptr(d, _d)))
+
+
+def gsbs_set_reactions(ctx, reactions):
+    arr = (gsbs_reaction * max(len(reactions), 1))()
+    for k, r in enumerate(reactions):
+        arr[k].a, arr[k].b, arr[k].k_in = int(r.a), int(r.b), float(r.k_in)
+        arr[k].n_products = len(r.products)
+        for j, p in enumerate(r.products):
+            arr[k].products[j] = int(p)
+        arr[k].keep_b = 1 if getattr(r, "keep_b", False) else 0
+    _chk(_lib.gsbs_set_reactions(ctx, len(reactions), arr))
+
+
+def gsbs_set_params(ctx, p: gsbs_params):
+    _chk(_lib.gsbs_set_params(ctx, C.byref(p)))
+
+
+def gsbs_get_radii(ctx, n):
+    out = np.zeros(max(n, 1))
+    _chk(_lib.gsbs_get_radii(ctx, _ptr(out, _d)))
+    return out[:n]
+
+
+def gsbs_get_dt_max(ctx, inst):
+    v = _d()
+    _chk(_lib.gsbs_get_dt_max(ctx, inst, C.byref(v)))
+    return v.value
+
+
+def gsbs_inject(ctx, inst, t, xyz, species, edep_ev=0.0):
+    """xyz (n,3) float32 and species (n,) uint8: numpy arrays (host) or torch
+    tensors on the device (passed as device pointers)."""
+    if torch is not None and isinstance(xyz, torch.Tensor):
+        assert xyz.is_cuda and species.is_cuda and xyz.dtype == torch.float32 and species.dtype == torch.uint8
+        xyz = xyz.contiguous()
+        species = species.contiguous()
+        n = species.numel()
+        _chk(_lib.gsbs_inject(ctx, inst, float(t), n, C.c_void_p(xyz.data_ptr()),
+                              C.c_void_p(species.data_ptr()), float(edep_ev), 1))
+        return
+    x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    s = np.ascontiguousarray(species, dtype=np.uint8)
+    _chk(_lib.gsbs_inject(ctx, inst, float(t), len(s), x.ctypes.data_as(_vp), s.ctypes.data_as(_vp),
+                          float(edep_ev), 0))
+
+
+def gsbs_set_records(ctx, inst, times):
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    _chk(_lib.gsbs_set_records(ctx, inst, len(t), _ptr(t, _d)))
+
+
+def gsbs_advance_to(ctx, targets):
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    _chk(_lib.gsbs_advance_to(ctx, _ptr(t, _d)))
+
+
+def gsbs_sync(ctx):
+    _chk(_lib.gsbs_sync(ctx))
+
+
+def gsbs_get_counts(ctx, inst, n_records, n_species):
+    out = np.zeros((max(n_records, 1), n_species), dtype=np.int64)
+    _chk(_lib.gsbs_get_counts(ctx, inst, _ptr(out, _i64)))
+    return out[:n_records]
+
+
+def gsbs_get_gvalues(ctx, inst, n_records, n_species):
+    out = np.zeros((max(n_records, 1), n_species))
+    _chk(_lib.gsbs_get_gvalues(ctx, inst, _ptr(out, _d)))
+    return out[:n_records]
+
+
+def gsbs_get_current_counts(ctx, inst, n_species):
+    out = np.zeros(n_species, dtype=np.int64)
+    _chk(_lib.gsbs_get_current_counts(ctx, inst, _ptr(out, _i64)))
+    return out
+
+
+def gsbs_get_time(ctx, inst):
+    v = _d()
+    _chk(_lib.gsbs_get_time(ctx, inst, C.byref(v)))
+    return v.value
+
+
+def gsbs_get_n(ctx, inst):
+    v = _i64()
+    _chk(_lib.gsbs_get_n(ctx, inst, C.byref(v)))
+    return v.value
+
+
+def gsbs_get_stats(ctx):
+    s = gsbs_stats()
+    _chk(_lib.gsbs_get_stats(ctx, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in gsbs_stats._fields_}
+
+
+def gsbs_set_profiling(ctx, on: bool):
+    _chk(_lib.gsbs_set_profiling(ctx, 1 if on else 0))
+
+
+def gsbs_get_profile(ctx):
+    """{kernel name: (total ms, launches)} of the profiled steps."""
+    names = C.create_string_buffer(32 * 16)
+    ms = np.zeros(16)
+    nl = np.zeros(16, dtype=np.int64)
+    n = _i32()
+    _chk(_lib.gsbs_get_profile(ctx, 16, names, _ptr(ms, _d), _ptr(nl, _i64), C.byref(n)))
+    raw = names.raw
+    out = {}
+    for k in range(n.value):
+        nm = raw[32 * k:32 * k + 32].split(b"\0")[0].decode()
+        out[nm] = (float(ms[k]), int(nl[k]))
+    return out
+
+
+def gsbs_plan_schedule(t_start, t_end, anchors, events, dt0, ratio, dt_max):
+    a = np.ascontiguousarray(anchors, dtype=np.float64)
+    e = np.ascontiguousarray(events, dtype=np.float64)
+    n = _i64()
+    _chk(_lib.gsbs_plan_schedule(t_start, t_end, len(a), _ptr(a, _d), len(e), _ptr(e, _d), dt0, ratio, dt_max,
+                                 None, 0, C.byref(n)))
+    out = np.zeros(max(n.value, 1))
+    _chk(_lib.gsbs_plan_schedule(t_start, t_end, len(a), _ptr(a, _d), len(e), _ptr(e, _d), dt0, ratio, dt_max,
+                                 _ptr(out, _d), n.value, C.byref(n)))
+    return out[:n.value]
+
+
+def gsbs_debug_get_state(ctx, inst):
+    n = _i64()
+    _chk(_lib.gsbs_debug_get_state(ctx, inst, 0, None, None, None, C.byref(n)))
+    m = n.value
+    x = np.zeros((max(m, 1), 3), dtype=np.float32)
+    s = np.zeros(max(m, 1), dtype=np.uint8)
+    u = np.zeros(max(m, 1), dtype=np.uint64)
+    _chk(_lib.gsbs_debug_get_state(ctx, inst, m, _ptr(x, C.c_float), _ptr(s, C.c_uint8), _ptr(u, _u64),
+                                   C.byref(n)))
+    return x[:m], s[:m], u[:m]
+
+
+def gsbs_debug_set_state(ctx, xyz, species, uid, step=0, next_uid=None):
+    x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    s = np.ascontiguousarray(species, dtype=np.uint8)
+    u = np.ascontiguousarray(uid, dtype=np.uint64)
+    nu = (int(u.max()) + 1 if len(u) else 0) if next_uid is None else int(next_uid)
+    _chk(_lib.gsbs_debug_set_state(ctx, len(s), _ptr(x, C.c_float), _ptr(s, C.c_uint8), _ptr(u, _u64),
+                                   int(step), nu))
+
+
+def gsbs_debug_step(ctx, dt, flags=0, xyz0=None, nc_force=0):
+    x0 = None
+    if xyz0 is not None:
+        x0 = np.ascontiguousarray(xyz0, dtype=np.float32).reshape(-1, 3)
+    _chk(_lib.gsbs_debug_step(ctx, float(dt), int(flags), None if x0 is None else _ptr(x0, C.c_float),
+                              int(nc_force)))
+
+
+def gsbs_debug_get_pairs(ctx):
+    n = _i64()
+    _chk(_lib.gsbs_debug_get_pairs(ctx, 0, None, None, None, None, None, C.byref(n)))
+    m = n.value
+    uid2 = np.zeros((max(m, 1), 2), dtype=np.uint64)
+    P = np.zeros(max(m, 1), dtype=np.float32)
+    u24 = np.zeros(max(m, 1), dtype=np.uint32)
+    rx = np.zeros(max(m, 1), dtype=np.int32)
+    fl = np.zeros(max(m, 1), dtype=np.int32)
+    _chk(_lib.gsbs_debug_get_pairs(ctx, m, _ptr(uid2, _u64), _ptr(P, C.c_float), _ptr(u24, C.c_uint32),
+                                   _ptr(rx, _i32), _ptr(fl, _i32), C.byref(n)))
+    return dict(uid=uid2[:m], P=P[:m], u24=u24[:m], rx=rx[:m], flag=fl[:m])
+
+
+def gsbs_debug_get_cells(ctx):
+    n = _i64()
+    nc = _i32()
+    _chk(_lib.gsbs_debug_get_cells(ctx, 0, None, None, C.byref(nc), C.byref(n)))
+    m = n.value
+    cell = np.zeros(max(m, 1), dtype=np.int32)
+    u = np.zeros(max(m, 1), dtype=np.uint64)
+    _chk(_lib.gsbs_debug_get_cells(ctx, m, _ptr(cell, _i32), _ptr(u, _u64), C.byref(nc), C.byref(n)))
+    return cell[:m], u[:m], nc.value
+
+
+DEBUG_FIXED = 1
+DEBUG_LOG_ALL = 2
+DEBUG_SEARCH_ONLY = 4
+
+
+# ----------------------------------------------------- convenience layer ---
+class Engine:
+    """One context: n instances sharing a species/reaction table."""
+
+    def __init__(self, L, seed, D, reactions, params: gsbs_params = None, stream=None, capacity=0):
+        Ls = list(L) if np.ndim(L) else [float(L)]
+        self.n_inst = len(Ls)
+        self.ns = len(D)
+        self.nr = len(reactions)
+        self.records = [np.zeros(0)] * self.n_inst
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self.ctx = gsbs_create([(x, capacity) for x in Ls], seed, stream)
+        gsbs_set_species(self.ctx, D)
+        if params is not None:
+            gsbs_set_params(self.ctx, params)
+        gsbs_set_reactions(self.ctx, reactions)
+
+    def close(self):
+        if self.ctx:
+            gsbs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def inject(self, inst, t, xyz, species, edep_ev=0.0):
+        gsbs_inject(self.ctx, inst, t, xyz, species, edep_ev)
+
+    def set_records(self, inst, times):
+        self.records[inst] = np.asarray(times, dtype=np.float64)
+        gsbs_set_records(self.ctx, inst, self.records[inst])
+
+    def advance_to(self, t):
+        tt = np.full(self.n_inst, float(t)) if np.ndim(t) == 0 else np.asarray(t, dtype=np.float64)
+        gsbs_advance_to(self.ctx, tt)
+
+    def counts(self, inst=0):
+        return gsbs_get_counts(self.ctx, inst, len(self.records[inst]), self.ns)
+
+    def gvalues(self, inst=0):
+        return gsbs_get_gvalues(self.ctx, inst, len(self.records[inst]), self.ns)
+
+    def current_counts(self, inst=0):
+        return gsbs_get_current_counts(self.ctx, inst, self.ns)
+
+    def time(self, inst=0):
+        return gsbs_get_time(self.ctx, inst)
+
+    def n(self, inst=0):
+        return gsbs_get_n(self.ctx, inst)
+
+    def stats(self):
+        return gsbs_get_stats(self.ctx)
+
+    def radii(self):
+        return gsbs_get_radii(self.ctx, self.nr)
+
+    def dt_max(self, inst=0):
+        return gsbs_get_dt_max(self.ctx, inst)
+
+    def load_workload(self, wl, inst=0, device=False):
+        """Queue the injections and records of a workload.Workload."""
+        for inj in wl.injections:
+            xyz, sp = inj.xyz, inj.species
+            if device:
+                xyz = torch.from_numpy(np.ascontiguousarray(xyz, dtype=np.float32)).cuda()
+                sp = torch.from_numpy(np.ascontiguousarray(sp, dtype=np.uint8)).cuda()
+            self.inject(inst, inj.t, xyz, sp, inj.edep_ev)
+        self.set_records(inst, wl.records)
