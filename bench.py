@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=40, help="SBS steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM counters")
     return ap.parse_args()
 
 
@@ -91,6 +93,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+        return
 
     from paper_2509_03313_amd import gsbs
     from paper_2509_03313_amd import workload as W
@@ -190,6 +202,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "profile_ms": {k: round(v[0], 3) for k, v in prof.items()} if prof else None,
+        "tuning": gsbs.gsbs_get_tuning(),
         "final_counts": counts[-1].tolist(),
         "G_H2O2_end": float(gv[-1][W.H2O2]),
     }

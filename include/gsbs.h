@@ -71,7 +71,10 @@ typedef struct {
     double dt0_ns;           /* first step end after an injection; 1e-3 */
     double ratio;            /* step end times after an injection: dt0 * ratio^j; 10^(6/1999) */
     double dt_max_ns;        /* cap of a step; 0 = largest step keeping every r_c below L/2 */
-    double k_occ;            /* target molecules per cell of the search grid; 0 = autotuned */
+    int32_t grid_config;     /* -1: search grid chosen per step by the autotuner (default);
+                                k >= 0: always grid configuration k (see gsbs_get_tuning) */
+    int32_t autotune;        /* 1: try untried configurations on live steps (default); 0: use
+                                the process-wide table as it is, defaults where it is empty */
 } gsbs_params;
 
 /* Counters since the context was created. */
@@ -110,7 +113,8 @@ int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
  * 2R >= L for some cube (PBC 2). */
 int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
 
-/* Replace the method parameters (before the first advance). */
+/* Replace the method parameters.  The search-grid fields (grid_config,
+ * autotune) may change between advances; the others before the first one. */
 int gsbs_set_params(gsbs_ctx* ctx, const gsbs_params* p);
 
 /* Reaction radii R[0..n_reactions) in nm. */
@@ -166,6 +170,16 @@ int gsbs_get_n(gsbs_ctx* ctx, int32_t inst, int64_t* n);
 
 int gsbs_get_stats(gsbs_ctx* ctx, gsbs_stats* out);
 
+/* The autotuner's process-wide table.  A step's search grid is one of a few
+ * configurations (search mode, cells per cutoff, molecules per cell); the
+ * grid never changes which pairs are candidates, only the speed, so the
+ * tuner times configurations on live steps (keyed by the occupancy of a
+ * cutoff-sized grid and the molecule count, both in octaves) and reuses the
+ * fastest.  For k < *n (at most max_k entries): keys[2k], keys[2k+1] = the two
+ * octaves, best[k] = the chosen configuration, best_ms[k] = its mean step
+ * time. */
+int gsbs_get_tuning(int32_t max_k, int32_t* keys, int32_t* best, double* best_ms, int32_t* n);
+
 /* Per-kernel timing with HIP events recorded around every step kernel on the
  * context's stream (on = 1).  Profiling drains the stream after each step, so
  * it is for measurement passes, not for production runs. */
@@ -175,6 +189,12 @@ int gsbs_set_profiling(gsbs_ctx* ctx, int32_t on);
  * in names[k*32 .. k*32+31]), total milliseconds and number of launches. */
 int gsbs_get_profile(gsbs_ctx* ctx, int32_t max_k, char* names, double* total_ms, int64_t* launches,
                      int32_t* n);
+
+/* Per-step log of the profiled steps of gsbs_advance_to (instance 0): Philox
+ * step index, step time in ms (first to last kernel), grid (nc, reach,
+ * species-bin search flag, configuration) as 4 ints, live-count estimate. */
+int gsbs_get_step_log(gsbs_ctx* ctx, int64_t max_n, int64_t* step, double* ms, int32_t* grid, int64_t* n_est,
+                      int64_t* n);
 
 /* ------------------------------------------------- schedule (host only) --- */
 
@@ -205,8 +225,9 @@ int gsbs_debug_set_state(gsbs_ctx* ctx, int64_t n, const float* xyz, const uint8
  * Brownian jump and treat xyz0 (n x 3, host) as the start positions of the
  * current state (pairs are then searched on fixed positions).  flags bit 1:
  * log every candidate pair, not only accepted ones.  flags bit 2: stop after
- * the pair search (no matching, no reactions, state unchanged).  nc_force > 0
- * forces the search grid to nc_force^3 cells. */
+ * the pair search (no matching, no reactions, state unchanged).  flags bit 3 /
+ * bit 4: force the species-bin / whole-cell search.  nc_force > 0 forces the
+ * search grid to nc_force^3 cells (the stencil widens to cover the cutoff). */
 int gsbs_debug_step(gsbs_ctx* ctx, double dt_ns, int32_t flags, const float* xyz0, int32_t nc_force);
 
 /* Pair log of the last debug step (host arrays of capacity max_n): uid pairs

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -168,6 +170,14 @@ struct gsbs_ctx {
     long long* rec = nullptr;
     int32_t max_rec = 0;
 
+    hipEvent_t tune_ev[2 * kChunk] = {};
+    // live-count estimate refreshed from lagged device counts while stepping
+    long long* h_cnt[2] = {nullptr, nullptr};
+    hipEvent_t cnt_ev[2] = {nullptr, nullptr};
+    bool cnt_pending[2] = {false, false};
+    std::vector<int64_t> cnt_mark[2];     // molecules injected per instance when the copy was queued
+    std::vector<int64_t> injected;        // molecules injected per instance so far
+    int cnt_slot = 0;
     InstStep* h_chunk[2] = {nullptr, nullptr};
     InstStep* d_chunk[2] = {nullptr, nullptr};
     hipEvent_t chunk_ev[2] = {nullptr, nullptr};
@@ -175,14 +185,23 @@ struct gsbs_ctx {
 
     int64_t steps = 0;
     int64_t max_live = 0;
+    bool tuning = true;
     // profiling
     bool profiling = false;
+    struct StepLog {
+        int64_t step;
+        double ms;
+        int32_t nc, reach, by_species, cfg;
+        int64_t n_est;
+    };
+    std::vector<StepLog> step_log;
     hipEvent_t prof_ev[2 * kStepKernels] = {};
     double prof_ms[kStepKernels] = {};
     int64_t prof_n[kStepKernels] = {};
     // last debug step
     int32_t dbg_nc = 0;
     int32_t dbg_cell_base = 0;
+    int32_t dbg_by_species = 0;
 };
 
 namespace {
@@ -308,6 +327,7 @@ int build_chem(gsbs_ctx* c) {
         h.keep_b[r] = q.keep_b;
         h.rb[r] = q.b;
         mask |= (1u << q.a) | (1u << q.b);
+        h.pmask[std::min(q.a, q.b)] |= 1u << std::max(q.a, q.b);
         const double Dab = c->D[q.a] + c->D[q.b];
         c->R[r] = Dab > 0 ? smol_radius(q.k_in, Dab) : 0.0;
     }
@@ -335,9 +355,9 @@ int build_chem(gsbs_ctx* c) {
     return GSBS_OK;
 }
 
-// Per-instance parameters of one step.  Returns the cells of the grid.
-int32_t fill_step(const gsbs_ctx* c, double L, uint64_t step, int64_t n_est, int idx, double dt, bool active,
-                  int32_t cell_base, int32_t nc_force, InstStep& S) {
+// Physics of one step for one instance: sigma per species, cutoffs, radii,
+// bridge scale, culling radii.  Returns the largest cutoff.
+double fill_physics(const gsbs_ctx* c, double L, uint64_t step, int idx, double dt, bool active, InstStep& S) {
     std::memset(&S, 0, sizeof(S));
     S.L = (float)L;
     S.halfL = 0.5f * S.L;
@@ -346,34 +366,149 @@ int32_t fill_step(const gsbs_ctx* c, double L, uint64_t step, int64_t n_est, int
     S.step = step;
     S.key0 = c->seed;
     S.key1 = (uint64_t)idx;
-    S.cell_base = cell_base;
     double rcmax = 0.0;
-    if (active) {
-        for (int s = 0; s < c->ns; ++s) S.sigma[s] = (float)std::sqrt(2.0 * c->D[s] * dt);
-        for (size_t r = 0; r < c->rx.size(); ++r) {
-            const double Dab = c->D[c->rx[r].a] + c->D[c->rx[r].b];
-            const double rc = cutoff_of(c->R[r], Dab, dt, c->prm.c_cut);
-            S.rc2[r] = (float)(rc * rc);
-            S.R[r] = (float)c->R[r];
-            S.inv_s[r] = (Dab * dt > 0) ? (float)(1.0 / (Dab * dt)) : 0.0f;
-            rcmax = std::max(rcmax, rc);
-        }
+    if (!active) return 0.0;
+    for (int s = 0; s < c->ns; ++s) S.sigma[s] = (float)std::sqrt(2.0 * c->D[s] * dt);
+    for (size_t r = 0; r < c->rx.size(); ++r) {
+        const gsbs_reaction& q = c->rx[r];
+        const double Dab = c->D[q.a] + c->D[q.b];
+        const double rc = cutoff_of(c->R[r], Dab, dt, c->prm.c_cut);
+        S.rc2[r] = (float)(rc * rc);
+        S.R[r] = (float)c->R[r];
+        S.inv_s[r] = (Dab * dt > 0) ? (float)(1.0 / (Dab * dt)) : 0.0f;
+        const float cull = (float)(rc * (1.0 + 1e-4) * rc * (1.0 + 1e-4));
+        S.cull2[r] = cull;
+        const int lo = std::min(q.a, q.b), hi = std::max(q.a, q.b);
+        S.cull2_sp[lo] = std::max(S.cull2_sp[lo], cull);
+        S.cull2_all[lo] = std::max(S.cull2_all[lo], cull);
+        S.cull2_all[hi] = std::max(S.cull2_all[hi], cull);
+        rcmax = std::max(rcmax, rc);
     }
+    return rcmax;
+}
+
+constexpr double kGridMargin = 1.0 + 1e-5;  // cells a little wider than cutoff/reach (FP32 binning)
+
+// Search-grid configurations the autotuner chooses from: search mode, cells
+// per cutoff when the cutoff sets the grid, target molecules per cell.
+struct GridCfg {
+    int by_species;
+    int reach;
+    double occ;
+};
+constexpr GridCfg kCfgs[] = {
+    {0, 1, 2.0}, {0, 1, 6.0}, {0, 2, 2.0}, {1, 1, 16.0}, {1, 2, 16.0}, {1, 2, 64.0}, {1, 3, 16.0},
+};
+constexpr int kNumCfg = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+
+// Grid of one instance for one configuration: nc cells per axis, no smaller
+// than (cutoff / reach) and at least `occ` molecules per cell on average.
+// Returns cells.
+int32_t fill_grid(double L, int64_t n_est, double rcmax, const GridCfg& g, int32_t nc_force, InstStep& S) {
     int64_t nc;
+    const int64_t nocc = std::max<int64_t>(1, (int64_t)std::floor(std::cbrt((double)std::max<int64_t>(n_est, 1) / g.occ)));
     if (nc_force > 0) {
-        nc = nc_force;  // validated by the caller
+        nc = nc_force;
+    } else if (rcmax <= 0) {
+        nc = nocc;
     } else {
-        // cells no smaller than the largest cutoff (with margin for FP32 binning)
-        nc = rcmax > 0 ? (int64_t)std::floor(L / (rcmax * (1.0 + 1e-5))) : 1024;
-        const double kocc = c->prm.k_occ > 0 ? c->prm.k_occ : 2.0;
-        const int64_t nocc = (int64_t)std::floor(std::cbrt((double)std::max<int64_t>(n_est, 1) / kocc));
-        nc = std::min<int64_t>(nc, std::max<int64_t>(nocc, 1));
-        nc = std::min<int64_t>(nc, 1024);
-        nc = std::max<int64_t>(nc, 1);
+        const int64_t ncr = std::max<int64_t>(1, (int64_t)std::floor(g.reach * L / (rcmax * kGridMargin)));
+        nc = std::min<int64_t>(ncr, nocc);
     }
+    nc = std::min<int64_t>(std::max<int64_t>(nc, 1), 1024);
     S.nc = (int32_t)nc;
     S.inv_h = (float)S.nc / S.L;
+    S.h = S.L / (float)S.nc;
+    S.reach = rcmax > 0 ? std::max(1, (int32_t)std::ceil(rcmax * kGridMargin * (double)nc / L)) : 1;
+    // slack of the FP32 cell-distance bound: a few ulps of the edge plus the binning rounding
+    S.cull_eps = 8.0f * std::nextafter(S.halfL, 2.0f * S.halfL) - 8.0f * S.halfL + 1e-6f * S.h;
+    S.by_species = g.by_species;
+    // species-bin work unit: about 64 molecules of one species along a z-row
+    const double per_cell_species = (double)std::max<int64_t>(n_est, 1) / ((double)nc * nc * nc * 4.0);
+    int64_t kseg = (int64_t)std::ceil(64.0 / std::max(per_cell_species, 1e-9));
+    S.kseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kseg, nc));
     return (int32_t)(nc * nc * nc);
+}
+
+// Work units of the species-bin search of one instance.
+int64_t units_of(const InstStep& S, int ns) {
+    if (!S.by_species) return 0;
+    const int64_t nseg = (S.nc + S.kseg - 1) / S.kseg;
+    return (int64_t)ns * S.nc * S.nc * nseg;
+}
+
+// Tuning key: occupancy of a grid whose cells equal the largest cutoff, in
+// octaves (the second key is kept for the table layout and is always 0).
+std::pair<int, int> tune_key(double L, int64_t n_est, double rcmax) {
+    const double n = (double)std::max<int64_t>(n_est, 1);
+    double ncr = rcmax > 0 ? std::floor(L / (rcmax * kGridMargin)) : 1024.0;
+    ncr = std::max(1.0, std::min(ncr, 1024.0));
+    const double occ = n / (ncr * ncr * ncr);
+    const int ko = std::max(-3, std::min(30, (int)std::floor(std::log2(occ))));
+    return {ko, 0};
+}
+
+// Process-wide autotuning cache: per key, accumulated step time of every
+// configuration tried.  The configuration changes nothing but speed -- the
+// candidate set of every step is the same for any grid -- so it is tried on
+// live steps of real runs; later runs of the same shape reuse the choice.
+struct TuneEntry {
+    double ms[kNumCfg] = {};
+    int cnt[kNumCfg] = {};
+    int pend[kNumCfg] = {};
+};
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, TuneEntry> g_tune;
+constexpr int kTuneSamples = 2;
+
+// species bins only pay off once cutoff-sized cells hold a few molecules
+bool cfg_eligible(int cfg, int ko) { return kCfgs[cfg].by_species == 0 || ko >= 0; }
+
+int default_cfg(int ko) { return ko < 3 ? 0 : 4; }
+
+// Configuration for a key: while exploring, the default first and then every
+// eligible configuration not yet sampled kTuneSamples times, except those whose
+// first sample was more than 3x the best mean so far; else the fastest.
+int pick_cfg(std::pair<int, int> key, bool explore_ok, bool* explore) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneEntry& e = g_tune[key];
+    if (explore_ok) {
+        double best_mean = -1.0;
+        for (int k = 0; k < kNumCfg; ++k)
+            if (e.cnt[k] > 0 && (best_mean < 0 || e.ms[k] / e.cnt[k] < best_mean)) best_mean = e.ms[k] / e.cnt[k];
+        const int d = default_cfg(key.first);
+        for (int r = -1; r < kNumCfg; ++r) {
+            const int k = r < 0 ? d : r;
+            if (r >= 0 && k == d) continue;
+            if (!cfg_eligible(k, key.first)) continue;
+            if (e.cnt[k] > 0 && best_mean > 0 && e.ms[k] / e.cnt[k] > 3.0 * best_mean) continue;
+            if (e.cnt[k] + e.pend[k] < kTuneSamples) {
+                if (r >= 0 && e.pend[k] > 0) continue;  // wait for its first sample before a second
+                e.pend[k]++;
+                if (explore) *explore = true;
+                return k;
+            }
+        }
+    }
+    int best = -1;
+    double bt = 0.0;
+    for (int k = 0; k < kNumCfg; ++k) {
+        if (!cfg_eligible(k, key.first) || e.cnt[k] == 0) continue;
+        const double t = e.ms[k] / e.cnt[k];
+        if (best < 0 || t < bt) {
+            best = k;
+            bt = t;
+        }
+    }
+    return best >= 0 ? best : default_cfg(key.first);
+}
+
+void tune_record(std::pair<int, int> key, int cfg, double ms) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneEntry& e = g_tune[key];
+    if (e.pend[cfg] > 0) e.pend[cfg]--;
+    e.ms[cfg] += ms;
+    e.cnt[cfg]++;
 }
 
 StepBuffers buffers(gsbs_ctx* c) {
@@ -399,10 +534,14 @@ StepBuffers buffers(gsbs_ctx* c) {
     return b;
 }
 
-int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_inst, int32_t cells, int32_t grid,
-             int32_t flags) {
-    launch_step(c->st, bf, P, c->chem_d, n_inst, cells, grid, flags, c->profiling ? c->prof_ev : nullptr);
+int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_inst, int32_t bins, int32_t units,
+             int32_t grid, int32_t flags, hipEvent_t* span = nullptr, const InstStep* row0 = nullptr, int cfg0 = -1,
+             int64_t nest0 = 0) {
+    if (span) HIPCHK(hipEventRecord(span[0], c->st));
+    launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags,
+                c->profiling ? c->prof_ev : nullptr);
     HIPCHK(hipGetLastError());
+    if (span) HIPCHK(hipEventRecord(span[1], c->st));
     if (c->profiling) {
         HIPCHK(hipEventSynchronize(c->prof_ev[2 * kStepKernels - 1]));
         for (int k = 0; k < kStepKernels; ++k) {
@@ -411,6 +550,11 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
             c->prof_ms[k] += ms;
             c->prof_n[k] += 1;
         }
+        float tot = 0.f;
+        HIPCHK(hipEventElapsedTime(&tot, c->prof_ev[0], c->prof_ev[2 * kStepKernels - 1]));
+        if (row0)
+            c->step_log.push_back({(int64_t)row0->step, (double)tot, row0->nc, row0->reach, row0->by_species, cfg0,
+                                   nest0});
     }
     return GSBS_OK;
 }
@@ -428,6 +572,7 @@ int apply_injection(gsbs_ctx* c, int idx, const Pending& p) {
     HIPCHK(hipGetLastError());
     in.next_uid += (uint64_t)p.n;
     in.edep += p.edep;
+    c->injected[idx] += p.n;
     return GSBS_OK;
 }
 
@@ -503,7 +648,8 @@ int gsbs_default_params(gsbs_params* p) {
     p->dt0_ns = 1e-3;
     p->ratio = std::pow(10.0, 6.0 / 1999.0);
     p->dt_max_ns = 0.0;
-    p->k_occ = 0.0;
+    p->grid_config = -1;
+    p->autotune = 1;
     return GSBS_OK;
 }
 
@@ -532,8 +678,12 @@ int gsbs_create(const gsbs_box* boxes, int32_t n_instances, uint64_t seed, void*
     hipError_t e = hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->counts, 0, sizeof(long long) * n_instances * kMaxSpecies, c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->msteps, 0, sizeof(unsigned long long) * n_instances, c->st);
+    c->injected.assign(n_instances, 0);
     for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-        e = hipHostMalloc((void**)&c->h_chunk[b], sizeof(InstStep) * kChunk * n_instances);
+        e = hipHostMalloc((void**)&c->h_cnt[b], sizeof(long long) * kMaxSpecies * n_instances);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->cnt_ev[b], hipEventDisableTiming);
+        c->cnt_mark[b].assign(n_instances, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunk[b], sizeof(InstStep) * kChunk * n_instances);
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_chunk[b], sizeof(InstStep) * kChunk * n_instances);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunk_ev[b], hipEventDisableTiming);
     }
@@ -580,6 +730,12 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->chem_d);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->tune_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < 2; ++b) {
+        if (c->h_cnt[b]) (void)hipHostFree(c->h_cnt[b]);
+        if (c->cnt_ev[b]) (void)hipEventDestroy(c->cnt_ev[b]);
+    }
     delete c;
     return GSBS_OK;
 }
@@ -621,9 +777,10 @@ int gsbs_set_reactions(gsbs_ctx* c, int32_t n, const gsbs_reaction* r) {
 int gsbs_set_params(gsbs_ctx* c, const gsbs_params* p) {
     if (!c || !p) return fail(GSBS_EINVAL, "null");
     if (!(p->c_cut > 0) || p->rounds < 1 || !(p->dt0_ns > 0) || !(p->ratio > 1.0) || p->dt_max_ns < 0 ||
-        p->k_occ < 0)
+        p->grid_config < -1 || p->grid_config >= kNumCfg)
         return fail(GSBS_EINVAL, "bad parameters");
     c->prm = *p;
+    c->tuning = p->autotune != 0;
     if (c->ns && !c->rx.empty()) return build_chem(c);
     return GSBS_OK;
 }
@@ -744,35 +901,85 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
     launch_record(c->st, c->counts, c->rec, c->max_rec, rl);
     rl.n = 0;
 
-    std::vector<int32_t> total_cells(kChunk);
+    std::vector<int32_t> total_cells(kChunk);  // bins of the step
+    std::vector<int32_t> total_units(kChunk);
+    std::vector<int32_t> step_flags(kChunk);
+    std::vector<int> tune_cfg(kChunk, -1);
+    std::vector<int> step_cfg(kChunk, -1);
+    std::vector<int64_t> step_nest(kChunk, 0);
+    std::vector<std::pair<int, int>> tune_key_of(kChunk);
+    if (c->tuning && !c->tune_ev[0])
+        for (auto& e : c->tune_ev) HIPCHK(hipEventCreate(&e));
     for (size_t g0 = 0; g0 < G; g0 += kChunk) {
         const int nstep = (int)std::min<size_t>(kChunk, G - g0);
         const int b = c->chunk_buf;
         HIPCHK(hipEventSynchronize(c->chunk_ev[b]));
         InstStep* hrow = c->h_chunk[b];
+        // refresh the live-count estimates from the newest finished copy of the counts
+        for (int q = 0; q < 2; ++q) {
+            const int sl = (c->cnt_slot + q) & 1;  // older slot first, newer overrides
+            if (!c->cnt_pending[sl] || hipEventQuery(c->cnt_ev[sl]) != hipSuccess) continue;
+            for (int i = 0; i < c->n_inst; ++i) {
+                int64_t s = 0;
+                for (int k = 0; k < kMaxSpecies; ++k) s += c->h_cnt[sl][(size_t)i * kMaxSpecies + k];
+                c->inst[i].n_est = s + (c->injected[i] - c->cnt_mark[sl][i]);
+            }
+        }
         // n_est evolves with the injections inside the chunk
         std::vector<int64_t> nest(c->n_inst);
         for (int i = 0; i < c->n_inst; ++i) nest[i] = c->inst[i].n_est;
         int64_t n_total = 0;
+        std::vector<double> rcm(c->n_inst);
         for (int k = 0; k < nstep; ++k) {
+            const size_t g = g0 + k;
+            int lead = -1;
+            for (int i = 0; i < c->n_inst; ++i)
+                if (g < sched[i].size() && (lead < 0 || nest[i] > nest[lead])) lead = i;
             int32_t base = 0;
+            int64_t ubase = 0;
+            int32_t fl = 0;
+            tune_cfg[k] = -1;
             for (int i = 0; i < c->n_inst; ++i) {
-                const size_t g = g0 + k;
                 const bool active = g < sched[i].size();
                 const double tprev = (g == 0) ? t0[i] : sched[i][g - 1];
                 const double dt = active ? sched[i][g] - tprev : 0.0;
                 const uint64_t stp = step0[i] + (uint64_t)std::min<size_t>(g, sched[i].size());
-                base += fill_step(c, c->inst[i].L, stp, nest[i], i, dt, active, base, 0,
-                                  hrow[(size_t)k * c->n_inst + i]);
+                InstStep& row = hrow[(size_t)k * c->n_inst + i];
+                rcm[i] = fill_physics(c, c->inst[i].L, stp, i, dt, active, row);
+                int cfg;
+                if (c->prm.grid_config >= 0) {
+                    cfg = c->prm.grid_config;
+                } else {
+                    const auto key = tune_key(c->inst[i].L, nest[i], rcm[i]);
+                    bool explore = false;
+                    cfg = pick_cfg(key, i == lead && c->tuning, &explore);
+                    if (explore) {
+                        tune_cfg[k] = cfg;
+                        tune_key_of[k] = key;
+                    }
+                }
+                row.bin_base = base;
+                if (i == 0) {
+                    step_cfg[k] = cfg;
+                    step_nest[k] = nest[i];
+                }
+                const int32_t cells = fill_grid(c->inst[i].L, nest[i], rcm[i], kCfgs[cfg], 0, row);
+                base += row.by_species ? cells * c->ns : cells;
+                row.unit_base = (int32_t)ubase;
+                ubase += units_of(row, c->ns);
+                if (active) fl |= row.by_species ? kStepHasSpecies : kStepHasWhole;
                 if (active)
                     for (auto& p : c->inst[i].pending)
                         if (p.t == sched[i][g]) nest[i] += p.n;
             }
             total_cells[k] = base;
+            total_units[k] = (int32_t)std::min<int64_t>(ubase, 0x7FFFFFF0);
+            step_flags[k] = fl;
         }
         for (int i = 0; i < c->n_inst; ++i) n_total += std::max(nest[i], c->inst[i].n_est);
-        int32_t maxc = 0;
-        for (int k = 0; k < nstep; ++k) maxc = std::max(maxc, total_cells[k]);
+        int64_t maxc = 0;
+        for (int k = 0; k < nstep; ++k) maxc = std::max<int64_t>(maxc, (int64_t)total_cells[k]);
+        if (maxc > 0x7FFFFFF0) return fail(GSBS_ECAPACITY, "search grid too large");
         CHK(ensure_cells(c, maxc));
         HIPCHK(hipMemcpyAsync(c->d_chunk[b], hrow, sizeof(InstStep) * nstep * c->n_inst, hipMemcpyHostToDevice,
                               c->st));
@@ -781,8 +988,10 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
         for (int k = 0; k < nstep; ++k) {
             const size_t g = g0 + k;
             StepBuffers bf = buffers(c);
-            CHK(run_step(c, bf, c->d_chunk[b] + (size_t)k * c->n_inst, c->n_inst, total_cells[k], grid_for(n_total),
-                         0));
+            CHK(run_step(c, bf, c->d_chunk[b] + (size_t)k * c->n_inst, c->n_inst, total_cells[k], total_units[k],
+                         grid_for(n_total),
+                         step_flags[k], tune_cfg[k] >= 0 ? &c->tune_ev[2 * k] : nullptr,
+                         &hrow[(size_t)k * c->n_inst], step_cfg[k], step_nest[k]));
             c->cur ^= 1;
             c->steps++;
             for (int i = 0; i < c->n_inst; ++i) {
@@ -797,6 +1006,28 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
             }
         }
         for (int i = 0; i < c->n_inst; ++i) c->inst[i].n_est = nest[i];
+        {
+            const int sl = c->cnt_slot;
+            if (!c->cnt_pending[sl] || hipEventQuery(c->cnt_ev[sl]) == hipSuccess) {
+                HIPCHK(hipMemcpyAsync(c->h_cnt[sl], c->counts, sizeof(long long) * kMaxSpecies * c->n_inst,
+                                      hipMemcpyDeviceToHost, c->st));
+                HIPCHK(hipEventRecord(c->cnt_ev[sl], c->st));
+                c->cnt_pending[sl] = true;
+                c->cnt_mark[sl] = c->injected;
+                c->cnt_slot ^= 1;
+            }
+        }
+        bool any = false;
+        for (int k = 0; k < nstep; ++k) any = any || tune_cfg[k] >= 0;
+        if (any) {
+            HIPCHK(hipStreamSynchronize(c->st));
+            for (int k = 0; k < nstep; ++k) {
+                if (tune_cfg[k] < 0) continue;
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, c->tune_ev[2 * k], c->tune_ev[2 * k + 1]));
+                tune_record(tune_key_of[k], tune_cfg[k], ms);
+            }
+        }
     }
     for (int i = 0; i < c->n_inst; ++i) c->inst[i].t = target[i];
     HIPCHK(hipStreamSynchronize(c->st));
@@ -884,10 +1115,61 @@ int gsbs_set_profiling(gsbs_ctx* c, int32_t on) {
     if (on && !c->prof_ev[0])
         for (auto& e : c->prof_ev) HIPCHK(hipEventCreate(&e));
     c->profiling = on != 0;
+    c->step_log.clear();
     for (int k = 0; k < kStepKernels; ++k) {
         c->prof_ms[k] = 0.0;
         c->prof_n[k] = 0;
     }
+    return GSBS_OK;
+}
+
+int gsbs_get_tuning(int32_t max_k, int32_t* keys, int32_t* best, double* best_ms, int32_t* n) {
+    if (!n) return fail(GSBS_EINVAL, "null");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int32_t k = 0;
+    for (const auto& kv : g_tune) {
+        int b = -1;
+        double bt = 0.0;
+        for (int q = 0; q < kNumCfg; ++q) {
+            if (kv.second.cnt[q] == 0) continue;
+            const double t = kv.second.ms[q] / kv.second.cnt[q];
+            if (b < 0 || t < bt) {
+                b = q;
+                bt = t;
+            }
+        }
+        if (b < 0) continue;
+        if (k < max_k) {
+            if (keys) {
+                keys[2 * k] = kv.first.first;
+                keys[2 * k + 1] = kv.first.second;
+            }
+            if (best) best[k] = b;
+            if (best_ms) best_ms[k] = bt;
+        }
+        ++k;
+    }
+    *n = k;
+    return GSBS_OK;
+}
+
+int gsbs_get_step_log(gsbs_ctx* c, int64_t max_n, int64_t* step, double* ms, int32_t* grid, int64_t* n_est,
+                      int64_t* n) {
+    if (!c || !n) return fail(GSBS_EINVAL, "null");
+    const int64_t m = (int64_t)c->step_log.size();
+    for (int64_t k = 0; k < std::min(m, max_n); ++k) {
+        const auto& e = c->step_log[(size_t)k];
+        if (step) step[k] = e.step;
+        if (ms) ms[k] = e.ms;
+        if (grid) {
+            grid[4 * k] = e.nc;
+            grid[4 * k + 1] = e.reach;
+            grid[4 * k + 2] = e.by_species;
+            grid[4 * k + 3] = e.cfg;
+        }
+        if (n_est) n_est[k] = e.n_est;
+    }
+    *n = m;
     return GSBS_OK;
 }
 
@@ -1014,20 +1296,31 @@ int gsbs_debug_step(gsbs_ctx* c, double dt, int32_t flags, const float* xyz0, in
             const double Dab = c->D[c->rx[r].a] + c->D[c->rx[r].b];
             rcmax = std::max(rcmax, cutoff_of(c->R[r], Dab, dt, c->prm.c_cut));
         }
-        if (rcmax > 0 && nc_force > (int64_t)std::floor(in.L / (rcmax * (1.0 + 1e-5))))
-            return fail(GSBS_EINVAL, "forced search grid has cells smaller than the cutoff");
+        (void)rcmax;
         if (nc_force > 1024) return fail(GSBS_EINVAL, "forced search grid too fine");
     }
-    const int32_t cells = fill_step(c, in.L, in.step, in.n_est, 0, dt, true, 0, nc_force, S[0]);
-    CHK(ensure_cells(c, cells));
+    const double rcmax = fill_physics(c, in.L, in.step, 0, dt, true, S[0]);
+    int cfg = default_cfg(tune_key(in.L, in.n_est, rcmax).first);
+    if (c->prm.grid_config >= 0) cfg = c->prm.grid_config;
+    GridCfg gc = kCfgs[cfg];
+    if (flags & kStepBySpecies) gc.by_species = 1;
+    if (flags & kStepWholeCells) gc.by_species = 0;
+    S[0].bin_base = 0;
+    const int32_t ncell = fill_grid(in.L, in.n_est, rcmax, gc, nc_force, S[0]);
+    S[0].unit_base = 0;
+    const int32_t units = (int32_t)units_of(S[0], c->ns);
+    const int32_t cells = S[0].by_species ? ncell * c->ns : ncell;
+    CHK(ensure_cells(c, (int64_t)cells));
     HIPCHK(hipMemcpyAsync(c->d_chunk[c->chunk_buf], S, sizeof(InstStep), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipEventRecord(c->chunk_ev[c->chunk_buf], c->st));
     StepBuffers bf = buffers(c);
-    CHK(run_step(c, bf, c->d_chunk[c->chunk_buf], 1, cells, grid_for(h.n_in), flags));
+    flags |= S[0].by_species ? kStepHasSpecies : kStepHasWhole;
+    CHK(run_step(c, bf, c->d_chunk[c->chunk_buf], 1, cells, units, grid_for(h.n_in), flags));
     c->chunk_buf ^= 1;
     c->cur ^= 1;
     c->dbg_nc = S[0].nc;
     c->dbg_cell_base = 0;
+    c->dbg_by_species = S[0].by_species;
     if (!(flags & kStepSearchOnly)) {
         in.step++;
         in.t += dt;
@@ -1080,7 +1373,8 @@ int gsbs_debug_get_cells(gsbs_ctx* c, int64_t max_n, int32_t* cell, uint64_t* ui
     for (int64_t k = 0; k < std::min<int64_t>(h.n_live, max_n); ++k) {
         uint32_t g;
         std::memcpy(&g, &p0[k].w, 4);
-        if (cell) cell[k] = (int32_t)g - c->dbg_cell_base;
+        const uint32_t ncell = (uint32_t)c->dbg_nc * (uint32_t)c->dbg_nc * (uint32_t)c->dbg_nc;
+        if (cell) cell[k] = (int32_t)((uint32_t)(g - (uint32_t)c->dbg_cell_base) % (c->dbg_by_species ? ncell : 0xFFFFFFFFu));
         if (uid) uid[k] = u[k];
     }
     if (nc) *nc = c->dbg_nc;

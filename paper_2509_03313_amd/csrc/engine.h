@@ -22,25 +22,39 @@ struct ChemDev {
     int32_t keep_b[kMaxReactions];
     int32_t rb[kMaxReactions];
     uint32_t reactive_mask;                  // bit s: species s takes part in a reaction
+    uint32_t pmask[kMaxSpecies];             // bit t of pmask[s]: pair (s, t), t >= s, is searched from s
     int32_t n_species;
     int32_t rounds;
     int32_t contact_only;
 };
 
 // Everything one instance needs for one step; rebuilt by the host per step.
+// The search grid has nc^3 cells of edge h = L/nc per instance.  Molecules are
+// sorted by bin: in the species-bin search bins are species-major (bin =
+// bin_base + species * nc^3 + cell), in the whole-cell search a cell is one
+// bin (bin = bin_base + cell); cell = (ix*nc + iy)*nc + iz.  A candidate of a molecule
+// lies at most `reach` cells away along each axis (reach * h >= the largest
+// cutoff).
 struct alignas(16) InstStep {
     float sigma[kMaxSpecies];      // sqrt(2 D dt) per species
     float rc2[kMaxReactions];      // squared candidate cutoff (FP32 of the FP64 square)
     float R[kMaxReactions];        // reaction radius
     float inv_s[kMaxReactions];    // 1 / (D_AB * dt), 0 when D_AB = 0
+    float cull2[kMaxReactions];    // squared cutoff widened for cell culling
+    float cull2_sp[kMaxSpecies];   // largest cull2 over the pairs searched from a species (species bins)
+    float cull2_all[kMaxSpecies];  // largest cull2 over every reaction of a species (whole cells)
     float L, halfL, invL, inv_h;   // edge, L/2, 1/L, nc/L (all FP32)
+    float h, cull_eps;             // cell edge L/nc, slack of the cell-distance bound
     int32_t nc;                    // cells per axis of the search grid
-    int32_t cell_base;             // first global cell index of this instance
+    int32_t reach;                 // stencil half-width in cells
+    int32_t bin_base;              // first global bin index of this instance
     int32_t active;                // 1: this instance takes a step now
-    int32_t pad0;
+    int32_t by_species;            // 1: search partner-species bins, 0: whole cells
+    int32_t kseg;                  // species-bin search: z-cells per work unit
+    int32_t unit_base;             // species-bin search: first global work unit of this instance
+    int32_t pad0[3];
     uint64_t step;                 // Philox step counter word
     uint64_t key0, key1;           // Philox key (seed, instance)
-    uint64_t pad1;
 };
 
 // Accepted (or, in debug logging, candidate) pair of sorted indices.
@@ -78,11 +92,11 @@ struct StepBuffers {
     float4* pos_in;       // current molecules: x, y, z, meta = (instance << 8) | species
     uint64_t* uid_in;
     float4* pos_out;      // sorted molecules after the jump
-    float4* pos0_out;     // sorted start-of-step positions; .w carries the global cell index
+    float4* pos0_out;     // sorted start-of-step positions; .w carries the global bin index
     uint64_t* uid_out;
-    uint2* cellrank;      // per input molecule: (global cell, rank inside the cell)
-    uint32_t* cell_count; // zero between steps
-    uint32_t* cell_start; // exclusive prefix sums, one extra entry at the end
+    uint2* cellrank;      // per input molecule: (global bin, rank inside the bin)
+    uint32_t* cell_count; // per bin, zero between steps
+    uint32_t* cell_start; // per bin exclusive prefix sums, one extra entry at the end
     uint32_t* block_sums;
     PairRec* pairs;
     uint32_t pair_cap;
@@ -102,7 +116,10 @@ void launch_inject(hipStream_t st, float4* pos, uint64_t* uid, long long* counts
 constexpr int kStepKernels = 6;
 extern const char* const kStepKernelNames[kStepKernels];
 void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const ChemDev* chem,
-                 int32_t n_inst, int32_t total_cells, int32_t grid, int32_t flags, hipEvent_t* ev = nullptr);
+                 int32_t n_inst, int32_t total_bins, int32_t total_units, int32_t n_species, int32_t grid,
+                 int32_t flags, hipEvent_t* ev = nullptr);
+// bins up to which k_bin counts in an LDS histogram (larger grids use global atomics)
+constexpr int32_t kLdsBins = 12288;
 void launch_record(hipStream_t st, const long long* counts, long long* rec, int32_t max_rec,
                    const RecordList& list);
 
@@ -110,5 +127,9 @@ void launch_record(hipStream_t st, const long long* counts, long long* rec, int3
 constexpr int32_t kStepLogAll = 2;
 constexpr int32_t kStepSearchOnly = 4;
 constexpr int32_t kStepFixed = 1;
+constexpr int32_t kStepBySpecies = 8;   // debug: force the species-bin search
+constexpr int32_t kStepWholeCells = 16;  // debug: force the whole-cell search
+constexpr int32_t kStepHasWhole = 32;    // some instance uses the whole-cell search this step
+constexpr int32_t kStepHasSpecies = 64;  // some instance uses the species-bin search this step
 
 }  // namespace gsbs

@@ -2,10 +2,11 @@
 // method of arXiv 2509.03313 (multi-pulse gMicroMC extension):
 //
 //   k_bin      Brownian jump (Philox4x64-10 + Box-Muller, FP32) and PBC 1
-//              (Eq. 1), cell of the moved position, per-cell count and rank
+//              (Eq. 1), (cell, species) bin of the moved position, per-bin
+//              count and rank (LDS histogram for small grids)
 //   k_scan_*   exclusive scan of the cell counts (wave64 shuffles + LDS)
 //   k_scatter  molecules into cell order (jump recomputed from the counter)
-//   k_pairs    27-cell minimum-image (Eq. 2) candidate search against the
+//   k_pairs    stencil minimum-image (Eq. 2) candidate search against the
 //              per-reaction cutoff, radial Brownian-bridge contact
 //              probability, pair uniform, accepted pairs appended
 //   k_react    mutual-best single-partner matching by 64-bit atomic min,
@@ -156,27 +157,94 @@ __global__ void k_add_n(DevCounters* ctr, int32_t n, int32_t cap) {
 }
 
 // ------------------------------------------------------------------ bin ---
+// Global bin of a moved molecule.
+__device__ __forceinline__ uint32_t bin_of(float3 x, const InstStep& S, int sp, int ns) {
+    const int c = local_cell(x, S);
+    return (uint32_t)(S.bin_base + (S.by_species ? sp * S.nc * S.nc * S.nc + c : c));
+}
+
+__device__ __forceinline__ uint32_t molecule_bin(const float4* __restrict__ pos, const uint64_t* __restrict__ uid,
+                                                 const InstStep* __restrict__ P, int i, int fixed, int ns) {
+    const float4 p = pos[i];
+    const int meta = __float_as_int(p.w);
+    const int sp = meta & 0xFF;
+    if (sp == kDead) return kNoCell;
+    const InstStep& S = P[meta >> 8];
+    const float3 x = fixed ? make_float3(p.x, p.y, p.z) : jump(p, uid[i], S, sp);
+    return bin_of(x, S, sp, ns);
+}
+
+// Few bins (late, large steps): count in an LDS histogram, one global atomic
+// per block and non-empty bin.  Each block owns `per_block` consecutive
+// molecules, handled in rounds of GSBS_BLOCK (at most kBinRounds).
+constexpr int kBinRounds = 8;
+
+__global__ __launch_bounds__(GSBS_BLOCK) void k_bin_lds(const float4* __restrict__ pos,
+                                                      const uint64_t* __restrict__ uid,
+                                                      DevCounters* __restrict__ ctr,
+                                                      const InstStep* __restrict__ P,
+                                                      uint32_t* __restrict__ cell_count,
+                                                      uint2* __restrict__ cellrank, int32_t fixed,
+                                                      int32_t total_bins, int32_t ns) {
+    extern __shared__ uint32_t hist[];
+    for (int b = threadIdx.x; b < total_bins; b += GSBS_BLOCK) hist[b] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_pairs = 0u;  // read by k_pairs, after this kernel
+    __syncthreads();
+    const int n = ctr->n_in;
+    const int per_block = ((n + gridDim.x - 1) / gridDim.x + GSBS_BLOCK - 1) / GSBS_BLOCK * GSBS_BLOCK;
+    const int first = blockIdx.x * per_block;
+    uint32_t bin[kBinRounds], lr[kBinRounds];
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) {
+        const int i = first + r * GSBS_BLOCK + threadIdx.x;
+        bin[r] = kNoCell;
+        lr[r] = 0u;
+        if (r * GSBS_BLOCK < per_block && i < n) {
+            bin[r] = molecule_bin(pos, uid, P, i, fixed, ns);
+            if (bin[r] != kNoCell) lr[r] = atomicAdd(&hist[bin[r]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < total_bins; b += GSBS_BLOCK) {
+        const uint32_t c = hist[b];
+        if (c) hist[b] = atomicAdd(&cell_count[b], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) {
+        const int i = first + r * GSBS_BLOCK + threadIdx.x;
+        if (r * GSBS_BLOCK < per_block && i < n)
+            cellrank[i] = make_uint2(bin[r], bin[r] == kNoCell ? 0u : hist[bin[r]] + lr[r]);
+    }
+}
+
+// Many bins (early, small steps): one global atomic per run of equal bins among
+// consecutive lanes (the input is still sorted from the previous step, so a
+// spur's molecules mostly form one run).
 __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ pos,
                                                   const uint64_t* __restrict__ uid,
                                                   DevCounters* __restrict__ ctr,
                                                   const InstStep* __restrict__ P,
                                                   uint32_t* __restrict__ cell_count,
-                                                  uint2* __restrict__ cellrank, int32_t fixed) {
+                                                  uint2* __restrict__ cellrank, int32_t fixed, int32_t ns) {
     const int n = ctr->n_in;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_pairs = 0u;  // read by k_pairs, after this kernel
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float4 p = pos[i];
-        const int meta = __float_as_int(p.w);
-        const int sp = meta & 0xFF;
-        if (sp == kDead) {
-            cellrank[i] = make_uint2(kNoCell, 0u);
-            continue;
-        }
-        const InstStep& S = P[meta >> 8];
-        const float3 x = fixed ? make_float3(p.x, p.y, p.z) : jump(p, uid[i], S, sp);
-        const uint32_t c = (uint32_t)(S.cell_base + local_cell(x, S));
-        const uint32_t r = atomicAdd(&cell_count[c], 1u);
-        cellrank[i] = make_uint2(c, r);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int i = base + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t bin = valid ? molecule_bin(pos, uid, P, i, fixed, ns) : kNoCell;
+        const uint32_t prev = __shfl_up(bin, 1, 64);
+        const bool head = (lane == 0) || (prev != bin);
+        const unsigned long long heads = __ballot(head);
+        const int start = 63 - __clzll(heads & upto);
+        const unsigned long long above = heads & ~upto;
+        const int next = above ? __ffsll((long long)above) - 1 : 64;
+        uint32_t b0 = 0u;
+        if (head && bin != kNoCell) b0 = atomicAdd(&cell_count[bin], (uint32_t)(next - lane));
+        b0 = __shfl(b0, start, 64);
+        if (valid) cellrank[i] = make_uint2(bin, bin == kNoCell ? 0u : b0 + (uint32_t)(lane - start));
     }
 }
 
@@ -292,7 +360,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scatter(const float4* __restrict
             p0 = p;
         }
         pos_out[dst] = make_float4(x.x, x.y, x.z, p.w);
-        pos0_out[dst] = make_float4(p0.x, p0.y, p0.z, __uint_as_float(cr.x));
+        pos0_out[dst] = make_float4(p0.x, p0.y, p0.z, __uint_as_float(cr.x));  // bin index
         uid_out[dst] = u;
     }
 }
@@ -309,6 +377,93 @@ __device__ __forceinline__ float bridge_f(float r0, float r1, float R, float inv
     return expf(-a) * (expm1f(-b) / expm1f(-c));
 }
 
+// One candidate pair (i, j) of reaction rx: minimum-image end separation
+// below the cutoff (FP32, fixed operation order), contact probability, pair
+// uniform, accepted pairs appended.
+// Squared minimum-image end separation in FP32 with a fixed operation order
+// (the oracle emulates it bit for bit).
+__device__ __forceinline__ float end_d2(const float4& pj, const float4& pi, float L, float hL) {
+    const float dx = minimg_f(__fsub_rn(pj.x, pi.x), L, hL);
+    const float dy = minimg_f(__fsub_rn(pj.y, pi.y), L, hL);
+    const float dz = minimg_f(__fsub_rn(pj.z, pi.z), L, hL);
+    return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
+// A candidate (end separation below the cutoff): start separation, contact
+// probability, pair uniform, accepted pair appended.
+__device__ __forceinline__ void eval_candidate(int i, int j, float d2, const float4* __restrict__ pos0,
+                                               const uint64_t* __restrict__ uid, const InstStep& S, int rx,
+                                               int contact_only, int log_all, DevCounters* __restrict__ ctr,
+                                               PairRec* __restrict__ pairs, uint32_t pair_cap) {
+    const float L = S.L, hL = S.halfL;
+    const float4 qi = pos0[i];
+    const float4 qj = pos0[j];
+    const float ex = minimg_f(qj.x - qi.x, L, hL);
+    const float ey = minimg_f(qj.y - qi.y, L, hL);
+    const float ez = minimg_f(qj.z - qi.z, L, hL);
+    const float r1 = sqrtf(d2);
+    const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
+    const float R = S.R[rx];
+    float Pc;
+    if (contact_only) {
+        Pc = (r0 <= R || r1 <= R) ? 1.0f : 0.0f;
+    } else {
+        // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
+        const float a = (r0 - R) * (r1 - R) * S.inv_s[rx];
+        if (!log_all && r0 > R && r1 > R && a > 18.0f) return;
+        Pc = bridge_f(r0, r1, R, S.inv_s[rx]);
+    }
+    if (!log_all && !(Pc > 0x1p-25f)) return;
+    const uint64_t ui = uid[i], uj = uid[j];
+    const uint64_t lo = ui < uj ? ui : uj, hi = ui < uj ? uj : ui;
+    uint64_t w[4];
+    philox(lo, hi, S.step, 1ull, S.key0, S.key1, w);
+    const uint32_t u24 = (uint32_t)(w[0] >> 40);
+    // u = (2 u24 + 1) 2^-25 < P, compared exactly in FP64
+    const bool acc = (double)(2u * u24 + 1u) * 0x1p-25 < (double)Pc;
+    if (acc || log_all) {
+        const uint32_t k = atomicAdd(&ctr->n_pairs, 1u);
+        if (k < pair_cap) {
+            PairRec r;
+            r.i = i;
+            r.j = j;
+            r.u24 = u24;
+            r.rx = rx;
+            r.P = Pc;
+            r.flags = acc ? 1 : 0;
+            pairs[k] = r;
+        } else {
+            atomicOr(&ctr->err, kErrPairOverflow);
+        }
+    }
+}
+
+__device__ __forceinline__ void test_pair(int i, int j, const float4& pi, const float4* __restrict__ pos,
+                                          const float4* __restrict__ pos0, const uint64_t* __restrict__ uid,
+                                          const InstStep& S, int rx, float rc2, int contact_only, int log_all,
+                                          DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                          uint32_t pair_cap, unsigned long long& ncand) {
+    const float d2 = end_d2(pos[j], pi, S.L, S.halfL);
+    if (!(d2 < rc2)) return;
+    ++ncand;
+    eval_candidate(i, j, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs, pair_cap);
+}
+
+// Lower bound of the distance along one axis from x to the cell `o` cells away
+// from its own cell q (unwrapped), minus a slack for FP32 binning.
+__device__ __forceinline__ float cell_gap(float x, int q, int o, float h, float hL, float eps) {
+    float g = 0.0f;
+    if (o > 0) g = (float)(q + o) * h - hL - x;
+    else if (o < 0) g = x - ((float)(q + o + 1) * h - hL);
+    g -= eps;
+    return g > 0.0f ? g : 0.0f;
+}
+
+// Whole-cell search (small cells, few molecules each): one thread per sorted
+// molecule reads every molecule of the stencil cells and checks its species;
+// a pair is searched from the molecule in the lower cell (or with the lower
+// index in one cell).  Cells whose distance from the molecule exceeds the
+// largest cutoff of its species are skipped.
 __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__ pos,
                                                     const float4* __restrict__ pos0,
                                                     const uint64_t* __restrict__ uid,
@@ -317,10 +472,12 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
                                                     const ChemDev* __restrict__ chem,
                                                     const uint32_t* __restrict__ start,
                                                     PairRec* __restrict__ pairs, uint32_t pair_cap,
-                                                    int32_t log_all) {
+                                                    int32_t log_all, int32_t ns) {
     __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
+    __shared__ unsigned long long s_cand;
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
+    if (threadIdx.x == 0) s_cand = 0ull;
     __syncthreads();
     const uint32_t reactive = chem->reactive_mask;
     const int contact_only = chem->contact_only;
@@ -332,83 +489,244 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
         const int si = mi & 0xFF;
         if (!((reactive >> si) & 1u)) continue;
         const InstStep& S = P[mi >> 8];
-        if (!S.active) continue;
-        const float4 qi = pos0[i];
-        const int ci = (int)__float_as_uint(qi.w);
-        const int nc = S.nc;
-        const int loc = ci - S.cell_base;
-        const int ix = loc / (nc * nc), iy = (loc / nc) % nc, iz = loc % nc;
-        const uint64_t ui = uid[i];
+        if (!S.active || S.by_species) continue;
+        const int cg = (int)__float_as_uint(pos0[i].w) - S.bin_base;  // local cell
+        const int nc = S.nc, m = S.reach;
+        const int ix = cg / (nc * nc), iy = (cg / nc) % nc, iz = cg % nc;
+        const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
+        const int lo = full ? 0 : -m, hi = full ? nc - 1 : m;
+        const float h = S.h, hL = S.halfL, eps = S.cull_eps;
+        const float cmax = S.cull2_all[si];
         const int* row = rmap + si * kMaxSpecies;
-        const float L = S.L, hL = S.halfL;
-        for (int ox = -1; ox <= 1; ++ox) {
-            if ((nc == 1 && ox != 0) || (nc == 2 && ox == 1)) continue;
-            const int qx = (ix + ox + nc) % nc;
-            for (int oy = -1; oy <= 1; ++oy) {
-                if ((nc == 1 && oy != 0) || (nc == 2 && oy == 1)) continue;
-                const int qy = (iy + oy + nc) % nc;
-                for (int oz = -1; oz <= 1; ++oz) {
-                    if ((nc == 1 && oz != 0) || (nc == 2 && oz == 1)) continue;
-                    const int qz = (iz + oz + nc) % nc;
-                    const int c2 = S.cell_base + (qx * nc + qy) * nc + qz;
-                    if (c2 < ci) continue;  // each unordered pair of cells once
-                    int j = (c2 == ci) ? i + 1 : (int)start[c2];
-                    const int j1 = (int)start[c2 + 1];
+        for (int ox = lo; ox <= hi; ++ox) {
+            const int qx = full ? ox : (ix + ox + nc) % nc;
+            const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
+            const float gx2 = gx * gx;
+            if (gx2 > cmax) continue;
+            for (int oy = lo; oy <= hi; ++oy) {
+                const int qy = full ? oy : (iy + oy + nc) % nc;
+                const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
+                const float gxy2 = gx2 + gy * gy;
+                if (gxy2 > cmax) continue;
+                for (int oz = lo; oz <= hi; ++oz) {
+                    const int qz = full ? oz : (iz + oz + nc) % nc;
+                    const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
+                    if (gxy2 + gz * gz > cmax) continue;
+                    const int c2 = (qx * nc + qy) * nc + qz;
+                    if (c2 < cg) continue;
+                    int j = (c2 == cg) ? i + 1 : (int)start[S.bin_base + c2];
+                    const int j1 = (int)start[S.bin_base + c2 + 1];
                     for (; j < j1; ++j) {
-                        const float4 pj = pos[j];
-                        const int rx = row[__float_as_int(pj.w) & 0xFF];
+                        const int sj = __float_as_int(pos[j].w) & 0xFF;
+                        const int rx = row[sj];
                         if (rx < 0) continue;
-                        const float dx = minimg_f(__fsub_rn(pj.x, pi.x), L, hL);
-                        const float dy = minimg_f(__fsub_rn(pj.y, pi.y), L, hL);
-                        const float dz = minimg_f(__fsub_rn(pj.z, pi.z), L, hL);
-                        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-                        if (!(d2 < S.rc2[rx])) continue;
-                        ++ncand;
-                        const float4 qj = pos0[j];
-                        const float ex = minimg_f(qj.x - qi.x, L, hL);
-                        const float ey = minimg_f(qj.y - qi.y, L, hL);
-                        const float ez = minimg_f(qj.z - qi.z, L, hL);
-                        const float r1 = sqrtf(d2);
-                        const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
-                        const float R = S.R[rx];
-                        float Pc;
-                        if (contact_only) {
-                            Pc = (r0 <= R || r1 <= R) ? 1.0f : 0.0f;
+                        test_pair(i, j, pi, pos, pos0, uid, S, rx, S.rc2[rx], contact_only, log_all, ctr, pairs,
+                                  pair_cap, ncand);
+                    }
+                }
+            }
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
+    if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_cand, ncand);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
+}
+
+// Per-wave candidate queue in LDS: the distance test runs on every lane, the
+// few pairs that pass it are compacted by a ballot and evaluated (start
+// separation, bridge, Philox) 64 at a time with every lane busy.  All lanes
+// of the wave must call qpush and qdrain together.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void qdrain(int4* q, int& qn, int lane, const float4* __restrict__ pos0,
+                                       const uint64_t* __restrict__ uid, const InstStep& S, int contact_only,
+                                       int log_all, DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                       uint32_t pair_cap) {
+    if (qn == 0) return;
+    wave_sync_lds();
+    const int4 v = q[lane];
+    const bool mine = lane < qn;
+    wave_sync_lds();
+    qn = 0;
+    if (mine) eval_candidate(v.x, v.y, __int_as_float(v.w), pos0, uid, S, v.z, contact_only, log_all, ctr, pairs,
+                             pair_cap);
+}
+
+__device__ __forceinline__ void qpush(int4* q, int& qn, int lane, bool cand, int i, int j, int rx, float d2,
+                                      const float4* __restrict__ pos0, const uint64_t* __restrict__ uid,
+                                      const InstStep& S, int contact_only, int log_all,
+                                      DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                      unsigned long long& ncand) {
+    const unsigned long long m = __ballot(cand);
+    if (m == 0ull) return;
+    if (cand) {
+        ++ncand;
+        q[qn + __popcll(m & ((1ull << lane) - 1ull))] = make_int4(i, j, rx, __float_as_int(d2));
+    }
+    qn += __popcll(m);
+    if (qn < 64) return;
+    wave_sync_lds();
+    const int4 v = q[lane];
+    const int rest = qn - 64;
+    int4 r = make_int4(0, 0, 0, 0);
+    if (lane < rest) r = q[64 + lane];
+    wave_sync_lds();
+    if (lane < rest) q[lane] = r;
+    qn = rest;
+    eval_candidate(v.x, v.y, __int_as_float(v.w), pos0, uid, S, v.z, contact_only, log_all, ctr, pairs, pair_cap);
+}
+
+// Species-bin search (large cells).  Bins are species-major (bin = bin_base +
+// species * nc^3 + cell, cell = (ix*nc + iy)*nc + iz), so one species'
+// molecules along a z-row of cells are contiguous.  A work unit is (species s,
+// row (ix, iy), segment of kseg cells in z); a wave takes up to 64 of the
+// unit's molecules, one per lane, and streams, with loads shared by the whole
+// wave, every partner row (ix+ox, iy+oy), |ox|,|oy| <= reach, of every partner
+// species t >= s over the z-cells within reach of the segment.  Rows whose
+// cell distance exceeds the pair's cutoff are skipped.  A pair of one species
+// is tested from the molecule with the lower sorted index.
+__global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restrict__ pos,
+                                                         const float4* __restrict__ pos0,
+                                                         const uint64_t* __restrict__ uid,
+                                                         DevCounters* __restrict__ ctr,
+                                                         const InstStep* __restrict__ P,
+                                                         const ChemDev* __restrict__ chem,
+                                                         const uint32_t* __restrict__ start,
+                                                         PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                                         int32_t log_all, int32_t n_inst, int32_t total_units) {
+    __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
+    __shared__ int32_t plist[kMaxSpecies * kMaxSpecies];  // partner species t >= s of s, ascending
+    __shared__ int32_t pcount[kMaxSpecies];
+    __shared__ unsigned long long s_cand;
+    __shared__ int4 q_all[GSBS_BLOCK / 64][128];
+    __shared__ float4 stage_all[GSBS_BLOCK / 64][64];
+    for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
+        rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
+    if (threadIdx.x < kMaxSpecies) {
+        const uint32_t pm = chem->pmask[threadIdx.x];
+        int q = 0;
+        for (int t = 0; t < kMaxSpecies; ++t)
+            if ((pm >> t) & 1u) plist[threadIdx.x * kMaxSpecies + q++] = t;
+        pcount[threadIdx.x] = q;
+    }
+    if (threadIdx.x == 0) s_cand = 0ull;
+    __syncthreads();
+    const int contact_only = chem->contact_only;
+    const int lane = threadIdx.x & 63;
+    const int waves = GSBS_BLOCK / 64;
+    int4* q = q_all[threadIdx.x >> 6];
+    float4* stage = stage_all[threadIdx.x >> 6];
+    int qn = 0;  // wave-uniform queue length
+    unsigned long long ncand = 0;
+    for (int u = blockIdx.x * waves + (threadIdx.x >> 6); u < total_units; u += gridDim.x * waves) {
+        // instance owning unit u (instances own consecutive unit ranges)
+        int lo_i = 0, hi_i = n_inst - 1;
+        while (lo_i < hi_i) {
+            const int mid = (lo_i + hi_i + 1) >> 1;
+            if (P[mid].unit_base <= u) lo_i = mid;
+            else hi_i = mid - 1;
+        }
+        const InstStep& S = P[lo_i];
+        if (!S.active || !S.by_species) continue;
+        const int nc = S.nc, m = S.reach, K = S.kseg;
+        const int nseg = (nc + K - 1) / K;
+        const int lu = u - S.unit_base;
+        if (lu >= chem->n_species * nc * nc * nseg) continue;
+        const int si = lu / (nc * nc * nseg);
+        const int nsp = pcount[si];
+        if (nsp == 0) continue;
+        const int r = lu - si * (nc * nc * nseg);
+        const int rowA = r / nseg, seg = r - rowA * nseg;
+        const int ix = rowA / nc, iy = rowA - ix * nc;
+        const int z0 = seg * K, z1 = min(z0 + K, nc);
+        const int ncell = nc * nc * nc;
+        const int binA = S.bin_base + si * ncell + rowA * nc + z0;
+        const int a0 = (int)start[binA], a1 = (int)start[binA + (z1 - z0)];
+        if (a0 == a1) continue;
+        const bool full = nc < 2 * m + 1;
+        const int lo = full ? 0 : -m, w = full ? nc : 2 * m + 1;
+        const float h = S.h, eps = S.cull_eps, L = S.L, hL = S.halfL;
+        const int* rrow = rmap + si * kMaxSpecies;
+        const int* pl = plist + si * kMaxSpecies;
+        // z-cells of the partner rows: [z0 - m, z1 - 1 + m], the whole row if that covers it
+        const bool zall = (z1 - z0) + 2 * m >= nc;
+        for (int ab = a0; ab < a1; ab += 64) {
+            const int ia = ab + lane;
+            const bool va = ia < a1;
+            const float4 pa = pos[va ? ia : a0];
+            for (int ox = lo; ox < lo + w; ++ox) {
+                const int qx = full ? ox : (ix + ox + nc) % nc;
+                const float gx = full ? 0.0f : fmaxf((float)(abs(ox) - 1) * h - eps, 0.0f);
+                for (int oy = lo; oy < lo + w; ++oy) {
+                    const int qy = full ? oy : (iy + oy + nc) % nc;
+                    const float gy = full ? 0.0f : fmaxf((float)(abs(oy) - 1) * h - eps, 0.0f);
+                    const float g2 = gx * gx + gy * gy;
+                    if (g2 > S.cull2_sp[si]) continue;
+                    const int rowB = qx * nc + qy;
+                    for (int qq = 0; qq < nsp; ++qq) {
+                        const int sj = pl[qq];
+                        const int rx = rrow[sj];
+                        if (g2 > S.cull2[rx]) continue;
+                        const bool same = (sj == si);
+                        if (same && rowB < rowA) continue;
+                        const float rc2 = S.rc2[rx];
+                        const int binB = S.bin_base + sj * ncell + rowB * nc;
+                        // up to two contiguous z pieces
+                        int zl[2], zh[2], np = 1;
+                        if (zall) {
+                            zl[0] = 0;
+                            zh[0] = nc - 1;
                         } else {
-                            // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
-                            const float a = (r0 - R) * (r1 - R) * S.inv_s[rx];
-                            if (!log_all && r0 > R && r1 > R && a > 18.0f) continue;
-                            Pc = bridge_f(r0, r1, R, S.inv_s[rx]);
-                        }
-                        if (!log_all && !(Pc > 0x1p-25f)) continue;
-                        const uint64_t uj = uid[j];
-                        const uint64_t lo = ui < uj ? ui : uj, hi = ui < uj ? uj : ui;
-                        uint64_t w[4];
-                        philox(lo, hi, S.step, 1ull, S.key0, S.key1, w);
-                        const uint32_t u24 = (uint32_t)(w[0] >> 40);
-                        // u = (2 u24 + 1) 2^-25 < P, compared exactly in FP64
-                        const bool acc = (double)(2u * u24 + 1u) * 0x1p-25 < (double)Pc;
-                        if (acc || log_all) {
-                            const uint32_t k = atomicAdd(&ctr->n_pairs, 1u);
-                            if (k < pair_cap) {
-                                PairRec r;
-                                r.i = i;
-                                r.j = j;
-                                r.u24 = u24;
-                                r.rx = rx;
-                                r.P = Pc;
-                                r.flags = acc ? 1 : 0;
-                                pairs[k] = r;
+                            const int zb0 = z0 - m, zb1 = z1 - 1 + m;
+                            if (zb0 < 0) {
+                                zl[0] = 0; zh[0] = zb1;
+                                zl[1] = zb0 + nc; zh[1] = nc - 1;
+                                np = 2;
+                            } else if (zb1 >= nc) {
+                                zl[0] = zb0; zh[0] = nc - 1;
+                                zl[1] = 0; zh[1] = zb1 - nc;
+                                np = 2;
                             } else {
-                                atomicOr(&ctr->err, kErrPairOverflow);
+                                zl[0] = zb0; zh[0] = zb1;
+                            }
+                        }
+                        for (int pc = 0; pc < np; ++pc) {
+                            const int jb0 = (int)start[binB + zl[pc]];
+                            const int jb1 = (int)start[binB + zh[pc] + 1];
+                            // 64 partners at a time: one coalesced load into LDS, then LDS broadcast reads
+                            for (int jc = jb0; jc < jb1; jc += 64) {
+                                const int cnt = min(64, jb1 - jc);
+                                wave_sync_lds();
+                                if (lane < cnt) stage[lane] = pos[jc + lane];
+                                wave_sync_lds();
+                                for (int t = 0; t < cnt; ++t) {
+                                    const float4 pj = stage[t];
+                                    const int j = jc + t;
+                                    float d2 = 0.0f;
+                                    bool cand = false;
+                                    if (va && (!same || j > ia)) {
+                                        d2 = end_d2(pj, pa, L, hL);
+                                        cand = d2 < rc2;
+                                    }
+                                    qpush(q, qn, lane, cand, ia, j, rx, d2, pos0, uid, S, contact_only, log_all,
+                                          ctr, pairs, pair_cap, ncand);
+                                }
                             }
                         }
                     }
                 }
             }
         }
+        qdrain(q, qn, lane, pos0, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
     }
-    if (ncand) atomicAdd(&ctr->cand, ncand);
+    for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
+    if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
 }
 
 // --------------------------------------------------------------- react ---
@@ -586,24 +904,34 @@ const char* const kStepKernelNames[kStepKernels] = {"k_bin", "k_scan_reduce", "k
                                                      "k_scatter", "k_pairs", "k_react"};
 
 void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const ChemDev* chem,
-                 int32_t n_inst, int32_t total_cells, int32_t grid, int32_t flags, hipEvent_t* ev) {
+                 int32_t n_inst, int32_t total_bins, int32_t total_units, int32_t ns, int32_t grid, int32_t flags,
+                 hipEvent_t* ev) {
     const int fixed = (flags & kStepFixed) ? 1 : 0;
-    const int nb = (total_cells + kScanTile - 1) / kScanTile;
+    const int nb = (total_bins + kScanTile - 1) / kScanTile;
     int k = 0;
     auto mark = [&](int end) {
         if (ev) (void)hipEventRecord(ev[2 * k + end], st);
         if (end) ++k;
     };
     mark(0);
-    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
-                       b.cell_count, b.cellrank, fixed);
+    if (total_bins <= kLdsBins) {
+        // enough blocks that no block owns more than kBinRounds * GSBS_BLOCK molecules
+        const int g = grid > (b.cap + kBinRounds * GSBS_BLOCK - 1) / (kBinRounds * GSBS_BLOCK)
+                          ? grid
+                          : (b.cap + kBinRounds * GSBS_BLOCK - 1) / (kBinRounds * GSBS_BLOCK);
+        hipLaunchKernelGGL(k_bin_lds, dim3(g), dim3(GSBS_BLOCK), total_bins * sizeof(uint32_t), st, b.pos_in,
+                           b.uid_in, b.ctr, P, b.cell_count, b.cellrank, fixed, total_bins, ns);
+    } else {
+        hipLaunchKernelGGL(k_bin, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
+                           b.cell_count, b.cellrank, fixed, ns);
+    }
     mark(1);
     mark(0);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_cells,
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins,
                        b.block_sums);
     mark(1);
     mark(0);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_cells,
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins,
                        b.block_sums, b.cell_start, b.ctr);
     mark(1);
     mark(0);
@@ -612,9 +940,16 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
                        fixed ? b.x0_override : nullptr);
     mark(1);
     mark(0);
-    hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
-                       b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap,
-                       (flags & kStepLogAll) ? 1 : 0);
+    if (flags & kStepHasWhole)
+        hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
+                           b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap, (flags & kStepLogAll) ? 1 : 0, ns);
+    if (flags & kStepHasSpecies) {
+        int gb = (total_units + GSBS_BLOCK / 64 - 1) / (GSBS_BLOCK / 64);
+        gb = gb < 1 ? 1 : (gb > 65536 ? 65536 : gb);
+        hipLaunchKernelGGL(k_pairs_rows, dim3(gb), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
+                           b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap, (flags & kStepLogAll) ? 1 : 0, n_inst,
+                           total_units);
+    }
     mark(1);
     mark(0);
     hipLaunchKernelGGL(k_react, dim3(1), dim3(kReactBlock), 0, st, b.pos_out, b.uid_out, b.ctr, P, chem,

@@ -51,7 +51,7 @@ class gsbs_reaction(C.Structure):
 class gsbs_params(C.Structure):
     _fields_ = [("c_cut", C.c_double), ("rounds", C.c_int32), ("contact_only", C.c_int32),
                 ("dt0_ns", C.c_double), ("ratio", C.c_double), ("dt_max_ns", C.c_double),
-                ("k_occ", C.c_double)]
+                ("grid_config", C.c_int32), ("autotune", C.c_int32)]
 
 
 class gsbs_stats(C.Structure):
@@ -81,6 +81,8 @@ _SIGS = {
     "gsbs_get_time": [_vp, _i32, _P(_d)],
     "gsbs_get_n": [_vp, _i32, _P(_i64)],
     "gsbs_get_stats": [_vp, _P(gsbs_stats)],
+    "gsbs_get_step_log": [_vp, _i64, _P(_i64), _P(_d), _P(_i32), _P(_i64), _P(_i64)],
+    "gsbs_get_tuning": [_i32, _P(_i32), _P(_i32), _P(_d), _P(_i32)],
     "gsbs_set_profiling": [_vp, _i32],
     "gsbs_get_profile": [_vp, _i32, C.c_char_p, _P(_d), _P(_i64), _P(_i32)],
     "gsbs_plan_schedule": [_d, _d, _i32, _P(_d), _i32, _P(_d), _d, _d, _d, _P(_d), _i64, _P(_i64)],
@@ -234,6 +236,34 @@ def gsbs_get_stats(ctx):
     return {k: getattr(s, k) for k, _ in gsbs_stats._fields_}
 
 
+def gsbs_get_step_log(ctx):
+    """Profiled steps: dict of arrays step, ms, nc, reach, by_species, cfg, n_est."""
+    n = _i64()
+    _chk(_lib.gsbs_get_step_log(ctx, 0, None, None, None, None, C.byref(n)))
+    m = max(n.value, 1)
+    st = np.zeros(m, dtype=np.int64)
+    ms = np.zeros(m)
+    gr = np.zeros(4 * m, dtype=np.int32)
+    ne = np.zeros(m, dtype=np.int64)
+    _chk(_lib.gsbs_get_step_log(ctx, m, _ptr(st, _i64), _ptr(ms, _d), _ptr(gr, _i32), _ptr(ne, _i64), C.byref(n)))
+    k = n.value
+    gr = gr.reshape(-1, 4)
+    return dict(step=st[:k], ms=ms[:k], nc=gr[:k, 0], reach=gr[:k, 1], by_species=gr[:k, 2], cfg=gr[:k, 3],
+                n_est=ne[:k])
+
+
+def gsbs_get_tuning():
+    """[(occupancy octave, molecule octave, best configuration, mean step ms)]."""
+    n = _i32()
+    _chk(_lib.gsbs_get_tuning(0, None, None, None, C.byref(n)))
+    m = max(n.value, 1)
+    keys = np.zeros(2 * m, dtype=np.int32)
+    best = np.zeros(m, dtype=np.int32)
+    ms = np.zeros(m)
+    _chk(_lib.gsbs_get_tuning(m, _ptr(keys, _i32), _ptr(best, _i32), _ptr(ms, _d), C.byref(n)))
+    return [(int(keys[2 * k]), int(keys[2 * k + 1]), int(best[k]), float(ms[k])) for k in range(n.value)]
+
+
 def gsbs_set_profiling(ctx, on: bool):
     _chk(_lib.gsbs_set_profiling(ctx, 1 if on else 0))
 
@@ -322,6 +352,8 @@ def gsbs_debug_get_cells(ctx):
 DEBUG_FIXED = 1
 DEBUG_LOG_ALL = 2
 DEBUG_SEARCH_ONLY = 4
+DEBUG_BY_SPECIES = 8
+DEBUG_WHOLE_CELLS = 16
 
 
 # ----------------------------------------------------- convenience layer ---

@@ -36,6 +36,7 @@ def test_default_params(g):
     p = g.gsbs_default_params()
     assert p.c_cut == 5.0 and p.rounds == 4 and p.contact_only == 0
     assert p.dt0_ns == 1e-3 and p.ratio == 10.0 ** (6.0 / 1999.0)
+    assert p.grid_config == -1 and p.autotune == 1
 
 
 def test_invalid_arguments_fail_cleanly(g):

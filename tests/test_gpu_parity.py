@@ -110,8 +110,17 @@ def test_binning_bit_exact(g, orc, nc):
 
 
 # ----------------------------------------------------- candidate pairs ---
-@pytest.mark.parametrize("dt,nc", [(0.05, 0), (3.0, 0), (3.0, 2), (40.0, 1), (40.0, 0)])
-def test_candidates_bit_exact(g, orc, dt, nc):
+MODES = {"auto": 0, "species": 8, "whole": 16}
+
+
+@pytest.mark.parametrize("dt,nc,mode", [(0.05, 0, "auto"), (3.0, 0, "species"), (3.0, 2, "whole"),
+                                        (40.0, 1, "whole"), (40.0, 1, "species"), (40.0, 0, "species"),
+                                        (3.0, 12, "species"), (0.5, 20, "species"), (3.0, 30, "whole"),
+                                        (3.0, 30, "species")])
+def test_candidates_bit_exact(g, orc, dt, nc, mode):
+    """Candidate pairs on fixed positions equal the oracle's FP32 brute force
+    for both search modes, coarse and fine grids (stencil reach 1-4) and grids
+    of fewer than 3 cells per axis; P and u24 match the oracle's."""
     L = 400.0
     rng = np.random.default_rng(int(dt * 100) + nc)
     n = 3000
@@ -122,10 +131,11 @@ def test_candidates_bit_exact(g, orc, dt, nc):
     x1 = ((x0 + rng.normal(0, math.sqrt(2 * 5 * dt), size=(n, 3)) + L / 2) % L - L / 2).astype(np.float32)
     sp = rng.integers(0, 7, size=n).astype(np.uint8)
     uid = np.arange(n, dtype=np.uint64)
-    say("candidates", dt, nc)
+    say("candidates", dt, nc, mode)
     e = make_engine(g, L, 9)
     g.gsbs_debug_set_state(e.ctx, x1, sp, uid, step=4)
-    g.gsbs_debug_step(e.ctx, dt, g.DEBUG_FIXED | g.DEBUG_SEARCH_ONLY | g.DEBUG_LOG_ALL, xyz0=x0, nc_force=nc)
+    g.gsbs_debug_step(e.ctx, dt, g.DEBUG_FIXED | g.DEBUG_SEARCH_ONLY | g.DEBUG_LOG_ALL | MODES[mode], xyz0=x0,
+                      nc_force=nc)
     pr = g.gsbs_debug_get_pairs(e.ctx)
     chem = orc.make_chem(W.D_CONFIG, W.REACTIONS)
     ref = orc.cand_f32(x1, sp, L, chem, dt)
