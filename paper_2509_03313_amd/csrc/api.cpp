@@ -67,6 +67,7 @@ struct InstHost {
     uint64_t next_uid = 0;
     double edep = 0;
     int64_t n_est = 0;
+    int64_t sp_est[kMaxSpecies] = {};  // species counts at the last refresh
     std::vector<double> anchors;
     std::vector<Pending> pending;
     std::vector<double> rec_t;
@@ -404,7 +405,8 @@ constexpr int kNumCfg = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 // Grid of one instance for one configuration: nc cells per axis, no smaller
 // than (cutoff / reach) and at least `occ` molecules per cell on average.
 // Returns cells.
-int32_t fill_grid(double L, int64_t n_est, double rcmax, const GridCfg& g, int32_t nc_force, InstStep& S) {
+int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_est, double rcmax, const GridCfg& g,
+                  int32_t nc_force, InstStep& S) {
     int64_t nc;
     const int64_t nocc = std::max<int64_t>(1, (int64_t)std::floor(std::cbrt((double)std::max<int64_t>(n_est, 1) / g.occ)));
     if (nc_force > 0) {
@@ -423,19 +425,37 @@ int32_t fill_grid(double L, int64_t n_est, double rcmax, const GridCfg& g, int32
     // slack of the FP32 cell-distance bound: a few ulps of the edge plus the binning rounding
     S.cull_eps = 8.0f * std::nextafter(S.halfL, 2.0f * S.halfL) - 8.0f * S.halfL + 1e-6f * S.h;
     S.by_species = g.by_species;
-    // species-bin work unit: about 64 molecules of one species along a z-row
-    const double per_cell_species = (double)std::max<int64_t>(n_est, 1) / ((double)nc * nc * nc * 4.0);
-    int64_t kseg = (int64_t)std::ceil(64.0 / std::max(per_cell_species, 1e-9));
-    S.kseg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kseg, nc));
+    if (g.by_species) {
+        // each pair of species is searched from the more abundant one (full waves)
+        for (size_t r = 0; r < c->rx.size(); ++r) {
+            const int a = c->rx[r].a, b = c->rx[r].b;
+            if (a == b) {
+                S.pm_dir[a] |= 1u << a;
+            } else if (sp_est[a] > sp_est[b] || (sp_est[a] == sp_est[b] && a < b)) {
+                S.pm_dir[a] |= 1u << b;
+            } else {
+                S.pm_dir[b] |= 1u << a;
+            }
+        }
+        // work unit: a cube of kb^3 cells holding about 64 molecules of one species
+        const double ncell = (double)nc * nc * nc;
+        int64_t off = 0;
+        for (int s = 0; s < c->ns; ++s) {
+            const double per_cell = (double)std::max<int64_t>(sp_est[s], 0) / ncell;
+            int64_t kb = per_cell > 0 ? (int64_t)std::ceil(std::cbrt(48.0 / per_cell)) : 8;
+            kb = std::max<int64_t>(1, std::min<int64_t>({kb, nc, 8}));
+            S.kseg_sp[s] = (int32_t)kb;
+            S.unit_off_sp[s] = (int32_t)off;
+            const int64_t nb = (nc + kb - 1) / kb;
+            if (S.pm_dir[s]) off += nb * nb * nb;
+        }
+        S.unit_off_sp[c->ns] = (int32_t)off;
+    }
     return (int32_t)(nc * nc * nc);
 }
 
 // Work units of the species-bin search of one instance.
-int64_t units_of(const InstStep& S, int ns) {
-    if (!S.by_species) return 0;
-    const int64_t nseg = (S.nc + S.kseg - 1) / S.kseg;
-    return (int64_t)ns * S.nc * S.nc * nseg;
-}
+int64_t units_of(const InstStep& S, int ns) { return S.by_species ? S.unit_off_sp[ns] : 0; }
 
 // Tuning key: occupancy of a grid whose cells equal the largest cutoff, in
 // octaves (the second key is kept for the table layout and is always 0).
@@ -624,7 +644,10 @@ int refresh_estimates(gsbs_ctx* c) {
     int64_t tot = 0;
     for (int i = 0; i < c->n_inst; ++i) {
         int64_t s = 0;
-        for (int k = 0; k < kMaxSpecies; ++k) s += cnt[(size_t)i * kMaxSpecies + k];
+        for (int k = 0; k < kMaxSpecies; ++k) {
+            s += cnt[(size_t)i * kMaxSpecies + k];
+            c->inst[i].sp_est[k] = cnt[(size_t)i * kMaxSpecies + k];
+        }
         c->inst[i].n_est = s;
         tot += s;
     }
@@ -921,7 +944,10 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
             if (!c->cnt_pending[sl] || hipEventQuery(c->cnt_ev[sl]) != hipSuccess) continue;
             for (int i = 0; i < c->n_inst; ++i) {
                 int64_t s = 0;
-                for (int k = 0; k < kMaxSpecies; ++k) s += c->h_cnt[sl][(size_t)i * kMaxSpecies + k];
+                for (int k = 0; k < kMaxSpecies; ++k) {
+                    s += c->h_cnt[sl][(size_t)i * kMaxSpecies + k];
+                    c->inst[i].sp_est[k] = c->h_cnt[sl][(size_t)i * kMaxSpecies + k];
+                }
                 c->inst[i].n_est = s + (c->injected[i] - c->cnt_mark[sl][i]);
             }
         }
@@ -963,7 +989,7 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
                     step_cfg[k] = cfg;
                     step_nest[k] = nest[i];
                 }
-                const int32_t cells = fill_grid(c->inst[i].L, nest[i], rcm[i], kCfgs[cfg], 0, row);
+                const int32_t cells = fill_grid(c, c->inst[i].sp_est, c->inst[i].L, nest[i], rcm[i], kCfgs[cfg], 0, row);
                 base += row.by_species ? cells * c->ns : cells;
                 row.unit_base = (int32_t)ubase;
                 ubase += units_of(row, c->ns);
@@ -1269,6 +1295,7 @@ int gsbs_debug_set_state(gsbs_ctx* c, int64_t n, const float* xyz, const uint8_t
     in.step = (uint64_t)step;
     in.next_uid = next_uid;
     in.n_est = n;
+    for (int k = 0; k < kMaxSpecies; ++k) in.sp_est[k] = cnt[k];
     return GSBS_OK;
 }
 
@@ -1306,7 +1333,7 @@ int gsbs_debug_step(gsbs_ctx* c, double dt, int32_t flags, const float* xyz0, in
     if (flags & kStepBySpecies) gc.by_species = 1;
     if (flags & kStepWholeCells) gc.by_species = 0;
     S[0].bin_base = 0;
-    const int32_t ncell = fill_grid(in.L, in.n_est, rcmax, gc, nc_force, S[0]);
+    const int32_t ncell = fill_grid(c, in.sp_est, in.L, in.n_est, rcmax, gc, nc_force, S[0]);
     S[0].unit_base = 0;
     const int32_t units = (int32_t)units_of(S[0], c->ns);
     const int32_t cells = S[0].by_species ? ncell * c->ns : ncell;

@@ -533,62 +533,194 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
     if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
 }
 
-// Per-wave candidate queue in LDS: the distance test runs on every lane, the
-// few pairs that pass it are compacted by a ballot and evaluated (start
-// separation, bridge, Philox) 64 at a time with every lane busy.  All lanes
-// of the wave must call qpush and qdrain together.
+// Per-wave queue in LDS of the candidates that need the contact probability:
+// the distance test runs on every lane, the few pairs that pass it (and whose
+// bridge exponent can still give an acceptance) are compacted by a ballot and
+// evaluated 64 at a time with every lane busy.  An entry carries everything
+// the evaluation needs, so draining issues no global loads.  All lanes of the
+// wave must call qpush / qdrain together.
+struct QEntry {
+    int4 a;    // i, j, rx, bits of r0
+    float4 b;  // r1, unused
+    ulonglong2 u;  // uid_i, uid_j
+};
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void qdrain(int4* q, int& qn, int lane, const float4* __restrict__ pos0,
-                                       const uint64_t* __restrict__ uid, const InstStep& S, int contact_only,
-                                       int log_all, DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
-                                       uint32_t pair_cap) {
-    if (qn == 0) return;
-    wave_sync_lds();
-    const int4 v = q[lane];
-    const bool mine = lane < qn;
-    wave_sync_lds();
-    qn = 0;
-    if (mine) eval_candidate(v.x, v.y, __int_as_float(v.w), pos0, uid, S, v.z, contact_only, log_all, ctr, pairs,
-                             pair_cap);
+// Bridge probability, pair uniform and acceptance of a queued candidate.
+__device__ __forceinline__ void eval_queued(const QEntry& e, const InstStep& S, int contact_only, int log_all,
+                                            DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                            uint32_t pair_cap) {
+    const int rx = e.a.z;
+    const float r0 = __int_as_float(e.a.w), r1 = e.b.x;
+    const float R = S.R[rx];
+    float Pc;
+    if (contact_only) Pc = (r0 <= R || r1 <= R) ? 1.0f : 0.0f;
+    else Pc = bridge_f(r0, r1, R, S.inv_s[rx]);
+    if (!log_all && !(Pc > 0x1p-25f)) return;
+    const uint64_t ui = e.u.x, uj = e.u.y;
+    const uint64_t lo = ui < uj ? ui : uj, hi = ui < uj ? uj : ui;
+    uint64_t w[4];
+    philox(lo, hi, S.step, 1ull, S.key0, S.key1, w);
+    const uint32_t u24 = (uint32_t)(w[0] >> 40);
+    const bool acc = (double)(2u * u24 + 1u) * 0x1p-25 < (double)Pc;
+    if (acc || log_all) {
+        const uint32_t k = atomicAdd(&ctr->n_pairs, 1u);
+        if (k < pair_cap) {
+            PairRec r;
+            r.i = e.a.x;
+            r.j = e.a.y;
+            r.u24 = u24;
+            r.rx = rx;
+            r.P = Pc;
+            r.flags = acc ? 1 : 0;
+            pairs[k] = r;
+        } else {
+            atomicOr(&ctr->err, kErrPairOverflow);
+        }
+    }
 }
 
-__device__ __forceinline__ void qpush(int4* q, int& qn, int lane, bool cand, int i, int j, int rx, float d2,
-                                      const float4* __restrict__ pos0, const uint64_t* __restrict__ uid,
+// Append the lanes' entries (need) and, once 64 are queued -- or, with
+// force, whatever is queued -- evaluate up to 64 of them, one per lane.  The
+// only place that evaluates, so the evaluation is inlined once.
+__device__ __forceinline__ void qpush(QEntry* q, int& qn, int lane, bool need, const QEntry& e, bool force,
                                       const InstStep& S, int contact_only, int log_all,
-                                      DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap,
-                                      unsigned long long& ncand) {
-    const unsigned long long m = __ballot(cand);
-    if (m == 0ull) return;
-    if (cand) {
-        ++ncand;
-        q[qn + __popcll(m & ((1ull << lane) - 1ull))] = make_int4(i, j, rx, __float_as_int(d2));
+                                      DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap) {
+    const unsigned long long m = __ballot(need);
+    if (m != 0ull) {
+        if (need) q[qn + __popcll(m & ((1ull << lane) - 1ull))] = e;
+        qn += __popcll(m);
     }
-    qn += __popcll(m);
-    if (qn < 64) return;
+    if (qn < 64 && !(force && qn > 0)) return;
     wave_sync_lds();
-    const int4 v = q[lane];
-    const int rest = qn - 64;
-    int4 r = make_int4(0, 0, 0, 0);
+    const int take = qn < 64 ? qn : 64;
+    const bool mine = lane < take;
+    QEntry v;
+    if (mine) v = q[lane];
+    const int rest = qn - take;
+    QEntry r;
     if (lane < rest) r = q[64 + lane];
     wave_sync_lds();
     if (lane < rest) q[lane] = r;
     qn = rest;
-    eval_candidate(v.x, v.y, __int_as_float(v.w), pos0, uid, S, v.z, contact_only, log_all, ctr, pairs, pair_cap);
+    if (mine) eval_queued(v, S, contact_only, log_all, ctr, pairs, pair_cap);
 }
 
 // Species-bin search (large cells).  Bins are species-major (bin = bin_base +
 // species * nc^3 + cell, cell = (ix*nc + iy)*nc + iz), so one species'
-// molecules along a z-row of cells are contiguous.  A work unit is (species s,
-// row (ix, iy), segment of kseg cells in z); a wave takes up to 64 of the
-// unit's molecules, one per lane, and streams, with loads shared by the whole
-// wave, every partner row (ix+ox, iy+oy), |ox|,|oy| <= reach, of every partner
-// species t >= s over the z-cells within reach of the segment.  Rows whose
-// cell distance exceeds the pair's cutoff are skipped.  A pair of one species
-// is tested from the molecule with the lower sorted index.
+// molecules along a z-row of cells are contiguous.  A work unit is a cube of
+// kblk_sp[s]^3 cells and species s (about 64 molecules); a wave holds the
+// unit's molecules, one per lane, and takes their bounding box.  For every
+// partner species t searched from s (pm_dir) the box is widened by the pair's
+// cutoff; every z-row of cells that meets the widened box is streamed, 64
+// molecules at a time through LDS, over the z-cells within the cutoff of the
+// box.  A pair of one species is tested from the molecule with the lower
+// sorted index.  When a widened box spans less than half the cube along every
+// axis, whether a row or z-piece crosses the periodic boundary is known per
+// range, so the minimum image of Eq. 2 reduces to one add or subtract of L on
+// that axis -- the same FP32 operation Eq. 2 performs, so candidate decisions
+// are unchanged.
+
+// One staged chunk: lanes hold A molecules (end position pa, start position
+// qa, uid ua), t runs over the staged B molecules.  First a branch-free pass
+// marks each lane's candidates in a 64-bit mask (exact FP32 distance test),
+// then the lanes walk their marks: start separation, bridge-exponent bound,
+// and the queue for the full evaluation.
+__device__ __forceinline__ void scan_stage(const float4* __restrict__ st_p, const float4* __restrict__ st_q,
+                                           const uint64_t* __restrict__ st_u, int cnt, int jc, bool shift,
+                                           const float4& pa, const float4& qa, uint64_t ua, int ia, bool va,
+                                           bool same, float rc2, float R, float inv_s, float L, float hL, float sx,
+                                           float sy, float sz, int rx, QEntry* q, int& qn, int lane,
+                                           const InstStep& S, int contact_only, int log_all,
+                                           DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                           uint32_t pair_cap, unsigned long long& ncand) {
+    // lanes test j = jc + t only when j > ia for pairs of one species
+    const int tmin = !va ? 64 : (same ? max(0, ia + 1 - jc) : 0);
+    unsigned long long mask = 0ull;
+    if (shift) {
+#pragma unroll 4
+        for (int t = 0; t < cnt; ++t) {
+            const float4 pj = st_p[t];
+            const float dx = __fadd_rn(__fsub_rn(pj.x, pa.x), sx);
+            const float dy = __fadd_rn(__fsub_rn(pj.y, pa.y), sy);
+            const float dz = __fadd_rn(__fsub_rn(pj.z, pa.z), sz);
+            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+            if (d2 < rc2 && t >= tmin) mask |= 1ull << t;
+        }
+    } else {
+#pragma unroll 4
+        for (int t = 0; t < cnt; ++t) {
+            const float d2 = end_d2(st_p[t], pa, L, hL);
+            if (d2 < rc2 && t >= tmin) mask |= 1ull << t;
+        }
+    }
+    while (__ballot(mask != 0ull)) {
+        bool need = false;
+        QEntry e;
+        if (mask) {
+            const int t = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            ++ncand;
+            const float4 pj = st_p[t];
+            const float d2 = shift ? [&] {
+                const float dx = __fadd_rn(__fsub_rn(pj.x, pa.x), sx);
+                const float dy = __fadd_rn(__fsub_rn(pj.y, pa.y), sy);
+                const float dz = __fadd_rn(__fsub_rn(pj.z, pa.z), sz);
+                return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+            }() : end_d2(pj, pa, L, hL);
+            const float4 qj = st_q[t];
+            const float ex = minimg_f(qj.x - qa.x, L, hL);
+            const float ey = minimg_f(qj.y - qa.y, L, hL);
+            const float ez = minimg_f(qj.z - qa.z, L, hL);
+            const float r1 = sqrtf(d2);
+            const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
+            // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
+            const float aexp = (r0 - R) * (r1 - R) * inv_s;
+            need = log_all || contact_only || r0 <= R || r1 <= R || !(aexp > 18.0f);
+            e.a = make_int4(ia, jc + t, rx, __float_as_int(r0));
+            e.b = make_float4(r1, 0.f, 0.f, 0.f);
+            e.u.x = ua;
+            e.u.y = st_u[t];
+        }
+        qpush(q, qn, lane, need, e, false, S, contact_only, log_all, ctr, pairs, pair_cap);
+    }
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Cells [c0, c1] (unwrapped, may leave [0, nc)) whose extent meets [lo, hi];
+// eps covers the FP32 rounding of the binning.  Returns false (and the whole
+// axis) when the span would reach nc cells.
+__device__ __forceinline__ bool cell_span(float lo, float hi, float hL, float inv_h, float eps, int nc, int& c0,
+                                          int& c1) {
+    c0 = (int)floorf((lo - eps + hL) * inv_h);
+    c1 = (int)floorf((hi + eps + hL) * inv_h);
+    if (c1 - c0 + 1 >= nc) {
+        c0 = 0;
+        c1 = nc - 1;
+        return false;
+    }
+    return true;
+}
+
+// Distance along one axis between the extent of (unwrapped) cell c and [lo, hi].
+__device__ __forceinline__ float cell_box_gap(int c, float lo, float hi, float h, float hL, float eps) {
+    const float clo = (float)c * h - hL, chi = (float)(c + 1) * h - hL;
+    float g = fmaxf(clo - hi, lo - chi) - eps;
+    return g > 0.0f ? g : 0.0f;
+}
+
 __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restrict__ pos,
                                                          const float4* __restrict__ pos0,
                                                          const uint64_t* __restrict__ uid,
@@ -599,30 +731,31 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restr
                                                          PairRec* __restrict__ pairs, uint32_t pair_cap,
                                                          int32_t log_all, int32_t n_inst, int32_t total_units) {
     __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
-    __shared__ int32_t plist[kMaxSpecies * kMaxSpecies];  // partner species t >= s of s, ascending
-    __shared__ int32_t pcount[kMaxSpecies];
     __shared__ unsigned long long s_cand;
-    __shared__ int4 q_all[GSBS_BLOCK / 64][128];
-    __shared__ float4 stage_all[GSBS_BLOCK / 64][64];
+    __shared__ QEntry q_all[GSBS_BLOCK / 64][128];
+    __shared__ float4 stp_all[GSBS_BLOCK / 64][64];
+    __shared__ float4 stq_all[GSBS_BLOCK / 64][64];
+    __shared__ uint64_t stu_all[GSBS_BLOCK / 64][64];
+    __shared__ int32_t rb_all[GSBS_BLOCK / 64][65];   // first molecule of each A row
+    __shared__ int32_t ro_all[GSBS_BLOCK / 64][65];   // lanes before each A row
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
-    if (threadIdx.x < kMaxSpecies) {
-        const uint32_t pm = chem->pmask[threadIdx.x];
-        int q = 0;
-        for (int t = 0; t < kMaxSpecies; ++t)
-            if ((pm >> t) & 1u) plist[threadIdx.x * kMaxSpecies + q++] = t;
-        pcount[threadIdx.x] = q;
-    }
     if (threadIdx.x == 0) s_cand = 0ull;
     __syncthreads();
     const int contact_only = chem->contact_only;
+    const int ns = chem->n_species;
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int waves = GSBS_BLOCK / 64;
-    int4* q = q_all[threadIdx.x >> 6];
-    float4* stage = stage_all[threadIdx.x >> 6];
+    QEntry* q = q_all[wv];
+    float4* st_p = stp_all[wv];
+    float4* st_q = stq_all[wv];
+    uint64_t* st_u = stu_all[wv];
+    int32_t* rbeg = rb_all[wv];
+    int32_t* roff = ro_all[wv];
     int qn = 0;  // wave-uniform queue length
     unsigned long long ncand = 0;
-    for (int u = blockIdx.x * waves + (threadIdx.x >> 6); u < total_units; u += gridDim.x * waves) {
+    for (int u = blockIdx.x * waves + wv; u < total_units; u += gridDim.x * waves) {
         // instance owning unit u (instances own consecutive unit ranges)
         int lo_i = 0, hi_i = n_inst - 1;
         while (lo_i < hi_i) {
@@ -632,96 +765,141 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restr
         }
         const InstStep& S = P[lo_i];
         if (!S.active || !S.by_species) continue;
-        const int nc = S.nc, m = S.reach, K = S.kseg;
-        const int nseg = (nc + K - 1) / K;
         const int lu = u - S.unit_base;
-        if (lu >= chem->n_species * nc * nc * nseg) continue;
-        const int si = lu / (nc * nc * nseg);
-        const int nsp = pcount[si];
-        if (nsp == 0) continue;
-        const int r = lu - si * (nc * nc * nseg);
-        const int rowA = r / nseg, seg = r - rowA * nseg;
-        const int ix = rowA / nc, iy = rowA - ix * nc;
-        const int z0 = seg * K, z1 = min(z0 + K, nc);
+        if (lu >= S.unit_off_sp[ns]) continue;
+        int si = 0;
+        while (si + 1 < ns && S.unit_off_sp[si + 1] <= lu) ++si;
+        const uint32_t pm = S.pm_dir[si];
+        if (pm == 0u) continue;
+        const int nc = S.nc, kb = S.kseg_sp[si];
+        const int nb = (nc + kb - 1) / kb;
+        const int r = lu - S.unit_off_sp[si];
+        const int bx = r / (nb * nb), by = (r / nb) % nb, bz = r % nb;
+        const int x0 = bx * kb, x1 = min(x0 + kb, nc), y0 = by * kb, y1 = min(y0 + kb, nc);
+        const int z0 = bz * kb, z1 = min(z0 + kb, nc);
         const int ncell = nc * nc * nc;
-        const int binA = S.bin_base + si * ncell + rowA * nc + z0;
-        const int a0 = (int)start[binA], a1 = (int)start[binA + (z1 - z0)];
-        if (a0 == a1) continue;
-        const bool full = nc < 2 * m + 1;
-        const int lo = full ? 0 : -m, w = full ? nc : 2 * m + 1;
-        const float h = S.h, eps = S.cull_eps, L = S.L, hL = S.halfL;
+        const int sbase = S.bin_base + si * ncell;
+        // A: the block's rows (x, y) over z-cells [z0, z1); kb^2 <= 64 rows
+        const int nrows = (x1 - x0) * (y1 - y0);
+        int cntA = 0, begA = 0;
+        if (lane < nrows) {
+            const int cx = x0 + lane / (y1 - y0), cy = y0 + lane % (y1 - y0);
+            const int b0 = sbase + (cx * nc + cy) * nc;
+            begA = (int)start[b0 + z0];
+            cntA = (int)start[b0 + z1] - begA;
+        }
+        int incl = cntA;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        const int nA = __shfl(incl, 63, 64);
+        if (nA == 0) continue;
+        wave_sync_lds();
+        if (lane < nrows) {
+            rbeg[lane] = begA;
+            roff[lane] = incl - cntA;
+        }
+        if (lane == 0) roff[nrows] = nA;
+        wave_sync_lds();
+        const float h = S.h, eps = S.cull_eps, L = S.L, hL = S.halfL, inv_h = S.inv_h;
         const int* rrow = rmap + si * kMaxSpecies;
-        const int* pl = plist + si * kMaxSpecies;
-        // z-cells of the partner rows: [z0 - m, z1 - 1 + m], the whole row if that covers it
-        const bool zall = (z1 - z0) + 2 * m >= nc;
-        for (int ab = a0; ab < a1; ab += 64) {
-            const int ia = ab + lane;
-            const bool va = ia < a1;
-            const float4 pa = pos[va ? ia : a0];
-            for (int ox = lo; ox < lo + w; ++ox) {
-                const int qx = full ? ox : (ix + ox + nc) % nc;
-                const float gx = full ? 0.0f : fmaxf((float)(abs(ox) - 1) * h - eps, 0.0f);
-                for (int oy = lo; oy < lo + w; ++oy) {
-                    const int qy = full ? oy : (iy + oy + nc) % nc;
-                    const float gy = full ? 0.0f : fmaxf((float)(abs(oy) - 1) * h - eps, 0.0f);
-                    const float g2 = gx * gx + gy * gy;
-                    if (g2 > S.cull2_sp[si]) continue;
-                    const int rowB = qx * nc + qy;
-                    for (int qq = 0; qq < nsp; ++qq) {
-                        const int sj = pl[qq];
-                        const int rx = rrow[sj];
-                        if (g2 > S.cull2[rx]) continue;
-                        const bool same = (sj == si);
-                        if (same && rowB < rowA) continue;
-                        const float rc2 = S.rc2[rx];
-                        const int binB = S.bin_base + sj * ncell + rowB * nc;
-                        // up to two contiguous z pieces
-                        int zl[2], zh[2], np = 1;
-                        if (zall) {
-                            zl[0] = 0;
-                            zh[0] = nc - 1;
-                        } else {
-                            const int zb0 = z0 - m, zb1 = z1 - 1 + m;
-                            if (zb0 < 0) {
-                                zl[0] = 0; zh[0] = zb1;
-                                zl[1] = zb0 + nc; zh[1] = nc - 1;
-                                np = 2;
-                            } else if (zb1 >= nc) {
-                                zl[0] = zb0; zh[0] = nc - 1;
-                                zl[1] = 0; zh[1] = zb1 - nc;
-                                np = 2;
-                            } else {
-                                zl[0] = zb0; zh[0] = zb1;
-                            }
+        int rsearch = 0;  // row of this lane's molecule (monotone over chunks)
+        for (int ab = 0; ab < nA; ab += 64) {
+            const int k = ab + lane;
+            const bool va = k < nA;
+            int ia = 0;
+            if (va) {
+                while (rsearch + 1 < nrows && roff[rsearch + 1] <= k) ++rsearch;
+                ia = rbeg[rsearch] + (k - roff[rsearch]);
+            }
+            const int ii = va ? ia : rbeg[0];
+            const float4 pa = pos[ii];
+            const float4 qa = pos0[ii];
+            const uint64_t ua = uid[ii];
+            // bounding box of the chunk's end positions (the block does not cross the cube faces)
+            const float blx = wave_min(va ? pa.x : 3.4e38f), bhx = wave_max(va ? pa.x : -3.4e38f);
+            const float bly = wave_min(va ? pa.y : 3.4e38f), bhy = wave_max(va ? pa.y : -3.4e38f);
+            const float blz = wave_min(va ? pa.z : 3.4e38f), bhz = wave_max(va ? pa.z : -3.4e38f);
+            uint32_t mm = pm;
+            while (mm) {
+                const int sj = __ffs(mm) - 1;
+                mm &= mm - 1u;
+                const int rx = rrow[sj];
+                const float c2 = S.cull2[rx];
+                const float rcu = sqrtf(c2);
+                const float rc2 = S.rc2[rx];
+                const float Rr = S.R[rx], inv_s = S.inv_s[rx];
+                const bool same = (sj == si);
+                // cells of the box widened by the cutoff; an axis whose span would wrap onto
+                // itself is taken whole and not culled
+                int cx0, cx1, cy0, cy1, czl, czh;
+                const bool cullx = cell_span(blx - rcu, bhx + rcu, hL, inv_h, eps, nc, cx0, cx1);
+                const bool cully = cell_span(bly - rcu, bhy + rcu, hL, inv_h, eps, nc, cy0, cy1);
+                const bool cullz = cell_span(blz - rcu, bhz + rcu, hL, inv_h, eps, nc, czl, czh);
+                // exact shifts need every A-B distance below L/2 along each axis
+                const bool shift = 2 * (cx1 - cx0 + 2) <= nc && 2 * (cy1 - cy0 + 2) <= nc && 2 * (czh - czl + 2) <= nc;
+                const float bxl = cullx ? blx : -3.4e38f, bxh = cullx ? bhx : 3.4e38f;
+                const float byl = cully ? bly : -3.4e38f, byh = cully ? bhy : 3.4e38f;
+                const int sbB = S.bin_base + sj * ncell;
+                for (int cx = cx0; cx <= cx1; ++cx) {
+                    const int qx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
+                    const float sx = cx < 0 ? -L : (cx >= nc ? L : 0.0f);
+                    const float gx = cullx ? cell_box_gap(cx, bxl, bxh, h, hL, eps) : 0.0f;
+                    if (gx * gx > c2) continue;
+                    for (int cy = cy0; cy <= cy1; ++cy) {
+                        const int qy = cy < 0 ? cy + nc : (cy >= nc ? cy - nc : cy);
+                        const float sy = cy < 0 ? -L : (cy >= nc ? L : 0.0f);
+                        const float gy = cully ? cell_box_gap(cy, byl, byh, h, hL, eps) : 0.0f;
+                        const float gxy2 = gx * gx + gy * gy;
+                        if (gxy2 > c2) continue;
+                        // z window of this row: the box widened by what is left of the cutoff
+                        int cz0 = czl, cz1 = czh;
+                        if (cullz) {
+                            const float rz = sqrtf(c2 - gxy2);
+                            cell_span(blz - rz, bhz + rz, hL, inv_h, eps, nc, cz0, cz1);
                         }
+                        const int rowB = qx * nc + qy;
+                        const int np = (cz0 < 0 || cz1 >= nc) ? 2 : 1;
                         for (int pc = 0; pc < np; ++pc) {
-                            const int jb0 = (int)start[binB + zl[pc]];
-                            const int jb1 = (int)start[binB + zh[pc] + 1];
-                            // 64 partners at a time: one coalesced load into LDS, then LDS broadcast reads
+                            int zl, zh;
+                            float sz = 0.0f;
+                            if (pc == 0) {
+                                zl = cz0 < 0 ? 0 : cz0;
+                                zh = cz1 >= nc ? nc - 1 : cz1;
+                            } else if (cz0 < 0) {  // cells below z = 0 are the top of the cube
+                                zl = cz0 + nc;
+                                zh = nc - 1;
+                                sz = -L;
+                            } else {  // cells above nc - 1 are the bottom of the cube
+                                zl = 0;
+                                zh = cz1 - nc;
+                                sz = L;
+                            }
+                            const int jb0 = (int)start[sbB + rowB * nc + zl];
+                            const int jb1 = (int)start[sbB + rowB * nc + zh + 1];
                             for (int jc = jb0; jc < jb1; jc += 64) {
                                 const int cnt = min(64, jb1 - jc);
                                 wave_sync_lds();
-                                if (lane < cnt) stage[lane] = pos[jc + lane];
-                                wave_sync_lds();
-                                for (int t = 0; t < cnt; ++t) {
-                                    const float4 pj = stage[t];
-                                    const int j = jc + t;
-                                    float d2 = 0.0f;
-                                    bool cand = false;
-                                    if (va && (!same || j > ia)) {
-                                        d2 = end_d2(pj, pa, L, hL);
-                                        cand = d2 < rc2;
-                                    }
-                                    qpush(q, qn, lane, cand, ia, j, rx, d2, pos0, uid, S, contact_only, log_all,
-                                          ctr, pairs, pair_cap, ncand);
+                                if (lane < cnt) {
+                                    st_p[lane] = pos[jc + lane];
+                                    st_q[lane] = pos0[jc + lane];
+                                    st_u[lane] = uid[jc + lane];
                                 }
+                                wave_sync_lds();
+                                scan_stage(st_p, st_q, st_u, cnt, jc, shift, pa, qa, ua, ia, va, same, rc2, Rr, inv_s,
+                                           L, hL, sx, sy, sz, rx, q, qn, lane, S, contact_only, log_all, ctr, pairs,
+                                           pair_cap, ncand);
                             }
                         }
                     }
                 }
             }
         }
-        qdrain(q, qn, lane, pos0, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
+        while (qn > 0) {
+            QEntry none;
+            qpush(q, qn, lane, false, none, true, S, contact_only, log_all, ctr, pairs, pair_cap);
+        }
     }
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
     if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
