@@ -115,8 +115,11 @@ def main():
     sp_d = torch.from_numpy(np.ascontiguousarray(inj.species)).to(dev)
     cap = int(len(inj.species) * 1.5) + 4096
 
-    def engine():
-        return gsbs.Engine(wl.L, 1000, W.D_CONFIG, W.REACTIONS, capacity=cap)
+    def engine(tune):
+        # warmup runs explore the search-grid configurations; timed runs use what they learned
+        p = gsbs.gsbs_default_params()
+        p.autotune = 1 if tune else 0
+        return gsbs.Engine(wl.L, 1000, W.D_CONFIG, W.REACTIONS, params=p, capacity=cap)
 
     def run(e):
         e.inject(0, 0.0, xyz_d, sp_d, inj.edep_ev)
@@ -128,12 +131,12 @@ def main():
         print("[bench]", *a, file=sys.stderr, flush=True)
 
     for k in range(args.warmup):
-        e = engine()
+        e = engine(True)
         t = time.perf_counter()
         run(e)
         note(f"warmup {k}: {time.perf_counter() - t:.2f} s, stats {e.stats()}")
         e.close()
-    engines = [engine() for _ in range(args.steps)]
+    engines = [engine(False) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for e in engines:
@@ -152,7 +155,7 @@ def main():
     roofline = None
     prof = None
     if not args.no_profile:
-        e = engine()
+        e = engine(False)
         gsbs.gsbs_set_profiling(e.ctx, True)
         run(e)
         prof = gsbs.gsbs_get_profile(e.ctx)
