@@ -437,17 +437,58 @@ int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_
                 S.pm_dir[b] |= 1u << a;
             }
         }
-        // work unit: a cube of kb^3 cells holding about 64 molecules of one species
+        // A box of each species: kx*ky*kz cells chosen to minimise the partner
+        // molecules streamed per A molecule (64 A molecules per wave pass, a fixed
+        // cost per pass); then the stream of every box is cut into nsplit slices so
+        // that the launch has enough waves
         const double ncell = (double)nc * nc * nc;
+        double units_total = 0.0, work_total = 0.0;
+        int64_t units_sp[kMaxSpecies] = {};
+        for (int s = 0; s < c->ns; ++s) {
+            S.kdim_sp[s] = 1 | (1 << 8) | (1 << 16);
+            if (!S.pm_dir[s]) continue;
+            const double per_cell = (double)std::max<int64_t>(sp_est[s], 0) / ncell;
+            double best = INFINITY, best_work = 0.0;
+            const int kmax = (int)std::min<int64_t>(nc, 8), kzmax = (int)std::min<int64_t>(nc, 16);
+            for (int kx = 1; kx <= kmax; ++kx)
+                for (int ky = 1; ky <= kmax && kx * ky <= 64; ++ky)
+                    for (int kz = 1; kz <= kzmax; ++kz) {
+                        const double E = per_cell * kx * ky * kz;
+                        const double passes = std::max(1.0, std::ceil((E + 2.0 * std::sqrt(E)) / 64.0));
+                        double streamed = 0.0;
+                        for (int p = 0; p < c->ns; ++p) {
+                            if (!((S.pm_dir[s] >> p) & 1u)) continue;
+                            const int rx = c->chem_h.rmap[s][p];
+                            const double rho = std::sqrt((double)S.cull2[rx]) / (double)S.h;
+                            const double dens = (double)std::max<int64_t>(sp_est[p], 0) / ncell;
+                            streamed += dens * (kx + 2.0 * rho + 1.0) * (ky + 2.0 * rho + 1.0) *
+                                        std::min((double)nc, kz + 2.0 * rho + 1.0);
+                        }
+                        const double cost = passes * (streamed + 128.0) / std::max(E, 0.5);
+                        if (cost < best) {
+                            best = cost;
+                            best_work = passes * streamed;
+                            S.kdim_sp[s] = kx | (ky << 8) | (kz << 16);
+                        }
+                    }
+            const int kx = S.kdim_sp[s] & 0xFF, ky = (S.kdim_sp[s] >> 8) & 0xFF, kz = (S.kdim_sp[s] >> 16) & 0xFF;
+            units_sp[s] = ((nc + kx - 1) / kx) * ((nc + ky - 1) / ky) * ((nc + kz - 1) / kz);
+            units_total += (double)units_sp[s];
+            work_total += (double)units_sp[s] * best_work;
+        }
+        constexpr double kTargetItems = 8192.0;  // waves per launch that keep every SIMD busy
+        const double n_inst = (double)std::max<size_t>(c->inst.size(), 1);
+        int64_t nsplit = 1;
+        if (units_total > 0) {
+            const double want = std::ceil(kTargetItems / (units_total * n_inst));
+            const double room = std::floor(work_total / units_total / 256.0);  // >= 4 stages per slice
+            nsplit = (int64_t)std::max(1.0, std::min({want, room, 16.0}));
+        }
+        S.nsplit = (int32_t)nsplit;
         int64_t off = 0;
         for (int s = 0; s < c->ns; ++s) {
-            const double per_cell = (double)std::max<int64_t>(sp_est[s], 0) / ncell;
-            int64_t kb = per_cell > 0 ? (int64_t)std::ceil(std::cbrt(48.0 / per_cell)) : 8;
-            kb = std::max<int64_t>(1, std::min<int64_t>({kb, nc, 8}));
-            S.kseg_sp[s] = (int32_t)kb;
             S.unit_off_sp[s] = (int32_t)off;
-            const int64_t nb = (nc + kb - 1) / kb;
-            if (S.pm_dir[s]) off += nb * nb * nb;
+            off += units_sp[s] * nsplit;
         }
         S.unit_off_sp[c->ns] = (int32_t)off;
     }

@@ -50,13 +50,15 @@ struct alignas(16) InstStep {
     int32_t bin_base;              // first global bin index of this instance
     int32_t active;                // 1: this instance takes a step now
     int32_t by_species;            // 1: search partner-species bins, 0: whole cells
-    int32_t unit_base;             // species-bin search: first global work unit of this instance
-    int32_t pad0[2];
+    int32_t unit_base;             // species-bin search: first global work item of this instance
+    int32_t nsplit;                // species-bin search: work items (stream slices) per A box
+    int32_t pad0;
     // species-bin search: partner species searched from each species (the more
-    // abundant side of every pair), edge in cells of the cubic work unit of each
-    // species, and the first work unit of each species inside the instance
+    // abundant side of every pair), A-box size in cells of each species
+    // (kx | ky << 8 | kz << 16), and the first work item of each species inside
+    // the instance
     uint32_t pm_dir[kMaxSpecies];
-    int32_t kseg_sp[kMaxSpecies];
+    int32_t kdim_sp[kMaxSpecies];
     int32_t unit_off_sp[kMaxSpecies + 4];
     uint64_t step;                 // Philox step counter word
     uint64_t key0, key1;           // Philox key (seed, instance)

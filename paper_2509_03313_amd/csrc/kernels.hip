@@ -79,16 +79,16 @@ __device__ __forceinline__ void sincos_2pi_u24(uint64_t w, float* s, float* c) {
 __device__ __forceinline__ float wrap_f(float x, float L, float hL, float invL) {
     const float k = floorf(__fmul_rn(__fadd_rn(x, hL), invL));
     x = __fsub_rn(x, __fmul_rn(k, L));
-    if (x >= hL) x = __fsub_rn(x, L);
-    if (x < -hL) x = __fadd_rn(x, L);
+    // selects of plain IEEE operations (no contraction is enabled) keep this branch-free
+    x = x >= hL ? x - L : x;
+    x = x < -hL ? x + L : x;
     return x;
 }
 
 // PBC 2 (Eq. 2).
 __device__ __forceinline__ float minimg_f(float d, float L, float hL) {
-    if (d >= hL) return __fsub_rn(d, L);
-    if (d < -hL) return __fadd_rn(d, L);
-    return d;
+    const float lo = d - L, hi = d + L;
+    return d >= hL ? lo : (d < -hL ? hi : d);
 }
 
 // Position after this step's Brownian jump: Gaussian of variance 2 D dt per
@@ -533,16 +533,50 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
     if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
 }
 
-// Per-wave queue in LDS of the candidates that need the contact probability:
-// the distance test runs on every lane, the few pairs that pass it (and whose
-// bridge exponent can still give an acceptance) are compacted by a ballot and
-// evaluated 64 at a time with every lane busy.  An entry carries everything
-// the evaluation needs, so draining issues no global loads.  All lanes of the
-// wave must call qpush / qdrain together.
-struct QEntry {
-    int4 a;    // i, j, rx, bits of r0
-    float4 b;  // r1, unused
-    ulonglong2 u;  // uid_i, uid_j
+// ------------------------------------------------ species-bin pair search ---
+// Large cells (many molecules per cell).  Bins are species-major (bin =
+// bin_base + species * nc^3 + cell, cell = (ix*nc + iy)*nc + iz), so the
+// molecules of one species along a z-run of cells are contiguous.
+//
+// Work item: species s, a box of kx*ky*kz cells (the A unit, about 50
+// molecules of s) and one of nsplit slices of the partner stream.  A wave
+// holds the A molecules one per lane and takes their bounding box.  For every
+// partner species t searched from s, the box widened by the pair's cutoff
+// gives a rectangle of (x, y) cell rows; 64 rows at a time are culled in
+// parallel (one per lane) by their distance from the box, each kept row gets
+// the z-window that the rest of the cutoff allows, and its z-runs of cells
+// (two when the window wraps) become segments of the partner stream.  The
+// wave takes its slice of the concatenated stream and stages it 64 molecules
+// at a time through LDS (the next stage's loads are in flight while one is
+// tested).  Every lane tests its A molecule against every staged B in a fully
+// unrolled loop (64-bit candidate mask); the candidates are then compacted into
+// an LDS list and evaluated with every lane busy.
+//
+// Minimum image (Eq. 2): for each segment the range of x_B - x_A over the box
+// and the segment's cells is known, so when it lies inside one branch of Eq. 2
+// the branch is a per-segment shift of 0 or -+L, added after the subtraction
+// exactly as Eq. 2 adds it -- the FP32 result is the same.  A stage that holds
+// a segment whose range straddles L/2 evaluates Eq. 2 per pair instead.
+// A pair of one species is tested from the molecule with the lower sorted index.
+
+constexpr int kSegCap = 128;   // segments of 64 rows (at most two z-runs per row)
+constexpr int kListCap = 1024;  // candidates compacted per pass (16 per lane)
+constexpr int kLaneQuota = kListCap / 64;
+constexpr float kFar = 3.0e38f;
+
+struct SpWave {
+    float4 bp[64];   // staged B end position, .w = bits of the sorted index (-1: padding)
+    float4 bs[64];   // staged B shift per axis, .w = 1 when the shift is exact
+    float4 bq[64];   // staged B start position
+    float4 ap[64];   // A end position, .w = bits of the sorted index
+    float4 aq[64];   // A start position
+    int32_t seg_j0[kSegCap];
+    int32_t seg_pre[kSegCap + 1];
+    int32_t seg_code[kSegCap];
+    uint16_t list[kListCap];
+    int4 qe[128];    // queued for evaluation: i, j, rx, bits of r0
+    float qr[128];   // queued r1
+    int32_t rbeg[65], roff[65];
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -550,18 +584,17 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Bridge probability, pair uniform and acceptance of a queued candidate.
-__device__ __forceinline__ void eval_queued(const QEntry& e, const InstStep& S, int contact_only, int log_all,
-                                            DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
-                                            uint32_t pair_cap) {
-    const int rx = e.a.z;
-    const float r0 = __int_as_float(e.a.w), r1 = e.b.x;
+// Contact probability, pair uniform and acceptance of one pair.
+__device__ __forceinline__ void eval_pair(int i, int j, int rx, float r0, float r1, const uint64_t* __restrict__ uid,
+                                          const InstStep& S, int contact_only, int log_all,
+                                          DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                          uint32_t pair_cap) {
     const float R = S.R[rx];
     float Pc;
     if (contact_only) Pc = (r0 <= R || r1 <= R) ? 1.0f : 0.0f;
     else Pc = bridge_f(r0, r1, R, S.inv_s[rx]);
     if (!log_all && !(Pc > 0x1p-25f)) return;
-    const uint64_t ui = e.u.x, uj = e.u.y;
+    const uint64_t ui = uid[i], uj = uid[j];
     const uint64_t lo = ui < uj ? ui : uj, hi = ui < uj ? uj : ui;
     uint64_t w[4];
     philox(lo, hi, S.step, 1ull, S.key0, S.key1, w);
@@ -571,8 +604,8 @@ __device__ __forceinline__ void eval_queued(const QEntry& e, const InstStep& S, 
         const uint32_t k = atomicAdd(&ctr->n_pairs, 1u);
         if (k < pair_cap) {
             PairRec r;
-            r.i = e.a.x;
-            r.j = e.a.y;
+            r.i = i;
+            r.j = j;
             r.u24 = u24;
             r.rx = rx;
             r.P = Pc;
@@ -584,109 +617,148 @@ __device__ __forceinline__ void eval_queued(const QEntry& e, const InstStep& S, 
     }
 }
 
-// Append the lanes' entries (need) and, once 64 are queued -- or, with
-// force, whatever is queued -- evaluate up to 64 of them, one per lane.  The
-// only place that evaluates, so the evaluation is inlined once.
-__device__ __forceinline__ void qpush(QEntry* q, int& qn, int lane, bool need, const QEntry& e, bool force,
-                                      const InstStep& S, int contact_only, int log_all,
-                                      DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap) {
+// Append the lanes' entries (need) to the wave's queue and, once 64 are
+// queued -- or, with force, whatever is queued -- evaluate up to 64 of them,
+// one per lane.  The only evaluation site, so it is inlined once.  All lanes
+// of the wave call it together.
+__device__ __forceinline__ void qpush(SpWave& w, int& qn, int lane, bool need, const int4& e, float r1, bool force,
+                                      const uint64_t* __restrict__ uid, const InstStep& S, int contact_only,
+                                      int log_all, DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
+                                      uint32_t pair_cap) {
     const unsigned long long m = __ballot(need);
     if (m != 0ull) {
-        if (need) q[qn + __popcll(m & ((1ull << lane) - 1ull))] = e;
-        qn += __popcll(m);
+        if (need) {
+            const int k = qn + (int)__popcll(m & ((1ull << lane) - 1ull));
+            w.qe[k] = e;
+            w.qr[k] = r1;
+        }
+        qn += (int)__popcll(m);
     }
     if (qn < 64 && !(force && qn > 0)) return;
     wave_sync_lds();
     const int take = qn < 64 ? qn : 64;
     const bool mine = lane < take;
-    QEntry v;
-    if (mine) v = q[lane];
+    int4 v = make_int4(0, 0, 0, 0);
+    float vr = 0.0f;
+    if (mine) {
+        v = w.qe[lane];
+        vr = w.qr[lane];
+    }
     const int rest = qn - take;
-    QEntry r;
-    if (lane < rest) r = q[64 + lane];
+    int4 rv = make_int4(0, 0, 0, 0);
+    float rr = 0.0f;
+    if (lane < rest) {
+        rv = w.qe[64 + lane];
+        rr = w.qr[64 + lane];
+    }
     wave_sync_lds();
-    if (lane < rest) q[lane] = r;
+    if (lane < rest) {
+        w.qe[lane] = rv;
+        w.qr[lane] = rr;
+    }
     qn = rest;
-    if (mine) eval_queued(v, S, contact_only, log_all, ctr, pairs, pair_cap);
+    if (mine) eval_pair(v.x, v.y, v.z, __int_as_float(v.w), vr, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
 }
 
-// Species-bin search (large cells).  Bins are species-major (bin = bin_base +
-// species * nc^3 + cell, cell = (ix*nc + iy)*nc + iz), so one species'
-// molecules along a z-row of cells are contiguous.  A work unit is a cube of
-// kblk_sp[s]^3 cells and species s (about 64 molecules); a wave holds the
-// unit's molecules, one per lane, and takes their bounding box.  For every
-// partner species t searched from s (pm_dir) the box is widened by the pair's
-// cutoff; every z-row of cells that meets the widened box is streamed, 64
-// molecules at a time through LDS, over the z-cells within the cutoff of the
-// box.  A pair of one species is tested from the molecule with the lower
-// sorted index.  When a widened box spans less than half the cube along every
-// axis, whether a row or z-piece crosses the periodic boundary is known per
-// range, so the minimum image of Eq. 2 reduces to one add or subtract of L on
-// that axis -- the same FP32 operation Eq. 2 performs, so candidate decisions
-// are unchanged.
-
-// One staged chunk: lanes hold A molecules (end position pa, start position
-// qa, uid ua), t runs over the staged B molecules.  First a branch-free pass
-// marks each lane's candidates in a 64-bit mask (exact FP32 distance test),
-// then the lanes walk their marks: start separation, bridge-exponent bound,
-// and the queue for the full evaluation.
-__device__ __forceinline__ void scan_stage(const float4* __restrict__ st_p, const float4* __restrict__ st_q,
-                                           const uint64_t* __restrict__ st_u, int cnt, int jc, bool shift,
-                                           const float4& pa, const float4& qa, uint64_t ua, int ia, bool va,
-                                           bool same, float rc2, float R, float inv_s, float L, float hL, float sx,
-                                           float sy, float sz, int rx, QEntry* q, int& qn, int lane,
-                                           const InstStep& S, int contact_only, int log_all,
-                                           DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs,
-                                           uint32_t pair_cap, unsigned long long& ncand) {
-    // lanes test j = jc + t only when j > ia for pairs of one species
-    const int tmin = !va ? 64 : (same ? max(0, ia + 1 - jc) : 0);
-    unsigned long long mask = 0ull;
-    if (shift) {
-#pragma unroll 4
-        for (int t = 0; t < cnt; ++t) {
-            const float4 pj = st_p[t];
-            const float dx = __fadd_rn(__fsub_rn(pj.x, pa.x), sx);
-            const float dy = __fadd_rn(__fsub_rn(pj.y, pa.y), sy);
-            const float dz = __fadd_rn(__fsub_rn(pj.z, pa.z), sz);
+// Candidate mask of one stage: bit t set when staged B t lies within the
+// cutoff of this lane's A (end separation, FP32, fixed operation order).
+template <bool kShift, bool kSame>
+__device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
+                                           uint32_t& mlo, uint32_t& mhi) {
+    uint32_t half[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        uint32_t m = 0u;
+#pragma unroll 8
+        for (int k = 0; k < 32; ++k) {
+            const int t = 32 * g + k;
+            const float4 p = w.bp[t];
+            float dx, dy, dz;
+            if (kShift) {
+                const float4 sh = w.bs[t];
+                dx = __fadd_rn(__fsub_rn(p.x, pa.x), sh.x);
+                dy = __fadd_rn(__fsub_rn(p.y, pa.y), sh.y);
+                dz = __fadd_rn(__fsub_rn(p.z, pa.z), sh.z);
+            } else {
+                dx = minimg_f(__fsub_rn(p.x, pa.x), L, hL);
+                dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
+                dz = minimg_f(__fsub_rn(p.z, pa.z), L, hL);
+            }
             const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-            if (d2 < rc2 && t >= tmin) mask |= 1ull << t;
+            bool c = d2 < rc2;
+            if (kSame) c = c && (__float_as_int(p.w) > ia);
+            m |= c ? (1u << k) : 0u;
         }
-    } else {
-#pragma unroll 4
-        for (int t = 0; t < cnt; ++t) {
-            const float d2 = end_d2(st_p[t], pa, L, hL);
-            if (d2 < rc2 && t >= tmin) mask |= 1ull << t;
-        }
+        half[g] = m;
     }
-    while (__ballot(mask != 0ull)) {
-        bool need = false;
-        QEntry e;
-        if (mask) {
-            const int t = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            ++ncand;
-            const float4 pj = st_p[t];
-            const float d2 = shift ? [&] {
-                const float dx = __fadd_rn(__fsub_rn(pj.x, pa.x), sx);
-                const float dy = __fadd_rn(__fsub_rn(pj.y, pa.y), sy);
-                const float dz = __fadd_rn(__fsub_rn(pj.z, pa.z), sz);
-                return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-            }() : end_d2(pj, pa, L, hL);
-            const float4 qj = st_q[t];
-            const float ex = minimg_f(qj.x - qa.x, L, hL);
-            const float ey = minimg_f(qj.y - qa.y, L, hL);
-            const float ez = minimg_f(qj.z - qa.z, L, hL);
-            const float r1 = sqrtf(d2);
-            const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
-            // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
-            const float aexp = (r0 - R) * (r1 - R) * inv_s;
-            need = log_all || contact_only || r0 <= R || r1 <= R || !(aexp > 18.0f);
-            e.a = make_int4(ia, jc + t, rx, __float_as_int(r0));
-            e.b = make_float4(r1, 0.f, 0.f, 0.f);
-            e.u.x = ua;
-            e.u.y = st_u[t];
+    const uint32_t lo = half[0], hi = half[1];
+    mlo = lo;
+    mhi = hi;
+}
+
+// Compact the stage's candidates (lane l, staged t) into the LDS list, at most
+// kLaneQuota per lane and pass, and evaluate the list with every lane busy:
+// start separation, bridge-exponent bound, queue.
+template <bool kShift>
+__device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32_t mhi, int lane, int rx, float R,
+                                                 float inv_s, float L, float hL, int& qn,
+                                                 const uint64_t* __restrict__ uid, const InstStep& S,
+                                                 int contact_only, int log_all, DevCounters* __restrict__ ctr,
+                                                 PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                                 unsigned long long& ncand) {
+    ncand += (unsigned long long)(__popc(mlo) + __popc(mhi));
+    while (__ballot((mlo | mhi) != 0u)) {
+        const int have = __popc(mlo) + __popc(mhi);
+        const int mine = have < kLaneQuota ? have : kLaneQuota;
+        const int incl = (int)wave_incl_scan((uint32_t)mine);
+        const int total = __shfl(incl, 63, 64);
+        const int at = incl - mine;
+        for (int k = 0; k < mine; ++k) {
+            int t;
+            if (mlo) {
+                t = __ffs(mlo) - 1;
+                mlo &= mlo - 1u;
+            } else {
+                t = 32 + __ffs(mhi) - 1;
+                mhi &= mhi - 1u;
+            }
+            w.list[at + k] = (uint16_t)((lane << 6) | t);
         }
-        qpush(q, qn, lane, need, e, false, S, contact_only, log_all, ctr, pairs, pair_cap);
+        wave_sync_lds();
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            bool need = false;
+            int4 e = make_int4(0, 0, 0, 0);
+            float r1 = 0.0f;
+            if (e0 + lane < total) {
+                const int code = w.list[e0 + lane];
+                const int l = code >> 6, t = code & 63;
+                const float4 pa = w.ap[l], qa = w.aq[l];
+                const float4 p = w.bp[t], q = w.bq[t];
+                float dx, dy, dz;
+                if (kShift) {
+                    const float4 sh = w.bs[t];
+                    dx = __fadd_rn(__fsub_rn(p.x, pa.x), sh.x);
+                    dy = __fadd_rn(__fsub_rn(p.y, pa.y), sh.y);
+                    dz = __fadd_rn(__fsub_rn(p.z, pa.z), sh.z);
+                } else {
+                    dx = minimg_f(__fsub_rn(p.x, pa.x), L, hL);
+                    dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
+                    dz = minimg_f(__fsub_rn(p.z, pa.z), L, hL);
+                }
+                const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+                const float ex = minimg_f(q.x - qa.x, L, hL);
+                const float ey = minimg_f(q.y - qa.y, L, hL);
+                const float ez = minimg_f(q.z - qa.z, L, hL);
+                r1 = sqrtf(d2);
+                const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
+                // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
+                const float aexp = (r0 - R) * (r1 - R) * inv_s;
+                need = log_all || contact_only || r0 <= R || r1 <= R || !(aexp > 18.0f);
+                e = make_int4(__float_as_int(pa.w), __float_as_int(p.w), rx, __float_as_int(r0));
+            }
+            qpush(w, qn, lane, need, e, r1, false, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
+        }
+        wave_sync_lds();
     }
 }
 
@@ -714,30 +786,44 @@ __device__ __forceinline__ bool cell_span(float lo, float hi, float hL, float in
     return true;
 }
 
-// Distance along one axis between the extent of (unwrapped) cell c and [lo, hi].
-__device__ __forceinline__ float cell_box_gap(int c, float lo, float hi, float h, float hL, float eps) {
-    const float clo = (float)c * h - hL, chi = (float)(c + 1) * h - hL;
-    float g = fmaxf(clo - hi, lo - chi) - eps;
-    return g > 0.0f ? g : 0.0f;
+// Cells [qlo, qhi] (wrapped) against the box [blo, bhi] along one axis: the
+// range of x_B - x_A lies in [dlo, dhi].  Picks the Eq. 2 branch that holds for
+// the whole range (code 0: none, 1: +L, 2: -L; valid false when the range
+// straddles +-L/2) and the smallest |minimum-image separation| over it (0 when
+// it straddles).
+__device__ __forceinline__ void axis_shift(int qlo, int qhi, float blo, float bhi, float h, float hL, float eps,
+                                           int& code, bool& valid, float& gap) {
+    const float dlo = (float)qlo * h - hL - bhi - eps;
+    const float dhi = (float)(qhi + 1) * h - hL - blo + eps;
+    if (dlo >= hL) {
+        code = 2;
+        valid = true;
+    } else if (dhi < -hL) {
+        code = 1;
+        valid = true;
+    } else {
+        code = 0;
+        valid = dlo >= -hL && dhi < hL;
+    }
+    const float s = code == 1 ? 2.0f * hL : (code == 2 ? -2.0f * hL : 0.0f);
+    const float a = dlo + s, b = dhi + s;
+    gap = valid ? fmaxf(0.0f, fmaxf(a, -b)) : 0.0f;
 }
 
-__global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restrict__ pos,
-                                                         const float4* __restrict__ pos0,
-                                                         const uint64_t* __restrict__ uid,
-                                                         DevCounters* __restrict__ ctr,
-                                                         const InstStep* __restrict__ P,
-                                                         const ChemDev* __restrict__ chem,
-                                                         const uint32_t* __restrict__ start,
-                                                         PairRec* __restrict__ pairs, uint32_t pair_cap,
-                                                         int32_t log_all, int32_t n_inst, int32_t total_units) {
+__device__ __forceinline__ float shift_of(int code, float L) { return code == 1 ? L : (code == 2 ? -L : 0.0f); }
+
+__global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restrict__ pos,
+                                                       const float4* __restrict__ pos0,
+                                                       const uint64_t* __restrict__ uid,
+                                                       DevCounters* __restrict__ ctr,
+                                                       const InstStep* __restrict__ P,
+                                                       const ChemDev* __restrict__ chem,
+                                                       const uint32_t* __restrict__ start,
+                                                       PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                                       int32_t log_all, int32_t n_inst, int32_t total_units) {
     __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
     __shared__ unsigned long long s_cand;
-    __shared__ QEntry q_all[GSBS_BLOCK / 64][128];
-    __shared__ float4 stp_all[GSBS_BLOCK / 64][64];
-    __shared__ float4 stq_all[GSBS_BLOCK / 64][64];
-    __shared__ uint64_t stu_all[GSBS_BLOCK / 64][64];
-    __shared__ int32_t rb_all[GSBS_BLOCK / 64][65];   // first molecule of each A row
-    __shared__ int32_t ro_all[GSBS_BLOCK / 64][65];   // lanes before each A row
+    __shared__ SpWave wall[GSBS_BLOCK / 64];
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
     if (threadIdx.x == 0) s_cand = 0ull;
@@ -745,18 +831,13 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restr
     const int contact_only = chem->contact_only;
     const int ns = chem->n_species;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
     const int waves = GSBS_BLOCK / 64;
-    QEntry* q = q_all[wv];
-    float4* st_p = stp_all[wv];
-    float4* st_q = stq_all[wv];
-    uint64_t* st_u = stu_all[wv];
-    int32_t* rbeg = rb_all[wv];
-    int32_t* roff = ro_all[wv];
+    SpWave& w = wall[threadIdx.x >> 6];
     int qn = 0;  // wave-uniform queue length
     unsigned long long ncand = 0;
-    for (int u = blockIdx.x * waves + wv; u < total_units; u += gridDim.x * waves) {
-        // instance owning unit u (instances own consecutive unit ranges)
+    const InstStep* Sq = nullptr;
+    for (int u = blockIdx.x * waves + (threadIdx.x >> 6); u < total_units; u += gridDim.x * waves) {
+        // instance owning work item u (instances own consecutive ranges)
         int lo_i = 0, hi_i = n_inst - 1;
         while (lo_i < hi_i) {
             const int mid = (lo_i + hi_i + 1) >> 1;
@@ -765,62 +846,72 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restr
         }
         const InstStep& S = P[lo_i];
         if (!S.active || !S.by_species) continue;
+        if (Sq != &S && qn > 0) {  // queued pairs belong to the previous instance's step data
+            while (qn > 0)
+                qpush(w, qn, lane, false, make_int4(0, 0, 0, 0), 0.0f, true, uid, *Sq, contact_only, log_all, ctr,
+                      pairs, pair_cap);
+        }
+        Sq = &S;
         const int lu = u - S.unit_base;
         if (lu >= S.unit_off_sp[ns]) continue;
         int si = 0;
         while (si + 1 < ns && S.unit_off_sp[si + 1] <= lu) ++si;
         const uint32_t pm = S.pm_dir[si];
         if (pm == 0u) continue;
-        const int nc = S.nc, kb = S.kseg_sp[si];
-        const int nb = (nc + kb - 1) / kb;
+        const int nc = S.nc, nsplit = S.nsplit;
+        const int kx = S.kdim_sp[si] & 0xFF, ky = (S.kdim_sp[si] >> 8) & 0xFF, kz = (S.kdim_sp[si] >> 16) & 0xFF;
+        const int nbx = (nc + kx - 1) / kx, nby = (nc + ky - 1) / ky, nbz = (nc + kz - 1) / kz;
         const int r = lu - S.unit_off_sp[si];
-        const int bx = r / (nb * nb), by = (r / nb) % nb, bz = r % nb;
-        const int x0 = bx * kb, x1 = min(x0 + kb, nc), y0 = by * kb, y1 = min(y0 + kb, nc);
-        const int z0 = bz * kb, z1 = min(z0 + kb, nc);
+        const int split = r % nsplit, unit = r / nsplit;
+        const int bx = unit / (nby * nbz), by = (unit / nbz) % nby, bz = unit % nbz;
+        const int x0 = bx * kx, x1 = min(x0 + kx, nc), y0 = by * ky, y1 = min(y0 + ky, nc);
+        const int z0 = bz * kz, z1 = min(z0 + kz, nc);
         const int ncell = nc * nc * nc;
         const int sbase = S.bin_base + si * ncell;
-        // A: the block's rows (x, y) over z-cells [z0, z1); kb^2 <= 64 rows
-        const int nrows = (x1 - x0) * (y1 - y0);
+        // A: the box's rows (x, y) over z-cells [z0, z1); kx * ky <= 64 rows
+        const int nyA = y1 - y0;
+        const int nrowsA = (x1 - x0) * nyA;
         int cntA = 0, begA = 0;
-        if (lane < nrows) {
-            const int cx = x0 + lane / (y1 - y0), cy = y0 + lane % (y1 - y0);
-            const int b0 = sbase + (cx * nc + cy) * nc;
+        if (lane < nrowsA) {
+            const int b0 = sbase + ((x0 + lane / nyA) * nc + y0 + lane % nyA) * nc;
             begA = (int)start[b0 + z0];
             cntA = (int)start[b0 + z1] - begA;
         }
-        int incl = cntA;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int t = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += t;
-        }
-        const int nA = __shfl(incl, 63, 64);
+        const int inclA = (int)wave_incl_scan((uint32_t)cntA);
+        const int nA = __shfl(inclA, 63, 64);
         if (nA == 0) continue;
         wave_sync_lds();
-        if (lane < nrows) {
-            rbeg[lane] = begA;
-            roff[lane] = incl - cntA;
+        if (lane < nrowsA) {
+            w.rbeg[lane] = begA;
+            w.roff[lane] = inclA - cntA;
         }
-        if (lane == 0) roff[nrows] = nA;
+        if (lane == 0) w.roff[nrowsA] = nA;
         wave_sync_lds();
         const float h = S.h, eps = S.cull_eps, L = S.L, hL = S.halfL, inv_h = S.inv_h;
         const int* rrow = rmap + si * kMaxSpecies;
-        int rsearch = 0;  // row of this lane's molecule (monotone over chunks)
+        int rsearch = 0;  // A row of this lane's molecule (monotone over chunks)
         for (int ab = 0; ab < nA; ab += 64) {
             const int k = ab + lane;
             const bool va = k < nA;
-            int ia = 0;
+            int ia = -1;
             if (va) {
-                while (rsearch + 1 < nrows && roff[rsearch + 1] <= k) ++rsearch;
-                ia = rbeg[rsearch] + (k - roff[rsearch]);
+                while (rsearch + 1 < nrowsA && w.roff[rsearch + 1] <= k) ++rsearch;
+                ia = w.rbeg[rsearch] + (k - w.roff[rsearch]);
             }
-            const int ii = va ? ia : rbeg[0];
-            const float4 pa = pos[ii];
-            const float4 qa = pos0[ii];
-            const uint64_t ua = uid[ii];
-            // bounding box of the chunk's end positions (the block does not cross the cube faces)
-            const float blx = wave_min(va ? pa.x : 3.4e38f), bhx = wave_max(va ? pa.x : -3.4e38f);
-            const float bly = wave_min(va ? pa.y : 3.4e38f), bhy = wave_max(va ? pa.y : -3.4e38f);
-            const float blz = wave_min(va ? pa.z : 3.4e38f), bhz = wave_max(va ? pa.z : -3.4e38f);
+            float4 pa = make_float4(kFar, kFar, kFar, __int_as_float(-1));
+            float4 qa = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (va) {
+                pa = pos[ia];
+                pa.w = __int_as_float(ia);
+                qa = pos0[ia];
+            }
+            wave_sync_lds();
+            w.ap[lane] = pa;
+            w.aq[lane] = qa;
+            // bounding box of the chunk's end positions (the box does not cross the cube faces)
+            const float blx = wave_min(va ? pa.x : kFar), bhx = wave_max(va ? pa.x : -kFar);
+            const float bly = wave_min(va ? pa.y : kFar), bhy = wave_max(va ? pa.y : -kFar);
+            const float blz = wave_min(va ? pa.z : kFar), bhz = wave_max(va ? pa.z : -kFar);
             uint32_t mm = pm;
             while (mm) {
                 const int sj = __ffs(mm) - 1;
@@ -831,76 +922,144 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_rows(const float4* __restr
                 const float rc2 = S.rc2[rx];
                 const float Rr = S.R[rx], inv_s = S.inv_s[rx];
                 const bool same = (sj == si);
-                // cells of the box widened by the cutoff; an axis whose span would wrap onto
-                // itself is taken whole and not culled
                 int cx0, cx1, cy0, cy1, czl, czh;
-                const bool cullx = cell_span(blx - rcu, bhx + rcu, hL, inv_h, eps, nc, cx0, cx1);
-                const bool cully = cell_span(bly - rcu, bhy + rcu, hL, inv_h, eps, nc, cy0, cy1);
+                cell_span(blx - rcu, bhx + rcu, hL, inv_h, eps, nc, cx0, cx1);
+                cell_span(bly - rcu, bhy + rcu, hL, inv_h, eps, nc, cy0, cy1);
                 const bool cullz = cell_span(blz - rcu, bhz + rcu, hL, inv_h, eps, nc, czl, czh);
-                // exact shifts need every A-B distance below L/2 along each axis
-                const bool shift = 2 * (cx1 - cx0 + 2) <= nc && 2 * (cy1 - cy0 + 2) <= nc && 2 * (czh - czl + 2) <= nc;
-                const float bxl = cullx ? blx : -3.4e38f, bxh = cullx ? bhx : 3.4e38f;
-                const float byl = cully ? bly : -3.4e38f, byh = cully ? bhy : 3.4e38f;
                 const int sbB = S.bin_base + sj * ncell;
-                for (int cx = cx0; cx <= cx1; ++cx) {
-                    const int qx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
-                    const float sx = cx < 0 ? -L : (cx >= nc ? L : 0.0f);
-                    const float gx = cullx ? cell_box_gap(cx, bxl, bxh, h, hL, eps) : 0.0f;
-                    if (gx * gx > c2) continue;
-                    for (int cy = cy0; cy <= cy1; ++cy) {
+                const int ny = cy1 - cy0 + 1;
+                const int nrows = (cx1 - cx0 + 1) * ny;
+                for (int rb = 0; rb < nrows; rb += 64) {
+                    // --- rows rb .. rb+63, one per lane: culling, z-window, segments
+                    const int rr = rb + lane;
+                    int n1 = 0, n2 = 0, j1 = 0, j2 = 0, code1 = 0, code2 = 0;
+                    if (rr < nrows) {
+                        const int cx = cx0 + rr / ny, cy = cy0 + rr % ny;
+                        const int qx = cx < 0 ? cx + nc : (cx >= nc ? cx - nc : cx);
                         const int qy = cy < 0 ? cy + nc : (cy >= nc ? cy - nc : cy);
-                        const float sy = cy < 0 ? -L : (cy >= nc ? L : 0.0f);
-                        const float gy = cully ? cell_box_gap(cy, byl, byh, h, hL, eps) : 0.0f;
+                        int sxc, syc;
+                        bool vx, vy;
+                        float gx, gy;
+                        axis_shift(qx, qx, blx, bhx, h, hL, eps, sxc, vx, gx);
+                        axis_shift(qy, qy, bly, bhy, h, hL, eps, syc, vy, gy);
                         const float gxy2 = gx * gx + gy * gy;
-                        if (gxy2 > c2) continue;
-                        // z window of this row: the box widened by what is left of the cutoff
-                        int cz0 = czl, cz1 = czh;
-                        if (cullz) {
-                            const float rz = sqrtf(c2 - gxy2);
-                            cell_span(blz - rz, bhz + rz, hL, inv_h, eps, nc, cz0, cz1);
+                        if (gxy2 <= c2) {
+                            int cz0 = czl, cz1 = czh;
+                            if (cullz) {
+                                const float rz = sqrtf(c2 - gxy2);
+                                cell_span(blz - rz, bhz + rz, hL, inv_h, eps, nc, cz0, cz1);
+                            }
+                            const int rowB = sbB + (qx * nc + qy) * nc;
+                            // main run inside [0, nc) and the wrapped run, if any
+                            const int ml = cz0 < 0 ? 0 : cz0, mh = cz1 >= nc ? nc - 1 : cz1;
+                            int wl = 1, wh = 0;
+                            if (cz0 < 0) {
+                                wl = cz0 + nc;
+                                wh = nc - 1;
+                            } else if (cz1 >= nc) {
+                                wl = 0;
+                                wh = cz1 - nc;
+                            }
+                            const int base_code = sxc | (syc << 2);
+                            const bool vxy = vx && vy;
+                            if (ml <= mh) {
+                                j1 = (int)start[rowB + ml];
+                                n1 = (int)start[rowB + mh + 1] - j1;
+                                int szc;
+                                bool vz;
+                                float gz;
+                                axis_shift(ml, mh, blz, bhz, h, hL, eps, szc, vz, gz);
+                                code1 = base_code | (szc << 4) | ((vxy && vz) ? 64 : 0);
+                            }
+                            if (wl <= wh) {
+                                j2 = (int)start[rowB + wl];
+                                n2 = (int)start[rowB + wh + 1] - j2;
+                                int szc;
+                                bool vz;
+                                float gz;
+                                axis_shift(wl, wh, blz, bhz, h, hL, eps, szc, vz, gz);
+                                code2 = base_code | (szc << 4) | ((vxy && vz) ? 64 : 0);
+                            }
                         }
-                        const int rowB = qx * nc + qy;
-                        const int np = (cz0 < 0 || cz1 >= nc) ? 2 : 1;
-                        for (int pc = 0; pc < np; ++pc) {
-                            int zl, zh;
-                            float sz = 0.0f;
-                            if (pc == 0) {
-                                zl = cz0 < 0 ? 0 : cz0;
-                                zh = cz1 >= nc ? nc - 1 : cz1;
-                            } else if (cz0 < 0) {  // cells below z = 0 are the top of the cube
-                                zl = cz0 + nc;
-                                zh = nc - 1;
-                                sz = -L;
-                            } else {  // cells above nc - 1 are the bottom of the cube
-                                zl = 0;
-                                zh = cz1 - nc;
-                                sz = L;
+                    }
+                    const int nseg_l = (n1 > 0 ? 1 : 0) + (n2 > 0 ? 1 : 0);
+                    const int sinc = (int)wave_incl_scan((uint32_t)nseg_l);
+                    const int nseg = __shfl(sinc, 63, 64);
+                    const int minc = (int)wave_incl_scan((uint32_t)(n1 + n2));
+                    const int T = __shfl(minc, 63, 64);
+                    if (T == 0) continue;
+                    wave_sync_lds();
+                    {
+                        int at = sinc - nseg_l, mp = minc - (n1 + n2);
+                        if (n1 > 0) {
+                            w.seg_j0[at] = j1;
+                            w.seg_pre[at] = mp;
+                            w.seg_code[at] = code1;
+                            ++at;
+                            mp += n1;
+                        }
+                        if (n2 > 0) {
+                            w.seg_j0[at] = j2;
+                            w.seg_pre[at] = mp;
+                            w.seg_code[at] = code2;
+                        }
+                        if (lane == 0) w.seg_pre[nseg] = T;
+                    }
+                    wave_sync_lds();
+                    // --- this wave's slice of the stream, 64 molecules per stage
+                    const int p0 = (int)(((long long)T * split) / nsplit);
+                    const int p1 = (int)(((long long)T * (split + 1)) / nsplit);
+                    auto fetch = [&](int b, float4& fp, float4& fq, int& fj, int& fc) {
+                        const int p = b + lane;
+                        fj = -1;
+                        fc = 64;
+                        fp = make_float4(-kFar, -kFar, -kFar, 0.f);
+                        fq = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (p < p1) {
+                            int lo = 0, hi = nseg - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (w.seg_pre[mid] <= p) lo = mid;
+                                else hi = mid - 1;
                             }
-                            const int jb0 = (int)start[sbB + rowB * nc + zl];
-                            const int jb1 = (int)start[sbB + rowB * nc + zh + 1];
-                            for (int jc = jb0; jc < jb1; jc += 64) {
-                                const int cnt = min(64, jb1 - jc);
-                                wave_sync_lds();
-                                if (lane < cnt) {
-                                    st_p[lane] = pos[jc + lane];
-                                    st_q[lane] = pos0[jc + lane];
-                                    st_u[lane] = uid[jc + lane];
-                                }
-                                wave_sync_lds();
-                                scan_stage(st_p, st_q, st_u, cnt, jc, shift, pa, qa, ua, ia, va, same, rc2, Rr, inv_s,
-                                           L, hL, sx, sy, sz, rx, q, qn, lane, S, contact_only, log_all, ctr, pairs,
-                                           pair_cap, ncand);
-                            }
+                            fj = w.seg_j0[lo] + (p - w.seg_pre[lo]);
+                            fc = w.seg_code[lo];
+                            fp = pos[fj];
+                            fq = pos0[fj];
+                        }
+                    };
+                    float4 fp, fq;
+                    int fj, fc;
+                    if (p0 < p1) fetch(p0, fp, fq, fj, fc);
+                    for (int b = p0; b < p1; b += 64) {
+                        wave_sync_lds();
+                        w.bp[lane] = make_float4(fp.x, fp.y, fp.z, __int_as_float(fj));
+                        w.bq[lane] = fq;
+                        w.bs[lane] = make_float4(shift_of(fc & 3, L), shift_of((fc >> 2) & 3, L),
+                                                 shift_of((fc >> 4) & 3, L), 0.f);
+                        const bool exact = __ballot((fc & 64) == 0) == 0ull;
+                        wave_sync_lds();
+                        if (b + 64 < p1) fetch(b + 64, fp, fq, fj, fc);
+                        uint32_t mlo, mhi;
+                        if (exact) {
+                            if (same) stage_mask<true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            else stage_mask<true, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, L, hL, qn, uid, S, contact_only,
+                                                   log_all, ctr, pairs, pair_cap, ncand);
+                        } else {
+                            if (same) stage_mask<false, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            else stage_mask<false, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            stage_candidates<false>(w, mlo, mhi, lane, rx, Rr, inv_s, L, hL, qn, uid, S,
+                                                    contact_only, log_all, ctr, pairs, pair_cap, ncand);
                         }
                     }
                 }
             }
         }
-        while (qn > 0) {
-            QEntry none;
-            qpush(q, qn, lane, false, none, true, S, contact_only, log_all, ctr, pairs, pair_cap);
-        }
     }
+    while (qn > 0)
+        qpush(w, qn, lane, false, make_int4(0, 0, 0, 0), 0.0f, true, uid, *Sq, contact_only, log_all, ctr, pairs,
+              pair_cap);
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
     if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
     __syncthreads();
@@ -1124,7 +1283,7 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
     if (flags & kStepHasSpecies) {
         int gb = (total_units + GSBS_BLOCK / 64 - 1) / (GSBS_BLOCK / 64);
         gb = gb < 1 ? 1 : (gb > 65536 ? 65536 : gb);
-        hipLaunchKernelGGL(k_pairs_rows, dim3(gb), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
+        hipLaunchKernelGGL(k_pairs_sp, dim3(gb), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
                            b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap, (flags & kStepLogAll) ? 1 : 0, n_inst,
                            total_units);
     }
