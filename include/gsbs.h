@@ -75,6 +75,10 @@ typedef struct {
                                 k >= 0: always grid configuration k (see gsbs_get_tuning) */
     int32_t autotune;        /* 1: try untried configurations on live steps (default); 0: use
                                 the process-wide table as it is, defaults where it is empty */
+    int32_t search_split;    /* species-bin search: slices of each partner stream, one wave
+                                each; 0 = chosen from the work per box (default), 1..16 */
+    int32_t search_box;      /* species-bin search: edge in cells of the box of molecules a
+                                wave holds; 0 = chosen per species (default), 1..8 */
 } gsbs_params;
 
 /* Counters since the context was created. */
@@ -113,8 +117,9 @@ int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
  * 2R >= L for some cube (PBC 2). */
 int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
 
-/* Replace the method parameters.  The search-grid fields (grid_config,
- * autotune) may change between advances; the others before the first one. */
+/* Replace the method parameters.  The search fields (grid_config, autotune,
+ * search_split, search_box) change only speed, never a result, and may change
+ * between advances; the others before the first one. */
 int gsbs_set_params(gsbs_ctx* ctx, const gsbs_params* p);
 
 /* Reaction radii R[0..n_reactions) in nm. */

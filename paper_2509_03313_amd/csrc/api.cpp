@@ -450,27 +450,34 @@ int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_
             const double per_cell = (double)std::max<int64_t>(sp_est[s], 0) / ncell;
             double best = INFINITY, best_work = 0.0;
             const int kmax = (int)std::min<int64_t>(nc, 8), kzmax = (int)std::min<int64_t>(nc, 16);
-            for (int kx = 1; kx <= kmax; ++kx)
-                for (int ky = 1; ky <= kmax && kx * ky <= 64; ++ky)
-                    for (int kz = 1; kz <= kzmax; ++kz) {
-                        const double E = per_cell * kx * ky * kz;
-                        const double passes = std::max(1.0, std::ceil((E + 2.0 * std::sqrt(E)) / 64.0));
-                        double streamed = 0.0;
-                        for (int p = 0; p < c->ns; ++p) {
-                            if (!((S.pm_dir[s] >> p) & 1u)) continue;
-                            const int rx = c->chem_h.rmap[s][p];
-                            const double rho = std::sqrt((double)S.cull2[rx]) / (double)S.h;
-                            const double dens = (double)std::max<int64_t>(sp_est[p], 0) / ncell;
-                            streamed += dens * (kx + 2.0 * rho + 1.0) * (ky + 2.0 * rho + 1.0) *
-                                        std::min((double)nc, kz + 2.0 * rho + 1.0);
-                        }
-                        const double cost = passes * (streamed + 128.0) / std::max(E, 0.5);
-                        if (cost < best) {
-                            best = cost;
-                            best_work = passes * streamed;
-                            S.kdim_sp[s] = kx | (ky << 8) | (kz << 16);
-                        }
+            double rho[kMaxSpecies], dens[kMaxSpecies];
+            int np = 0;
+            for (int p = 0; p < c->ns; ++p) {
+                if (!((S.pm_dir[s] >> p) & 1u)) continue;
+                rho[np] = std::sqrt((double)S.cull2[c->chem_h.rmap[s][p]]) / (double)S.h;
+                dens[np] = (double)std::max<int64_t>(sp_est[p], 0) / ncell;
+                ++np;
+            }
+            // square boxes in x and y (kx = ky), any depth in z; search_box fixes a cube
+            const int klo = c->prm.search_box > 0 ? std::min(c->prm.search_box, kmax) : 1;
+            const int khi = c->prm.search_box > 0 ? klo : kmax;
+            for (int kx = klo; kx <= khi; ++kx)
+                for (int kz = (c->prm.search_box > 0 ? std::min(c->prm.search_box, kzmax) : 1);
+                     kz <= (c->prm.search_box > 0 ? std::min(c->prm.search_box, kzmax) : kzmax); ++kz) {
+                    const int ky = kx;
+                    const double E = per_cell * kx * ky * kz;
+                    const double passes = std::max(1.0, std::ceil((E + 2.0 * std::sqrt(E)) / 64.0));
+                    double streamed = 0.0;
+                    for (int q = 0; q < np; ++q)
+                        streamed += dens[q] * (kx + 2.0 * rho[q] + 1.0) * (ky + 2.0 * rho[q] + 1.0) *
+                                    std::min((double)nc, kz + 2.0 * rho[q] + 1.0);
+                    const double cost = passes * (streamed + 128.0) / std::max(E, 0.5);
+                    if (cost < best) {
+                        best = cost;
+                        best_work = passes * streamed;
+                        S.kdim_sp[s] = kx | (ky << 8) | (kz << 16);
                     }
+                }
             const int kx = S.kdim_sp[s] & 0xFF, ky = (S.kdim_sp[s] >> 8) & 0xFF, kz = (S.kdim_sp[s] >> 16) & 0xFF;
             units_sp[s] = ((nc + kx - 1) / kx) * ((nc + ky - 1) / ky) * ((nc + kz - 1) / kz);
             units_total += (double)units_sp[s];
@@ -484,6 +491,7 @@ int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_
             const double room = std::floor(work_total / units_total / 256.0);  // >= 4 stages per slice
             nsplit = (int64_t)std::max(1.0, std::min({want, room, 16.0}));
         }
+        if (c->prm.search_split > 0) nsplit = c->prm.search_split;
         S.nsplit = (int32_t)nsplit;
         int64_t off = 0;
         for (int s = 0; s < c->ns; ++s) {
@@ -714,6 +722,8 @@ int gsbs_default_params(gsbs_params* p) {
     p->dt_max_ns = 0.0;
     p->grid_config = -1;
     p->autotune = 1;
+    p->search_split = 0;
+    p->search_box = 0;
     return GSBS_OK;
 }
 
@@ -841,7 +851,8 @@ int gsbs_set_reactions(gsbs_ctx* c, int32_t n, const gsbs_reaction* r) {
 int gsbs_set_params(gsbs_ctx* c, const gsbs_params* p) {
     if (!c || !p) return fail(GSBS_EINVAL, "null");
     if (!(p->c_cut > 0) || p->rounds < 1 || !(p->dt0_ns > 0) || !(p->ratio > 1.0) || p->dt_max_ns < 0 ||
-        p->grid_config < -1 || p->grid_config >= kNumCfg)
+        p->grid_config < -1 || p->grid_config >= kNumCfg || p->search_split < 0 || p->search_split > 16 ||
+        p->search_box < 0 || p->search_box > 8)
         return fail(GSBS_EINVAL, "bad parameters");
     c->prm = *p;
     c->tuning = p->autotune != 0;

@@ -161,6 +161,40 @@ def test_candidates_bit_exact(g, orc, dt, nc, mode):
     e.close()
 
 
+@pytest.mark.parametrize("dt,nc", [(3.0, 5), (3.0, 9), (40.0, 4), (40.0, 9)])
+def test_candidates_independent_of_search_shape(g, orc, dt, nc):
+    """The species-bin search's work split (stream slices per box) and box
+    shape change only speed: every setting gives the oracle's FP32 candidate
+    set, including cutoffs near L/2 where windows wrap and shifts straddle."""
+    L = 400.0
+    rng = np.random.default_rng(500 + nc)
+    n = 3000
+    x0 = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    x0[: n // 2] = rng.uniform(-L / 2, L / 2, size=(n // 30, 3)).repeat(15, axis=0) + rng.normal(0, 1.5, size=(n // 2, 3))
+    x0 = ((x0 + L / 2) % L - L / 2).astype(np.float32)
+    x1 = ((x0 + rng.normal(0, math.sqrt(2 * 5 * dt), size=(n, 3)) + L / 2) % L - L / 2).astype(np.float32)
+    sp = rng.integers(0, 7, size=n).astype(np.uint8)
+    uid = np.arange(n, dtype=np.uint64)
+    chem = orc.make_chem(W.D_CONFIG, W.REACTIONS)
+    ref = set(map(tuple, orc.cand_f32(x1, sp, L, chem, dt).tolist()))
+    assert len(ref) > 50
+    for split in (1, 3, 16):
+        for box in (1, 3):
+            say("search shape", dt, nc, split, box)
+            p = g.gsbs_default_params()
+            p.search_split = split
+            p.search_box = box
+            e = make_engine(g, L, 9, params=p)
+            g.gsbs_debug_set_state(e.ctx, x1, sp, uid, step=4)
+            g.gsbs_debug_step(e.ctx, dt, g.DEBUG_FIXED | g.DEBUG_SEARCH_ONLY | g.DEBUG_LOG_ALL | MODES["species"],
+                              xyz0=x0, nc_force=nc)
+            pr = g.gsbs_debug_get_pairs(e.ctx)
+            got = [tuple(u) for u in pr["uid"].astype(np.int64).tolist()]
+            assert len(got) == len(set(got)), "a pair was tested twice"
+            assert set(got) == ref, (split, box, len(got), len(ref))
+            e.close()
+
+
 # ------------------------------------------------ short trajectory parity ---
 def test_first_steps_match_oracle(g, orc):
     """Same initial spurs, same Philox streams: the GPU and the oracle follow
