@@ -614,6 +614,8 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
     if (c->profiling) {
         HIPCHK(hipEventSynchronize(c->prof_ev[2 * kStepKernels - 1]));
         for (int k = 0; k < kStepKernels; ++k) {
+            // slots 3 and 4 (whole-cell and species-bin search) run only when some instance uses them
+            if ((k == 3 && !(flags & kStepHasWhole)) || (k == 4 && !(flags & kStepHasSpecies))) continue;
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
             c->prof_ms[k] += ms;

@@ -157,6 +157,8 @@ __global__ void k_add_n(DevCounters* ctr, int32_t n, int32_t cap) {
 }
 
 // ------------------------------------------------------------------ bin ---
+constexpr int kScanItems = 16;
+constexpr int kScanTile = GSBS_BLOCK * kScanItems;
 // Global bin of a moved molecule.
 __device__ __forceinline__ uint32_t bin_of(float3 x, const InstStep& S, int sp, int ns) {
     const int c = local_cell(x, S);
@@ -249,8 +251,6 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ p
 }
 
 // ----------------------------------------------------------------- scan ---
-constexpr int kScanItems = 16;
-constexpr int kScanTile = GSBS_BLOCK * kScanItems;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -366,6 +366,12 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scatter(const float4* __restrict
 }
 
 // ---------------------------------------------------------- pair search ---
+// Orders LDS accesses of the lanes of one wave (no workgroup barrier needed).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Probability that the pair touched R during the step given start/end
 // separations r0, r1 (radial Brownian bridge; method of images for the pair
 // density of the supplement), inv_s = 1 / (D_AB dt).
@@ -459,11 +465,55 @@ __device__ __forceinline__ float cell_gap(float x, int q, int o, float h, float 
     return g > 0.0f ? g : 0.0f;
 }
 
+// Out of line: candidates are rare in the whole-cell search and the
+// evaluation's registers would otherwise cap the occupancy of its loops.
+__device__ __noinline__ void eval_candidate_call(int i, int j, float d2, const float4* __restrict__ pos0,
+                                                 const uint64_t* __restrict__ uid, const InstStep& S, int rx,
+                                                 int contact_only, int log_all, DevCounters* __restrict__ ctr,
+                                                 PairRec* __restrict__ pairs, uint32_t pair_cap) {
+    eval_candidate(i, j, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs, pair_cap);
+}
+
+// Molecules [j0, j1) of one cell against molecule i, four loads in flight at a time.
+__device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, const float4* __restrict__ pos,
+                                         const float4* __restrict__ pos0, const uint64_t* __restrict__ uid,
+                                         const InstStep& S, const int* row, int contact_only, int log_all,
+                                         DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                         unsigned long long& ncand) {
+    for (int j = j0; j < j1; j += 4) {
+        float4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = (j + u < j1) ? pos[j + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float d2v[4];
+        int rxv[4];
+        uint32_t m = 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rxv[u] = row[__float_as_int(q[u].w) & 0xFF];
+            d2v[u] = end_d2(q[u], pi, S.L, S.halfL);
+            if (j + u < j1 && rxv[u] >= 0 && d2v[u] < S.rc2[rxv[u]]) m |= 1u << u;
+        }
+        while (m) {  // one evaluation site for the (rare) candidates
+            const int u = __ffs(m) - 1;
+            m &= m - 1u;
+            const float d2 = u == 0 ? d2v[0] : (u == 1 ? d2v[1] : (u == 2 ? d2v[2] : d2v[3]));
+            const int rx = u == 0 ? rxv[0] : (u == 1 ? rxv[1] : (u == 2 ? rxv[2] : rxv[3]));
+            ++ncand;
+            eval_candidate_call(i, j + u, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs, pair_cap);
+        }
+    }
+}
+
 // Whole-cell search (small cells, few molecules each): one thread per sorted
-// molecule reads every molecule of the stencil cells and checks its species;
-// a pair is searched from the molecule in the lower cell (or with the lower
-// index in one cell).  Cells whose distance from the molecule exceeds the
-// largest cutoff of its species are skipped.
+// molecule; a pair is searched from the molecule in the lower cell (or with the
+// lower index in one cell).  Each wave first stages the 128 sorted molecules
+// from its first one into LDS, so the partners in a molecule's own cell --
+// contiguous in sorted order, and most of the work when the cutoff is small
+// against the cell -- are read from LDS; the rest of a very full cell and the
+// stencil cells come from global memory.  Cells whose distance from the
+// molecule exceeds the largest cutoff of its species are skipped.
+constexpr int kWin = 128;
+
 __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__ pos,
                                                     const float4* __restrict__ pos0,
                                                     const uint64_t* __restrict__ uid,
@@ -475,6 +525,8 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
                                                     int32_t log_all, int32_t ns) {
     __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
     __shared__ unsigned long long s_cand;
+    __shared__ float4 wpos_all[GSBS_BLOCK / 64][kWin];
+    __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
     if (threadIdx.x == 0) s_cand = 0ull;
@@ -482,22 +534,57 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
     const uint32_t reactive = chem->reactive_mask;
     const int contact_only = chem->contact_only;
     const int n = ctr->n_live;
+    const int lane = threadIdx.x & 63;
+    float4* wpos = wpos_all[threadIdx.x >> 6];
+    uint32_t* wbin = wbin_all[threadIdx.x >> 6];
     unsigned long long ncand = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float4 pi = pos[i];
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int i0 = base + (threadIdx.x & ~63);
+        const int i = i0 + lane;
+        wave_sync_lds();
+#pragma unroll
+        for (int h2 = 0; h2 < kWin; h2 += 64) {
+            const int j = i0 + h2 + lane;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            uint32_t bn = kNoCell;
+            if (j < n) {
+                v = pos[j];
+                bn = __float_as_uint(pos0[j].w);
+            }
+            wpos[h2 + lane] = v;
+            wbin[h2 + lane] = bn;
+        }
+        wave_sync_lds();
+        if (i >= n) continue;
+        const float4 pi = wpos[lane];
         const int mi = __float_as_int(pi.w);
         const int si = mi & 0xFF;
         if (!((reactive >> si) & 1u)) continue;
         const InstStep& S = P[mi >> 8];
         if (!S.active || S.by_species) continue;
-        const int cg = (int)__float_as_uint(pos0[i].w) - S.bin_base;  // local cell
+        const uint32_t bi = wbin[lane];
+        const int cg = (int)bi - S.bin_base;  // local cell
+        const int* row = rmap + si * kMaxSpecies;
+        // own cell: the sorted molecules after i while they share its bin
+        int k = lane + 1;
+        for (; k < kWin && wbin[k] == bi; ++k) {
+            const float4 pj = wpos[k];
+            const int rx = row[__float_as_int(pj.w) & 0xFF];
+            if (rx < 0) continue;
+            const float d2 = end_d2(pj, pi, S.L, S.halfL);
+            if (!(d2 < S.rc2[rx])) continue;
+            ++ncand;
+            eval_candidate_call(i, i0 + k, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs, pair_cap);
+        }
+        if (k == kWin) scan_run(i, pi, i0 + kWin, (int)start[bi + 1], pos, pos0, uid, S, row, contact_only, log_all,
+                                ctr, pairs, pair_cap, ncand);
+        // stencil cells after the own cell in cell order
         const int nc = S.nc, m = S.reach;
         const int ix = cg / (nc * nc), iy = (cg / nc) % nc, iz = cg % nc;
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
         const int lo = full ? 0 : -m, hi = full ? nc - 1 : m;
         const float h = S.h, hL = S.halfL, eps = S.cull_eps;
         const float cmax = S.cull2_all[si];
-        const int* row = rmap + si * kMaxSpecies;
         for (int ox = lo; ox <= hi; ++ox) {
             const int qx = full ? ox : (ix + ox + nc) % nc;
             const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
@@ -513,22 +600,15 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
                     const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
                     if (gxy2 + gz * gz > cmax) continue;
                     const int c2 = (qx * nc + qy) * nc + qz;
-                    if (c2 < cg) continue;
-                    int j = (c2 == cg) ? i + 1 : (int)start[S.bin_base + c2];
-                    const int j1 = (int)start[S.bin_base + c2 + 1];
-                    for (; j < j1; ++j) {
-                        const int sj = __float_as_int(pos[j].w) & 0xFF;
-                        const int rx = row[sj];
-                        if (rx < 0) continue;
-                        test_pair(i, j, pi, pos, pos0, uid, S, rx, S.rc2[rx], contact_only, log_all, ctr, pairs,
-                                  pair_cap, ncand);
-                    }
+                    if (c2 <= cg) continue;
+                    scan_run(i, pi, (int)start[S.bin_base + c2], (int)start[S.bin_base + c2 + 1], pos, pos0, uid,
+                             S, row, contact_only, log_all, ctr, pairs, pair_cap, ncand);
                 }
             }
         }
     }
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
-    if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_cand, ncand);
+    if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
     __syncthreads();
     if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
 }
@@ -578,11 +658,6 @@ struct SpWave {
     float qr[128];   // queued r1
     int32_t rbeg[65], roff[65];
 };
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // Contact probability, pair uniform and acceptance of one pair.
 __device__ __forceinline__ void eval_pair(int i, int j, int rx, float r0, float r1, const uint64_t* __restrict__ uid,
@@ -1091,7 +1166,7 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
                                                      long long* __restrict__ counts,
                                                      unsigned long long* __restrict__ msteps,
                                                      int32_t n_inst, int32_t cap, int32_t search_only) {
-    __shared__ int n_new, n_prod, n_react;
+    __shared__ int n_new, n_wait, n_prod, n_react;
     const int tid = threadIdx.x;
     // molecule-steps of the instances that stepped (counts before this step's reactions)
     for (int t = tid; t < n_inst; t += kReactBlock) {
@@ -1119,7 +1194,10 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
             atomicMin(&claim[r.i], match_key(r.u24, uid[r.j]));
             atomicMin(&claim[r.j], match_key(r.u24, uid[r.i]));
         }
-        if (tid == 0) n_new = 0;
+        if (tid == 0) {
+            n_new = 0;
+            n_wait = 0;
+        }
         __syncthreads();
         for (int p = tid; p < np; p += kReactBlock) {
             const PairRec r = pairs[p];
@@ -1129,6 +1207,8 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
             if (ci == match_key(r.u24, uid[r.j]) && cj == match_key(r.u24, uid[r.i])) {
                 pairs[p].flags = r.flags | 4;
                 atomicAdd(&n_new, 1);
+            } else {
+                atomicAdd(&n_wait, 1);
             }
         }
         __syncthreads();
@@ -1145,7 +1225,8 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
             }
         }
         __syncthreads();
-        if (n_new == 0) break;
+        // eligible pairs only lose eligibility: with none left waiting, later rounds find nothing
+        if (n_new == 0 || n_wait == 0) break;
         __syncthreads();
     }
     // products, removals, counts
@@ -1237,20 +1318,18 @@ void launch_inject(hipStream_t st, float4* pos, uint64_t* uid, long long* counts
     hipLaunchKernelGGL(k_add_n, dim3(1), dim3(1), 0, st, ctr, n, cap);
 }
 
-const char* const kStepKernelNames[kStepKernels] = {"k_bin", "k_scan_reduce", "k_scan_apply",
-                                                     "k_scatter", "k_pairs", "k_react"};
+const char* const kStepKernelNames[kStepKernels] = {"k_bin", "k_scan", "k_scatter", "k_pairs", "k_pairs_sp", "k_react"};
 
 void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const ChemDev* chem,
                  int32_t n_inst, int32_t total_bins, int32_t total_units, int32_t ns, int32_t grid, int32_t flags,
                  hipEvent_t* ev) {
     const int fixed = (flags & kStepFixed) ? 1 : 0;
     const int nb = (total_bins + kScanTile - 1) / kScanTile;
-    int k = 0;
-    auto mark = [&](int end) {
-        if (ev) (void)hipEventRecord(ev[2 * k + end], st);
-        if (end) ++k;
+    // every kernel slot gets its two events, also when the kernel is not launched
+    auto mark = [&](int slot, int end) {
+        if (ev) (void)hipEventRecord(ev[2 * slot + end], st);
     };
-    mark(0);
+    mark(0, 0);
     if (total_bins <= kLdsBins) {
         // enough blocks that no block owns more than kBinRounds * GSBS_BLOCK molecules
         const int g = grid > (b.cap + kBinRounds * GSBS_BLOCK - 1) / (kBinRounds * GSBS_BLOCK)
@@ -1262,24 +1341,23 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
         hipLaunchKernelGGL(k_bin, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
                            b.cell_count, b.cellrank, fixed, ns);
     }
-    mark(1);
-    mark(0);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins,
-                       b.block_sums);
-    mark(1);
-    mark(0);
+    mark(0, 1);
+    mark(1, 0);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins, b.block_sums);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins,
                        b.block_sums, b.cell_start, b.ctr);
-    mark(1);
-    mark(0);
+    mark(1, 1);
+    mark(2, 0);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
                        b.cellrank, b.cell_start, b.pos_out, b.pos0_out, b.uid_out,
                        fixed ? b.x0_override : nullptr);
-    mark(1);
-    mark(0);
+    mark(2, 1);
+    mark(3, 0);
     if (flags & kStepHasWhole)
         hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.pos0_out, b.uid_out,
                            b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap, (flags & kStepLogAll) ? 1 : 0, ns);
+    mark(3, 1);
+    mark(4, 0);
     if (flags & kStepHasSpecies) {
         int gb = (total_units + GSBS_BLOCK / 64 - 1) / (GSBS_BLOCK / 64);
         gb = gb < 1 ? 1 : (gb > 65536 ? 65536 : gb);
@@ -1287,12 +1365,12 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
                            b.ctr, P, chem, b.cell_start, b.pairs, b.pair_cap, (flags & kStepLogAll) ? 1 : 0, n_inst,
                            total_units);
     }
-    mark(1);
-    mark(0);
+    mark(4, 1);
+    mark(5, 0);
     hipLaunchKernelGGL(k_react, dim3(1), dim3(kReactBlock), 0, st, b.pos_out, b.uid_out, b.ctr, P, chem,
                        b.pairs, b.pair_cap, b.claim, b.mate, b.counts, b.msteps, n_inst, b.cap,
                        (flags & kStepSearchOnly) ? 1 : 0);
-    mark(1);
+    mark(5, 1);
 }
 
 void launch_record(hipStream_t st, const long long* counts, long long* rec, int32_t max_rec,
