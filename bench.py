@@ -28,16 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per molecule processed by each step kernel (what the
-# kernel must move at least once; neighbour reads of the pair search are
-# served by L2/LDS and are not counted).
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic HBM bytes per work unit of the streaming kernels (what the kernel
+# must move at least once): per live molecule for k_bin / k_scatter, per bin
+# for the scan.
 ALG_BYTES = {
-    "k_bin": 16 + 8 + 8,                 # read position+meta, uid; write (cell, rank)
-    "k_scatter": 16 + 8 + 8 + 4 + 16 + 16 + 8,  # read pos, uid, (cell,rank), start; write pos, pos0, uid
-    "k_pairs": 16 + 16 + 8,              # read sorted end/start positions and uid once
+    "k_bin": 16 + 8 + 8,                          # read position+meta, uid; write (bin, rank)
+    "k_scan": 4 + 4 + 4 + 4,                      # per bin: read count twice (reduce, apply); write start; clear count
+    "k_scatter": 16 + 8 + 8 + 4 + 16 + 16 + 8,    # read pos, uid, (bin, rank), start; write pos, pos0, uid
+    "k_pairs": 16 + 16 + 8,                       # read sorted end/start positions and uid once
 }
-# Vector-ALU peak of MI355X: 256 CUs x 2.4 GHz x 128 FP32 lanes per CU and clock.
-VALU_LANE_OPS = 256 * 2.4e9 * 128
+# Algorithmic FP32 operations per candidate pair of the species-bin search
+# (many molecules per cell, the arithmetic dominates): the minimum-image end
+# separation (3 subtract, 3 multiply, 2 add).
+ALG_FLOP_PER_CANDIDATE = 8
 
 
 def parse():
@@ -163,20 +167,25 @@ def main():
         note(f"profile: {prof}")
         e.close()
         dom = max(prof, key=lambda k: prof[k][0])
-        tot_ms, launches = prof[dom]
+        tot_ms, launches, work, cand = prof[dom]
         avg_s = tot_ms / 1e3 / max(launches, 1)
-        mol_per_launch = pst["molecule_steps"] / max(launches, 1)
         if dom in ALG_BYTES:
-            ach = ALG_BYTES[dom] * mol_per_launch / avg_s / 1e9
+            ach = ALG_BYTES[dom] * work / (tot_ms / 1e3) / 1e9
             roofline = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                             frac=round(ach / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                            avg_launch_us=round(avg_s * 1e6, 3),
-                            alg_bytes_per_molecule=ALG_BYTES[dom])
+                            avg_launch_us=round(avg_s * 1e6, 3), alg_bytes_per_unit=ALG_BYTES[dom],
+                            units_per_launch=round(work / max(launches, 1), 1))
+        elif dom == "k_pairs_sp":
+            ach = ALG_FLOP_PER_CANDIDATE * cand / (tot_ms / 1e3) / 1e12
+            roofline = dict(bound="alu", achieved=round(ach, 4), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=round(ach / FP32_PEAK_TFLOPS, 6), traffic=None, kernel=dom,
+                            avg_launch_us=round(avg_s * 1e6, 3), alg_flop_per_candidate=ALG_FLOP_PER_CANDIDATE,
+                            candidates_per_launch=round(cand / max(launches, 1), 1))
         else:
             roofline = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                             kernel=dom, avg_launch_us=round(avg_s * 1e6, 3))
         tr = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tr) and roofline.get("achieved") is not None:
+        if os.path.exists(tr):
             t = json.load(open(tr))
             if t.get("kernels_hash") == kernels_hash() and dom in t.get("per_launch_bytes", {}):
                 roofline["traffic"] = t["per_launch_bytes"][dom]
@@ -205,6 +214,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "profile_ms": {k: round(v[0], 3) for k, v in prof.items()} if prof else None,
+        "profile_work": {k: v[2] for k, v in prof.items()} if prof else None,
+        "profile_launches": {k: v[1] for k, v in prof.items()} if prof else None,
+        "profile_candidates": {k: v[3] for k, v in prof.items() if v[3]} if prof else None,
         "tuning": gsbs.gsbs_get_tuning(),
         "final_counts": counts[-1].tolist(),
         "G_H2O2_end": float(gv[-1][W.H2O2]),

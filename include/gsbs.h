@@ -191,9 +191,12 @@ int gsbs_get_tuning(int32_t max_k, int32_t* keys, int32_t* best, double* best_ms
 int gsbs_set_profiling(gsbs_ctx* ctx, int32_t on);
 
 /* Accumulated profile: for k < *n (at most max_k) the kernel name (NUL-padded
- * in names[k*32 .. k*32+31]), total milliseconds and number of launches. */
+ * in names[k*32 .. k*32+31]), total milliseconds, number of launches, work
+ * units processed (bins for the scan, live molecules for every other kernel)
+ * and candidate pairs found (end separation below r_c; non-zero for the two
+ * pair-search kernels only).  Any output pointer may be NULL. */
 int gsbs_get_profile(gsbs_ctx* ctx, int32_t max_k, char* names, double* total_ms, int64_t* launches,
-                     int32_t* n);
+                     int64_t* work, int64_t* candidates, int32_t* n);
 
 /* Per-step log of the profiled steps of gsbs_advance_to (instance 0): Philox
  * step index, step time in ms (first to last kernel), grid (nc, reach,

@@ -199,6 +199,9 @@ struct gsbs_ctx {
     hipEvent_t prof_ev[2 * kStepKernels] = {};
     double prof_ms[kStepKernels] = {};
     int64_t prof_n[kStepKernels] = {};
+    int64_t prof_work[kStepKernels] = {};
+    int64_t prof_cnd[kStepKernels] = {};
+    unsigned long long prof_cand = 0;  // candidate counter at the last profiled step
     // last debug step
     int32_t dbg_nc = 0;
     int32_t dbg_cell_base = 0;
@@ -613,6 +616,10 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
     if (span) HIPCHK(hipEventRecord(span[1], c->st));
     if (c->profiling) {
         HIPCHK(hipEventSynchronize(c->prof_ev[2 * kStepKernels - 1]));
+        DevCounters h{};
+        HIPCHK(hipMemcpy(&h, c->ctr, sizeof(h), hipMemcpyDeviceToHost));
+        const int64_t dcand = (int64_t)(h.cand - c->prof_cand);
+        c->prof_cand = h.cand;
         for (int k = 0; k < kStepKernels; ++k) {
             // slots 3 and 4 (whole-cell and species-bin search) run only when some instance uses them
             if ((k == 3 && !(flags & kStepHasWhole)) || (k == 4 && !(flags & kStepHasSpecies))) continue;
@@ -621,6 +628,13 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
             c->prof_ms[k] += ms;
             c->prof_n[k] += 1;
         }
+        // work units; a step that used both searches counts its molecules and candidates
+        // for the species-bin one
+        const int ks = (flags & kStepHasSpecies) ? 4 : 3;
+        for (int k = 0; k < kStepKernels; ++k)
+            if (k != 3 && k != 4) c->prof_work[k] += (k == 1) ? (int64_t)bins : (int64_t)h.n_live;
+        c->prof_work[ks] += h.n_live;
+        c->prof_cnd[ks] += dcand;
         float tot = 0.f;
         HIPCHK(hipEventElapsedTime(&tot, c->prof_ev[0], c->prof_ev[2 * kStepKernels - 1]));
         if (row0)
@@ -1199,6 +1213,13 @@ int gsbs_set_profiling(gsbs_ctx* c, int32_t on) {
     for (int k = 0; k < kStepKernels; ++k) {
         c->prof_ms[k] = 0.0;
         c->prof_n[k] = 0;
+        c->prof_work[k] = 0;
+        c->prof_cnd[k] = 0;
+    }
+    if (on) {
+        DevCounters h{};
+        HIPCHK(hipMemcpy(&h, c->ctr, sizeof(h), hipMemcpyDeviceToHost));
+        c->prof_cand = h.cand;
     }
     return GSBS_OK;
 }
@@ -1253,7 +1274,8 @@ int gsbs_get_step_log(gsbs_ctx* c, int64_t max_n, int64_t* step, double* ms, int
     return GSBS_OK;
 }
 
-int gsbs_get_profile(gsbs_ctx* c, int32_t max_k, char* names, double* total_ms, int64_t* launches, int32_t* n) {
+int gsbs_get_profile(gsbs_ctx* c, int32_t max_k, char* names, double* total_ms, int64_t* launches, int64_t* work,
+                     int64_t* candidates, int32_t* n) {
     if (!c || !n) return fail(GSBS_EINVAL, "null");
     for (int k = 0; k < std::min(max_k, kStepKernels); ++k) {
         if (names) {
@@ -1262,6 +1284,8 @@ int gsbs_get_profile(gsbs_ctx* c, int32_t max_k, char* names, double* total_ms, 
         }
         if (total_ms) total_ms[k] = c->prof_ms[k];
         if (launches) launches[k] = c->prof_n[k];
+        if (work) work[k] = c->prof_work[k];
+        if (candidates) candidates[k] = c->prof_cnd[k];
     }
     *n = kStepKernels;
     return GSBS_OK;

@@ -737,7 +737,7 @@ __device__ __forceinline__ void qpush(SpWave& w, int& qn, int lane, bool need, c
 
 // Candidate mask of one stage: bit t set when staged B t lies within the
 // cutoff of this lane's A (end separation, FP32, fixed operation order).
-template <bool kShift, bool kSame>
+template <bool kShift, bool kSame, bool kZero = false>
 __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
                                            uint32_t& mlo, uint32_t& mhi) {
     uint32_t half[2];
@@ -749,7 +749,11 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
             const int t = 32 * g + k;
             const float4 p = w.bp[t];
             float dx, dy, dz;
-            if (kShift) {
+            if (kZero) {  // every shift of the stage is 0: adding it would change nothing
+                dx = __fsub_rn(p.x, pa.x);
+                dy = __fsub_rn(p.y, pa.y);
+                dz = __fsub_rn(p.z, pa.z);
+            } else if (kShift) {
                 const float4 sh = w.bs[t];
                 dx = __fadd_rn(__fsub_rn(p.x, pa.x), sh.x);
                 dy = __fadd_rn(__fsub_rn(p.y, pa.y), sh.y);
@@ -1113,12 +1117,18 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                         w.bs[lane] = make_float4(shift_of(fc & 3, L), shift_of((fc >> 2) & 3, L),
                                                  shift_of((fc >> 4) & 3, L), 0.f);
                         const bool exact = __ballot((fc & 64) == 0) == 0ull;
+                        const bool zero = __ballot((fc & 63) != 0) == 0ull;
                         wave_sync_lds();
                         if (b + 64 < p1) fetch(b + 64, fp, fq, fj, fc);
                         uint32_t mlo, mhi;
                         if (exact) {
-                            if (same) stage_mask<true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
-                            else stage_mask<true, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            if (zero) {
+                                if (same) stage_mask<true, true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                                else stage_mask<true, false, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            } else {
+                                if (same) stage_mask<true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                                else stage_mask<true, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            }
                             stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, L, hL, qn, uid, S, contact_only,
                                                    log_all, ctr, pairs, pair_cap, ncand);
                         } else {

@@ -85,7 +85,7 @@ _SIGS = {
     "gsbs_get_step_log": [_vp, _i64, _P(_i64), _P(_d), _P(_i32), _P(_i64), _P(_i64)],
     "gsbs_get_tuning": [_i32, _P(_i32), _P(_i32), _P(_d), _P(_i32)],
     "gsbs_set_profiling": [_vp, _i32],
-    "gsbs_get_profile": [_vp, _i32, C.c_char_p, _P(_d), _P(_i64), _P(_i32)],
+    "gsbs_get_profile": [_vp, _i32, C.c_char_p, _P(_d), _P(_i64), _P(_i64), _P(_i64), _P(_i32)],
     "gsbs_plan_schedule": [_d, _d, _i32, _P(_d), _i32, _P(_d), _d, _d, _d, _P(_d), _i64, _P(_i64)],
     "gsbs_debug_get_state": [_vp, _i32, _i64, _P(C.c_float), _P(C.c_uint8), _P(_u64), _P(_i64)],
     "gsbs_debug_set_state": [_vp, _i64, _P(C.c_float), _P(C.c_uint8), _P(_u64), _i64, _u64],
@@ -270,17 +270,20 @@ def gsbs_set_profiling(ctx, on: bool):
 
 
 def gsbs_get_profile(ctx):
-    """{kernel name: (total ms, launches)} of the profiled steps."""
+    """{kernel name: (total ms, launches, work units, candidate pairs)} of the profiled steps."""
     names = C.create_string_buffer(32 * 16)
     ms = np.zeros(16)
     nl = np.zeros(16, dtype=np.int64)
+    wk = np.zeros(16, dtype=np.int64)
+    cd = np.zeros(16, dtype=np.int64)
     n = _i32()
-    _chk(_lib.gsbs_get_profile(ctx, 16, names, _ptr(ms, _d), _ptr(nl, _i64), C.byref(n)))
+    _chk(_lib.gsbs_get_profile(ctx, 16, names, _ptr(ms, _d), _ptr(nl, _i64), _ptr(wk, _i64), _ptr(cd, _i64),
+                               C.byref(n)))
     raw = names.raw
     out = {}
     for k in range(n.value):
         nm = raw[32 * k:32 * k + 32].split(b"\0")[0].decode()
-        out[nm] = (float(ms[k]), int(nl[k]))
+        out[nm] = (float(ms[k]), int(nl[k]), int(wk[k]), int(cd[k]))
     return out
 
 
