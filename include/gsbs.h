@@ -250,6 +250,58 @@ int gsbs_debug_get_pairs(gsbs_ctx* ctx, int64_t max_n, uint64_t* uid2, float* P,
 int gsbs_debug_get_cells(gsbs_ctx* ctx, int64_t max_n, int32_t* cell, uint64_t* uid, int32_t* nc,
                          int64_t* n);
 
+/* ------------------------------------------- inter-pulse surrogate MLP --- */
+/* A perceptron that maps the state at the end of a pulse's SBS segment
+ * (species concentrations, binned pair-correlation features, log of the time
+ * to the next pulse: 296 inputs) to the 7 log-concentrations at the next
+ * pulse, standing in for the long homogeneous evolution between pulses that
+ * the paper integrates with rate equations (its Eq. 3-4, "NumODEs").  Layers
+ * 296-256-256-256-256-7, erf-GELU after each hidden layer, BF16 weights and
+ * activations, FP32 accumulation, FP32 master weights updated by Adam.  All
+ * x / t / y arrays are device pointers, row-major [batch][width], read and
+ * written in order on the stream given at creation; every call returns after
+ * queueing its kernels unless it returns host data. */
+typedef struct gsbs_mlp gsbs_mlp;
+
+/* Number of parameters of the flat FP32 layout used by set/get: per layer the
+ * weight matrix W[n_out][n_in] row-major, then the bias b[n_out]. */
+int gsbs_mlp_param_count(int64_t* n);
+
+/* Allocate a network for batches of up to max_batch rows on `stream` (a
+ * hipStream_t, NULL for the null stream).  Weights start at zero. */
+int gsbs_mlp_create(int32_t max_batch, void* stream, gsbs_mlp** out);
+int gsbs_mlp_destroy(gsbs_mlp* m);
+
+/* Replace / read the FP32 master weights (host arrays of n = param_count
+ * floats).  Setting resets the Adam moments and step counter and refreshes
+ * the BF16 copies (round to nearest even). */
+int gsbs_mlp_set_weights(gsbs_mlp* m, const float* w, int64_t n);
+int gsbs_mlp_get_weights(gsbs_mlp* m, float* w, int64_t n);
+
+/* y[batch][7] = network(x[batch][296]); x is rounded to BF16 on entry. */
+int gsbs_mlp_forward(gsbs_mlp* m, const float* x, int32_t batch, float* y);
+
+/* BF16 activations entering layer `layer` (0: the rounded input, 1..4: the
+ * hidden outputs) of the last forward pass, as FP32 host array
+ * out[batch][width] (width 296 for layer 0, else 256). */
+int gsbs_mlp_get_activation(gsbs_mlp* m, int32_t layer, int32_t batch, float* out);
+
+/* Forward and backward pass of the mean squared error over the batch x 7
+ * outputs against t[batch][7]; keeps the FP32 gradients (read them with
+ * gsbs_mlp_get_grads, same layout as the weights); *loss (host, may be NULL)
+ * receives the mean squared error.  The product operands (activations,
+ * output gradients, weights) are BF16, accumulation FP32. */
+int gsbs_mlp_backward(gsbs_mlp* m, const float* x, const float* t, int32_t batch, float* loss);
+int gsbs_mlp_get_grads(gsbs_mlp* m, float* g, int64_t n);
+
+/* One Adam step (bias-corrected, step counter inside the network) on the FP32
+ * master weights with the last gradients, then the BF16 copies refresh. */
+int gsbs_mlp_adam(gsbs_mlp* m, float lr, float beta1, float beta2, float eps);
+
+/* gsbs_mlp_backward followed by gsbs_mlp_adam. */
+int gsbs_mlp_train_step(gsbs_mlp* m, const float* x, const float* t, int32_t batch, float lr, float beta1,
+                        float beta2, float eps, float* loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,11 +26,14 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+SOURCES = (("kernels.hip", True), ("mlp.hip", True), ("api.cpp", False), ("mlp_api.cpp", False))
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
-    for src, dev in (("kernels.hip", True), ("api.cpp", False)):
+    objs, procs = [], []
+    for src, dev in SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         cmd = [hipcc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
         if dev:
@@ -39,8 +42,11 @@ def build(verbose: bool = False) -> str:
             cmd += ["-D__HIP_PLATFORM_AMD__"]
         if verbose:
             print(" ".join(cmd))
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     subprocess.run(cmd, check=True)

@@ -32,6 +32,13 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
+}  // namespace
+
+// Error channel shared with the other ABI files (gsbs_last_error reads it).
+int gsbs::set_error(int code, const char* msg) { return fail(code, msg); }
+
+namespace {
+
 #define HIPCHK(x)                                                                              \
     do {                                                                                       \
         hipError_t e_ = (x);                                                                   \

@@ -130,6 +130,9 @@ constexpr int32_t kLdsBins = 12288;
 void launch_record(hipStream_t st, const long long* counts, long long* rec, int32_t max_rec,
                    const RecordList& list);
 
+// Sets the message gsbs_last_error returns and passes the code through.
+int set_error(int code, const char* msg);
+
 // debug flags of launch_step
 constexpr int32_t kStepLogAll = 2;
 constexpr int32_t kStepSearchOnly = 4;

@@ -1,0 +1,30 @@
+// mlp.h -- launch helpers of the surrogate perceptron kernels (mlp.hip), used by
+// the C ABI in mlp_api.cpp.  Internal: not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsbs {
+
+// Architecture: 296 inputs, four hidden layers of 256 (GELU), 7 outputs.
+constexpr int kMlpIn = 296;
+constexpr int kMlpHidden = 256;
+constexpr int kMlpOut = 7;
+constexpr int kMlpLayers = 5;
+
+void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
+                 int N, int K);
+void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp);
+void mlp_epilogue(hipStream_t st, const float* C, const float* bias, int B, int Mp, int Np, int n_valid, int hidden,
+                  float* Z, uint16_t* A, uint16_t* AT, float* Y);
+void mlp_loss(hipStream_t st, const float* Y, const float* T, int B, int n_out, int Mp, int Np, float* dZ,
+              uint16_t* dZb, uint16_t* dZT, float* loss);
+void mlp_act_grad(hipStream_t st, const float* dA, const float* Z, int B, int Mp, int Np, int n_valid, float* dZ,
+                  uint16_t* dZb, uint16_t* dZT);
+void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db);
+void mlp_adam(hipStream_t st, float* w, float* m1, float* m2, const float* grad, int64_t n, int rows, int cols,
+              float lr, float beta1, float beta2, float eps, float c1, float c2, uint16_t* wb, uint16_t* wbt);
+void mlp_cast(hipStream_t st, const float* w, int64_t n, int rows, int cols, uint16_t* wb, uint16_t* wbt);
+
+}  // namespace gsbs

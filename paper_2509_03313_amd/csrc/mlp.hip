@@ -1,0 +1,217 @@
+// mlp.hip -- gfx950 kernels of the inter-pulse surrogate: a 296-256-256-256-256-7
+// perceptron with erf-GELU hidden layers, BF16 weights and activations and FP32
+// accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), its backward pass
+// and an Adam update on FP32 master weights.
+//
+// Every matrix product has the form C[M x N] = A[M x K] * B[N x K]^T with both
+// operands K-contiguous in BF16 and M, N, K multiples of 16 (zero padded), so
+// one kernel serves the forward product (X W^T), the input gradient
+// (dZ (W^T)^T) and the weight gradient (dZ^T (X^T)^T): the producers also
+// write the transposed copies the products need.
+#include "mlp.h"
+
+namespace gsbs {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpBlock = 256;
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// GELU (erf form) and its derivative.  The normal CDF is taken as
+// erfc(-z/sqrt 2)/2, which keeps its relative accuracy in the lower tail where
+// 1 + erf(z/sqrt 2) would cancel in FP32.
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * erfcf(-z * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float cdf = 0.5f * erfcf(-z * 0.70710678118654752f);
+    const float pdf = 0.39894228040143268f * expf(-0.5f * z * z);
+    return cdf + z * pdf;
+}
+
+// C = A B^T: one wave per 16 x 16 tile of C, K in steps of 16.  Lane l feeds
+// row l%16 of the A tile and row l%16 of the B tile (k = 4*(l/16) .. +3) and
+// receives C[4*(l/16) + i][l%16], i = 0..3.
+__global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restrict__ A, int32_t lda,
+                                                     const uint16_t* __restrict__ B, int32_t ldb,
+                                                     float* __restrict__ C, int32_t ldc, int32_t M, int32_t N,
+                                                     int32_t K) {
+    const int tiles_n = N >> 4;
+    const int t = blockIdx.x * (kMlpBlock / 64) + (threadIdx.x >> 6);
+    if (t >= (M >> 4) * tiles_n) return;
+    const int tm = t / tiles_n, tn = t % tiles_n;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const uint16_t* pa = A + (size_t)(tm * 16 + r) * lda + 4 * g;
+    const uint16_t* pb = B + (size_t)(tn * 16 + r) * ldb + 4 * g;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + k0);
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(pb + k0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[(size_t)(tm * 16 + 4 * g + i) * ldc + tn * 16 + r] = acc[i];
+}
+
+// Input features (FP32, rows of n_in) -> BF16 activations X [Mp x Kp] and X^T
+// [Kp x Mp], zero padded.
+__global__ void k_mlp_input(const float* __restrict__ x, int32_t B, int32_t n_in, uint16_t* __restrict__ X,
+                            uint16_t* __restrict__ XT, int32_t Mp, int32_t Kp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Mp * Kp) return;
+    const int m = (int)(e / Kp), k = (int)(e % Kp);
+    const float v = (m < B && k < n_in) ? x[(size_t)m * n_in + k] : 0.0f;
+    const uint16_t h = to_bf16(v);
+    X[e] = h;
+    XT[(size_t)k * Mp + m] = h;
+}
+
+// Z = C + bias; hidden layers: A = BF16(GELU(Z)) and its transpose (rows >= B
+// and columns >= n_valid stay 0); output layer: Y = Z (FP32, B x n_valid).
+__global__ void k_mlp_epilogue(const float* __restrict__ C, const float* __restrict__ bias, int32_t B,
+                               int32_t Mp, int32_t Np, int32_t n_valid, int32_t hidden, float* __restrict__ Z,
+                               uint16_t* __restrict__ A, uint16_t* __restrict__ AT, float* __restrict__ Y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Mp * Np) return;
+    const int m = (int)(e / Np), n = (int)(e % Np);
+    const bool valid = m < B && n < n_valid;
+    const float z = valid ? C[e] + bias[n] : 0.0f;
+    if (hidden) {
+        Z[e] = z;
+        const uint16_t h = to_bf16(valid ? gelu(z) : 0.0f);
+        A[e] = h;
+        AT[(size_t)n * Mp + m] = h;
+    } else if (valid) {
+        Y[(size_t)m * n_valid + n] = z;
+    }
+}
+
+// Mean squared error over the B x n_out outputs and its gradient dY =
+// 2 (Y - T) / (B n_out) as BF16 (and transpose) for the products, FP32 for
+// the bias gradient.  loss accumulates the sum of squares (host divides).
+__global__ void k_mlp_loss(const float* __restrict__ Y, const float* __restrict__ T, int32_t B, int32_t n_out,
+                           int32_t Mp, int32_t Np, float* __restrict__ dZ, uint16_t* __restrict__ dZb,
+                           uint16_t* __restrict__ dZT, float* __restrict__ loss) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.0f;
+    if (e < (int64_t)Mp * Np) {
+        const int m = (int)(e / Np), n = (int)(e % Np);
+        float d = 0.0f;
+        if (m < B && n < n_out) {
+            const float r = Y[(size_t)m * n_out + n] - T[(size_t)m * n_out + n];
+            sq = r * r;
+            d = 2.0f * r / (float)(B * n_out);
+        }
+        dZ[e] = d;
+        const uint16_t h = to_bf16(d);
+        dZb[e] = h;
+        dZT[(size_t)n * Mp + m] = h;
+    }
+    for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0 && sq != 0.0f) atomicAdd(loss, sq);
+}
+
+// dZ = dA * GELU'(Z) on the valid part (FP32, BF16 and BF16 transpose).
+__global__ void k_mlp_act_grad(const float* __restrict__ dA, const float* __restrict__ Z, int32_t B, int32_t Mp,
+                               int32_t Np, int32_t n_valid, float* __restrict__ dZ, uint16_t* __restrict__ dZb,
+                               uint16_t* __restrict__ dZT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Mp * Np) return;
+    const int m = (int)(e / Np), n = (int)(e % Np);
+    const float d = (m < B && n < n_valid) ? dA[e] * gelu_grad(Z[e]) : 0.0f;
+    dZ[e] = d;
+    const uint16_t h = to_bf16(d);
+    dZb[e] = h;
+    dZT[(size_t)n * Mp + m] = h;
+}
+
+// Bias gradient: column sums of dZ over the batch (one thread per column).
+__global__ void k_mlp_colsum(const float* __restrict__ dZ, int32_t Mp, int32_t Np, float* __restrict__ db) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= Np) return;
+    float s = 0.0f;
+    for (int m = 0; m < Mp; ++m) s += dZ[(size_t)m * Np + n];
+    db[n] = s;
+}
+
+// Adam on one parameter block; the BF16 copy (and its transpose for weight
+// matrices, rows x cols = Np x Kp) is refreshed from the FP32 master.
+__global__ void k_mlp_adam(float* __restrict__ w, float* __restrict__ m1, float* __restrict__ m2,
+                           const float* __restrict__ grad, int64_t n, int32_t rows, int32_t cols, float lr,
+                           float beta1, float beta2, float eps, float c1, float c2, uint16_t* __restrict__ wb,
+                           uint16_t* __restrict__ wbt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gr = grad[e];
+    const float a = beta1 * m1[e] + (1.0f - beta1) * gr;
+    const float b = beta2 * m2[e] + (1.0f - beta2) * gr * gr;
+    m1[e] = a;
+    m2[e] = b;
+    const float mh = a / c1, vh = b / c2;
+    const float v = w[e] - lr * mh / (sqrtf(vh) + eps);
+    w[e] = v;
+    if (wb) {
+        const uint16_t h = to_bf16(v);
+        wb[e] = h;
+        const int r = (int)(e / cols), c = (int)(e % cols);
+        wbt[(size_t)c * rows + r] = h;
+    }
+}
+
+// Refresh BF16 weights (and transpose) from the FP32 master, keeping padding 0.
+__global__ void k_mlp_cast(const float* __restrict__ w, int64_t n, int32_t rows, int32_t cols,
+                           uint16_t* __restrict__ wb, uint16_t* __restrict__ wbt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint16_t h = to_bf16(w[e]);
+    wb[e] = h;
+    wbt[(size_t)(e % cols) * rows + e / cols] = h;
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kMlpBlock - 1) / kMlpBlock); }
+
+void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
+                 int N, int K) {
+    const int tiles = (M / 16) * (N / 16);
+    hipLaunchKernelGGL(k_gemm_nt, dim3((tiles + 3) / 4), dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+}
+void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp) {
+    hipLaunchKernelGGL(k_mlp_input, dim3(blocks_for((int64_t)Mp * Kp)), dim3(kMlpBlock), 0, st, x, B, n_in, X, XT,
+                       Mp, Kp);
+}
+void mlp_epilogue(hipStream_t st, const float* C, const float* bias, int B, int Mp, int Np, int n_valid, int hidden,
+                  float* Z, uint16_t* A, uint16_t* AT, float* Y) {
+    hipLaunchKernelGGL(k_mlp_epilogue, dim3(blocks_for((int64_t)Mp * Np)), dim3(kMlpBlock), 0, st, C, bias, B, Mp,
+                       Np, n_valid, hidden, Z, A, AT, Y);
+}
+void mlp_loss(hipStream_t st, const float* Y, const float* T, int B, int n_out, int Mp, int Np, float* dZ,
+              uint16_t* dZb, uint16_t* dZT, float* loss) {
+    hipLaunchKernelGGL(k_mlp_loss, dim3(blocks_for((int64_t)Mp * Np)), dim3(kMlpBlock), 0, st, Y, T, B, n_out, Mp,
+                       Np, dZ, dZb, dZT, loss);
+}
+void mlp_act_grad(hipStream_t st, const float* dA, const float* Z, int B, int Mp, int Np, int n_valid, float* dZ,
+                  uint16_t* dZb, uint16_t* dZT) {
+    hipLaunchKernelGGL(k_mlp_act_grad, dim3(blocks_for((int64_t)Mp * Np)), dim3(kMlpBlock), 0, st, dA, Z, B, Mp, Np,
+                       n_valid, dZ, dZb, dZT);
+}
+void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db) {
+    hipLaunchKernelGGL(k_mlp_colsum, dim3(blocks_for(Np)), dim3(kMlpBlock), 0, st, dZ, Mp, Np, db);
+}
+void mlp_adam(hipStream_t st, float* w, float* m1, float* m2, const float* grad, int64_t n, int rows, int cols,
+              float lr, float beta1, float beta2, float eps, float c1, float c2, uint16_t* wb, uint16_t* wbt) {
+    hipLaunchKernelGGL(k_mlp_adam, dim3(blocks_for(n)), dim3(kMlpBlock), 0, st, w, m1, m2, grad, n, rows, cols, lr,
+                       beta1, beta2, eps, c1, c2, wb, wbt);
+}
+void mlp_cast(hipStream_t st, const float* w, int64_t n, int rows, int cols, uint16_t* wb, uint16_t* wbt) {
+    hipLaunchKernelGGL(k_mlp_cast, dim3(blocks_for(n)), dim3(kMlpBlock), 0, st, w, n, rows, cols, wb, wbt);
+}
+
+}  // namespace gsbs

@@ -93,6 +93,17 @@ _SIGS = {
     "gsbs_debug_get_pairs": [_vp, _i64, _P(_u64), _P(C.c_float), _P(C.c_uint32), _P(_i32), _P(_i32),
                              _P(_i64)],
     "gsbs_debug_get_cells": [_vp, _i64, _P(_i32), _P(_u64), _P(_i32), _P(_i64)],
+    "gsbs_mlp_param_count": [_P(_i64)],
+    "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
+    "gsbs_mlp_destroy": [_vp],
+    "gsbs_mlp_set_weights": [_vp, _P(C.c_float), _i64],
+    "gsbs_mlp_get_weights": [_vp, _P(C.c_float), _i64],
+    "gsbs_mlp_forward": [_vp, _vp, _i32, _vp],
+    "gsbs_mlp_get_activation": [_vp, _i32, _i32, _P(C.c_float)],
+    "gsbs_mlp_backward": [_vp, _vp, _vp, _i32, _P(C.c_float)],
+    "gsbs_mlp_get_grads": [_vp, _P(C.c_float), _i64],
+    "gsbs_mlp_adam": [_vp, C.c_float, C.c_float, C.c_float, C.c_float],
+    "gsbs_mlp_train_step": [_vp, _vp, _vp, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _P(C.c_float)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -433,3 +444,80 @@ class Engine:
                 sp = torch.from_numpy(np.ascontiguousarray(sp, dtype=np.uint8)).cuda()
             self.inject(inst, inj.t, xyz, sp, inj.edep_ev)
         self.set_records(inst, wl.records)
+
+
+# ------------------------------------------------------------- surrogate MLP ---
+MLP_IN, MLP_OUT, MLP_HIDDEN = 296, 7, 256
+
+
+def mlp_param_count() -> int:
+    n = _i64()
+    _chk(_lib.gsbs_mlp_param_count(C.byref(n)))
+    return n.value
+
+
+class Mlp:
+    """The surrogate perceptron on the device (gsbs_mlp_*).  x / t / y are
+    device tensors (float32, contiguous, [batch][width])."""
+
+    def __init__(self, max_batch: int, stream=None):
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        h = _vp()
+        _chk(_lib.gsbs_mlp_create(int(max_batch), stream, C.byref(h)))
+        self.h = h
+        self.n = mlp_param_count()
+
+    def close(self):
+        if self.h:
+            _chk(_lib.gsbs_mlp_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.n
+        _chk(_lib.gsbs_mlp_set_weights(self.h, _ptr(w, C.c_float), self.n))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.n, dtype=np.float32)
+        _chk(_lib.gsbs_mlp_get_weights(self.h, _ptr(w, C.c_float), self.n))
+        return w
+
+    def get_grads(self) -> np.ndarray:
+        g = np.zeros(self.n, dtype=np.float32)
+        _chk(_lib.gsbs_mlp_get_grads(self.h, _ptr(g, C.c_float), self.n))
+        return g
+
+    def forward(self, x, y=None):
+        B = int(x.shape[0])
+        if y is None:
+            y = torch.empty((B, MLP_OUT), dtype=torch.float32, device=x.device)
+        _chk(_lib.gsbs_mlp_forward(self.h, C.c_void_p(x.data_ptr()), B, C.c_void_p(y.data_ptr())))
+        return y
+
+    def activation(self, layer: int, batch: int) -> np.ndarray:
+        width = MLP_IN if layer == 0 else MLP_HIDDEN
+        out = np.zeros((batch, width), dtype=np.float32)
+        _chk(_lib.gsbs_mlp_get_activation(self.h, int(layer), int(batch), _ptr(out, C.c_float)))
+        return out
+
+    def backward(self, x, t) -> float:
+        loss = C.c_float()
+        _chk(_lib.gsbs_mlp_backward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), int(x.shape[0]),
+                                    C.byref(loss)))
+        return loss.value
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _chk(_lib.gsbs_mlp_adam(self.h, lr, beta1, beta2, eps))
+
+    def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+        loss = C.c_float()
+        _chk(_lib.gsbs_mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), int(x.shape[0]),
+                                      lr, beta1, beta2, eps, C.byref(loss)))
+        return loss.value
