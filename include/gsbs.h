@@ -250,6 +250,38 @@ int gsbs_debug_get_pairs(gsbs_ctx* ctx, int64_t max_n, uint64_t* uid2, float* P,
 int gsbs_debug_get_cells(gsbs_ctx* ctx, int64_t max_n, int32_t* cell, uint64_t* uid, int32_t* nc,
                          int64_t* n);
 
+/* ---------------------------------------- surrogate state (features) --- */
+/* Input features of the surrogate for instance inst in its present state
+ * (7 species and 9 reactions required), 296 floats:
+ *   [0..7)    log10(C_s + c_floor_M), C_s the concentration in mol/L;
+ *   [7..295)  g_r(k), reaction r = 0..8, shell k = 0..31: the pair-correlation
+ *             function of the reactants (a, b) of reaction r, i.e. the count of
+ *             b molecules in shell k around reference a molecules divided by
+ *             its ideal-gas expectation n_ref (N_b - [a == b]) / L^3 V_k.
+ *             Shells are log-spaced, edges e_k = R_r (r_m / R_r)^(k/32),
+ *             r_m = min(L/2, r_max_nm), R_r the reaction radius; shell 0 also
+ *             holds r < R_r; distances are FP32 minimum-image (Eq. 2).  The
+ *             references are the molecules of species a with uid % m_a == 0,
+ *             m_a = ceil(N_a / n_ref_max) (1 when no reference or partner);
+ *   [295]     log10(dt_next_ns).
+ * Each feature f is returned as (f - mu[f]) / sd[f] (mu, sd: host arrays of
+ * 296, NULL for 0 and 1).  out is a device pointer when out_is_device = 1,
+ * else a host array.  Synchronises the context's stream. */
+int gsbs_features(gsbs_ctx* ctx, int32_t inst, double dt_next_ns, double r_max_nm, int32_t n_ref_max,
+                  double c_floor_M, const float* mu, const float* sd, float* out, int32_t out_is_device);
+
+/* Replace every molecule of instance inst by a homogeneous population and
+ * move the instance's clock to t_new_ns (>= its present time, before any of
+ * its queued injections): y[7] (device pointer when y_is_device, else host)
+ * holds normalised log10 concentrations, C_s = 10^(y_s sd_y[s] + mu_y[s]) -
+ * c_floor_M (mol/L, clipped at 0); the mean count C_s N_A L^3 is rounded
+ * down or up with the Philox uniform at counter (s, step, 0, 3); positions
+ * are uniform in the cube from the Philox words at counter (uid, step, 1, 3),
+ * key (seed, inst); uids continue the instance's counter.  Records strictly
+ * between the old and the new time are left unrecorded.  Synchronises. */
+int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y, int32_t y_is_device,
+                    const float* mu_y, const float* sd_y, double c_floor_M);
+
 /* ------------------------------------------- inter-pulse surrogate MLP --- */
 /* A perceptron that maps the state at the end of a pulse's SBS segment
  * (species concentrations, binned pair-correlation features, log of the time

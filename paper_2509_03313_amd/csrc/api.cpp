@@ -204,6 +204,16 @@ struct gsbs_ctx {
     };
     std::vector<StepLog> step_log;
     hipEvent_t prof_ev[2 * kStepKernels] = {};
+    // surrogate state buffers (allocated on first use)
+    int32_t sur_cap = 0;
+    int32_t* sur_ref_idx = nullptr;
+    int32_t* sur_ref_cnt = nullptr;
+    int32_t* sur_pair_ab = nullptr;
+    float* sur_edges2 = nullptr;
+    double* sur_shell = nullptr;
+    unsigned long long* sur_hist = nullptr;
+    float* sur_vec = nullptr;  // 3 x 296: mu, sd, and a staging row / network output
+    long long* sur_newc = nullptr;
     double prof_ms[kStepKernels] = {};
     int64_t prof_n[kStepKernels] = {};
     int64_t prof_work[kStepKernels] = {};
@@ -825,6 +835,14 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->ctr);
     dfree(c->rec);
     dfree(c->chem_d);
+    dfree(c->sur_ref_idx);
+    dfree(c->sur_ref_cnt);
+    dfree(c->sur_pair_ab);
+    dfree(c->sur_edges2);
+    dfree(c->sur_shell);
+    dfree(c->sur_hist);
+    dfree(c->sur_vec);
+    dfree(c->sur_newc);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->tune_ev)
@@ -1177,6 +1195,152 @@ int gsbs_get_current_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
     HIPCHK(hipStreamSynchronize(c->st));
     for (int s = 0; s < c->ns; ++s) out[s] = buf[s];
     return GSBS_OK;
+}
+
+// ------------------------------------------------------------ surrogate ---
+namespace {
+
+constexpr int kFeatures = 7 + 9 * kSurBins + 1;
+
+// Reference subsample, pair-correlation shell counts and shell volumes of
+// instance i (device), for the current state.
+int sur_pair_counts(gsbs_ctx* c, int i, double r_max, int n_ref_max, std::vector<long long>& cnt) {
+    InstHost& in = c->inst[i];
+    const int nr = (int)c->rx.size();
+    cnt.assign(kMaxSpecies, 0);
+    HIPCHK(hipMemcpyAsync(cnt.data(), c->counts + (size_t)i * kMaxSpecies, sizeof(long long) * kMaxSpecies,
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int cap = 2 * n_ref_max + 64;
+    if (cap > c->sur_cap) {
+        dfree(c->sur_ref_idx);
+        CHK(dalloc(&c->sur_ref_idx, (size_t)kMaxSpecies * cap));
+        c->sur_cap = cap;
+    }
+    if (!c->sur_ref_cnt) {
+        CHK(dalloc(&c->sur_ref_cnt, kMaxSpecies));
+        CHK(dalloc(&c->sur_pair_ab, 2 * kMaxReactions));
+        CHK(dalloc(&c->sur_edges2, (size_t)kMaxReactions * (kSurBins + 1)));
+        CHK(dalloc(&c->sur_shell, (size_t)kMaxReactions * kSurBins));
+        CHK(dalloc(&c->sur_hist, (size_t)kMaxReactions * kSurBins));
+        CHK(dalloc(&c->sur_vec, 3 * (size_t)kFeatures));
+        CHK(dalloc(&c->sur_newc, kMaxSpecies));
+    }
+    SurStrides st{};
+    for (int s = 0; s < kMaxSpecies; ++s)
+        st.s[s] = (int32_t)std::max<long long>(1, (cnt[s] + n_ref_max - 1) / std::max(n_ref_max, 1));
+    // log-spaced shells from R to r_max: e_k = R (r_max / R)^(k / 32)
+    std::vector<int32_t> ab(2 * nr);
+    std::vector<float> e2((size_t)nr * (kSurBins + 1));
+    std::vector<double> vol((size_t)nr * kSurBins);
+    const double rmax = std::min(0.5 * in.L, r_max);
+    for (int r = 0; r < nr; ++r) {
+        ab[2 * r] = c->rx[r].a;
+        ab[2 * r + 1] = c->rx[r].b;
+        const double R = std::min(c->R[r], 0.5 * rmax);
+        std::vector<double> e(kSurBins + 1);
+        for (int k = 0; k <= kSurBins; ++k) e[k] = R * std::pow(rmax / R, (double)k / kSurBins);
+        for (int k = 0; k <= kSurBins; ++k) e2[(size_t)r * (kSurBins + 1) + k] = (float)(e[k] * e[k]);
+        const double f = 4.0 / 3.0 * 3.14159265358979323846;
+        for (int k = 0; k < kSurBins; ++k)
+            vol[(size_t)r * kSurBins + k] = f * (k == 0 ? e[1] * e[1] * e[1] : e[k + 1] * e[k + 1] * e[k + 1] - e[k] * e[k] * e[k]);
+    }
+    HIPCHK(hipMemcpyAsync(c->sur_pair_ab, ab.data(), sizeof(int32_t) * ab.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->sur_edges2, e2.data(), sizeof(float) * e2.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->sur_shell, vol.data(), sizeof(double) * vol.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemsetAsync(c->sur_ref_cnt, 0, sizeof(int32_t) * kMaxSpecies, c->st));
+    HIPCHK(hipMemsetAsync(c->sur_hist, 0, sizeof(unsigned long long) * nr * kSurBins, c->st));
+    int64_t n_all = 0;
+    for (auto& q : c->inst) n_all += q.n_est;
+    launch_collect_refs(c->st, c->pos[c->cur], c->uid[c->cur], c->ctr, i, st, cap, c->sur_ref_idx, c->sur_ref_cnt,
+                        &c->ctr->err, grid_for(std::max<int64_t>(n_all, 1)));
+    launch_pair_corr(c->st, c->pos[c->cur], c->ctr, i, c->sur_ref_idx, c->sur_ref_cnt, cap, c->sur_pair_ab,
+                     c->sur_edges2, nr, (float)in.L, c->sur_hist, n_all);
+    HIPCHK(hipGetLastError());
+    return GSBS_OK;
+}
+
+}  // namespace
+
+int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, int32_t n_ref_max, double c_floor_M,
+                  const float* mu, const float* sd, float* out, int32_t out_is_device) {
+    if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    if (!c->chem_ready || c->ns != 7 || c->rx.size() != 9)
+        return fail(GSBS_ESTATE, "features are defined for 7 species and 9 reactions");
+    if (!(dt_next_ns > 0) || !(r_max_nm > 0) || n_ref_max < 1 || !(c_floor_M > 0))
+        return fail(GSBS_EINVAL, "bad feature parameters");
+    std::vector<long long> cnt;
+    CHK(sur_pair_counts(c, i, r_max_nm, n_ref_max, cnt));
+    int32_t rc[kMaxSpecies];
+    HIPCHK(hipMemcpyAsync(rc, c->sur_ref_cnt, sizeof(rc), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int s = 0; s < kMaxSpecies; ++s)
+        if (rc[s] > c->sur_cap) return fail(GSBS_ECAPACITY, "reference subsample above its capacity");
+    std::vector<float> ms(2 * kFeatures);
+    for (int f = 0; f < kFeatures; ++f) {
+        ms[f] = mu ? mu[f] : 0.0f;
+        ms[kFeatures + f] = sd ? sd[f] : 1.0f;
+    }
+    HIPCHK(hipMemcpyAsync(c->sur_vec, ms.data(), sizeof(float) * ms.size(), hipMemcpyHostToDevice, c->st));
+    float* dst = out_is_device ? out : c->sur_vec + 2 * kFeatures;
+    launch_features(c->st, c->counts, i, c->ns, c->sur_hist, c->sur_ref_cnt, c->sur_cap, c->sur_pair_ab, c->sur_shell,
+                    (int)c->rx.size(), c->inst[i].L, dt_next_ns, c_floor_M, c->sur_vec, c->sur_vec + kFeatures, dst);
+    HIPCHK(hipGetLastError());
+    if (!out_is_device) {
+        HIPCHK(hipMemcpyAsync(out, dst, sizeof(float) * kFeatures, hipMemcpyDeviceToHost, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    return check_device_errors(c);
+}
+
+int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_t y_is_device, const float* mu_y,
+                    const float* sd_y, double c_floor_M) {
+    if (!c || !y || !mu_y || !sd_y || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    InstHost& in = c->inst[i];
+    if (!(t_new >= in.t)) return fail(GSBS_ESTATE, "re-population before the instance's present time");
+    for (auto& p : in.pending)
+        if (p.t < t_new) return fail(GSBS_ESTATE, "an injection falls before the re-population time");
+    if (!(c_floor_M > 0)) return fail(GSBS_EINVAL, "bad concentration floor");
+    if (!c->sur_vec) {
+        std::vector<long long> tmp;
+        CHK(sur_pair_counts(c, i, 1.0, 1, tmp));  // allocates the buffers
+    }
+    // staging: mu_y, sd_y and y in the 3 rows of sur_vec
+    std::vector<float> ms(2 * kFeatures, 0.0f);
+    for (int s = 0; s < c->ns; ++s) {
+        ms[s] = mu_y[s];
+        ms[kFeatures + s] = sd_y[s];
+    }
+    HIPCHK(hipMemcpyAsync(c->sur_vec, ms.data(), sizeof(float) * ms.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->sur_vec + 2 * kFeatures, y, sizeof(float) * c->ns,
+                          y_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
+    const double vol_litre = in.L * in.L * in.L * 1e-24;
+    launch_repop_counts(c->st, c->sur_vec + 2 * kFeatures, c->sur_vec, c->sur_vec + kFeatures, c->ns, c_floor_M,
+                        vol_litre, c->seed, i, in.step, c->sur_newc);
+    std::vector<long long> nc(kMaxSpecies, 0);
+    HIPCHK(hipMemcpyAsync(nc.data(), c->sur_newc, sizeof(long long) * kMaxSpecies, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    int64_t total = 0;
+    for (int s = 0; s < c->ns; ++s) total += nc[s];
+    if (total > 0x3FFFFFFF) return fail(GSBS_ECAPACITY, "re-population count too large");
+    DevCounters h{};
+    CHK(read_counters(c, &h));
+    CHK(ensure_capacity(c, (int64_t)h.n_in + total + 1024));
+    int64_t n_all = 0;
+    for (auto& q : c->inst) n_all += q.n_est;
+    launch_repop(c->st, c->pos[c->cur], c->uid[c->cur], c->ctr, c->sur_newc, c->ns, (int)total, i, in.next_uid,
+                 c->seed, in.step, (float)in.L, c->cap, c->counts, grid_for(std::max<int64_t>(n_all + total, 1)));
+    HIPCHK(hipGetLastError());
+    in.next_uid += (uint64_t)total;
+    // records strictly between the old and the new time are not taken
+    for (size_t r = 0; r < in.rec_t.size(); ++r)
+        if (!in.rec_done[r] && in.rec_t[r] > in.t && in.rec_t[r] < t_new) in.rec_done[r] = 1;
+    in.t = t_new;
+    in.n_est = total;
+    for (int s = 0; s < kMaxSpecies; ++s) in.sp_est[s] = nc[s];
+    HIPCHK(hipStreamSynchronize(c->st));
+    return check_device_errors(c);
 }
 
 int gsbs_get_time(gsbs_ctx* c, int32_t i, double* t) {

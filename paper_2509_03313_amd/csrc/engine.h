@@ -133,6 +133,28 @@ void launch_record(hipStream_t st, const long long* counts, long long* rec, int3
 // Sets the message gsbs_last_error returns and passes the code through.
 int set_error(int code, const char* msg);
 
+// Surrogate state kernels (surrogate.hip): pair-correlation shells per reaction,
+// reference subsample stride per species, error flag of a reference overflow.
+constexpr int kSurBins = 32;
+constexpr uint32_t kErrRefOverflow = 8u;
+struct SurStrides {
+    int32_t s[kMaxSpecies];
+};
+void launch_collect_refs(hipStream_t st, const float4* pos, const uint64_t* uid, const DevCounters* ctr, int inst,
+                         const SurStrides& strides, int cap, int32_t* ref_idx, int32_t* ref_cnt, uint32_t* err,
+                         int grid);
+void launch_pair_corr(hipStream_t st, const float4* pos, const DevCounters* ctr, int inst, const int32_t* ref_idx,
+                      const int32_t* ref_cnt, int cap, const int32_t* pair_ab, const float* edges2, int n_pairs,
+                      float L, unsigned long long* hist, int64_t n_est);
+void launch_features(hipStream_t st, const long long* counts, int inst, int ns, const unsigned long long* hist,
+                     const int32_t* ref_cnt, int cap, const int32_t* pair_ab, const double* shell_vol, int n_pairs,
+                     double L, double dt_next, double c_floor, const float* mu, const float* sd, float* out);
+void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const float* sd, int ns, double c_floor,
+                         double vol_litre, uint64_t seed, int inst, uint64_t step, long long* out);
+void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,
+                  int n_new, int inst, uint64_t uid_base, uint64_t seed, uint64_t step, float L, int cap,
+                  long long* counts, int grid);
+
 // debug flags of launch_step
 constexpr int32_t kStepLogAll = 2;
 constexpr int32_t kStepSearchOnly = 4;

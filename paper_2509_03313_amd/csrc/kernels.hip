@@ -16,39 +16,12 @@
 // All molecules of all instances live in one array; the sort groups them by
 // instance (each instance owns a contiguous range of global cells).  Removed
 // molecules stay in the array, flagged, until the next sort drops them.
+#include "device_common.h"
 #include "engine.h"
 
 namespace gsbs {
 
 #define GSBS_BLOCK 256
-
-// --------------------------------------------------------------- Philox ---
-// Philox4x64-10 (Salmon et al., SC'11): multipliers 0xD2E7470EE14C6C93 and
-// 0xCA5A826395121157, Weyl increments 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B.
-__device__ __forceinline__ void philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                       uint64_t k0, uint64_t k1, uint64_t out[4]) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B97F4A7C15ull;
-            k1 += 0xBB67AE8584CAA73Bull;
-        }
-        const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c0;
-        const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
-        const uint64_t lo1 = 0xCA5A826395121157ull * c2;
-        const uint64_t hi1 = __umul64hi(0xCA5A826395121157ull, c2);
-        const uint64_t n0 = hi1 ^ c1 ^ k0;
-        const uint64_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-    }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
-}
 
 // ln(u) for u = (k + 1/2) 2^-24, k = top 24 bits of w.  Both branches feed an
 // exactly representable FP32 argument: 2k+1 < 2^24 below the midpoint, and
@@ -73,22 +46,6 @@ __device__ __forceinline__ void sincos_2pi_u24(uint64_t w, float* s, float* c) {
         *s = -ss;
         *c = cc;
     }
-}
-
-// PBC 1 (Eq. 1); a jump may exceed one edge, so whole edges are removed first.
-__device__ __forceinline__ float wrap_f(float x, float L, float hL, float invL) {
-    const float k = floorf(__fmul_rn(__fadd_rn(x, hL), invL));
-    x = __fsub_rn(x, __fmul_rn(k, L));
-    // selects of plain IEEE operations (no contraction is enabled) keep this branch-free
-    x = x >= hL ? x - L : x;
-    x = x < -hL ? x + L : x;
-    return x;
-}
-
-// PBC 2 (Eq. 2).
-__device__ __forceinline__ float minimg_f(float d, float L, float hL) {
-    const float lo = d - L, hi = d + L;
-    return d >= hL ? lo : (d < -hL ? hi : d);
 }
 
 // Position after this step's Brownian jump: Gaussian of variance 2 D dt per

@@ -93,6 +93,8 @@ _SIGS = {
     "gsbs_debug_get_pairs": [_vp, _i64, _P(_u64), _P(C.c_float), _P(C.c_uint32), _P(_i32), _P(_i32),
                              _P(_i64)],
     "gsbs_debug_get_cells": [_vp, _i64, _P(_i32), _P(_u64), _P(_i32), _P(_i64)],
+    "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
+    "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
     "gsbs_mlp_destroy": [_vp],
@@ -444,6 +446,45 @@ class Engine:
                 sp = torch.from_numpy(np.ascontiguousarray(sp, dtype=np.uint8)).cuda()
             self.inject(inst, inj.t, xyz, sp, inj.edep_ev)
         self.set_records(inst, wl.records)
+
+
+# ----------------------------------------------------------- surrogate state ---
+N_FEATURES = 296
+
+
+def _host_f32(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a
+
+
+def gsbs_features(ctx, inst, dt_next, r_max=200.0, n_ref_max=1024, c_floor=1e-10, mu=None, sd=None, out=None):
+    """Feature row of instance inst: a host numpy array, or written into the
+    device tensor `out` (float32, 296 contiguous values)."""
+    mu_h, sd_h = _host_f32(mu), _host_f32(sd)
+    mu_p = mu_h.ctypes.data_as(_vp) if mu_h is not None else None
+    sd_p = sd_h.ctypes.data_as(_vp) if sd_h is not None else None
+    if out is None:
+        host = np.zeros(N_FEATURES, dtype=np.float32)
+        _chk(_lib.gsbs_features(ctx, inst, dt_next, r_max, n_ref_max, c_floor, mu_p, sd_p,
+                                host.ctypes.data_as(_vp), 0))
+        return host
+    _chk(_lib.gsbs_features(ctx, inst, dt_next, r_max, n_ref_max, c_floor, mu_p, sd_p, C.c_void_p(out.data_ptr()), 1))
+    return out
+
+
+def gsbs_repopulate(ctx, inst, t_new, y, mu_y, sd_y, c_floor=1e-10):
+    """Homogeneous re-population from normalised log10 concentrations y (host
+    array of 7 or a device tensor)."""
+    mu_h, sd_h = _host_f32(mu_y), _host_f32(sd_y)
+    if hasattr(y, "data_ptr"):
+        yp, dev = C.c_void_p(y.data_ptr()), 1
+    else:
+        yh = _host_f32(y)
+        yp, dev = yh.ctypes.data_as(_vp), 0
+    _chk(_lib.gsbs_repopulate(ctx, inst, t_new, yp, dev, mu_h.ctypes.data_as(_vp), sd_h.ctypes.data_as(_vp),
+                              c_floor))
 
 
 # ------------------------------------------------------------- surrogate MLP ---

@@ -1,0 +1,108 @@
+"""Parity of the surrogate's state kernels (features, re-population) with the
+FP64 oracle, through the C ABI.
+
+  * features: the pair-correlation shell counts are integers decided in FP32
+    with Eq. 2's operation order on both sides, so the g values (FP64
+    normalisation on both sides) agree to 1e-9 relative; log10 concentrations
+    and log10 dt to 1e-12; normalisation (f - mu) / sd to FP32 rounding;
+  * re-population: counts equal the oracle's stochastic rounding (same Philox
+    counter); every new molecule lies in [-L/2, L/2)^3 with consecutive uids;
+    the old molecules of the instance are gone and the other instance of the
+    context is untouched; positions are uniform (KS test per axis).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from oracle import surrogate_oracle as S  # noqa: E402
+from paper_2509_03313_amd import workload as W  # noqa: E402
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the device"
+    from paper_2509_03313_amd import gsbs
+    return gsbs
+
+
+def state(seed, L, n):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    # half in tight clusters so that the short shells are populated
+    c = rng.uniform(-L / 2, L / 2, size=(n // 20, 3)).repeat(10, axis=0)
+    x[: len(c)] = c + rng.normal(0, 3.0, size=c.shape)
+    x = ((x + L / 2) % L - L / 2).astype(np.float32)
+    sp = rng.choice(7, size=n, p=[0.2, 0.25, 0.1, 0.2, 0.1, 0.1, 0.05]).astype(np.uint8)
+    uid = rng.permutation(np.arange(n, dtype=np.uint64) * 3 + 5)
+    return x, sp, uid
+
+
+@pytest.mark.parametrize("L,n,nref", [(400.0, 3000, 100), (1000.0, 5000, 2000)])
+def test_features_match_oracle(g, L, n, nref):
+    x, sp, uid = state(int(L) + n, L, n)
+    say("features", L, n, nref)
+    e = g.Engine(L, 5, W.D_CONFIG, W.REACTIONS)
+    g.gsbs_debug_set_state(e.ctx, x, sp, uid, step=2)
+    got = g.gsbs_features(e.ctx, 0, 1234.5, r_max=150.0, n_ref_max=nref).astype(np.float64)
+    ref = S.features(x, sp.astype(np.int64), uid, L, W.D_CONFIG, W.REACTIONS, 1234.5, r_max=150.0, n_ref_max=nref)
+    assert got.shape == (296,)
+    assert np.allclose(got[:7], ref[:7], rtol=0, atol=1e-5)
+    assert abs(got[-1] - ref[-1]) < 1e-6
+    gg, gr = got[7:-1], ref[7:-1]
+    bad = np.nonzero(~np.isclose(gg, gr, rtol=2e-7, atol=0))[0]
+    say("g features off", len(bad), "max g", gr.max())
+    assert len(bad) == 0, (bad[:5], gg[bad[:5]], gr[bad[:5]])
+    # normalisation
+    mu = np.linspace(-1, 1, 296).astype(np.float32)
+    sd = np.linspace(0.5, 2, 296).astype(np.float32)
+    gn = g.gsbs_features(e.ctx, 0, 1234.5, r_max=150.0, n_ref_max=nref, mu=mu, sd=sd).astype(np.float64)
+    assert np.allclose(gn, (ref - mu) / sd, rtol=1e-5, atol=1e-5)
+    e.close()
+
+
+def test_repopulate(g):
+    L = 500.0
+    say("repopulate")
+    e = g.Engine([L, L], 77, W.D_CONFIG, W.REACTIONS)
+    x, sp, uid = state(3, L, 2000)
+    e.inject(0, 0.0, x, sp)
+    e.inject(1, 0.0, x[:500], sp[:500])
+    e.advance_to([5.0, 5.0])
+    before1 = e.current_counts(1)
+    mu = np.full(7, -6.0, dtype=np.float32)
+    sd = np.full(7, 1.0, dtype=np.float32)
+    y = np.array([0.1, 0.5, -0.3, 0.2, 0.0, 0.9, -1.0], dtype=np.float32)
+    g.gsbs_repopulate(e.ctx, 0, 1e5, y, mu, sd)
+    got = e.current_counts(0)
+    assert np.array_equal(e.current_counts(1), before1)
+    xs, ss, us = g.gsbs_debug_get_state(e.ctx, 0)
+    assert np.all(us >= 2000)  # every old molecule is gone (uids continue the counter)
+    assert np.array_equal(np.bincount(ss, minlength=7)[:7], got)
+    assert np.all(xs >= -L / 2) and np.all(xs < L / 2)
+    assert len(np.unique(us)) == len(us)
+    # counts: the oracle's stochastic rounding with the same Philox counter
+    t0 = g.gsbs_get_time(e.ctx, 0)
+    assert t0 == 1e5
+    n_steps = e.stats()["steps"]
+    ref = S.repop_counts(y, mu, sd, L, 77, 0, n_steps)
+    say("counts", got.tolist(), ref.tolist())
+    assert np.array_equal(got, ref)
+    from scipy import stats
+    for a in range(3):
+        assert stats.kstest((xs[:, a] + L / 2) / L, "uniform").pvalue > 1e-4
+    # the instance keeps stepping from its new time
+    e.advance_to([1.5e5, 1.5e5])
+    assert g.gsbs_get_time(e.ctx, 0) == 1.5e5
+    e.close()

@@ -88,3 +88,34 @@ def test_zero_weights_give_last_bias():
     y, _, _ = M.forward(w, np.random.default_rng(0).normal(size=(3, 296)), emulate_bf16=True)
     assert np.array_equal(y, np.tile(b, (3, 1)))
     assert M.param_count() == 275207
+
+
+# ------------------------------------------------------ feature oracle pins ---
+def test_feature_pair_counts_ideal_gas_and_hand_cases():
+    """g(r) of uniform points is 1 within Poisson error; a pair at a known
+    separation lands in the shell floor(32 ln(r/R) / ln(r_m/R)); the
+    concentration of one molecule in 1 um^3 is 1/(N_A 1e-15 L)."""
+    from oracle import surrogate_oracle as S
+    rng = np.random.default_rng(0)
+    L = 400.0
+    n = 6000
+    xyz = rng.uniform(-L / 2, L / 2, size=(n, 3)).astype(np.float32)
+    sp = np.zeros(n, dtype=np.int64)
+    uid = np.arange(n, dtype=np.uint64)
+    _, e2, vol = S.shells(1.0, L, 150.0)
+    hist, nref = S.pair_counts(xyz, sp, uid, 0, 0, L, e2, 300)
+    assert 280 <= nref <= 320
+    expect = nref * ((n - 1) / L ** 3) * vol
+    z = (hist - expect) / np.sqrt(expect)
+    assert np.all(np.abs(z[expect > 50]) < 5) and abs(hist.sum() / expect.sum() - 1) < 0.02
+    # two molecules at a known separation
+    R, rm = 0.5, 100.0
+    e, e2, _ = S.shells(R, 1000.0, rm)
+    for r in (0.3, 0.7, 3.0, 42.0, 99.0):
+        xyz2 = np.array([[0, 0, 0], [r, 0, 0]], dtype=np.float32)
+        h2, _ = S.pair_counts(xyz2, np.array([0, 1]), np.array([0, 1], dtype=np.uint64), 0, 1, 1000.0, e2, 10)
+        k = max(0, int(math.floor(32 * math.log(r / R) / math.log(rm / R)))) if r >= R else 0
+        assert h2[k] == 1 and h2.sum() == 1, (r, k, np.nonzero(h2))
+    f = S.features(np.zeros((1, 3), dtype=np.float32), np.array([1]), np.array([0], dtype=np.uint64), 1000.0,
+                   [1.0] * 7, [], 10.0, c_floor=1e-30)
+    assert abs(10 ** f[1] - 1.0 / (6.02214076e23 * 1e-15)) < 1e-12 * 10 ** f[1] and abs(f[-1] - 1.0) < 1e-15
