@@ -264,8 +264,9 @@ int gsbs_debug_get_cells(gsbs_ctx* ctx, int64_t max_n, int32_t* cell, uint64_t* 
  *             references are the molecules of species a with uid % m_a == 0,
  *             m_a = ceil(N_a / n_ref_max) (1 when no reference or partner);
  *   [295]     log10(dt_next_ns).
- * Each feature f is returned as (f - mu[f]) / sd[f] (mu, sd: host arrays of
- * 296, NULL for 0 and 1).  out is a device pointer when out_is_device = 1,
+ * Each feature f is returned as (f - mu[f]) / sd[f] clamped to [-8, 8] (mu,
+ * sd: host arrays of 296); with both NULL the raw value, unclamped.  out is a
+ * device pointer when out_is_device = 1,
  * else a host array.  Synchronises the context's stream. */
 int gsbs_features(gsbs_ctx* ctx, int32_t inst, double dt_next_ns, double r_max_nm, int32_t n_ref_max,
                   double c_floor_M, const float* mu, const float* sd, float* out, int32_t out_is_device);
@@ -274,13 +275,15 @@ int gsbs_features(gsbs_ctx* ctx, int32_t inst, double dt_next_ns, double r_max_n
  * move the instance's clock to t_new_ns (>= its present time, before any of
  * its queued injections): y[7] (device pointer when y_is_device, else host)
  * holds normalised log10 concentrations, C_s = 10^(y_s sd_y[s] + mu_y[s]) -
- * c_floor_M (mol/L, clipped at 0); the mean count C_s N_A L^3 is rounded
+ * c_floor_M (mol/L, clipped at 0), or with relative = 1 their change from the
+ * present state, C_s = 10^(y_s sd_y[s] + mu_y[s] + log10(C_s,now + c_floor_M))
+ * - c_floor_M; the mean count C_s N_A L^3 is rounded
  * down or up with the Philox uniform at counter (s, step, 0, 3); positions
  * are uniform in the cube from the Philox words at counter (uid, step, 1, 3),
  * key (seed, inst); uids continue the instance's counter.  Records strictly
  * between the old and the new time are left unrecorded.  Synchronises. */
 int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y, int32_t y_is_device,
-                    const float* mu_y, const float* sd_y, double c_floor_M);
+                    const float* mu_y, const float* sd_y, double c_floor_M, int32_t relative);
 
 /* ------------------------------------------- inter-pulse surrogate MLP --- */
 /* A perceptron that maps the state at the end of a pulse's SBS segment

@@ -84,10 +84,14 @@ def features(xyz, species, uid, L, D, reactions, dt_next, r_max=200.0, n_ref_max
     return np.array(f)
 
 
-def repop_counts(y, mu, sd, L, seed, inst, step, c_floor=1e-10):
+def repop_counts(y, mu, sd, L, seed, inst, step, c_floor=1e-10, now=None):
+    """now: present counts when y is the change of log10(C + c_floor)."""
     out = []
     for s in range(len(y)):
-        conc = max(0.0, 10.0 ** (float(y[s]) * float(sd[s]) + float(mu[s])) - c_floor)
+        lc = float(y[s]) * float(sd[s]) + float(mu[s])
+        if now is not None:
+            lc += math.log10(float(now[s]) / (NA * L ** 3 * 1e-24) + c_floor)
+        conc = max(0.0, 10.0 ** lc - c_floor)
         mean = conc * NA * L ** 3 * 1e-24
         w = philox([s, step, 0, 3], [seed, inst])
         u = (float(int(w[0]) >> 11) + 0.5) * 2.0 ** -53

@@ -1284,7 +1284,8 @@ int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, in
     HIPCHK(hipMemcpyAsync(c->sur_vec, ms.data(), sizeof(float) * ms.size(), hipMemcpyHostToDevice, c->st));
     float* dst = out_is_device ? out : c->sur_vec + 2 * kFeatures;
     launch_features(c->st, c->counts, i, c->ns, c->sur_hist, c->sur_ref_cnt, c->sur_cap, c->sur_pair_ab, c->sur_shell,
-                    (int)c->rx.size(), c->inst[i].L, dt_next_ns, c_floor_M, c->sur_vec, c->sur_vec + kFeatures, dst);
+                    (int)c->rx.size(), c->inst[i].L, dt_next_ns, c_floor_M, c->sur_vec, c->sur_vec + kFeatures,
+                    (mu || sd) ? 1 : 0, dst);
     HIPCHK(hipGetLastError());
     if (!out_is_device) {
         HIPCHK(hipMemcpyAsync(out, dst, sizeof(float) * kFeatures, hipMemcpyDeviceToHost, c->st));
@@ -1294,7 +1295,7 @@ int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, in
 }
 
 int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_t y_is_device, const float* mu_y,
-                    const float* sd_y, double c_floor_M) {
+                    const float* sd_y, double c_floor_M, int32_t relative) {
     if (!c || !y || !mu_y || !sd_y || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");
     if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
     InstHost& in = c->inst[i];
@@ -1317,7 +1318,7 @@ int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_
                           y_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
     const double vol_litre = in.L * in.L * in.L * 1e-24;
     launch_repop_counts(c->st, c->sur_vec + 2 * kFeatures, c->sur_vec, c->sur_vec + kFeatures, c->ns, c_floor_M,
-                        vol_litre, c->seed, i, in.step, c->sur_newc);
+                        vol_litre, c->seed, i, in.step, relative ? 1 : 0, c->counts, c->sur_newc);
     std::vector<long long> nc(kMaxSpecies, 0);
     HIPCHK(hipMemcpyAsync(nc.data(), c->sur_newc, sizeof(long long) * kMaxSpecies, hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));

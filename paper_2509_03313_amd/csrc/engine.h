@@ -148,9 +148,11 @@ void launch_pair_corr(hipStream_t st, const float4* pos, const DevCounters* ctr,
                       float L, unsigned long long* hist, int64_t n_est);
 void launch_features(hipStream_t st, const long long* counts, int inst, int ns, const unsigned long long* hist,
                      const int32_t* ref_cnt, int cap, const int32_t* pair_ab, const double* shell_vol, int n_pairs,
-                     double L, double dt_next, double c_floor, const float* mu, const float* sd, float* out);
+                     double L, double dt_next, double c_floor, const float* mu, const float* sd, int clamp,
+                     float* out);
 void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const float* sd, int ns, double c_floor,
-                         double vol_litre, uint64_t seed, int inst, uint64_t step, long long* out);
+                         double vol_litre, uint64_t seed, int inst, uint64_t step, int relative,
+                         const long long* counts, long long* out);
 void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,
                   int n_new, int inst, uint64_t uid_base, uint64_t seed, uint64_t step, float L, int cap,
                   long long* counts, int grid);

@@ -9,6 +9,7 @@ namespace gsbs {
 
 constexpr int kSurBlock = 256;
 constexpr int kPcTile = 1024;  // molecules staged per LDS tile in the pair-correlation kernel
+constexpr double kFeatureClamp = 8.0;  // |normalised feature| limit
 
 // Reference molecules of each species: live molecules of instance `inst` with
 // uid % stride[s] == 0 (a subsample that depends on the state only), at most
@@ -93,14 +94,14 @@ __global__ __launch_bounds__(kSurBlock) void k_pair_corr(const float4* __restric
 }
 
 // The 296 features of the perceptron for one instance, normalised as
-// (f - mu) / sd: log10(C_s + c_floor) of the 7 species (C in mol/L), the
+// (f - mu) / sd (clamped to +-8 when clamp is set): log10(C_s + c_floor) of the 7 species (C in mol/L), the
 // pair correlations g_p(k) = hist / (n_ref rho_b V_k) of the 9 reactions x 32
 // shells (1 where a pair has no reference or no partner), log10(dt_next / ns).
 __global__ void k_features(const long long* __restrict__ counts, int32_t inst, int32_t ns,
                            const unsigned long long* __restrict__ hist, const int32_t* __restrict__ ref_cnt,
                            int32_t cap, const int32_t* __restrict__ pair_ab, const double* __restrict__ shell_vol,
                            int32_t n_pairs, double L, double dt_next, double c_floor, const float* __restrict__ mu,
-                           const float* __restrict__ sd, float* __restrict__ out) {
+                           const float* __restrict__ sd, int32_t clamp, float* __restrict__ out) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     const int nf = ns + n_pairs * kSurBins + 1;
     if (f >= nf) return;
@@ -119,18 +120,25 @@ __global__ void k_features(const long long* __restrict__ counts, int32_t inst, i
     } else {
         v = log10(dt_next);
     }
-    out[f] = (float)((v - (double)mu[f]) / (double)sd[f]);
+    // normalised, and clamped so that a feature far outside the training range
+    // cannot drive the network into extrapolation without bound
+    const double z = (v - (double)mu[f]) / (double)sd[f];
+    out[f] = (float)(clamp ? fmin(kFeatureClamp, fmax(-kFeatureClamp, z)) : z);
 }
 
 // Counts of the re-populated instance: the network output y (normalised
-// log10 concentrations) back to mol/L, to a mean count in the cube, rounded
-// stochastically with the Philox word at counter (species, step, 0, 3).
+// log10 concentrations, or their change from the present state) back to
+// mol/L, to a mean count in the cube, rounded stochastically with the Philox
+// word at counter (species, step, 0, 3).
 __global__ void k_repop_counts(const float* __restrict__ y, const float* __restrict__ mu,
                                const float* __restrict__ sd, int32_t ns, double c_floor, double vol_litre,
-                               uint64_t seed, int32_t inst, uint64_t step, long long* __restrict__ out) {
+                               uint64_t seed, int32_t inst, uint64_t step, int32_t relative,
+                               const long long* __restrict__ counts, long long* __restrict__ out) {
     const int s = threadIdx.x;
     if (s >= ns) return;
-    const double lc = (double)y[s] * (double)sd[s] + (double)mu[s];
+    double lc = (double)y[s] * (double)sd[s] + (double)mu[s];
+    // relative: y encodes the change of log10(C + c_floor) from the present state
+    if (relative) lc += log10((double)counts[inst * kMaxSpecies + s] / (6.02214076e23 * vol_litre) + c_floor);
     const double conc = fmax(0.0, pow(10.0, lc) - c_floor);
     const double mean = conc * 6.02214076e23 * vol_litre;
     uint64_t w[4];
@@ -203,15 +211,17 @@ void launch_pair_corr(hipStream_t st, const float4* pos, const DevCounters* ctr,
 }
 void launch_features(hipStream_t st, const long long* counts, int inst, int ns, const unsigned long long* hist,
                      const int32_t* ref_cnt, int cap, const int32_t* pair_ab, const double* shell_vol, int n_pairs,
-                     double L, double dt_next, double c_floor, const float* mu, const float* sd, float* out) {
+                     double L, double dt_next, double c_floor, const float* mu, const float* sd, int clamp,
+                     float* out) {
     const int nf = ns + n_pairs * kSurBins + 1;
     hipLaunchKernelGGL(k_features, dim3((nf + kSurBlock - 1) / kSurBlock), dim3(kSurBlock), 0, st, counts, inst, ns,
-                       hist, ref_cnt, cap, pair_ab, shell_vol, n_pairs, L, dt_next, c_floor, mu, sd, out);
+                       hist, ref_cnt, cap, pair_ab, shell_vol, n_pairs, L, dt_next, c_floor, mu, sd, clamp, out);
 }
 void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const float* sd, int ns, double c_floor,
-                         double vol_litre, uint64_t seed, int inst, uint64_t step, long long* out) {
+                         double vol_litre, uint64_t seed, int inst, uint64_t step, int relative,
+                         const long long* counts, long long* out) {
     hipLaunchKernelGGL(k_repop_counts, dim3(1), dim3(kMaxSpecies), 0, st, y, mu, sd, ns, c_floor, vol_litre, seed,
-                       inst, step, out);
+                       inst, step, relative, counts, out);
 }
 __global__ void k_sur_add_n(DevCounters* ctr, int32_t n, int32_t cap) {
     const int v = ctr->n_in + n;

@@ -94,7 +94,7 @@ _SIGS = {
                              _P(_i64)],
     "gsbs_debug_get_cells": [_vp, _i64, _P(_i32), _P(_u64), _P(_i32), _P(_i64)],
     "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
-    "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d],
+    "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
     "gsbs_mlp_destroy": [_vp],
@@ -474,9 +474,9 @@ def gsbs_features(ctx, inst, dt_next, r_max=200.0, n_ref_max=1024, c_floor=1e-10
     return out
 
 
-def gsbs_repopulate(ctx, inst, t_new, y, mu_y, sd_y, c_floor=1e-10):
+def gsbs_repopulate(ctx, inst, t_new, y, mu_y, sd_y, c_floor=1e-10, relative=False):
     """Homogeneous re-population from normalised log10 concentrations y (host
-    array of 7 or a device tensor)."""
+    array of 7 or a device tensor), or their change from the present state."""
     mu_h, sd_h = _host_f32(mu_y), _host_f32(sd_y)
     if hasattr(y, "data_ptr"):
         yp, dev = C.c_void_p(y.data_ptr()), 1
@@ -484,7 +484,7 @@ def gsbs_repopulate(ctx, inst, t_new, y, mu_y, sd_y, c_floor=1e-10):
         yh = _host_f32(y)
         yp, dev = yh.ctypes.data_as(_vp), 0
     _chk(_lib.gsbs_repopulate(ctx, inst, t_new, yp, dev, mu_h.ctypes.data_as(_vp), sd_h.ctypes.data_as(_vp),
-                              c_floor))
+                              c_floor, 1 if relative else 0))
 
 
 # ------------------------------------------------------------- surrogate MLP ---

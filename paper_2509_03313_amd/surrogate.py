@@ -1,0 +1,304 @@
+"""Inter-pulse surrogate of the multi-pulse SBS run.
+
+Between pulses the chemistry relaxes towards a homogeneous mixture; the paper
+integrates that stretch with rate equations (its Eq. 3-4).  Here a perceptron
+(device kernels behind gsbs_mlp_*) maps the state a settle time after a
+pulse's last batch -- species concentrations, pair-correlation features of
+the 9 reactions and the time to the next pulse (gsbs_features) -- to the
+change of the log concentrations at the next pulse; the instance is then
+re-populated homogeneously at those counts (gsbs_repopulate) and the next
+pulse is injected into it.  Plain SBS is the fallback whenever a held-out
+error table says the network's G(H2O2) error could exceed 1 %, and it is the
+judge of that error.
+
+This module drives the library: it builds pulse plans from the synthetic track
+generator, runs the engine to make training samples (features at the switch
+time, log concentrations at the next pulse), trains the network with the
+device kernels, fills the error table, and runs the hybrid or the plain
+multi-pulse schedule.  All arithmetic of the step, the features, the network
+and the re-population runs in the library's kernels; this file only prepares
+inputs, normalisation constants and bookkeeping.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import gsbs
+from . import workload as W
+
+NA = 6.02214076e23
+C_FLOOR = 1e-10       # mol/L added to a concentration before its logarithm
+R_MAX = 200.0         # nm, outer edge of the pair-correlation shells
+N_REF = 1024          # references per species for the pair correlations
+TAU_SETTLE = 1000.0   # ns after a pulse's last batch before the network takes over
+H2O2 = W.H2O2
+
+
+@dataclasses.dataclass
+class PulsePlan:
+    """Pulsed irradiation of one cube (rectangular pulses, batches as in the
+    workload generator)."""
+    L: float
+    seed: int
+    n_pulses: int
+    dose: float            # Gy per pulse
+    pulse_rate: float      # Gy/s during a pulse
+    avg_rate: float        # Gy/s averaged over the run
+    n_batches: int = 2
+
+    @property
+    def width(self) -> float:  # ns
+        return self.dose / self.pulse_rate * 1e9
+
+    @property
+    def period(self) -> float:  # ns
+        return self.dose / self.avg_rate * 1e9
+
+    def start(self, p: int) -> float:
+        return p * self.period
+
+    def switch(self, p: int) -> float:
+        return self.start(p) + self.width + TAU_SETTLE
+
+    def injections(self) -> List[W.Injection]:
+        rng = np.random.default_rng([self.seed, 7])
+        n_tr = int(round(W.tracks_per_gray(self.L) * self.dose))
+        out = []
+        for p in range(self.n_pulses):
+            arrive = rng.uniform(0.0, self.width, size=n_tr)
+            batch = np.minimum((arrive / self.width * self.n_batches).astype(int), self.n_batches - 1)
+            for b in range(self.n_batches):
+                k = int(np.sum(batch == b))
+                if k == 0:
+                    continue
+                pos, sp = W.tracks_z(rng, self.L, k)
+                out.append(W.Injection(self.start(p) + b * self.width / self.n_batches, W._into_box(pos, self.L), sp,
+                                       k * self.L * W.LET_KEV_PER_UM))
+        return out
+
+    def edep_until(self, t: float, inj: List[W.Injection]) -> float:
+        return float(sum(i.edep_ev for i in inj if i.t <= t))
+
+
+def log_conc(counts, L) -> np.ndarray:
+    return np.log10(np.asarray(counts, dtype=np.float64) / (NA * L ** 3 * 1e-24) + C_FLOOR)
+
+
+def _engine(Ls, seed, capacity=0):
+    p = gsbs.gsbs_default_params()
+    p.autotune = 1
+    return gsbs.Engine(Ls, seed, W.D_CONFIG, W.REACTIONS, params=p, capacity=capacity)
+
+
+# ------------------------------------------------------------- training data ---
+def generate(plans: List[PulsePlan], seed: int, log=None) -> dict:
+    """Run every plan with plain SBS as one batched context (one instance per
+    plan) and collect, for every pulse but the last, the raw features at the
+    switch time and the log concentrations there and at the next pulse."""
+    n = len(plans)
+    e = _engine([pl.L for pl in plans], seed)
+    inj = [pl.injections() for pl in plans]
+    for i, pl in enumerate(plans):
+        for j in inj[i]:
+            e.inject(i, j.t, j.xyz, j.species, j.edep_ev)
+    events = []
+    for i, pl in enumerate(plans):
+        ev = []
+        for p in range(pl.n_pulses - 1):
+            ev.append((pl.switch(p), "switch", p))
+            ev.append((pl.start(p + 1), "next", p))
+        events.append(ev)
+    pos = [0] * n
+    X, Y0, Y1, meta = [], [], [], []
+    pending = {}
+    t0 = time.perf_counter()
+    while any(pos[i] < len(events[i]) for i in range(n)):
+        tgt = [events[i][pos[i]][0] if pos[i] < len(events[i]) else e.time(i) for i in range(n)]
+        e.advance_to(tgt)
+        for i in range(n):
+            if pos[i] >= len(events[i]):
+                continue
+            t, kind, p = events[i][pos[i]]
+            pl = plans[i]
+            if kind == "switch":
+                x = gsbs.gsbs_features(e.ctx, i, pl.start(p + 1) - t, R_MAX, N_REF, C_FLOOR)
+                pending[i] = (x, log_conc(e.current_counts(i), pl.L), pl.start(p + 1) - t)
+            else:
+                x, y0, dt = pending.pop(i)
+                X.append(x)
+                Y0.append(y0)
+                Y1.append(log_conc(e.current_counts(i), pl.L))
+                meta.append((math.log10(dt), math.log10(pl.avg_rate), float(np.sum(10.0 ** y0))))
+            pos[i] += 1
+        if log:
+            log(f"generate: {sum(pos)}/{sum(len(v) for v in events)} events, {time.perf_counter() - t0:.1f} s")
+    e.close()
+    return dict(X=np.array(X, dtype=np.float32), Y0=np.array(Y0), Y1=np.array(Y1), meta=np.array(meta))
+
+
+def random_plans(seed: int, n: int, L: float = 2000.0, n_pulses: int = 6, rates=(300.0, 1e4),
+                 doses=(0.5, 1.5)) -> List[PulsePlan]:
+    rng = np.random.default_rng([seed, 11])
+    out = []
+    for k in range(n):
+        rate = float(10 ** rng.uniform(math.log10(rates[0]), math.log10(rates[1])))
+        dose = float(rng.uniform(*doses))
+        out.append(PulsePlan(L, seed * 100003 + k, n_pulses, dose, 1e6, rate))
+    return out
+
+
+# ------------------------------------------------------------------ network ---
+class Surrogate:
+    """Network weights, normalisation constants and the held-out error table."""
+
+    def __init__(self, max_batch: int = 4096):
+        self.net = gsbs.Mlp(max_batch)
+        self.max_batch = max_batch
+        self.mu = self.sd = self.mu_y = self.sd_y = None
+        self.lo = self.hi = None
+        self.table = None       # 95th percentile of |dN_H2O2| / N_H2O2 per (log dt, log C_tot) bin
+        self.dt_edges = self.c_edges = None
+
+    def init_weights(self, seed: int):
+        """He-uniform weights, zero biases (seeded)."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        sizes = [gsbs.MLP_IN] + [gsbs.MLP_HIDDEN] * 4 + [gsbs.MLP_OUT]
+        for l in range(5):
+            k, n = sizes[l], sizes[l + 1]
+            lim = math.sqrt(6.0 / k) * (0.1 if l == 4 else 1.0)
+            parts += [rng.uniform(-lim, lim, size=n * k), np.zeros(n)]
+        self.net.set_weights(np.concatenate(parts).astype(np.float32))
+
+    def fit(self, data: dict, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed: int = 0, log=None):
+        import torch
+        X, Y = data["X"].astype(np.float64), (data["Y1"] - data["Y0"])
+        self.mu = X.mean(axis=0).astype(np.float32)
+        # features that barely vary in the training set are only centred, not
+        # stretched: a small change elsewhere must not become a large input
+        sd = X.std(axis=0)
+        self.sd = np.where(sd < 1e-2 * (1.0 + np.abs(self.mu)), 1.0 + np.abs(self.mu), sd).astype(np.float32)
+        self.mu_y = Y.mean(axis=0).astype(np.float32)
+        self.sd_y = np.maximum(Y.std(axis=0), 1e-4).astype(np.float32)
+        Xn = np.clip((X - self.mu) / self.sd, -8.0, 8.0).astype(np.float32)
+        Yn = ((Y - self.mu_y) / self.sd_y).astype(np.float32)
+        self.lo, self.hi = Xn.min(axis=0), Xn.max(axis=0)
+        xd = torch.from_numpy(Xn).cuda()
+        yd = torch.from_numpy(Yn).cuda()
+        n = len(Xn)
+        rng = np.random.default_rng(seed)
+        hist = []
+        steps = 0
+        total = epochs * max(1, n // batch)
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(n)).cuda()
+            ls = []
+            for b0 in range(0, n - batch + 1 if n >= batch else 1, batch):
+                idx = perm[b0:b0 + batch]
+                rate = lr * 0.5 * (1.0 + math.cos(math.pi * steps / total))
+                ls.append(self.net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), rate))
+                steps += 1
+            hist.append(float(np.mean(ls)))
+            if log and (ep % 20 == 0 or ep == epochs - 1):
+                log(f"epoch {ep}: loss {hist[-1]:.5f}")
+        return hist
+
+    def predict_log(self, X_raw: np.ndarray, Y0: np.ndarray) -> np.ndarray:
+        """Predicted log10 concentrations at the next pulse (for evaluation)."""
+        import torch
+        Xn = np.clip((X_raw.astype(np.float64) - self.mu) / self.sd, -8.0, 8.0).astype(np.float32)
+        yn = self.net.forward(torch.from_numpy(Xn).cuda()).cpu().numpy().astype(np.float64)
+        return Y0 + yn * self.sd_y + self.mu_y
+
+    def build_table(self, data: dict, n_dt: int = 4, n_c: int = 3):
+        """95th percentile of the relative H2O2 error per (log dt, log C_tot) bin
+        on held-out samples; empty bins get infinity (always plain SBS)."""
+        pred = self.predict_log(data["X"], data["Y0"])
+        n_true = 10.0 ** data["Y1"][:, H2O2]
+        n_pred = 10.0 ** pred[:, H2O2]
+        err = np.abs(n_pred - n_true) / np.maximum(n_true, 1e-30)
+        ldt, lc = data["meta"][:, 0], np.log10(data["meta"][:, 2])
+        self.dt_edges = np.quantile(ldt, np.linspace(0, 1, n_dt + 1))
+        self.c_edges = np.quantile(lc, np.linspace(0, 1, n_c + 1))
+        self.table = np.full((n_dt, n_c), np.inf)
+        i = np.clip(np.searchsorted(self.dt_edges, ldt, side="right") - 1, 0, n_dt - 1)
+        j = np.clip(np.searchsorted(self.c_edges, lc, side="right") - 1, 0, n_c - 1)
+        for a in range(n_dt):
+            for b in range(n_c):
+                m = (i == a) & (j == b)
+                if m.sum() >= 5:
+                    self.table[a, b] = float(np.quantile(err[m], 0.95))
+        return err
+
+    def usable(self, log_dt: float, c_tot: float, x_norm: np.ndarray, tol: float = 0.01) -> bool:
+        if self.table is None:
+            return False
+        if log_dt < self.dt_edges[0] or log_dt > self.dt_edges[-1]:
+            return False
+        lc = math.log10(c_tot)
+        if lc < self.c_edges[0] or lc > self.c_edges[-1]:
+            return False
+        span = self.hi - self.lo
+        if np.any(x_norm < self.lo - 0.1 * span - 1e-3) or np.any(x_norm > self.hi + 0.1 * span + 1e-3):
+            return False
+        a = int(np.clip(np.searchsorted(self.dt_edges, log_dt, side="right") - 1, 0, len(self.dt_edges) - 2))
+        b = int(np.clip(np.searchsorted(self.c_edges, lc, side="right") - 1, 0, len(self.c_edges) - 2))
+        return bool(self.table[a, b] <= tol)
+
+    def save(self, path: str):
+        np.savez(path, w=self.net.get_weights(), mu=self.mu, sd=self.sd, mu_y=self.mu_y, sd_y=self.sd_y, lo=self.lo,
+                 hi=self.hi, table=self.table, dt_edges=self.dt_edges, c_edges=self.c_edges)
+
+    def load(self, path: str):
+        z = np.load(path)
+        self.net.set_weights(z["w"])
+        for k in ("mu", "sd", "mu_y", "sd_y", "lo", "hi", "table", "dt_edges", "c_edges"):
+            setattr(self, k, z[k])
+
+
+# ------------------------------------------------------------ multi-pulse run ---
+def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01) -> dict:
+    """Plain (surrogate None) or hybrid multi-pulse run of one cube.  Returns
+    the H2O2 count and G(H2O2) at every pulse start after the first and at the
+    end, the wall time and the number of intervals the network took."""
+    import torch
+    inj = plan.injections()
+    e = _engine(plan.L, seed)
+    for j in inj:
+        e.inject(0, j.t, j.xyz, j.species, j.edep_ev)
+    times, n_h2o2, g_h2o2, used = [], [], [], []
+    row = torch.empty((1, gsbs.N_FEATURES), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in range(plan.n_pulses):
+        t_next = plan.start(p + 1)
+        took = False
+        if surrogate is not None and p + 1 < plan.n_pulses:
+            ts = plan.switch(p)
+            e.advance_to(ts)
+            gsbs.gsbs_features(e.ctx, 0, t_next - ts, R_MAX, N_REF, C_FLOOR, surrogate.mu, surrogate.sd, out=row[0])
+            c_tot = float(np.sum(e.current_counts(0))) / (NA * plan.L ** 3 * 1e-24)
+            x_norm = row[0].cpu().numpy()
+            if surrogate.usable(math.log10(t_next - ts), c_tot, x_norm, tol):
+                y = surrogate.net.forward(row)
+                gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_y, surrogate.sd_y, C_FLOOR, relative=True)
+                took = True
+        if not took:
+            e.advance_to(t_next)
+        used.append(took)
+        cnt = e.current_counts(0)
+        ed = plan.edep_until(t_next - 1e-9, inj)
+        times.append(t_next)
+        n_h2o2.append(int(cnt[H2O2]))
+        g_h2o2.append(cnt[H2O2] / (ed / 100.0))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = e.stats()
+    e.close()
+    return dict(t=np.array(times), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
+                intervals_by_network=int(sum(used)), steps=st["steps"], molecule_steps=st["molecule_steps"])
