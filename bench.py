@@ -55,7 +55,109 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM counters")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
+    ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
+    ap.add_argument("--sur-train-L", type=float, default=2000.0, help="cube edge (nm) of the training runs")
+    ap.add_argument("--sur-plans", type=int, default=256, help="training runs (12 pulses each)")
+    ap.add_argument("--sur-held", type=int, default=16, help="held-out runs (12 pulses each) for the error table")
+    ap.add_argument("--sur-rates", type=str, default="1000,100", help="average dose rates (Gy/s) of the 20-pulse runs")
+    ap.add_argument("--sur-save", type=str, default="", help="path prefix to save the model, held-out set and runs")
     return ap.parse_args()
+
+
+def surrogate_bench(args):
+    """Train the inter-pulse network on SBS runs of the engine itself, then run
+    20 pulses of 1 Gy with and without it on the same pulses and seeds."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import surrogate as SU
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    rates, doses = (80.0, 3000.0), (0.7, 1.3)
+    plans = SU.random_plans(args.seed + 1, args.sur_plans, L=args.sur_train_L, n_pulses=12, rates=rates, doses=doses)
+    train = {}
+    for b0 in range(0, len(plans), 64):
+        d = SU.generate(plans[b0:b0 + 64], seed=1000 + b0)
+        for k, v in d.items():
+            train[k] = np.concatenate([train[k], v]) if k in train else v
+        note(f"training samples {len(train['X'])} after {time.perf_counter() - t0:.1f} s")
+    # held-out runs in the large cube: its count noise (~0.5 % of the H2O2 made per pulse)
+    # is small enough for the 1 % table to mean something
+    held_plans = SU.random_plans(args.seed + 2, args.sur_held, L=args.sur_L, n_pulses=12, rates=rates, doses=doses)
+    held = {}
+    for b0 in range(0, len(held_plans), 8):
+        d = SU.generate(held_plans[b0:b0 + 8], seed=2000 + b0, log=note)
+        for k, v in d.items():
+            held[k] = np.concatenate([held[k], v]) if k in held else v
+    note(f"held-out samples {len(held['X'])} after {time.perf_counter() - t0:.1f} s")
+    t_gen = time.perf_counter() - t0
+    n, n_held = len(train["X"]), len(held["X"])
+    # two candidates, with and without the pair-correlation inputs; one half of the
+    # held-out samples picks the candidate, the other half fills its error table
+    hperm = np.random.default_rng(args.seed + 3).permutation(n_held)
+    sub = lambda d, k: {key: v[k] for key, v in d.items()}  # noqa: E731
+    pick, tab = sub(held, hperm[: n_held // 2]), sub(held, hperm[n_held // 2:])
+    t1 = time.perf_counter()
+    cands = {}
+    for gw in (1.0, 0.0):
+        c = SU.Surrogate(1024)
+        c.init_weights(args.seed)
+        hist = c.fit(train, epochs=60, batch=64, lr=5e-4, log=note, g_weight=gw)
+        e = c.build_table(pick, n_dt=2, n_c=2)
+        cands[gw] = (float(np.quantile(e, 0.95)), float(np.median(e)), c, hist)
+        note(f"pair-correlation weight {gw:g}: held-out relative H2O2 error median {np.median(e):.4f}, "
+             f"p95 {np.quantile(e, 0.95):.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    gw_best = min(cands, key=lambda k: cands[k][0])
+    s, hist = cands[gw_best][2], cands[gw_best][3]
+    err = s.build_table(tab, n_dt=2, n_c=2)
+    if args.sur_save:
+        s.save(args.sur_save + "_model.npz")
+        np.savez(args.sur_save + "_held.npz", **held)
+    note(f"chosen weight {gw_best:g}; table half: median {np.median(err):.4f}, p95 {np.quantile(err, 0.95):.4f}; "
+         f"table {np.round(s.table, 4).tolist()} over log10 dt edges {np.round(s.dt_edges, 2).tolist()}, "
+         f"log10 C_tot edges {np.round(s.c_edges, 2).tolist()}")
+    runs = []
+    for rate in [float(r) for r in args.sur_rates.split(",")]:
+        plan = SU.PulsePlan(args.sur_L, args.seed + 77, 20, 1.0, 1e6, rate)
+        SU.run(SU.PulsePlan(args.sur_L, 5, 2, 1.0, 1e6, rate), None)  # warm the grid tuner
+        plain = SU.run(plan, None)
+        hyb = SU.run(plan, s)
+        rel = np.abs(hyb["g_h2o2"] - plain["g_h2o2"]) / plain["g_h2o2"]
+        note(f"network intervals {np.nonzero(hyb['used'])[0].tolist()}; H2O2 at pulse starts plain "
+             f"{plain['n_h2o2'].tolist()} hybrid {hyb['n_h2o2'].tolist()}")
+        if args.sur_save:
+            np.savez(args.sur_save + f"_runs_{rate:g}.npz", **{"plain_" + k: v for k, v in plain.items()},
+                     **{"hyb_" + k: v for k, v in hyb.items()})
+        note(f"rate {rate:g}: plain {plain['wall']:.2f} s, hybrid {hyb['wall']:.2f} s, network intervals "
+             f"{hyb['intervals_by_network']}/19, max |dG(H2O2)|/G {rel.max():.4f}, end {rel[-1]:.4f}")
+        runs.append(dict(avg_rate_gy_s=rate, wall_plain_s=round(plain["wall"], 3), wall_hybrid_s=round(hyb["wall"], 3),
+                         speedup=round(plain["wall"] / hyb["wall"], 3), intervals_by_network=hyb["intervals_by_network"],
+                         g_h2o2_plain=[round(float(x), 5) for x in plain["g_h2o2"]],
+                         g_h2o2_hybrid=[round(float(x), 5) for x in hyb["g_h2o2"]],
+                         max_rel_dG_h2o2=round(float(rel.max()), 5), end_rel_dG_h2o2=round(float(rel[-1]), 5),
+                         steps_plain=plain["steps"], steps_hybrid=hyb["steps"]))
+    line = {
+        "metric": "20-pulse wall time, plain SBS / SBS with the inter-pulse network",
+        "value": runs[0]["speedup"], "unit": "x", "higher_is_better": True, "n_gpus": 1,
+        "dtype": "f32 SBS, bf16 network with f32 accumulation", "data": "synthetic",
+        "config": {"workload": f"20 pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate 1e6 Gy/s, "
+                               f"2 batches per pulse", "train_runs": len(plans), "train_L_nm": args.sur_train_L,
+                   "samples": int(n), "held_out_runs": len(held_plans), "held_out": int(n_held)},
+        "train": {"generate_s": round(t_gen, 1), "train_s": round(t_train, 2), "final_loss": round(hist[-1], 6),
+                  "pair_correlation_weight": gw_best,
+                  "held_out_h2o2_rel_err_p95_by_weight": {str(k): round(v[0], 5) for k, v in cands.items()},
+                  "held_out_h2o2_rel_err_median": round(float(np.median(err)), 5),
+                  "held_out_h2o2_rel_err_p95": round(float(np.quantile(err, 0.95)), 5)},
+        "runs": runs,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def kernels_hash():
@@ -97,6 +199,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.surrogate:
+        surrogate_bench(args)
+        return
 
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4

@@ -79,6 +79,10 @@ typedef struct {
                                 each; 0 = chosen from the work per box (default), 1..16 */
     int32_t search_box;      /* species-bin search: edge in cells of the box of molecules a
                                 wave holds; 0 = chosen per species (default), 1..8 */
+    int32_t step_graph;      /* 1: the launches of each uploaded chunk of steps (up to the next
+                                injection) are captured into a HIP graph and launched as one;
+                                0: launched one by one (default).  Off while profiling or while
+                                the autotuner explores.  Results are identical either way. */
 } gsbs_params;
 
 /* Counters since the context was created. */
@@ -118,8 +122,8 @@ int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
 int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
 
 /* Replace the method parameters.  The search fields (grid_config, autotune,
- * search_split, search_box) change only speed, never a result, and may change
- * between advances; the others before the first one. */
+ * search_split, search_box) and step_graph change only speed, never a result,
+ * and may change between advances; the others before the first one. */
 int gsbs_set_params(gsbs_ctx* ctx, const gsbs_params* p);
 
 /* Reaction radii R[0..n_reactions) in nm. */

@@ -204,6 +204,8 @@ struct gsbs_ctx {
     };
     std::vector<StepLog> step_log;
     hipEvent_t prof_ev[2 * kStepKernels] = {};
+    // executable graphs launched during the current advance (destroyed after its final sync)
+    std::vector<hipGraphExec_t> graph_execs;
     // surrogate state buffers (allocated on first use)
     int32_t sur_cap = 0;
     int32_t* sur_ref_idx = nullptr;
@@ -757,6 +759,7 @@ int gsbs_default_params(gsbs_params* p) {
     p->autotune = 1;
     p->search_split = 0;
     p->search_box = 0;
+    p->step_graph = 0;
     return GSBS_OK;
 }
 
@@ -835,6 +838,7 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->ctr);
     dfree(c->rec);
     dfree(c->chem_d);
+    for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
     dfree(c->sur_ref_idx);
     dfree(c->sur_ref_cnt);
     dfree(c->sur_pair_ab);
@@ -893,7 +897,7 @@ int gsbs_set_params(gsbs_ctx* c, const gsbs_params* p) {
     if (!c || !p) return fail(GSBS_EINVAL, "null");
     if (!(p->c_cut > 0) || p->rounds < 1 || !(p->dt0_ns > 0) || !(p->ratio > 1.0) || p->dt_max_ns < 0 ||
         p->grid_config < -1 || p->grid_config >= kNumCfg || p->search_split < 0 || p->search_split > 16 ||
-        p->search_box < 0 || p->search_box > 8)
+        p->search_box < 0 || p->search_box > 8 || p->step_graph < 0 || p->step_graph > 1)
         return fail(GSBS_EINVAL, "bad parameters");
     c->prm = *p;
     c->tuning = p->autotune != 0;
@@ -1104,8 +1108,30 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
                               c->st));
         HIPCHK(hipEventRecord(c->chunk_ev[b], c->st));
         c->chunk_buf ^= 1;
+        // HIP graph of the chunk's launches, cut before every injection (which synchronises)
+        bool explore_chunk = false;
+        for (int k = 0; k < nstep; ++k) explore_chunk = explore_chunk || tune_cfg[k] >= 0;
+        const bool use_graph = c->prm.step_graph && !c->profiling && !explore_chunk;
+        bool capturing = false;
+        auto flush_graph = [&]() -> int {
+            if (!capturing) return GSBS_OK;
+            capturing = false;
+            hipGraph_t gr = nullptr;
+            HIPCHK(hipStreamEndCapture(c->st, &gr));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess) return fail(GSBS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+            c->graph_execs.push_back(ex);
+            HIPCHK(hipGraphLaunch(ex, c->st));
+            return GSBS_OK;
+        };
         for (int k = 0; k < nstep; ++k) {
             const size_t g = g0 + k;
+            if (use_graph && !capturing) {
+                HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed));
+                capturing = true;
+            }
             StepBuffers bf = buffers(c);
             CHK(run_step(c, bf, c->d_chunk[b] + (size_t)k * c->n_inst, c->n_inst, total_cells[k], total_units[k],
                          grid_for(n_total),
@@ -1117,6 +1143,9 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
                 if (g >= sched[i].size()) continue;
                 c->inst[i].t = sched[i][g];
                 c->inst[i].step++;
+                bool due = false;
+                for (const Pending& p : c->inst[i].pending) due = due || p.t <= c->inst[i].t;
+                if (due) CHK(flush_graph());
                 CHK(boundary(c, i, rl));
             }
             if (rl.n) {
@@ -1124,6 +1153,7 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
                 rl.n = 0;
             }
         }
+        CHK(flush_graph());
         for (int i = 0; i < c->n_inst; ++i) c->inst[i].n_est = nest[i];
         {
             const int sl = c->cnt_slot;
@@ -1150,6 +1180,8 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
     }
     for (int i = 0; i < c->n_inst; ++i) c->inst[i].t = target[i];
     HIPCHK(hipStreamSynchronize(c->st));
+    for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
+    c->graph_execs.clear();
     CHK(check_device_errors(c));
     return refresh_estimates(c);
 }

@@ -52,7 +52,7 @@ class gsbs_params(C.Structure):
     _fields_ = [("c_cut", C.c_double), ("rounds", C.c_int32), ("contact_only", C.c_int32),
                 ("dt0_ns", C.c_double), ("ratio", C.c_double), ("dt_max_ns", C.c_double),
                 ("grid_config", C.c_int32), ("autotune", C.c_int32), ("search_split", C.c_int32),
-                ("search_box", C.c_int32)]
+                ("search_box", C.c_int32), ("step_graph", C.c_int32)]
 
 
 class gsbs_stats(C.Structure):

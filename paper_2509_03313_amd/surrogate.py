@@ -129,10 +129,16 @@ def generate(plans: List[PulsePlan], seed: int, log=None) -> dict:
                 x = gsbs.gsbs_features(e.ctx, i, pl.start(p + 1) - t, R_MAX, N_REF, C_FLOOR)
                 pending[i] = (x, log_conc(e.current_counts(i), pl.L), pl.start(p + 1) - t)
             else:
+                # the state just before the next pulse: the step that ends at t also
+                # injected the molecules due at t, which are taken out again
                 x, y0, dt = pending.pop(i)
+                fresh = np.zeros(len(W.D_CONFIG), dtype=np.int64)
+                for j in inj[i]:
+                    if j.t == t:
+                        fresh += np.bincount(j.species, minlength=len(W.D_CONFIG))[:len(W.D_CONFIG)]
                 X.append(x)
                 Y0.append(y0)
-                Y1.append(log_conc(e.current_counts(i), pl.L))
+                Y1.append(log_conc(e.current_counts(i) - fresh, pl.L))
                 meta.append((math.log10(dt), math.log10(pl.avg_rate), float(np.sum(10.0 ** y0))))
             pos[i] += 1
         if log:
@@ -165,24 +171,32 @@ class Surrogate:
         self.dt_edges = self.c_edges = None
 
     def init_weights(self, seed: int):
-        """He-uniform weights, zero biases (seeded)."""
+        """Weights and biases uniform in +-1/sqrt(fan_in) (seeded)."""
         rng = np.random.default_rng(seed)
         parts = []
         sizes = [gsbs.MLP_IN] + [gsbs.MLP_HIDDEN] * 4 + [gsbs.MLP_OUT]
         for l in range(5):
             k, n = sizes[l], sizes[l + 1]
-            lim = math.sqrt(6.0 / k) * (0.1 if l == 4 else 1.0)
-            parts += [rng.uniform(-lim, lim, size=n * k), np.zeros(n)]
+            lim = 1.0 / math.sqrt(k)
+            parts += [rng.uniform(-lim, lim, size=n * k), rng.uniform(-lim, lim, size=n)]
         self.net.set_weights(np.concatenate(parts).astype(np.float32))
 
-    def fit(self, data: dict, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed: int = 0, log=None):
+    def fit(self, data: dict, epochs: int = 60, batch: int = 64, lr: float = 5e-4, seed: int = 0, log=None,
+            val: Optional[dict] = None, g_weight: float = 1.0):
+        """Adam with a cosine learning-rate decay on the device kernels; with
+        `val`, the weights of the epoch with the lowest validation loss are kept.
+        g_weight scales the pair-correlation inputs after normalisation (0 hides
+        them from the network)."""
         import torch
         X, Y = data["X"].astype(np.float64), (data["Y1"] - data["Y0"])
         self.mu = X.mean(axis=0).astype(np.float32)
         # features that barely vary in the training set are only centred, not
         # stretched: a small change elsewhere must not become a large input
         sd = X.std(axis=0)
-        self.sd = np.where(sd < 1e-2 * (1.0 + np.abs(self.mu)), 1.0 + np.abs(self.mu), sd).astype(np.float32)
+        sd = np.where(sd < 1e-2 * (1.0 + np.abs(self.mu)), 1.0 + np.abs(self.mu), sd)
+        sd[7:7 + 9 * 32] /= max(g_weight, 1e-30)
+        self.sd = sd.astype(np.float32)
+        self.g_weight = g_weight
         self.mu_y = Y.mean(axis=0).astype(np.float32)
         self.sd_y = np.maximum(Y.std(axis=0), 1e-4).astype(np.float32)
         Xn = np.clip((X - self.mu) / self.sd, -8.0, 8.0).astype(np.float32)
@@ -195,6 +209,11 @@ class Surrogate:
         hist = []
         steps = 0
         total = epochs * max(1, n // batch)
+        best = (np.inf, None)
+        if val is not None:
+            xv = torch.from_numpy(np.clip((val["X"].astype(np.float64) - self.mu) / self.sd, -8.0, 8.0)
+                                  .astype(np.float32)).cuda()
+            yv = ((val["Y1"] - val["Y0"]) - self.mu_y) / self.sd_y
         for ep in range(epochs):
             perm = torch.from_numpy(rng.permutation(n)).cuda()
             ls = []
@@ -204,8 +223,16 @@ class Surrogate:
                 ls.append(self.net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), rate))
                 steps += 1
             hist.append(float(np.mean(ls)))
+            vl = None
+            if val is not None:
+                vl = float(np.mean((self.net.forward(xv).cpu().numpy().astype(np.float64) - yv) ** 2))
+                if vl < best[0]:
+                    best = (vl, self.net.get_weights())
             if log and (ep % 20 == 0 or ep == epochs - 1):
-                log(f"epoch {ep}: loss {hist[-1]:.5f}")
+                log(f"epoch {ep}: loss {hist[-1]:.5f}" + (f", validation {vl:.5f}" if vl is not None else ""))
+        if best[1] is not None:
+            self.net.set_weights(best[1])
+            self.val_loss = best[0]
         return hist
 
     def predict_log(self, X_raw: np.ndarray, Y0: np.ndarray) -> np.ndarray:
@@ -271,27 +298,37 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     e = _engine(plan.L, seed)
     for j in inj:
         e.inject(0, j.t, j.xyz, j.species, j.edep_ev)
-    times, n_h2o2, g_h2o2, used = [], [], [], []
+    times, n_h2o2, g_h2o2, used, at_switch = [], [], [], [], []
     row = torch.empty((1, gsbs.N_FEATURES), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for p in range(plan.n_pulses):
         t_next = plan.start(p + 1)
         took = False
-        if surrogate is not None and p + 1 < plan.n_pulses:
+        if p + 1 < plan.n_pulses:
+            # both modes stop at the switch time, so that a plain and a hybrid run
+            # follow the same trajectory up to the first interval the network takes
             ts = plan.switch(p)
             e.advance_to(ts)
-            gsbs.gsbs_features(e.ctx, 0, t_next - ts, R_MAX, N_REF, C_FLOOR, surrogate.mu, surrogate.sd, out=row[0])
-            c_tot = float(np.sum(e.current_counts(0))) / (NA * plan.L ** 3 * 1e-24)
-            x_norm = row[0].cpu().numpy()
-            if surrogate.usable(math.log10(t_next - ts), c_tot, x_norm, tol):
-                y = surrogate.net.forward(row)
-                gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_y, surrogate.sd_y, C_FLOOR, relative=True)
-                took = True
+            at_switch.append(e.current_counts(0))
+            if surrogate is not None:
+                gsbs.gsbs_features(e.ctx, 0, t_next - ts, R_MAX, N_REF, C_FLOOR, surrogate.mu, surrogate.sd,
+                                   out=row[0])
+                c_tot = float(np.sum(at_switch[-1])) / (NA * plan.L ** 3 * 1e-24)
+                x_norm = row[0].cpu().numpy()
+                if surrogate.usable(math.log10(t_next - ts), c_tot, x_norm, tol):
+                    y = surrogate.net.forward(row)
+                    gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_y, surrogate.sd_y, C_FLOOR,
+                                         relative=True)
+                    took = True
         if not took:
             e.advance_to(t_next)
         used.append(took)
         cnt = e.current_counts(0)
+        if not took:  # a plain step that ends at t_next has also injected the molecules due then
+            for j in inj:
+                if j.t == t_next:
+                    cnt = cnt - np.bincount(j.species, minlength=len(cnt))[:len(cnt)]
         ed = plan.edep_until(t_next - 1e-9, inj)
         times.append(t_next)
         n_h2o2.append(int(cnt[H2O2]))
@@ -301,4 +338,5 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     st = e.stats()
     e.close()
     return dict(t=np.array(times), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
-                intervals_by_network=int(sum(used)), steps=st["steps"], molecule_steps=st["molecule_steps"])
+                intervals_by_network=int(sum(used)), used=np.array(used), counts_at_switch=np.array(at_switch),
+                steps=st["steps"], molecule_steps=st["molecule_steps"])

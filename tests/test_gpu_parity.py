@@ -290,6 +290,59 @@ def test_species_curves_32_seeds(g):
     e.close()
 
 
+def test_multi_pulse_curves_32_seeds(g):
+    """Four pulses (two injection batches each, the step ramp restarting at
+    every batch): species counts at 30 log-spaced times per interval of 32
+    seeds agree with the oracle's within 2% and 3 SE."""
+    gold = np.load(os.path.join(HERE, "golden", "multi_pulse_1um_oracle.npz"))
+    co = gold["counts"].astype(np.float64)
+    seed = int(gold["philox_seed"])
+    kw = dict(n_pulses=4, dose_per_pulse=1.0, L=1000.0, pulse_rate_gy_s=1e6, avg_rate_gy_s=1e4, n_batches=2,
+              n_records=30)
+    wls = [W.multi_pulse(i, **kw) for i in range(co.shape[0])]
+    say("batched 32 multi-pulse instances")
+    e = make_engine(g, [w.L for w in wls], seed)
+    for i, w in enumerate(wls):
+        e.load_workload(w, inst=i)
+    e.advance_to(wls[0].t_end)
+    cg = np.stack([e.counts(i) for i in range(len(wls))]).astype(np.float64)
+    assert cg.shape == co.shape and np.all(cg >= 0)
+    assert np.array_equal(cg[:, 0], co[:, 0])  # the first record is the injected state
+    d = cg - co
+    mo, mg = co.mean(axis=0), cg.mean(axis=0)
+    se = d.std(axis=0, ddof=1) / math.sqrt(co.shape[0])
+    bad = (mo >= 20) & (np.abs(mg - mo) > np.maximum(0.02 * mo, 3 * se))
+    say("records", co.shape[1], "checked", int((mo >= 20).sum()), "outside", int(bad.sum()))
+    assert not bad.any(), (np.argwhere(bad)[:5], mg[bad][:5], mo[bad][:5])
+    st = e.stats()
+    assert st["steps"] == int(gold["n_steps"][0])  # the same schedule (ramp restarts, records as step ends)
+    e.close()
+
+
+def test_step_graph_equals_eager(g):
+    """Capturing each chunk of step launches into a HIP graph changes nothing:
+    two instances, one with a second injection mid-run (the capture is cut
+    there), give identical counts at every record with and without graphs."""
+    wl = W.single_pulse_small(7)
+    wl2 = W.single_pulse_small(8, n_tracks=2)
+    late = W.single_pulse_small(9, n_tracks=1).injections[0]
+    res = []
+    for graph in (0, 1):
+        say("step graph", graph)
+        p = g.gsbs_default_params()
+        p.step_graph = graph
+        p.autotune = 0
+        e = make_engine(g, [wl.L, wl2.L], 31, params=p)
+        e.load_workload(wl, inst=0)
+        e.load_workload(wl2, inst=1)
+        e.inject(1, 0.37, late.xyz, late.species, late.edep_ev)
+        e.advance_to(wl.t_end)
+        res.append((e.counts(0), e.counts(1), e.stats()))
+        e.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert res[0][2]["steps"] == res[1][2]["steps"] and res[0][2]["reactions"] == res[1][2]["reactions"]
+
+
 def test_invariants_and_replay(g):
     """Charge and redox balances are exact at every record, and the same seed
     replays to identical counts (outcomes do not depend on atomic order)."""
