@@ -81,8 +81,9 @@ typedef struct {
                                 wave holds; 0 = chosen per species (default), 1..8 */
     int32_t step_graph;      /* 1: the launches of each uploaded chunk of steps (up to the next
                                 injection) are captured into a HIP graph and launched as one;
-                                0: launched one by one (default).  Off while profiling or while
-                                the autotuner explores.  Results are identical either way. */
+                                0: launched one by one (default).  Off while profiling, while
+                                the autotuner explores, and on the null stream (which cannot be
+                                captured).  Results are identical either way. */
 } gsbs_params;
 
 /* Counters since the context was created. */

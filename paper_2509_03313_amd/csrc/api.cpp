@@ -1111,7 +1111,8 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
         // HIP graph of the chunk's launches, cut before every injection (which synchronises)
         bool explore_chunk = false;
         for (int k = 0; k < nstep; ++k) explore_chunk = explore_chunk || tune_cfg[k] >= 0;
-        const bool use_graph = c->prm.step_graph && !c->profiling && !explore_chunk;
+        // (the legacy null stream cannot be captured)
+        const bool use_graph = c->prm.step_graph && !c->profiling && !explore_chunk && c->st != nullptr;
         bool capturing = false;
         auto flush_graph = [&]() -> int {
             if (!capturing) return GSBS_OK;

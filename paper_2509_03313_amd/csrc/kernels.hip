@@ -422,6 +422,20 @@ __device__ __forceinline__ float cell_gap(float x, int q, int o, float h, float 
     return g > 0.0f ? g : 0.0f;
 }
 
+// Offsets [lo, hi] within +-m along one axis whose cells can hold a partner of
+// x (cell q) within reach_d: the slab k cells below starts (k - 1) h beyond the
+// distance from x to its cell's lower face, likewise above.
+__device__ __forceinline__ void stencil_range(float x, int q, float h, float hL, float reach_d, int m, int& lo,
+                                              int& hi) {
+    const float a = x - ((float)q * h - hL);        // to the lower face
+    const float b = ((float)(q + 1) * h - hL) - x;  // to the upper face
+    const float ta = reach_d - a, tb = reach_d - b;
+    lo = ta < 0.0f ? 0 : -min(m, (int)floorf(ta / h) + 1);
+    hi = tb < 0.0f ? 0 : min(m, (int)floorf(tb / h) + 1);
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
 // Out of line: candidates are rare in the whole-cell search and the
 // evaluation's registers would otherwise cap the occupancy of its loops.
 __device__ __noinline__ void eval_candidate_call(int i, int j, float d2, const float4* __restrict__ pos0,
@@ -535,25 +549,33 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
         }
         if (k == kWin) scan_run(i, pi, i0 + kWin, (int)start[bi + 1], pos, pos0, uid, S, row, contact_only, log_all,
                                 ctr, pairs, pair_cap, ncand);
-        // stencil cells after the own cell in cell order
+        // stencil cells after the own cell in cell order; along each axis only the
+        // offsets whose slab can lie within the species' largest cutoff are visited
         const int nc = S.nc, m = S.reach;
-        const int ix = cg / (nc * nc), iy = (cg / nc) % nc, iz = cg % nc;
+        const int ncc = nc * nc;
+        const int ix = cg / ncc, rem = cg - ix * ncc, iy = rem / nc, iz = rem - iy * nc;
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
-        const int lo = full ? 0 : -m, hi = full ? nc - 1 : m;
         const float h = S.h, hL = S.halfL, eps = S.cull_eps;
         const float cmax = S.cull2_all[si];
-        for (int ox = lo; ox <= hi; ++ox) {
-            const int qx = full ? ox : (ix + ox + nc) % nc;
+        int xlo = 0, xhi = nc - 1, ylo = 0, yhi = nc - 1, zlo = 0, zhi = nc - 1;
+        if (!full) {
+            const float reach_d = sqrtf(cmax) + eps + 1e-3f * h;  // generous: the gap tests below decide
+            stencil_range(pi.x, ix, h, hL, reach_d, m, xlo, xhi);
+            stencil_range(pi.y, iy, h, hL, reach_d, m, ylo, yhi);
+            stencil_range(pi.z, iz, h, hL, reach_d, m, zlo, zhi);
+        }
+        for (int ox = xlo; ox <= xhi; ++ox) {
+            const int qx = full ? ox : wrap_cell(ix + ox, nc);
             const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
             const float gx2 = gx * gx;
             if (gx2 > cmax) continue;
-            for (int oy = lo; oy <= hi; ++oy) {
-                const int qy = full ? oy : (iy + oy + nc) % nc;
+            for (int oy = ylo; oy <= yhi; ++oy) {
+                const int qy = full ? oy : wrap_cell(iy + oy, nc);
                 const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
                 const float gxy2 = gx2 + gy * gy;
                 if (gxy2 > cmax) continue;
-                for (int oz = lo; oz <= hi; ++oz) {
-                    const int qz = full ? oz : (iz + oz + nc) % nc;
+                for (int oz = zlo; oz <= zhi; ++oz) {
+                    const int qz = full ? oz : wrap_cell(iz + oz, nc);
                     const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
                     if (gxy2 + gz * gz > cmax) continue;
                     const int c2 = (qx * nc + qy) * nc + qz;

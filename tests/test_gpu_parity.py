@@ -326,13 +326,16 @@ def test_step_graph_equals_eager(g):
     wl = W.single_pulse_small(7)
     wl2 = W.single_pulse_small(8, n_tracks=2)
     late = W.single_pulse_small(9, n_tracks=1).injections[0]
+    import ctypes
+    import torch
+    stream = torch.cuda.Stream()  # a capturable stream (not the null stream), default priority
     res = []
     for graph in (0, 1):
         say("step graph", graph)
         p = g.gsbs_default_params()
         p.step_graph = graph
         p.autotune = 0
-        e = make_engine(g, [wl.L, wl2.L], 31, params=p)
+        e = make_engine(g, [wl.L, wl2.L], 31, params=p, stream=ctypes.c_void_p(stream.cuda_stream))
         e.load_workload(wl, inst=0)
         e.load_workload(wl2, inst=1)
         e.inject(1, 0.37, late.xyz, late.species, late.edep_ev)
