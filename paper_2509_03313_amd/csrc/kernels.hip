@@ -1040,16 +1040,25 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                             }
                         }
                     }
-                    const int nseg_l = (n1 > 0 ? 1 : 0) + (n2 > 0 ? 1 : 0);
-                    const int sinc = (int)wave_incl_scan((uint32_t)nseg_l);
-                    const int nseg = __shfl(sinc, 63, 64);
-                    const int minc = (int)wave_incl_scan((uint32_t)(n1 + n2));
-                    const int T = __shfl(minc, 63, 64);
+                    // segments whose exact shift is 0 on every axis go first in the
+                    // stream, so that most stages need no shift at all
+                    const bool z1 = n1 > 0 && (code1 & 127) == 64, z2 = n2 > 0 && (code2 & 127) == 64;
+                    const int nz_l = (z1 ? 1 : 0) + (z2 ? 1 : 0);
+                    const int no_l = (n1 > 0 ? 1 : 0) + (n2 > 0 ? 1 : 0) - nz_l;
+                    const int mz_l = (z1 ? n1 : 0) + (z2 ? n2 : 0), mo_l = n1 + n2 - mz_l;
+                    const int sz = (int)wave_incl_scan((uint32_t)nz_l), so = (int)wave_incl_scan((uint32_t)no_l);
+                    const int mz = (int)wave_incl_scan((uint32_t)mz_l), mo = (int)wave_incl_scan((uint32_t)mo_l);
+                    const int NZ = __shfl(sz, 63, 64), NO = __shfl(so, 63, 64);
+                    const int MZ = __shfl(mz, 63, 64), MO = __shfl(mo, 63, 64);
+                    const int nseg = NZ + NO, T = MZ + MO;
                     if (T == 0) continue;
                     wave_sync_lds();
                     {
-                        int at = sinc - nseg_l, mp = minc - (n1 + n2);
+                        int atz = sz - nz_l, ato = NZ + so - no_l;
+                        int mpz = mz - mz_l, mpo = MZ + mo - mo_l;
                         if (n1 > 0) {
+                            int& at = z1 ? atz : ato;
+                            int& mp = z1 ? mpz : mpo;
                             w.seg_j0[at] = j1;
                             w.seg_pre[at] = mp;
                             w.seg_code[at] = code1;
@@ -1057,6 +1066,8 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                             mp += n1;
                         }
                         if (n2 > 0) {
+                            int& at = z2 ? atz : ato;
+                            int& mp = z2 ? mpz : mpo;
                             w.seg_j0[at] = j2;
                             w.seg_pre[at] = mp;
                             w.seg_code[at] = code2;
