@@ -116,6 +116,10 @@ def surrogate_bench(args):
     t_train = time.perf_counter() - t1
     gw_best = min(cands, key=lambda k: cands[k][0])
     s, hist = cands[gw_best][2], cands[gw_best][3]
+    # the half that picked the candidate also gives its mean residual; the table half
+    # then measures the calibrated network
+    bias = s.calibrate(pick)
+    note(f"calibration: mean log10 residual per species {np.round(bias, 5).tolist()}")
     err = s.build_table(tab, n_dt=2, n_c=2)
     if args.sur_save:
         s.save(args.sur_save + "_model.npz")
@@ -152,6 +156,7 @@ def surrogate_bench(args):
                    "samples": int(n), "held_out_runs": len(held_plans), "held_out": int(n_held)},
         "train": {"generate_s": round(t_gen, 1), "train_s": round(t_train, 2), "final_loss": round(hist[-1], 6),
                   "pair_correlation_weight": gw_best,
+                  "calibration_log10_bias": [round(float(b), 6) for b in bias],
                   "held_out_h2o2_rel_err_p95_by_weight": {str(k): round(v[0], 5) for k, v in cands.items()},
                   "held_out_h2o2_rel_err_median": round(float(np.median(err)), 5),
                   "held_out_h2o2_rel_err_p95": round(float(np.quantile(err, 0.95)), 5)},
@@ -195,7 +200,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
-              "(instances shard across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+              "(independent instances would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

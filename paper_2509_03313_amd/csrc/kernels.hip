@@ -485,19 +485,33 @@ __device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1
 // molecule exceeds the largest cutoff of its species are skipped.
 constexpr int kWin = 128;
 
-__global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__ pos,
-                                                    const float4* __restrict__ pos0,
-                                                    const uint64_t* __restrict__ uid,
-                                                    DevCounters* __restrict__ ctr,
-                                                    const InstStep* __restrict__ P,
-                                                    const ChemDev* __restrict__ chem,
-                                                    const uint32_t* __restrict__ start,
-                                                    PairRec* __restrict__ pairs, uint32_t pair_cap,
-                                                    int32_t log_all, int32_t ns) {
+constexpr int kNbrQ = 256;  // neighbour-cell items queued per wave
+
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restrict__ pos,
+                                                       const float4* __restrict__ pos0,
+                                                       const uint64_t* __restrict__ uid,
+                                                       DevCounters* __restrict__ ctr,
+                                                       const InstStep* __restrict__ P,
+                                                       const ChemDev* __restrict__ chem,
+                                                       const uint32_t* __restrict__ start,
+                                                       PairRec* __restrict__ pairs, uint32_t pair_cap,
+                                                       int32_t log_all, int32_t ns) {
     __shared__ int32_t rmap[kMaxSpecies * kMaxSpecies];
     __shared__ unsigned long long s_cand;
     __shared__ float4 wpos_all[GSBS_BLOCK / 64][kWin];
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
+    __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 6) | lane
+    __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
+    __shared__ int home_s;
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
     if (threadIdx.x == 0) s_cand = 0ull;
@@ -508,8 +522,18 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
     const int lane = threadIdx.x & 63;
     float4* wpos = wpos_all[threadIdx.x >> 6];
     uint32_t* wbin = wbin_all[threadIdx.x >> 6];
+    unsigned long long* nq = nq_all[threadIdx.x >> 6];
     unsigned long long ncand = 0;
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        // the block's home instance (that of its first molecule) gets its cutoffs in
+        // LDS: the own-cell loop then reads no global memory per partner
+        __syncthreads();
+        if (threadIdx.x == 0) home_s = __float_as_int(pos[base].w) >> 8;
+        __syncthreads();
+        const int home = home_s;
+        for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
+            rc2s[k] = rmap[k] >= 0 ? P[home].rc2[rmap[k]] : -1.0f;
+        __syncthreads();
         const int i0 = base + (threadIdx.x & ~63);
         const int i = i0 + lane;
         wave_sync_lds();
@@ -526,65 +550,115 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs(const float4* __restrict__
             wbin[h2 + lane] = bn;
         }
         wave_sync_lds();
-        if (i >= n) continue;
+        // lanes without work stay in the loop: the neighbour queue below works in lockstep
         const float4 pi = wpos[lane];
         const int mi = __float_as_int(pi.w);
         const int si = mi & 0xFF;
-        if (!((reactive >> si) & 1u)) continue;
-        const InstStep& S = P[mi >> 8];
-        if (!S.active || S.by_species) continue;
+        const InstStep& S = P[i < n ? (mi >> 8) : home];
+        const bool act = i < n && ((reactive >> si) & 1u) && S.active && !S.by_species;
+        const int* row = rmap + (si & (kMaxSpecies - 1)) * kMaxSpecies;
         const uint32_t bi = wbin[lane];
         const int cg = (int)bi - S.bin_base;  // local cell
-        const int* row = rmap + si * kMaxSpecies;
-        // own cell: the sorted molecules after i while they share its bin
-        int k = lane + 1;
-        for (; k < kWin && wbin[k] == bi; ++k) {
-            const float4 pj = wpos[k];
-            const int rx = row[__float_as_int(pj.w) & 0xFF];
-            if (rx < 0) continue;
-            const float d2 = end_d2(pj, pi, S.L, S.halfL);
-            if (!(d2 < S.rc2[rx])) continue;
-            ++ncand;
-            eval_candidate_call(i, i0 + k, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs, pair_cap);
+        if (act) {
+            // own cell: the sorted molecules after i while they share its bin
+            int k = lane + 1;
+            if ((mi >> 8) == home) {
+                const float* rcrow = rc2s + si * kMaxSpecies;
+                const float Lh = S.L, hLh = S.halfL;
+                for (; k < kWin && wbin[k] == bi; ++k) {
+                    const float4 pj = wpos[k];
+                    const int sj = __float_as_int(pj.w) & 0xFF;
+                    const float d2 = end_d2(pj, pi, Lh, hLh);
+                    if (!(d2 < rcrow[sj])) continue;
+                    ++ncand;
+                    eval_candidate_call(i, i0 + k, d2, pos0, uid, S, row[sj], contact_only, log_all, ctr, pairs,
+                                        pair_cap);
+                }
+            } else {
+                for (; k < kWin && wbin[k] == bi; ++k) {
+                    const float4 pj = wpos[k];
+                    const int rx = row[__float_as_int(pj.w) & 0xFF];
+                    if (rx < 0) continue;
+                    const float d2 = end_d2(pj, pi, S.L, S.halfL);
+                    if (!(d2 < S.rc2[rx])) continue;
+                    ++ncand;
+                    eval_candidate_call(i, i0 + k, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs,
+                                        pair_cap);
+                }
+            }
+            if (k == kWin)
+                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], pos, pos0, uid, S, row, contact_only, log_all, ctr,
+                         pairs, pair_cap, ncand);
         }
-        if (k == kWin) scan_run(i, pi, i0 + kWin, (int)start[bi + 1], pos, pos0, uid, S, row, contact_only, log_all,
-                                ctr, pairs, pair_cap, ncand);
-        // stencil cells after the own cell in cell order; along each axis only the
-        // offsets whose slab can lie within the species' largest cutoff are visited
+        // stencil cells after the own cell in cell order: along each axis only the
+        // offsets whose slab can lie within the species' largest cutoff; the wave walks
+        // the union of its lanes' offsets in lockstep and queues (molecule, cell) items,
+        // then scans the queued cells one item per lane
         const int nc = S.nc, m = S.reach;
         const int ncc = nc * nc;
         const int ix = cg / ncc, rem = cg - ix * ncc, iy = rem / nc, iz = rem - iy * nc;
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
         const float h = S.h, hL = S.halfL, eps = S.cull_eps;
-        const float cmax = S.cull2_all[si];
-        int xlo = 0, xhi = nc - 1, ylo = 0, yhi = nc - 1, zlo = 0, zhi = nc - 1;
-        if (!full) {
-            const float reach_d = sqrtf(cmax) + eps + 1e-3f * h;  // generous: the gap tests below decide
-            stencil_range(pi.x, ix, h, hL, reach_d, m, xlo, xhi);
-            stencil_range(pi.y, iy, h, hL, reach_d, m, ylo, yhi);
-            stencil_range(pi.z, iz, h, hL, reach_d, m, zlo, zhi);
+        const float cmax = act ? S.cull2_all[si] : -1.0f;
+        int xlo = 1, xhi = 0, ylo = 1, yhi = 0, zlo = 1, zhi = 0;  // empty for idle lanes
+        if (act) {
+            if (full) {  // every cell along each axis, as offsets 0 .. nc-1 taken modulo nc
+                xlo = ylo = zlo = 0;
+                xhi = yhi = zhi = nc - 1;
+            } else {
+                const float reach_d = sqrtf(cmax) + eps + 1e-3f * h;  // generous: the gap tests decide
+                stencil_range(pi.x, ix, h, hL, reach_d, m, xlo, xhi);
+                stencil_range(pi.y, iy, h, hL, reach_d, m, ylo, yhi);
+                stencil_range(pi.z, iz, h, hL, reach_d, m, zlo, zhi);
+            }
         }
-        for (int ox = xlo; ox <= xhi; ++ox) {
-            const int qx = full ? ox : wrap_cell(ix + ox, nc);
+        const int wxlo = wave_min_i(act ? xlo : 1 << 20), wxhi = wave_max_i(act ? xhi : -(1 << 20));
+        const int wylo = wave_min_i(act ? ylo : 1 << 20), wyhi = wave_max_i(act ? yhi : -(1 << 20));
+        const int wzlo = wave_min_i(act ? zlo : 1 << 20), wzhi = wave_max_i(act ? zhi : -(1 << 20));
+        int qn = 0;
+        auto drain = [&]() {
+            wave_sync_lds();
+            for (int e0 = 0; e0 < qn; e0 += 64) {
+                if (e0 + lane < qn) {
+                    const unsigned long long it = nq[e0 + lane];
+                    const int ml = (int)(it & 63ull);
+                    const int b = (int)(it >> 6);
+                    const float4 pm = wpos[ml];
+                    const int mm = __float_as_int(pm.w);
+                    const InstStep& Sm = P[mm >> 8];
+                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], pos, pos0, uid, Sm,
+                             rmap + (mm & 0xFF) * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap, ncand);
+                }
+            }
+            wave_sync_lds();
+            qn = 0;
+        };
+        for (int ox = wxlo; ox <= wxhi; ++ox) {
+            const bool inx = ox >= xlo && ox <= xhi;
+            const int qx = wrap_cell(ix + ox, nc);
             const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
-            const float gx2 = gx * gx;
-            if (gx2 > cmax) continue;
-            for (int oy = ylo; oy <= yhi; ++oy) {
-                const int qy = full ? oy : wrap_cell(iy + oy, nc);
+            for (int oy = wylo; oy <= wyhi; ++oy) {
+                const bool inxy = inx && oy >= ylo && oy <= yhi;
+                const int qy = wrap_cell(iy + oy, nc);
                 const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
-                const float gxy2 = gx2 + gy * gy;
-                if (gxy2 > cmax) continue;
-                for (int oz = zlo; oz <= zhi; ++oz) {
-                    const int qz = full ? oz : wrap_cell(iz + oz, nc);
+                const float gxy2 = gx * gx + gy * gy;
+                for (int oz = wzlo; oz <= wzhi; ++oz) {
+                    const int qz = wrap_cell(iz + oz, nc);
                     const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
-                    if (gxy2 + gz * gz > cmax) continue;
                     const int c2 = (qx * nc + qy) * nc + qz;
-                    if (c2 <= cg) continue;
-                    scan_run(i, pi, (int)start[S.bin_base + c2], (int)start[S.bin_base + c2 + 1], pos, pos0, uid,
-                             S, row, contact_only, log_all, ctr, pairs, pair_cap, ncand);
+                    const bool need = inxy && oz >= zlo && oz <= zhi && !(gxy2 + gz * gz > cmax) && c2 > cg;
+                    const unsigned long long bal = __ballot(need);
+                    if (bal) {
+                        if (need)
+                            nq[qn + __popcll(bal & ((1ull << lane) - 1ull))] =
+                                ((unsigned long long)(uint32_t)(S.bin_base + c2) << 6) | (unsigned long long)lane;
+                        qn += __popcll(bal);
+                        if (qn > kNbrQ - 64) drain();
+                    }
                 }
             }
         }
+        if (qn > 0) drain();
     }
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
     if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);

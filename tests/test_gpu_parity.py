@@ -1,6 +1,6 @@
 """Parity of the HIP engine (through the C ABI) with the FP64 oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (each follows from the FP32 arithmetic of the step):
   * cell binning and candidate pair lists on fixed positions: bit-exact
     (both sides decide in FP32 with the same operation order);
   * pair uniforms (24-bit integers): bit-exact;
