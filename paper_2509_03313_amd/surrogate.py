@@ -169,6 +169,7 @@ class Surrogate:
         self.lo = self.hi = None
         self.table = None       # 95th percentile of |dN_H2O2| / N_H2O2 per (log dt, log C_tot) bin
         self.dt_edges = self.c_edges = None
+        self.bias = np.zeros(gsbs.MLP_OUT, dtype=np.float32)  # mean held-out log10 residual, subtracted
 
     def init_weights(self, seed: int):
         """Weights and biases uniform in +-1/sqrt(fan_in) (seeded)."""
@@ -240,7 +241,21 @@ class Surrogate:
         import torch
         Xn = np.clip((X_raw.astype(np.float64) - self.mu) / self.sd, -8.0, 8.0).astype(np.float32)
         yn = self.net.forward(torch.from_numpy(Xn).cuda()).cpu().numpy().astype(np.float64)
-        return Y0 + yn * self.sd_y + self.mu_y
+        return Y0 + yn * self.sd_y + self.mu_y - self.bias
+
+    def calibrate(self, data: dict) -> np.ndarray:
+        """Mean signed residual of the predicted log10 concentrations on held-out
+        samples, per species; later predictions subtract it.  A small systematic
+        offset is harmless for one interval but adds up over consecutive
+        intervals the network takes."""
+        self.bias = np.zeros(gsbs.MLP_OUT, dtype=np.float32)
+        r = self.predict_log(data["X"], data["Y0"]) - data["Y1"]
+        self.bias = r.mean(axis=0).astype(np.float32)
+        return self.bias
+
+    def mu_out(self) -> np.ndarray:
+        """Output offsets for the re-population (the calibration folded in)."""
+        return (self.mu_y.astype(np.float64) - self.bias).astype(np.float32)
 
     def build_table(self, data: dict, n_dt: int = 4, n_c: int = 3):
         """95th percentile of the relative H2O2 error per (log dt, log C_tot) bin
@@ -279,13 +294,14 @@ class Surrogate:
 
     def save(self, path: str):
         np.savez(path, w=self.net.get_weights(), mu=self.mu, sd=self.sd, mu_y=self.mu_y, sd_y=self.sd_y, lo=self.lo,
-                 hi=self.hi, table=self.table, dt_edges=self.dt_edges, c_edges=self.c_edges)
+                 hi=self.hi, table=self.table, dt_edges=self.dt_edges, c_edges=self.c_edges, bias=self.bias)
 
     def load(self, path: str):
         z = np.load(path)
         self.net.set_weights(z["w"])
         for k in ("mu", "sd", "mu_y", "sd_y", "lo", "hi", "table", "dt_edges", "c_edges"):
             setattr(self, k, z[k])
+        self.bias = z["bias"] if "bias" in z.files else np.zeros(gsbs.MLP_OUT, dtype=np.float32)
 
 
 # ------------------------------------------------------------ multi-pulse run ---
@@ -318,7 +334,7 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
                 x_norm = row[0].cpu().numpy()
                 if surrogate.usable(math.log10(t_next - ts), c_tot, x_norm, tol):
                     y = surrogate.net.forward(row)
-                    gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_y, surrogate.sd_y, C_FLOOR,
+                    gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_out(), surrogate.sd_y, C_FLOOR,
                                          relative=True)
                     took = True
         if not took:
