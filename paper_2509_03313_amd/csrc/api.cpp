@@ -421,6 +421,7 @@ struct GridCfg {
 };
 constexpr GridCfg kCfgs[] = {
     {0, 1, 2.0}, {0, 1, 6.0}, {0, 2, 2.0}, {1, 1, 16.0}, {1, 2, 16.0}, {1, 2, 64.0}, {1, 3, 16.0},
+    {1, 3, 4.0}, {1, 3, 1.0}, {1, 4, 1.0},
 };
 constexpr int kNumCfg = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 

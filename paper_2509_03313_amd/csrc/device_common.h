@@ -7,6 +7,56 @@
 
 namespace gsbs {
 
+// -------------------------------------------------------- wave primitives ---
+// Prefix operations over the 64 lanes of a wave built from DPP row shifts and
+// row broadcasts: plain VALU instructions, no LDS round trip (the HIP shuffle
+// intrinsics go through ds_bpermute).  Every lane of the wave must be active.
+// DPP controls (GFX9): row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, wave_shr:1 = 0x138.  A lane with no source (or in a row
+// the row mask leaves out) receives `ident`.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_src(int ident, int v) {
+    return __builtin_amdgcn_update_dpp(ident, v, kCtrl, kRowMask, 0xf, false);
+}
+
+// Inclusive scan with an associative operation op(int, int) and its identity.
+template <class Op>
+__device__ __forceinline__ int wave_scan_op(int v, int ident, Op op) {
+    v = op(v, dpp_src<0x111, 0xf>(ident, v));
+    v = op(v, dpp_src<0x112, 0xf>(ident, v));
+    v = op(v, dpp_src<0x114, 0xf>(ident, v));
+    v = op(v, dpp_src<0x118, 0xf>(ident, v));
+    v = op(v, dpp_src<0x142, 0xa>(ident, v));
+    v = op(v, dpp_src<0x143, 0xc>(ident, v));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    return (uint32_t)wave_scan_op((int)v, 0, [](int a, int b) { return (int)((uint32_t)a + (uint32_t)b); });
+}
+// The value of lane 63 (wave-uniform).
+__device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ int wave_min_i(int v) {
+    return wave_last(wave_scan_op(v, INT32_MAX, [](int a, int b) { return a < b ? a : b; }));
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    return wave_last(wave_scan_op(v, INT32_MIN, [](int a, int b) { return a > b ? a : b; }));
+}
+__device__ __forceinline__ float wave_min_f(float v) {
+    return __int_as_float(wave_last(wave_scan_op(__float_as_int(v), __float_as_int(INFINITY), [](int a, int b) {
+        return __float_as_int(fminf(__int_as_float(a), __int_as_float(b)));
+    })));
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    return __int_as_float(wave_last(wave_scan_op(__float_as_int(v), __float_as_int(-INFINITY), [](int a, int b) {
+        return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
+    })));
+}
+// The value of the previous lane (lane 0 receives `first`).
+__device__ __forceinline__ uint32_t wave_prev(uint32_t v, uint32_t first) {
+    return (uint32_t)dpp_src<0x138, 0xf>((int)first, (int)v);
+}
+
 // --------------------------------------------------------------- Philox ---
 // Philox4x64-10 (Salmon et al., SC'11): multipliers 0xD2E7470EE14C6C93 and
 // 0xCA5A826395121157, Weyl increments 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B.

@@ -194,7 +194,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ p
         const int i = base + threadIdx.x;
         const bool valid = i < n;
         const uint32_t bin = valid ? molecule_bin(pos, uid, P, i, fixed, ns) : kNoCell;
-        const uint32_t prev = __shfl_up(bin, 1, 64);
+        const uint32_t prev = wave_prev(bin, kNoCell);
         const bool head = (lane == 0) || (prev != bin);
         const unsigned long long heads = __ballot(head);
         const int start = 63 - __clzll(heads & upto);
@@ -209,15 +209,6 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ p
 
 // ----------------------------------------------------------------- scan ---
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
 
 // exclusive scan of one value per thread over the block; *total gets the sum
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
@@ -487,14 +478,6 @@ constexpr int kWin = 128;
 
 constexpr int kNbrQ = 256;  // neighbour-cell items queued per wave
 
-__device__ __forceinline__ int wave_min_i(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
-}
 
 __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restrict__ pos,
                                                        const float4* __restrict__ pos0,
@@ -843,7 +826,7 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
         const int have = __popc(mlo) + __popc(mhi);
         const int mine = have < kLaneQuota ? have : kLaneQuota;
         const int incl = (int)wave_incl_scan((uint32_t)mine);
-        const int total = __shfl(incl, 63, 64);
+        const int total = wave_last(incl);
         const int at = incl - mine;
         for (int k = 0; k < mine; ++k) {
             int t;
@@ -894,14 +877,6 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
     }
 }
 
-__device__ __forceinline__ float wave_min(float v) {
-    for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
-    return v;
-}
-__device__ __forceinline__ float wave_max(float v) {
-    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
-    return v;
-}
 
 // Cells [c0, c1] (unwrapped, may leave [0, nc)) whose extent meets [lo, hi];
 // eps covers the FP32 rounding of the binning.  Returns false (and the whole
@@ -1010,7 +985,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
             cntA = (int)start[b0 + z1] - begA;
         }
         const int inclA = (int)wave_incl_scan((uint32_t)cntA);
-        const int nA = __shfl(inclA, 63, 64);
+        const int nA = wave_last(inclA);
         if (nA == 0) continue;
         wave_sync_lds();
         if (lane < nrowsA) {
@@ -1041,9 +1016,9 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
             w.ap[lane] = pa;
             w.aq[lane] = qa;
             // bounding box of the chunk's end positions (the box does not cross the cube faces)
-            const float blx = wave_min(va ? pa.x : kFar), bhx = wave_max(va ? pa.x : -kFar);
-            const float bly = wave_min(va ? pa.y : kFar), bhy = wave_max(va ? pa.y : -kFar);
-            const float blz = wave_min(va ? pa.z : kFar), bhz = wave_max(va ? pa.z : -kFar);
+            const float blx = wave_min_f(va ? pa.x : kFar), bhx = wave_max_f(va ? pa.x : -kFar);
+            const float bly = wave_min_f(va ? pa.y : kFar), bhy = wave_max_f(va ? pa.y : -kFar);
+            const float blz = wave_min_f(va ? pa.z : kFar), bhz = wave_max_f(va ? pa.z : -kFar);
             uint32_t mm = pm;
             while (mm) {
                 const int sj = __ffs(mm) - 1;
@@ -1122,8 +1097,8 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                     const int mz_l = (z1 ? n1 : 0) + (z2 ? n2 : 0), mo_l = n1 + n2 - mz_l;
                     const int sz = (int)wave_incl_scan((uint32_t)nz_l), so = (int)wave_incl_scan((uint32_t)no_l);
                     const int mz = (int)wave_incl_scan((uint32_t)mz_l), mo = (int)wave_incl_scan((uint32_t)mo_l);
-                    const int NZ = __shfl(sz, 63, 64), NO = __shfl(so, 63, 64);
-                    const int MZ = __shfl(mz, 63, 64), MO = __shfl(mo, 63, 64);
+                    const int NZ = wave_last(sz), NO = wave_last(so);
+                    const int MZ = wave_last(mz), MO = wave_last(mo);
                     const int nseg = NZ + NO, T = MZ + MO;
                     if (T == 0) continue;
                     wave_sync_lds();
