@@ -690,8 +690,8 @@ struct SpWave {
     int32_t seg_pre[kSegCap + 1];
     int32_t seg_code[kSegCap];
     uint16_t list[kListCap];
-    int4 qe[128];    // queued for evaluation: i, j, rx, bits of r0
-    float qr[128];   // queued r1
+    int4 qe[128];    // queued for evaluation: i, j, rx, bits of r0^2
+    float qr[128];   // queued r1^2
     int32_t rbeg[65], roff[65];
 };
 
@@ -768,11 +768,25 @@ __device__ __forceinline__ void qpush(SpWave& w, int& qn, int lane, bool need, c
         w.qr[lane] = rr;
     }
     qn = rest;
-    if (mine) eval_pair(v.x, v.y, v.z, __int_as_float(v.w), vr, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
+    if (mine)
+        eval_pair(v.x, v.y, v.z, sqrtf(__int_as_float(v.w)), sqrtf(vr), uid, S, contact_only, log_all, ctr, pairs,
+                  pair_cap);
+}
+
+// m = 2 m + (d2 < rc2): one compare into VCC and one add-with-carry per test
+// (NaN compares false).  A VALU read of VCC written by the previous VALU
+// instruction needs two wait states on this target (the compiler inserts the
+// same s_nop between a compare and a select).
+__device__ __forceinline__ void mask_push(uint32_t& m, float d2, float rc2) {
+    asm("v_cmp_lt_f32 vcc, %1, %2\n\ts_nop 1\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(m)
+        : "v"(d2), "v"(rc2)
+        : "vcc");
 }
 
 // Candidate mask of one stage: bit t set when staged B t lies within the
-// cutoff of this lane's A (end separation, FP32, fixed operation order).
+// cutoff of this lane's A (end separation, FP32, fixed operation order).  The
+// tests run from t = 31 down so that doubling the mask lands bit t at t.
 template <bool kShift, bool kSame, bool kZero = false>
 __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
                                            uint32_t& mlo, uint32_t& mhi) {
@@ -781,8 +795,8 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
     for (int g = 0; g < 2; ++g) {
         uint32_t m = 0u;
 #pragma unroll 8
-        for (int k = 0; k < 32; ++k) {
-            const int t = 32 * g + k;
+        for (int kk = 0; kk < 32; ++kk) {
+            const int t = 32 * g + 31 - kk;
             const float4 p = w.bp[t];
             float dx, dy, dz;
             if (kZero) {  // every shift of the stage is 0: adding it would change nothing
@@ -799,10 +813,9 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
                 dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
                 dz = minimg_f(__fsub_rn(p.z, pa.z), L, hL);
             }
-            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
-            bool c = d2 < rc2;
-            if (kSame) c = c && (__float_as_int(p.w) > ia);
-            m |= c ? (1u << k) : 0u;
+            float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+            if (kSame) d2 = (__float_as_int(p.w) > ia) ? d2 : INFINITY;  // each pair once
+            mask_push(m, d2, rc2);
         }
         half[g] = m;
     }
@@ -816,7 +829,7 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
 // start separation, bridge-exponent bound, queue.
 template <bool kShift>
 __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32_t mhi, int lane, int rx, float R,
-                                                 float inv_s, float L, float hL, int& qn,
+                                                 float inv_s, float rc2, float L, float hL, int& qn,
                                                  const uint64_t* __restrict__ uid, const InstStep& S,
                                                  int contact_only, int log_all, DevCounters* __restrict__ ctr,
                                                  PairRec* __restrict__ pairs, uint32_t pair_cap,
@@ -864,12 +877,19 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
                 const float ex = minimg_f(q.x - qa.x, L, hL);
                 const float ey = minimg_f(q.y - qa.y, L, hL);
                 const float ez = minimg_f(q.z - qa.z, L, hL);
-                r1 = sqrtf(d2);
-                const float r0 = sqrtf(ex * ex + ey * ey + ez * ez);
-                // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P
-                const float aexp = (r0 - R) * (r1 - R) * inv_s;
-                need = log_all || contact_only || r0 <= R || r1 <= R || !(aexp > 18.0f);
-                e = make_int4(__float_as_int(pa.w), __float_as_int(p.w), rx, __float_as_int(r0));
+                const float e2 = ex * ex + ey * ey + ez * ez;
+                // exp(-a) bounds P; below 1.5e-8 no 24-bit uniform can fall under P.
+                // The test runs on the hardware square root (within 1 ulp) with
+                // margins that keep every pair the correctly rounded roots keep:
+                // the error of a is below 3e-4 once both separations exceed 1.01 R.
+                const float r1a = __builtin_amdgcn_sqrtf(d2), r0a = __builtin_amdgcn_sqrtf(e2);
+                const float aexp = (r0a - R) * (r1a - R) * inv_s;
+                // (the end separation is tested again: padding, whose positions lie
+                // far outside the cube, never reaches the evaluation)
+                need = d2 < rc2 &&
+                       (log_all || contact_only || r0a <= 1.01f * R || r1a <= 1.01f * R || !(aexp > 18.01f));
+                r1 = d2;
+                e = make_int4(__float_as_int(pa.w), __float_as_int(p.w), rx, __float_as_int(e2));
             }
             qpush(w, qn, lane, need, e, r1, false, uid, S, contact_only, log_all, ctr, pairs, pair_cap);
         }
@@ -1168,12 +1188,12 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                                 if (same) stage_mask<true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
                                 else stage_mask<true, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
                             }
-                            stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, L, hL, qn, uid, S, contact_only,
+                            stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S, contact_only,
                                                    log_all, ctr, pairs, pair_cap, ncand);
                         } else {
                             if (same) stage_mask<false, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
                             else stage_mask<false, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
-                            stage_candidates<false>(w, mlo, mhi, lane, rx, Rr, inv_s, L, hL, qn, uid, S,
+                            stage_candidates<false>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S,
                                                     contact_only, log_all, ctr, pairs, pair_cap, ncand);
                         }
                     }
