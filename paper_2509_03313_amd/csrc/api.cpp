@@ -166,6 +166,7 @@ struct gsbs_ctx {
     unsigned long long* claim = nullptr;
     int32_t* mate = nullptr;
     float4* x0_dbg = nullptr;
+    float4* xnew = nullptr;
     int32_t cell_cap = 0;
     uint32_t* cell_count = nullptr;
     uint32_t* cell_start = nullptr;
@@ -290,11 +291,13 @@ int ensure_capacity(gsbs_ctx* c, int64_t need) {
     dfree(c->claim);
     dfree(c->mate);
     dfree(c->x0_dbg);
+    dfree(c->xnew);
     CHK(dalloc(&c->pos0, nc));
     CHK(dalloc(&c->cellrank, nc));
     CHK(dalloc(&c->claim, nc));
     CHK(dalloc(&c->mate, nc));
     CHK(dalloc(&c->x0_dbg, nc));
+    CHK(dalloc(&c->xnew, nc));
     HIPCHK(hipMemsetAsync(c->claim, 0xFF, sizeof(unsigned long long) * nc, c->st));
     HIPCHK(hipMemsetAsync(c->mate, 0xFF, sizeof(int32_t) * nc, c->st));
     c->cap = (int32_t)nc;
@@ -611,6 +614,7 @@ StepBuffers buffers(gsbs_ctx* c) {
     b.uid_out = c->uid[c->cur ^ 1];
     b.pos0_out = c->pos0;
     b.cellrank = c->cellrank;
+    b.xnew = c->xnew;
     b.cell_count = c->cell_count;
     b.cell_start = c->cell_start;
     b.block_sums = c->block_sums;
@@ -830,6 +834,7 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->claim);
     dfree(c->mate);
     dfree(c->x0_dbg);
+    dfree(c->xnew);
     dfree(c->cell_count);
     dfree(c->cell_start);
     dfree(c->block_sums);

@@ -102,6 +102,7 @@ struct StepBuffers {
     float4* pos0_out;     // sorted start-of-step positions; .w carries the global bin index
     uint64_t* uid_out;
     uint2* cellrank;      // per input molecule: (global bin, rank inside the bin)
+    float4* xnew;         // per input molecule: end position of the step (meta in .w)
     uint32_t* cell_count; // per bin, zero between steps
     uint32_t* cell_start; // per bin exclusive prefix sums, one extra entry at the end
     uint32_t* block_sums;

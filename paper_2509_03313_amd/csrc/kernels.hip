@@ -3,12 +3,14 @@
 //
 //   k_bin      Brownian jump (Philox4x64-10 + Box-Muller, FP32) and PBC 1
 //              (Eq. 1), (cell, species) bin of the moved position, per-bin
-//              count and rank (LDS histogram for small grids)
-//   k_scan_*   exclusive scan of the cell counts (wave64 shuffles + LDS)
-//   k_scatter  molecules into cell order (jump recomputed from the counter)
+//              count and rank (LDS histogram for small grids); the moved
+//              position is kept for the scatter
+//   k_scan_*   exclusive scan of the cell counts (DPP wave scans + LDS)
+//   k_scatter  molecules into cell order
 //   k_pairs    stencil minimum-image (Eq. 2) candidate search against the
 //              per-reaction cutoff, radial Brownian-bridge contact
 //              probability, pair uniform, accepted pairs appended
+//   k_pairs_sp the same search over species bins (late, large cutoffs)
 //   k_react    mutual-best single-partner matching by 64-bit atomic min,
 //              products of Table 1 appended, reactants removed, species
 //              counts updated
@@ -122,14 +124,18 @@ __device__ __forceinline__ uint32_t bin_of(float3 x, const InstStep& S, int sp, 
     return (uint32_t)(S.bin_base + (S.by_species ? sp * S.nc * S.nc * S.nc + c : c));
 }
 
+// Bin of molecule i after its jump; the end position is kept in xnew[i] so
+// that the scatter does not draw the jump a second time.
 __device__ __forceinline__ uint32_t molecule_bin(const float4* __restrict__ pos, const uint64_t* __restrict__ uid,
-                                                 const InstStep* __restrict__ P, int i, int fixed, int ns) {
+                                                 const InstStep* __restrict__ P, int i, int fixed, int ns,
+                                                 float4* __restrict__ xnew) {
     const float4 p = pos[i];
     const int meta = __float_as_int(p.w);
     const int sp = meta & 0xFF;
     if (sp == kDead) return kNoCell;
     const InstStep& S = P[meta >> 8];
     const float3 x = fixed ? make_float3(p.x, p.y, p.z) : jump(p, uid[i], S, sp);
+    xnew[i] = make_float4(x.x, x.y, x.z, p.w);
     return bin_of(x, S, sp, ns);
 }
 
@@ -143,8 +149,8 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin_lds(const float4* __restrict
                                                       DevCounters* __restrict__ ctr,
                                                       const InstStep* __restrict__ P,
                                                       uint32_t* __restrict__ cell_count,
-                                                      uint2* __restrict__ cellrank, int32_t fixed,
-                                                      int32_t total_bins, int32_t ns) {
+                                                      uint2* __restrict__ cellrank, float4* __restrict__ xnew,
+                                                      int32_t fixed, int32_t total_bins, int32_t ns) {
     extern __shared__ uint32_t hist[];
     for (int b = threadIdx.x; b < total_bins; b += GSBS_BLOCK) hist[b] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_pairs = 0u;  // read by k_pairs, after this kernel
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin_lds(const float4* __restrict
         bin[r] = kNoCell;
         lr[r] = 0u;
         if (r * GSBS_BLOCK < per_block && i < n) {
-            bin[r] = molecule_bin(pos, uid, P, i, fixed, ns);
+            bin[r] = molecule_bin(pos, uid, P, i, fixed, ns, xnew);
             if (bin[r] != kNoCell) lr[r] = atomicAdd(&hist[bin[r]], 1u);
         }
     }
@@ -185,7 +191,8 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ p
                                                   DevCounters* __restrict__ ctr,
                                                   const InstStep* __restrict__ P,
                                                   uint32_t* __restrict__ cell_count,
-                                                  uint2* __restrict__ cellrank, int32_t fixed, int32_t ns) {
+                                                  uint2* __restrict__ cellrank, float4* __restrict__ xnew,
+                                                  int32_t fixed, int32_t ns) {
     const int n = ctr->n_in;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_pairs = 0u;  // read by k_pairs, after this kernel
     const int lane = threadIdx.x & 63;
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_bin(const float4* __restrict__ p
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const int i = base + threadIdx.x;
         const bool valid = i < n;
-        const uint32_t bin = valid ? molecule_bin(pos, uid, P, i, fixed, ns) : kNoCell;
+        const uint32_t bin = valid ? molecule_bin(pos, uid, P, i, fixed, ns, xnew) : kNoCell;
         const uint32_t prev = wave_prev(bin, kNoCell);
         const bool head = (lane == 0) || (prev != bin);
         const unsigned long long heads = __ballot(head);
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scan_apply(uint32_t* __restrict_
 __global__ __launch_bounds__(GSBS_BLOCK) void k_scatter(const float4* __restrict__ pos,
                                                       const uint64_t* __restrict__ uid,
                                                       const DevCounters* __restrict__ ctr,
-                                                      const InstStep* __restrict__ P,
+                                                      const float4* __restrict__ xnew,
                                                       const uint2* __restrict__ cellrank,
                                                       const uint32_t* __restrict__ start,
                                                       float4* __restrict__ pos_out,
@@ -295,19 +302,11 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scatter(const float4* __restrict
         const uint2 cr = cellrank[i];
         if (cr.x == kNoCell) continue;
         const float4 p = pos[i];
-        const int meta = __float_as_int(p.w);
         const uint64_t u = uid[i];
         const uint32_t dst = start[cr.x] + cr.y;
-        float3 x;
-        float4 p0;
-        if (x0_override) {
-            x = make_float3(p.x, p.y, p.z);
-            p0 = x0_override[i];
-        } else {
-            x = jump(p, u, P[meta >> 8], meta & 0xFF);
-            p0 = p;
-        }
-        pos_out[dst] = make_float4(x.x, x.y, x.z, p.w);
+        const float4 x = xnew[i];
+        const float4 p0 = x0_override ? x0_override[i] : p;
+        pos_out[dst] = x;
         pos0_out[dst] = make_float4(p0.x, p0.y, p0.z, __uint_as_float(cr.x));  // bin index
         uid_out[dst] = u;
     }
@@ -1225,6 +1224,80 @@ __device__ __forceinline__ void st_mate(int32_t* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Outcome of one reacted pair: reactants flagged removed, products of Table 1
+// appended after the live molecules at the weighted position, counts updated.
+__device__ __forceinline__ void apply_reaction(const PairRec& r, float4* __restrict__ pos, uint64_t* __restrict__ uid,
+                                               DevCounters* __restrict__ ctr, const InstStep* __restrict__ P,
+                                               const ChemDev* __restrict__ chem, long long* __restrict__ counts,
+                                               int n_live, int cap, int* n_prod, int* n_react) {
+    int a = r.i, b = r.j;
+    uint64_t ua = uid[a], ub = uid[b];
+    if (ub < ua) {
+        const int t = a; a = b; b = t;
+        const uint64_t tu = ua; ua = ub; ub = tu;
+    }
+    const float4 pa = pos[a], pb = pos[b];
+    const int ma = __float_as_int(pa.w), mb = __float_as_int(pb.w);
+    const int inst = ma >> 8;
+    const int sa = ma & 0xFF, sb = mb & 0xFF;
+    const int rx = r.rx;
+    long long* cnt = counts + inst * kMaxSpecies;
+    atomicAdd(n_react, 1);
+    if (chem->keep_b[rx]) {
+        const int gone = (sa == chem->rb[rx]) ? b : a;
+        const int sg = (gone == a) ? sa : sb;
+        pos[gone].w = __int_as_float((inst << 8) | kDead);
+        atomicAdd((unsigned long long*)&cnt[sg], (unsigned long long)(-1ll));
+        return;
+    }
+    pos[a].w = __int_as_float((inst << 8) | kDead);
+    pos[b].w = __int_as_float((inst << 8) | kDead);
+    atomicAdd((unsigned long long*)&cnt[sa], (unsigned long long)(-1ll));
+    atomicAdd((unsigned long long*)&cnt[sb], (unsigned long long)(-1ll));
+    const int npr = chem->nprod[rx];
+    if (npr == 0) return;
+    const InstStep& S = P[inst];
+    const float Da = chem->D[sa], Db = chem->D[sb];
+    const float wgt = (Da + Db > 0.0f) ? Da / (Da + Db) : 0.5f;
+    const float px = wrap_f(pa.x + wgt * minimg_f(pb.x - pa.x, S.L, S.halfL), S.L, S.halfL, S.invL);
+    const float py = wrap_f(pa.y + wgt * minimg_f(pb.y - pa.y, S.L, S.halfL), S.L, S.halfL, S.invL);
+    const float pz = wrap_f(pa.z + wgt * minimg_f(pb.z - pa.z, S.L, S.halfL), S.L, S.halfL, S.invL);
+    const int base = atomicAdd(n_prod, npr);
+    for (int k = 0; k < npr; ++k) {
+        const int dst = n_live + base + k;
+        if (dst >= cap) {
+            atomicOr(&ctr->err, kErrMolOverflow);
+            continue;
+        }
+        uint64_t u;
+        if (k == 0) u = ua;
+        else if (k == 1) u = ub;
+        else {
+            uint64_t w[4];
+            philox(ua, ub, S.step, 2ull, S.key0, S.key1, w);
+            u = w[0] | 0x8000000000000000ull;
+        }
+        const int ps = chem->prod[rx][k];
+        pos[dst] = make_float4(px, py, pz, __int_as_float((inst << 8) | ps));
+        uid[dst] = u;
+        atomicAdd((unsigned long long*)&cnt[ps], 1ull);
+    }
+}
+
+// Slot of molecule `mol` in the block's open-addressing table (inserted when
+// absent).  The table holds at most two molecules per pair and is at most
+// half full, so the probe ends.
+constexpr int kReactHash = 2048;
+constexpr int kReactFast = kReactHash / 4;  // pairs handled in LDS
+__device__ __forceinline__ int react_slot(int* key, int mol) {
+    int h = (int)(((uint32_t)mol * 2654435761u) >> (32 - 11)) & (kReactHash - 1);
+    while (true) {
+        const int prev = atomicCAS(&key[h], -1, mol);
+        if (prev == -1 || prev == mol) return h;
+        h = (h + 1) & (kReactHash - 1);
+    }
+}
+
 __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos, uint64_t* __restrict__ uid,
                                                      DevCounters* __restrict__ ctr,
                                                      const InstStep* __restrict__ P,
@@ -1236,6 +1309,9 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
                                                      unsigned long long* __restrict__ msteps,
                                                      int32_t n_inst, int32_t cap, int32_t search_only) {
     __shared__ int n_new, n_wait, n_prod, n_react;
+    __shared__ int ht_key[kReactHash];
+    __shared__ unsigned long long ht_claim[kReactHash];
+    __shared__ int ht_mate[kReactHash];
     const int tid = threadIdx.x;
     // molecule-steps of the instances that stepped (counts before this step's reactions)
     for (int t = tid; t < n_inst; t += kReactBlock) {
@@ -1256,105 +1332,120 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
         if (tid == 0) ctr->n_in = n_live;
         return;
     }
-    for (int round = 0; round < chem->rounds; ++round) {
-        for (int p = tid; p < np; p += kReactBlock) {
-            const PairRec r = pairs[p];
-            if (!(r.flags & 1) || ld_mate(&mate[r.i]) >= 0 || ld_mate(&mate[r.j]) >= 0) continue;
-            atomicMin(&claim[r.i], match_key(r.u24, uid[r.j]));
-            atomicMin(&claim[r.j], match_key(r.u24, uid[r.i]));
-        }
-        if (tid == 0) {
-            n_new = 0;
-            n_wait = 0;
+    if (np <= kReactFast) {
+        // Few pairs (every step but debug logging): one pair per thread, claims
+        // and mates in an LDS table instead of the per-molecule global arrays.
+        for (int k = tid; k < kReactHash; k += kReactBlock) {
+            ht_key[k] = -1;
+            ht_claim[k] = ~0ull;
+            ht_mate[k] = -1;
         }
         __syncthreads();
-        for (int p = tid; p < np; p += kReactBlock) {
-            const PairRec r = pairs[p];
-            if (!(r.flags & 1) || ld_mate(&mate[r.i]) >= 0 || ld_mate(&mate[r.j]) >= 0) continue;
-            const unsigned long long ci = __hip_atomic_load(&claim[r.i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned long long cj = __hip_atomic_load(&claim[r.j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ci == match_key(r.u24, uid[r.j]) && cj == match_key(r.u24, uid[r.i])) {
-                pairs[p].flags = r.flags | 4;
-                atomicAdd(&n_new, 1);
-            } else {
-                atomicAdd(&n_wait, 1);
+        PairRec r{};
+        bool acc = false;
+        int si = 0, sj = 0;
+        unsigned long long ki = 0, kj = 0;  // claim keys written to i and to j
+        if (tid < np) {
+            r = pairs[tid];
+            acc = (r.flags & 1) != 0;
+            if (acc) {
+                si = react_slot(ht_key, r.i);
+                sj = react_slot(ht_key, r.j);
+                ki = match_key(r.u24, uid[r.j]);
+                kj = match_key(r.u24, uid[r.i]);
             }
         }
-        __syncthreads();
-        for (int p = tid; p < np; p += kReactBlock) {
-            const PairRec r = pairs[p];
-            if (!(r.flags & 1)) continue;
-            __hip_atomic_store(&claim[r.i], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&claim[r.j], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (r.flags & 4) {
+        bool reacted = false;
+        for (int round = 0; round < chem->rounds; ++round) {
+            if (tid == 0) {
+                n_new = 0;
+                n_wait = 0;
+            }
+            __syncthreads();
+            const bool open = acc && !reacted && ht_mate[si] < 0 && ht_mate[sj] < 0;
+            if (open) {
+                atomicMin(&ht_claim[si], ki);
+                atomicMin(&ht_claim[sj], kj);
+            }
+            __syncthreads();
+            bool matched = false;
+            if (open) {
+                matched = ht_claim[si] == ki && ht_claim[sj] == kj;
+                atomicAdd(matched ? &n_new : &n_wait, 1);
+            }
+            __syncthreads();
+            if (acc) {
+                ht_claim[si] = ~0ull;
+                ht_claim[sj] = ~0ull;
+            }
+            if (matched) {
                 // a molecule in two mutual pairs needs two pairs with equal keys
-                if (atomicCAS(&mate[r.i], -1, r.j) != -1) atomicOr(&ctr->err, kErrTie);
-                if (atomicCAS(&mate[r.j], -1, r.i) != -1) atomicOr(&ctr->err, kErrTie);
-                pairs[p].flags = (r.flags & ~4) | 2;
+                if (atomicCAS(&ht_mate[si], -1, r.j) != -1) atomicOr(&ctr->err, kErrTie);
+                if (atomicCAS(&ht_mate[sj], -1, r.i) != -1) atomicOr(&ctr->err, kErrTie);
+                reacted = true;
             }
+            __syncthreads();
+            // eligible pairs only lose eligibility: with none left waiting, later rounds find nothing
+            const bool stop = n_new == 0 || n_wait == 0;
+            __syncthreads();  // every thread has read the counters before the next round resets them
+            if (stop) break;
         }
-        __syncthreads();
-        // eligible pairs only lose eligibility: with none left waiting, later rounds find nothing
-        if (n_new == 0 || n_wait == 0) break;
-        __syncthreads();
-    }
-    // products, removals, counts
-    for (int p = tid; p < np; p += kReactBlock) {
-        const PairRec r = pairs[p];
-        if (!(r.flags & 2)) continue;
-        int a = r.i, b = r.j;
-        uint64_t ua = uid[a], ub = uid[b];
-        if (ub < ua) {
-            const int t = a; a = b; b = t;
-            const uint64_t tu = ua; ua = ub; ub = tu;
+        if (tid < np && acc) {
+            if (reacted) pairs[tid].flags = r.flags | 2;
+            if (reacted) apply_reaction(r, pos, uid, ctr, P, chem, counts, n_live, cap, &n_prod, &n_react);
         }
-        st_mate(&mate[a], -1);
-        st_mate(&mate[b], -1);
-        const float4 pa = pos[a], pb = pos[b];
-        const int ma = __float_as_int(pa.w), mb = __float_as_int(pb.w);
-        const int inst = ma >> 8;
-        const int sa = ma & 0xFF, sb = mb & 0xFF;
-        const int rx = r.rx;
-        long long* cnt = counts + inst * kMaxSpecies;
-        atomicAdd(&n_react, 1);
-        if (chem->keep_b[rx]) {
-            const int gone = (sa == chem->rb[rx]) ? b : a;
-            const int sg = (gone == a) ? sa : sb;
-            pos[gone].w = __int_as_float((inst << 8) | kDead);
-            atomicAdd((unsigned long long*)&cnt[sg], (unsigned long long)(-1ll));
-            continue;
-        }
-        pos[a].w = __int_as_float((inst << 8) | kDead);
-        pos[b].w = __int_as_float((inst << 8) | kDead);
-        atomicAdd((unsigned long long*)&cnt[sa], (unsigned long long)(-1ll));
-        atomicAdd((unsigned long long*)&cnt[sb], (unsigned long long)(-1ll));
-        const int npr = chem->nprod[rx];
-        if (npr == 0) continue;
-        const InstStep& S = P[inst];
-        const float Da = chem->D[sa], Db = chem->D[sb];
-        const float wgt = (Da + Db > 0.0f) ? Da / (Da + Db) : 0.5f;
-        const float px = wrap_f(pa.x + wgt * minimg_f(pb.x - pa.x, S.L, S.halfL), S.L, S.halfL, S.invL);
-        const float py = wrap_f(pa.y + wgt * minimg_f(pb.y - pa.y, S.L, S.halfL), S.L, S.halfL, S.invL);
-        const float pz = wrap_f(pa.z + wgt * minimg_f(pb.z - pa.z, S.L, S.halfL), S.L, S.halfL, S.invL);
-        const int base = atomicAdd(&n_prod, npr);
-        for (int k = 0; k < npr; ++k) {
-            const int dst = n_live + base + k;
-            if (dst >= cap) {
-                atomicOr(&ctr->err, kErrMolOverflow);
-                continue;
+    } else {
+        for (int round = 0; round < chem->rounds; ++round) {
+            for (int p = tid; p < np; p += kReactBlock) {
+                const PairRec r = pairs[p];
+                if (!(r.flags & 1) || ld_mate(&mate[r.i]) >= 0 || ld_mate(&mate[r.j]) >= 0) continue;
+                atomicMin(&claim[r.i], match_key(r.u24, uid[r.j]));
+                atomicMin(&claim[r.j], match_key(r.u24, uid[r.i]));
             }
-            uint64_t u;
-            if (k == 0) u = ua;
-            else if (k == 1) u = ub;
-            else {
-                uint64_t w[4];
-                philox(ua, ub, S.step, 2ull, S.key0, S.key1, w);
-                u = w[0] | 0x8000000000000000ull;
+            if (tid == 0) {
+                n_new = 0;
+                n_wait = 0;
             }
-            const int ps = chem->prod[rx][k];
-            pos[dst] = make_float4(px, py, pz, __int_as_float((inst << 8) | ps));
-            uid[dst] = u;
-            atomicAdd((unsigned long long*)&cnt[ps], 1ull);
+            __syncthreads();
+            for (int p = tid; p < np; p += kReactBlock) {
+                const PairRec r = pairs[p];
+                if (!(r.flags & 1) || ld_mate(&mate[r.i]) >= 0 || ld_mate(&mate[r.j]) >= 0) continue;
+                const unsigned long long ci =
+                    __hip_atomic_load(&claim[r.i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long cj =
+                    __hip_atomic_load(&claim[r.j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ci == match_key(r.u24, uid[r.j]) && cj == match_key(r.u24, uid[r.i])) {
+                    pairs[p].flags = r.flags | 4;
+                    atomicAdd(&n_new, 1);
+                } else {
+                    atomicAdd(&n_wait, 1);
+                }
+            }
+            __syncthreads();
+            for (int p = tid; p < np; p += kReactBlock) {
+                const PairRec r = pairs[p];
+                if (!(r.flags & 1)) continue;
+                __hip_atomic_store(&claim[r.i], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&claim[r.j], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (r.flags & 4) {
+                    // a molecule in two mutual pairs needs two pairs with equal keys
+                    if (atomicCAS(&mate[r.i], -1, r.j) != -1) atomicOr(&ctr->err, kErrTie);
+                    if (atomicCAS(&mate[r.j], -1, r.i) != -1) atomicOr(&ctr->err, kErrTie);
+                    pairs[p].flags = (r.flags & ~4) | 2;
+                }
+            }
+            __syncthreads();
+            // eligible pairs only lose eligibility: with none left waiting, later rounds find nothing
+            if (n_new == 0 || n_wait == 0) break;
+            __syncthreads();
+        }
+        // products, removals, counts
+        for (int p = tid; p < np; p += kReactBlock) {
+            const PairRec r = pairs[p];
+            if (!(r.flags & 2)) continue;
+            st_mate(&mate[r.i], -1);
+            st_mate(&mate[r.j], -1);
+            apply_reaction(r, pos, uid, ctr, P, chem, counts, n_live, cap, &n_prod, &n_react);
         }
     }
     __syncthreads();
@@ -1405,10 +1496,10 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
                           ? grid
                           : (b.cap + kBinRounds * GSBS_BLOCK - 1) / (kBinRounds * GSBS_BLOCK);
         hipLaunchKernelGGL(k_bin_lds, dim3(g), dim3(GSBS_BLOCK), total_bins * sizeof(uint32_t), st, b.pos_in,
-                           b.uid_in, b.ctr, P, b.cell_count, b.cellrank, fixed, total_bins, ns);
+                           b.uid_in, b.ctr, P, b.cell_count, b.cellrank, b.xnew, fixed, total_bins, ns);
     } else {
         hipLaunchKernelGGL(k_bin, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
-                           b.cell_count, b.cellrank, fixed, ns);
+                           b.cell_count, b.cellrank, b.xnew, fixed, ns);
     }
     mark(0, 1);
     mark(1, 0);
@@ -1417,7 +1508,7 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
                        b.block_sums, b.cell_start, b.ctr);
     mark(1, 1);
     mark(2, 0);
-    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, P,
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, b.xnew,
                        b.cellrank, b.cell_start, b.pos_out, b.pos0_out, b.uid_out,
                        fixed ? b.x0_override : nullptr);
     mark(2, 1);
