@@ -170,7 +170,8 @@ struct gsbs_ctx {
     int32_t cell_cap = 0;
     uint32_t* cell_count = nullptr;
     uint32_t* cell_start = nullptr;
-    uint32_t* block_sums = nullptr;
+    unsigned long long* scan_status = nullptr;
+    uint32_t scan_epoch = 0;
     PairRec* pairs = nullptr;
     uint32_t pair_cap = 0;
     long long* counts = nullptr;
@@ -318,11 +319,12 @@ int ensure_cells(gsbs_ctx* c, int64_t total) {
     HIPCHK(hipStreamSynchronize(c->st));
     dfree(c->cell_count);
     dfree(c->cell_start);
-    dfree(c->block_sums);
+    dfree(c->scan_status);
     CHK(dalloc(&c->cell_count, nc + 1));
     CHK(dalloc(&c->cell_start, nc + 1));
-    CHK(dalloc(&c->block_sums, nc / 4096 + 2));
+    CHK(dalloc(&c->scan_status, nc / 4096 + 2));
     HIPCHK(hipMemsetAsync(c->cell_count, 0, sizeof(uint32_t) * (nc + 1), c->st));
+    HIPCHK(hipMemsetAsync(c->scan_status, 0, sizeof(unsigned long long) * (nc / 4096 + 2), c->st));
     c->cell_cap = (int32_t)nc;
     return GSBS_OK;
 }
@@ -617,7 +619,9 @@ StepBuffers buffers(gsbs_ctx* c) {
     b.xnew = c->xnew;
     b.cell_count = c->cell_count;
     b.cell_start = c->cell_start;
-    b.block_sums = c->block_sums;
+    b.scan_status = c->scan_status;
+    c->scan_epoch = c->scan_epoch >= 0x7FFFFFFFu ? 1u : c->scan_epoch + 1u;
+    b.scan_epoch = c->scan_epoch;
     b.pairs = c->pairs;
     b.pair_cap = c->pair_cap;
     b.claim = c->claim;
@@ -723,6 +727,7 @@ int check_device_errors(gsbs_ctx* c) {
     if (h.err & kErrMolOverflow) return fail(GSBS_ECAPACITY, "molecule capacity exceeded on the device");
     if (h.err & kErrPairOverflow) return fail(GSBS_ECAPACITY, "pair list capacity exceeded on the device");
     if (h.err & kErrTie) return fail(GSBS_ESTATE, "two pairs with identical matching keys");
+    if (h.err & kErrScanStall) return fail(GSBS_EHIP, "cell scan: look-back did not complete");
     return GSBS_OK;
 }
 
@@ -837,7 +842,7 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->xnew);
     dfree(c->cell_count);
     dfree(c->cell_start);
-    dfree(c->block_sums);
+    dfree(c->scan_status);
     dfree(c->pairs);
     dfree(c->counts);
     dfree(c->msteps);

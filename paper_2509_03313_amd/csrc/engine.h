@@ -87,6 +87,7 @@ struct DevCounters {
 constexpr uint32_t kErrMolOverflow = 1u;
 constexpr uint32_t kErrPairOverflow = 2u;
 constexpr uint32_t kErrTie = 4u;
+constexpr uint32_t kErrScanStall = 16u;  // a scan tile waited too long for its predecessors
 
 struct RecordList {
     int32_t n;
@@ -105,7 +106,8 @@ struct StepBuffers {
     float4* xnew;         // per input molecule: end position of the step (meta in .w)
     uint32_t* cell_count; // per bin, zero between steps
     uint32_t* cell_start; // per bin exclusive prefix sums, one extra entry at the end
-    uint32_t* block_sums;
+    unsigned long long* scan_status;  // per scan tile: look-back status word
+    uint32_t scan_epoch;              // 1 .. 2^31 - 1, one per step
     PairRec* pairs;
     uint32_t pair_cap;
     unsigned long long* claim;  // per sorted index, all ones between steps

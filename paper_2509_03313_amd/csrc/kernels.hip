@@ -5,7 +5,7 @@
 //              (Eq. 1), (cell, species) bin of the moved position, per-bin
 //              count and rank (LDS histogram for small grids); the moved
 //              position is kept for the scatter
-//   k_scan_*   exclusive scan of the cell counts (DPP wave scans + LDS)
+//   k_scan     exclusive scan of the cell counts (one pass, decoupled look-back)
 //   k_scatter  molecules into cell order
 //   k_pairs    stencil minimum-image (Eq. 2) candidate search against the
 //              per-reaction cutoff, radial Brownian-bridge contact
@@ -235,32 +235,22 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
     return off + inc - v;
 }
 
-__global__ __launch_bounds__(GSBS_BLOCK) void k_scan_reduce(const uint32_t* __restrict__ cnt, int32_t total,
-                                                          uint32_t* __restrict__ block_sums) {
-    const int base = blockIdx.x * kScanTile;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int c = base + k * GSBS_BLOCK + threadIdx.x;
-        if (c < total) s += cnt[c];
-    }
-    uint32_t tot;
-    block_excl_scan(s, &tot);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+// Single-pass scan with decoupled look-back: each tile publishes its total,
+// then wave 0 walks back over the status words of the tiles before it (64 at a
+// time) until it meets one that carries an inclusive prefix.  A status word is
+// (epoch: 31 bits, inclusive flag, value: 32 bits); words of other steps never
+// match the epoch, so the array is not cleared between steps.  Tiles wait only
+// on tiles with lower indices, which are dispatched first.
+__device__ __forceinline__ unsigned long long scan_word(uint32_t epoch, uint32_t incl, uint32_t v) {
+    return ((unsigned long long)((epoch << 1) | incl) << 32) | v;
 }
 
-__global__ __launch_bounds__(GSBS_BLOCK) void k_scan_apply(uint32_t* __restrict__ cnt, int32_t total,
-                                                         const uint32_t* __restrict__ block_sums,
-                                                         uint32_t* __restrict__ start,
-                                                         DevCounters* __restrict__ ctr) {
-    // offset of this tile: sum of the block sums before it
-    uint32_t part = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += GSBS_BLOCK) part += block_sums[b];
-    uint32_t off_total;
-    block_excl_scan(part, &off_total);
-    const uint32_t tile_off = off_total;
-
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+__global__ __launch_bounds__(GSBS_BLOCK) void k_scan(uint32_t* __restrict__ cnt, int32_t total,
+                                                   unsigned long long* __restrict__ status, uint32_t epoch,
+                                                   uint32_t* __restrict__ start, DevCounters* __restrict__ ctr) {
+    __shared__ uint32_t s_prefix;
+    const int b = blockIdx.x;
+    const int base = b * kScanTile + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t sum = 0;
 #pragma unroll
@@ -270,7 +260,46 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scan_apply(uint32_t* __restrict_
         sum += v[k];
     }
     uint32_t blk_total;
-    uint32_t run = tile_off + block_excl_scan(sum, &blk_total);
+    const uint32_t excl = block_excl_scan(sum, &blk_total);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint32_t prefix = 0;
+        if (b > 0) {
+            if (lane == 0)
+                __hip_atomic_store(&status[b], scan_word(epoch, 0u, blk_total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int j0 = b - 1;; j0 -= 64) {
+                const int j = j0 - lane;
+                unsigned long long w = scan_word(epoch, 1u, 0u);  // before tile 0: an inclusive zero
+                if (j >= 0) {
+                    // bounded: a stall is reported instead of hanging the device
+                    for (int spin = 0;; ++spin) {
+                        w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((uint32_t)(w >> 33) == epoch) break;
+                        if (spin > (1 << 20)) {
+                            atomicOr(&ctr->err, kErrScanStall);
+                            w = scan_word(epoch, 1u, 0u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                const unsigned long long incl = __ballot(((w >> 32) & 1ull) != 0ull);
+                const int stop = incl ? __ffsll((long long)incl) - 1 : 64;  // nearest inclusive word
+                const uint32_t part = lane <= stop ? (uint32_t)w : 0u;
+                prefix += (uint32_t)wave_last((int)wave_incl_scan(part));
+                if (incl) break;
+            }
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&status[b], scan_word(epoch, 1u, prefix + blk_total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = prefix;
+        }
+    }
+    __syncthreads();
+    const uint32_t tile_off = s_prefix;
+    uint32_t run = tile_off + excl;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int c = base + k;
@@ -280,10 +309,14 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scan_apply(uint32_t* __restrict_
         }
         run += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    if (b == gridDim.x - 1 && threadIdx.x == 0) {
         start[total] = tile_off + blk_total;
         ctr->n_live = (int32_t)(tile_off + blk_total);
     }
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int32_t n, unsigned long long v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 // -------------------------------------------------------------- scatter ---
@@ -1503,9 +1536,10 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
     }
     mark(0, 1);
     mark(1, 0);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins, b.block_sums);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins,
-                       b.block_sums, b.cell_start, b.ctr);
+    if (b.scan_epoch == 1u)  // first step, or the epoch counter wrapped: no stale word may match
+        hipLaunchKernelGGL(k_fill_u64, dim3((nb + 255) / 256), dim3(256), 0, st, b.scan_status, nb, 0ull);
+    hipLaunchKernelGGL(k_scan, dim3(nb), dim3(GSBS_BLOCK), 0, st, b.cell_count, total_bins, b.scan_status,
+                       b.scan_epoch, b.cell_start, b.ctr);
     mark(1, 1);
     mark(2, 0);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_in, b.uid_in, b.ctr, b.xnew,
