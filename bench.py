@@ -33,15 +33,18 @@ FP32_PEAK_TFLOPS = 157.3
 # must move at least once): per live molecule for k_bin / k_scatter, per bin
 # for the scan.
 ALG_BYTES = {
-    "k_bin": 16 + 8 + 8,                          # read position+meta, uid; write (bin, rank)
-    "k_scan": 4 + 4 + 4 + 4,                      # per bin: read count twice (reduce, apply); write start; clear count
-    "k_scatter": 16 + 8 + 8 + 4 + 16 + 16 + 8,    # read pos, uid, (bin, rank), start; write pos, pos0, uid
+    "k_bin": 16 + 8 + 8 + 16,                     # read position+meta, uid; write (bin, rank), moved position
+    "k_scan": 4 + 4 + 4,                          # per bin: read count; write start; clear count
+    "k_scatter": 8 + 16 + 16 + 8 + 4 + 16 + 16 + 8,  # read (bin, rank), moved and start position, uid, start;
+                                                  # write pos, pos0, uid
     "k_pairs": 16 + 16 + 8,                       # read sorted end/start positions and uid once
 }
 # Algorithmic FP32 operations per candidate pair of the species-bin search
 # (many molecules per cell, the arithmetic dominates): the minimum-image end
-# separation (3 subtract, 3 multiply, 2 add).
-ALG_FLOP_PER_CANDIDATE = 8
+# separation (3 subtract, 3 multiply, 2 add), the same for the start
+# separation, and the bridge exponent bound (r0 - R)(r1 - R) / s (2 subtract,
+# 2 multiply) that decides whether the pair is evaluated.
+ALG_FLOP_PER_CANDIDATE = 20
 
 
 def parse():
