@@ -469,11 +469,14 @@ __device__ __noinline__ void eval_candidate_call(int i, int j, float d2, const f
 }
 
 // Molecules [j0, j1) of one cell against molecule i, four loads in flight at a time.
-__device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, const float4* __restrict__ pos,
-                                         const float4* __restrict__ pos0, const uint64_t* __restrict__ uid,
-                                         const InstStep& S, const int* row, int contact_only, int log_all,
-                                         DevCounters* __restrict__ ctr, PairRec* __restrict__ pairs, uint32_t pair_cap,
-                                         unsigned long long& ncand) {
+// Molecules j0 .. j1-1 of the sorted array against molecule i.  cpre bounds
+// every cutoff of i's species from above, so the per-partner cutoff lookups
+// (dependent loads) run only for the rare pairs that pass it.
+__device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, float cpre,
+                                         const float4* __restrict__ pos, const float4* __restrict__ pos0,
+                                         const uint64_t* __restrict__ uid, const InstStep& S, const int* row,
+                                         int contact_only, int log_all, DevCounters* __restrict__ ctr,
+                                         PairRec* __restrict__ pairs, uint32_t pair_cap, unsigned long long& ncand) {
     for (int j = j0; j < j1; j += 4) {
         float4 q[4];
 #pragma unroll
@@ -483,9 +486,12 @@ __device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1
         uint32_t m = 0u;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            rxv[u] = row[__float_as_int(q[u].w) & 0xFF];
             d2v[u] = end_d2(q[u], pi, S.L, S.halfL);
-            if (j + u < j1 && rxv[u] >= 0 && d2v[u] < S.rc2[rxv[u]]) m |= 1u << u;
+            rxv[u] = -1;
+            if (j + u < j1 && d2v[u] < cpre) {
+                rxv[u] = row[__float_as_int(q[u].w) & 0xFF];
+                if (rxv[u] >= 0 && d2v[u] < S.rc2[rxv[u]]) m |= 1u << u;
+            }
         }
         while (m) {  // one evaluation site for the (rare) candidates
             const int u = __ffs(m) - 1;
@@ -574,36 +580,45 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         const int* row = rmap + (si & (kMaxSpecies - 1)) * kMaxSpecies;
         const uint32_t bi = wbin[lane];
         const int cg = (int)bi - S.bin_base;  // local cell
+        const float cmax = act ? S.cull2_all[si] : -1.0f;  // bounds every cutoff of the species
+        // End of this lane's bin inside the window: the first position q >= lane whose
+        // successor lies in another bin (position kWin - 1 always ends a run)
+        const unsigned long long ends_lo = __ballot(wbin[lane] != wbin[lane + 1]);
+        const unsigned long long ends_hi = __ballot(lane == 63 || wbin[lane + 64] != wbin[min(lane + 65, kWin - 1)]);
+        const unsigned long long mine = ends_lo & (~0ull << lane);
+        const int run_end = 1 + (mine ? __ffsll((long long)mine) - 1 : 64 + __ffsll((long long)ends_hi) - 1);
         if (act) {
-            // own cell: the sorted molecules after i while they share its bin
-            int k = lane + 1;
+            // own cell: the sorted molecules after i in its bin; the largest cutoff of
+            // the species screens each partner before its own cutoff is looked up
             if ((mi >> 8) == home) {
                 const float* rcrow = rc2s + si * kMaxSpecies;
                 const float Lh = S.L, hLh = S.halfL;
-                for (; k < kWin && wbin[k] == bi; ++k) {
+#pragma unroll 4
+                for (int k = lane + 1; k < run_end; ++k) {
                     const float4 pj = wpos[k];
-                    const int sj = __float_as_int(pj.w) & 0xFF;
                     const float d2 = end_d2(pj, pi, Lh, hLh);
+                    if (!(d2 < cmax)) continue;
+                    const int sj = __float_as_int(pj.w) & 0xFF;
                     if (!(d2 < rcrow[sj])) continue;
                     ++ncand;
                     eval_candidate_call(i, i0 + k, d2, pos0, uid, S, row[sj], contact_only, log_all, ctr, pairs,
                                         pair_cap);
                 }
             } else {
-                for (; k < kWin && wbin[k] == bi; ++k) {
+                for (int k = lane + 1; k < run_end; ++k) {
                     const float4 pj = wpos[k];
-                    const int rx = row[__float_as_int(pj.w) & 0xFF];
-                    if (rx < 0) continue;
                     const float d2 = end_d2(pj, pi, S.L, S.halfL);
-                    if (!(d2 < S.rc2[rx])) continue;
+                    if (!(d2 < cmax)) continue;
+                    const int rx = row[__float_as_int(pj.w) & 0xFF];
+                    if (rx < 0 || !(d2 < S.rc2[rx])) continue;
                     ++ncand;
                     eval_candidate_call(i, i0 + k, d2, pos0, uid, S, rx, contact_only, log_all, ctr, pairs,
                                         pair_cap);
                 }
             }
-            if (k == kWin)
-                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], pos, pos0, uid, S, row, contact_only, log_all, ctr,
-                         pairs, pair_cap, ncand);
+            if (run_end == kWin)  // the bin may continue past the window
+                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], cmax, pos, pos0, uid, S, row, contact_only, log_all,
+                         ctr, pairs, pair_cap, ncand);
         }
         // stencil cells after the own cell in cell order: along each axis only the
         // offsets whose slab can lie within the species' largest cutoff; the wave walks
@@ -614,7 +629,6 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         const int ix = cg / ncc, rem = cg - ix * ncc, iy = rem / nc, iz = rem - iy * nc;
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
         const float h = S.h, hL = S.halfL, eps = S.cull_eps;
-        const float cmax = act ? S.cull2_all[si] : -1.0f;
         int xlo = 1, xhi = 0, ylo = 1, yhi = 0, zlo = 1, zhi = 0;  // empty for idle lanes
         if (act) {
             if (full) {  // every cell along each axis, as offsets 0 .. nc-1 taken modulo nc
@@ -641,8 +655,9 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                     const float4 pm = wpos[ml];
                     const int mm = __float_as_int(pm.w);
                     const InstStep& Sm = P[mm >> 8];
-                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], pos, pos0, uid, Sm,
-                             rmap + (mm & 0xFF) * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap, ncand);
+                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], Sm.cull2_all[mm & 0xFF], pos, pos0,
+                             uid, Sm, rmap + (mm & 0xFF) * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
+                             ncand);
                 }
             }
             wave_sync_lds();
