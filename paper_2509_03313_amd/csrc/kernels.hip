@@ -472,7 +472,7 @@ __device__ __noinline__ void eval_candidate_call(int i, int j, float d2, const f
 // Molecules j0 .. j1-1 of the sorted array against molecule i.  cpre bounds
 // every cutoff of i's species from above, so the per-partner cutoff lookups
 // (dependent loads) run only for the rare pairs that pass it.
-__device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, float cpre,
+__device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, float cpre, float L, float hL,
                                          const float4* __restrict__ pos, const float4* __restrict__ pos0,
                                          const uint64_t* __restrict__ uid, const InstStep& S, const int* row,
                                          int contact_only, int log_all, DevCounters* __restrict__ ctr,
@@ -486,7 +486,7 @@ __device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1
         uint32_t m = 0u;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            d2v[u] = end_d2(q[u], pi, S.L, S.halfL);
+            d2v[u] = end_d2(q[u], pi, L, hL);
             rxv[u] = -1;
             if (j + u < j1 && d2v[u] < cpre) {
                 rxv[u] = row[__float_as_int(q[u].w) & 0xFF];
@@ -532,6 +532,8 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
     __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 6) | lane
     __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
+    __shared__ float hs_f[4 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, cull2_all[]
+    __shared__ int hs_i[4];                            // home instance: nc, reach, bin_base, searched here
     __shared__ int home_s;
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
         rmap[k] = chem->rmap[k / kMaxSpecies][k % kMaxSpecies];
@@ -546,55 +548,108 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     unsigned long long* nq = nq_all[threadIdx.x >> 6];
     unsigned long long ncand = 0;
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        // the block's home instance (that of its first molecule) gets its cutoffs in
-        // LDS: the own-cell loop then reads no global memory per partner
-        __syncthreads();
-        if (threadIdx.x == 0) home_s = __float_as_int(pos[base].w) >> 8;
-        __syncthreads();
-        const int home = home_s;
-        for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
-            rc2s[k] = rmap[k] >= 0 ? P[home].rc2[rmap[k]] : -1.0f;
-        __syncthreads();
         const int i0 = base + (threadIdx.x & ~63);
         const int i = i0 + lane;
-        wave_sync_lds();
+        // the wave's window of 128 sorted molecules, loaded before anything that
+        // depends on it; the block's home instance (that of its first molecule, the
+        // first window entry of thread 0) gets its step parameters and cutoffs in
+        // LDS, so that molecules of that instance -- nearly all -- read no step
+        // parameters from global memory
+        float4 wv[kWin / 64];
+        uint32_t wb[kWin / 64];
 #pragma unroll
-        for (int h2 = 0; h2 < kWin; h2 += 64) {
-            const int j = i0 + h2 + lane;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            uint32_t bn = kNoCell;
+        for (int h2 = 0; h2 < kWin / 64; ++h2) {
+            const int j = i0 + 64 * h2 + lane;
+            wv[h2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            wb[h2] = kNoCell;
             if (j < n) {
-                v = pos[j];
-                bn = __float_as_uint(pos0[j].w);
+                wv[h2] = pos[j];
+                wb[h2] = __float_as_uint(pos0[j].w);
             }
-            wpos[h2 + lane] = v;
-            wbin[h2 + lane] = bn;
         }
-        wave_sync_lds();
+        __syncthreads();  // the previous iteration is done with the block's tables
+        if (threadIdx.x == 0) home_s = __float_as_int(wv[0].w) >> 8;
+        __syncthreads();
+        const int home = home_s;
+        {
+            const InstStep& H = P[home];
+            const int t = threadIdx.x;
+            if (t < kMaxSpecies * kMaxSpecies) rc2s[t] = rmap[t] >= 0 ? H.rc2[rmap[t]] : -1.0f;
+            if (t >= 64 && t < 64 + kMaxSpecies) hs_f[4 + t - 64] = H.cull2_all[t - 64];
+            if (t == 128) {
+                hs_f[0] = H.L;
+                hs_f[1] = H.halfL;
+                hs_f[2] = H.h;
+                hs_f[3] = H.cull_eps;
+            }
+            if (t == 192) {
+                hs_i[0] = H.nc;
+                hs_i[1] = H.reach;
+                hs_i[2] = H.bin_base;
+                hs_i[3] = (H.active && !H.by_species) ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int h2 = 0; h2 < kWin / 64; ++h2) {
+            wpos[64 * h2 + lane] = wv[h2];
+            wbin[64 * h2 + lane] = wb[h2];
+        }
+        __syncthreads();
         // lanes without work stay in the loop: the neighbour queue below works in lockstep
         const float4 pi = wpos[lane];
         const int mi = __float_as_int(pi.w);
         const int si = mi & 0xFF;
-        const InstStep& S = P[i < n ? (mi >> 8) : home];
-        const bool act = i < n && ((reactive >> si) & 1u) && S.active && !S.by_species;
+        const int inst = i < n ? (mi >> 8) : home;
+        const InstStep& S = P[inst];
+        float sL, sHL, sH, sEps, cmax;
+        int sNc, sReach, sBase;
+        bool sOk;
+        if (inst == home) {
+            sL = hs_f[0], sHL = hs_f[1], sH = hs_f[2], sEps = hs_f[3];
+            cmax = hs_f[4 + (si & (kMaxSpecies - 1))];
+            sNc = hs_i[0], sReach = hs_i[1], sBase = hs_i[2], sOk = hs_i[3] != 0;
+        } else {
+            sL = S.L, sHL = S.halfL, sH = S.h, sEps = S.cull_eps;
+            cmax = S.cull2_all[si & (kMaxSpecies - 1)];
+            sNc = S.nc, sReach = S.reach, sBase = S.bin_base, sOk = S.active && !S.by_species;
+        }
+        const bool act = i < n && ((reactive >> si) & 1u) && sOk;
+        if (!act) cmax = -1.0f;  // bounds every cutoff of the species
         const int* row = rmap + (si & (kMaxSpecies - 1)) * kMaxSpecies;
         const uint32_t bi = wbin[lane];
-        const int cg = (int)bi - S.bin_base;  // local cell
-        const float cmax = act ? S.cull2_all[si] : -1.0f;  // bounds every cutoff of the species
+        const int cg = (int)bi - sBase;  // local cell
         // End of this lane's bin inside the window: the first position q >= lane whose
         // successor lies in another bin (position kWin - 1 always ends a run)
         const unsigned long long ends_lo = __ballot(wbin[lane] != wbin[lane + 1]);
         const unsigned long long ends_hi = __ballot(lane == 63 || wbin[lane + 64] != wbin[min(lane + 65, kWin - 1)]);
         const unsigned long long mine = ends_lo & (~0ull << lane);
         const int run_end = 1 + (mine ? __ffsll((long long)mine) - 1 : 64 + __ffsll((long long)ends_hi) - 1);
+        // Own-cell pairs.  Among the lanes of one run (a bin, possibly begun in the
+        // wave before) each pair is taken once, cyclically: lane r of c takes the
+        // members r+1 .. r+(c-1)/2 (mod c), and for even c the first c/2 lanes also
+        // take r + c/2 -- every lane does about c/2 tests instead of c-1-r.  Members
+        // after the lanes (window positions 64 .. run_end-1, then beyond the window)
+        // are taken by every lane of the run.
+        const unsigned long long heads = __ballot(lane == 0 || wbin[lane] != wbin[max(lane - 1, 0)]);
+        const int run_beg = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
+        const int run_lanes = min(run_end, 64) - run_beg;
+        const int rel = lane - run_beg;
+        const int ncyc = (run_lanes - 1) / 2 + (((run_lanes & 1) == 0 && rel < run_lanes / 2) ? 1 : 0);
+        const int nown = ncyc + (run_end > 64 ? run_end - 64 : 0);
+        auto own_partner = [&](int t) {
+            if (t >= ncyc) return 64 + (t - ncyc);
+            const int q = rel + 1 + t;
+            return run_beg + (q >= run_lanes ? q - run_lanes : q);
+        };
         if (act) {
-            // own cell: the sorted molecules after i in its bin; the largest cutoff of
-            // the species screens each partner before its own cutoff is looked up
-            if ((mi >> 8) == home) {
+            // the largest cutoff of the species screens each partner before its own
+            // cutoff is looked up
+            if (inst == home) {
                 const float* rcrow = rc2s + si * kMaxSpecies;
-                const float Lh = S.L, hLh = S.halfL;
+                const float Lh = sL, hLh = sHL;
 #pragma unroll 4
-                for (int k = lane + 1; k < run_end; ++k) {
+                for (int t = 0; t < nown; ++t) {
+                    const int k = own_partner(t);
                     const float4 pj = wpos[k];
                     const float d2 = end_d2(pj, pi, Lh, hLh);
                     if (!(d2 < cmax)) continue;
@@ -605,9 +660,10 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                                         pair_cap);
                 }
             } else {
-                for (int k = lane + 1; k < run_end; ++k) {
+                for (int t = 0; t < nown; ++t) {
+                    const int k = own_partner(t);
                     const float4 pj = wpos[k];
-                    const float d2 = end_d2(pj, pi, S.L, S.halfL);
+                    const float d2 = end_d2(pj, pi, sL, sHL);
                     if (!(d2 < cmax)) continue;
                     const int rx = row[__float_as_int(pj.w) & 0xFF];
                     if (rx < 0 || !(d2 < S.rc2[rx])) continue;
@@ -617,18 +673,18 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                 }
             }
             if (run_end == kWin)  // the bin may continue past the window
-                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], cmax, pos, pos0, uid, S, row, contact_only, log_all,
-                         ctr, pairs, pair_cap, ncand);
+                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], cmax, sL, sHL, pos, pos0, uid, S, row, contact_only,
+                         log_all, ctr, pairs, pair_cap, ncand);
         }
         // stencil cells after the own cell in cell order: along each axis only the
-        // offsets whose slab can lie within the species' largest cutoff; the wave walks
-        // the union of its lanes' offsets in lockstep and queues (molecule, cell) items,
-        // then scans the queued cells one item per lane
-        const int nc = S.nc, m = S.reach;
+        // offsets whose slab can lie within the species' largest cutoff; every lane
+        // walks its own offsets (the wave as long as its longest list) and queues
+        // (molecule, cell) items, then the queued cells are scanned one item per lane
+        const int nc = sNc, m = sReach;
         const int ncc = nc * nc;
         const int ix = cg / ncc, rem = cg - ix * ncc, iy = rem / nc, iz = rem - iy * nc;
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
-        const float h = S.h, hL = S.halfL, eps = S.cull_eps;
+        const float h = sH, hL = sHL, eps = sEps;
         int xlo = 1, xhi = 0, ylo = 1, yhi = 0, zlo = 1, zhi = 0;  // empty for idle lanes
         if (act) {
             if (full) {  // every cell along each axis, as offsets 0 .. nc-1 taken modulo nc
@@ -641,9 +697,9 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                 stencil_range(pi.z, iz, h, hL, reach_d, m, zlo, zhi);
             }
         }
-        const int wxlo = wave_min_i(act ? xlo : 1 << 20), wxhi = wave_max_i(act ? xhi : -(1 << 20));
-        const int wylo = wave_min_i(act ? ylo : 1 << 20), wyhi = wave_max_i(act ? yhi : -(1 << 20));
-        const int wzlo = wave_min_i(act ? zlo : 1 << 20), wzhi = wave_max_i(act ? zhi : -(1 << 20));
+        const int nxr = xhi - xlo + 1, nyr = yhi - ylo + 1, nzr = zhi - zlo + 1;
+        const int nitem = act ? nxr * nyr * nzr : 0;
+        const int witem = wave_max_i(nitem);
         int qn = 0;
         auto drain = [&]() {
             wave_sync_lds();
@@ -654,38 +710,41 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                     const int b = (int)(it >> 6);
                     const float4 pm = wpos[ml];
                     const int mm = __float_as_int(pm.w);
+                    const int sm = mm & (kMaxSpecies - 1);
                     const InstStep& Sm = P[mm >> 8];
-                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], Sm.cull2_all[mm & 0xFF], pos, pos0,
-                             uid, Sm, rmap + (mm & 0xFF) * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
-                             ncand);
+                    float cm, Lm, hLm;
+                    if ((mm >> 8) == home) {
+                        cm = hs_f[4 + sm], Lm = hs_f[0], hLm = hs_f[1];
+                    } else {
+                        cm = Sm.cull2_all[sm], Lm = Sm.L, hLm = Sm.halfL;
+                    }
+                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid, Sm,
+                             rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap, ncand);
                 }
             }
             wave_sync_lds();
             qn = 0;
         };
-        for (int ox = wxlo; ox <= wxhi; ++ox) {
-            const bool inx = ox >= xlo && ox <= xhi;
-            const int qx = wrap_cell(ix + ox, nc);
-            const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
-            for (int oy = wylo; oy <= wyhi; ++oy) {
-                const bool inxy = inx && oy >= ylo && oy <= yhi;
-                const int qy = wrap_cell(iy + oy, nc);
+        for (int it = 0; it < witem; ++it) {
+            bool need = false;
+            int c2 = 0;
+            if (it < nitem) {
+                const int oz = zlo + it % nzr, t2 = it / nzr;
+                const int oy = ylo + t2 % nyr, ox = xlo + t2 / nyr;
+                const int qx = wrap_cell(ix + ox, nc), qy = wrap_cell(iy + oy, nc), qz = wrap_cell(iz + oz, nc);
+                const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
                 const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
-                const float gxy2 = gx * gx + gy * gy;
-                for (int oz = wzlo; oz <= wzhi; ++oz) {
-                    const int qz = wrap_cell(iz + oz, nc);
-                    const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
-                    const int c2 = (qx * nc + qy) * nc + qz;
-                    const bool need = inxy && oz >= zlo && oz <= zhi && !(gxy2 + gz * gz > cmax) && c2 > cg;
-                    const unsigned long long bal = __ballot(need);
-                    if (bal) {
-                        if (need)
-                            nq[qn + __popcll(bal & ((1ull << lane) - 1ull))] =
-                                ((unsigned long long)(uint32_t)(S.bin_base + c2) << 6) | (unsigned long long)lane;
-                        qn += __popcll(bal);
-                        if (qn > kNbrQ - 64) drain();
-                    }
-                }
+                const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
+                c2 = (qx * nc + qy) * nc + qz;
+                need = !(gx * gx + gy * gy + gz * gz > cmax) && c2 > cg;
+            }
+            const unsigned long long bal = __ballot(need);
+            if (bal) {
+                if (need)
+                    nq[qn + __popcll(bal & ((1ull << lane) - 1ull))] =
+                        ((unsigned long long)(uint32_t)(sBase + c2) << 6) | (unsigned long long)lane;
+                qn += __popcll(bal);
+                if (qn > kNbrQ - 64) drain();
             }
         }
         if (qn > 0) drain();
