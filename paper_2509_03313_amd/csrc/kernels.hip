@@ -448,13 +448,13 @@ __device__ __forceinline__ float cell_gap(float x, int q, int o, float h, float 
 // Offsets [lo, hi] within +-m along one axis whose cells can hold a partner of
 // x (cell q) within reach_d: the slab k cells below starts (k - 1) h beyond the
 // distance from x to its cell's lower face, likewise above.
-__device__ __forceinline__ void stencil_range(float x, int q, float h, float hL, float reach_d, int m, int& lo,
-                                              int& hi) {
+__device__ __forceinline__ void stencil_range(float x, int q, float h, float inv_h, float hL, float reach_d, int m,
+                                              int& lo, int& hi) {
     const float a = x - ((float)q * h - hL);        // to the lower face
     const float b = ((float)(q + 1) * h - hL) - x;  // to the upper face
     const float ta = reach_d - a, tb = reach_d - b;
-    lo = ta < 0.0f ? 0 : -min(m, (int)floorf(ta / h) + 1);
-    hi = tb < 0.0f ? 0 : min(m, (int)floorf(tb / h) + 1);
+    lo = ta < 0.0f ? 0 : -min(m, (int)floorf(ta * inv_h) + 1);
+    hi = tb < 0.0f ? 0 : min(m, (int)floorf(tb * inv_h) + 1);
 }
 
 __device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
     __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 6) | lane
     __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
-    __shared__ float hs_f[4 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, cull2_all[]
+    __shared__ float hs_f[5 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, 1/h, cull2_all[]
     __shared__ int hs_i[4];                            // home instance: nc, reach, bin_base, searched here
     __shared__ int home_s;
     for (int k = threadIdx.x; k < kMaxSpecies * kMaxSpecies; k += blockDim.x)
@@ -575,12 +575,13 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
             const InstStep& H = P[home];
             const int t = threadIdx.x;
             if (t < kMaxSpecies * kMaxSpecies) rc2s[t] = rmap[t] >= 0 ? H.rc2[rmap[t]] : -1.0f;
-            if (t >= 64 && t < 64 + kMaxSpecies) hs_f[4 + t - 64] = H.cull2_all[t - 64];
+            if (t >= 64 && t < 64 + kMaxSpecies) hs_f[5 + t - 64] = H.cull2_all[t - 64];
             if (t == 128) {
                 hs_f[0] = H.L;
                 hs_f[1] = H.halfL;
                 hs_f[2] = H.h;
                 hs_f[3] = H.cull_eps;
+                hs_f[4] = H.inv_h;
             }
             if (t == 192) {
                 hs_i[0] = H.nc;
@@ -601,15 +602,15 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         const int si = mi & 0xFF;
         const int inst = i < n ? (mi >> 8) : home;
         const InstStep& S = P[inst];
-        float sL, sHL, sH, sEps, cmax;
+        float sL, sHL, sH, sEps, sInvH, cmax;
         int sNc, sReach, sBase;
         bool sOk;
         if (inst == home) {
-            sL = hs_f[0], sHL = hs_f[1], sH = hs_f[2], sEps = hs_f[3];
-            cmax = hs_f[4 + (si & (kMaxSpecies - 1))];
+            sL = hs_f[0], sHL = hs_f[1], sH = hs_f[2], sEps = hs_f[3], sInvH = hs_f[4];
+            cmax = hs_f[5 + (si & (kMaxSpecies - 1))];
             sNc = hs_i[0], sReach = hs_i[1], sBase = hs_i[2], sOk = hs_i[3] != 0;
         } else {
-            sL = S.L, sHL = S.halfL, sH = S.h, sEps = S.cull_eps;
+            sL = S.L, sHL = S.halfL, sH = S.h, sEps = S.cull_eps, sInvH = S.inv_h;
             cmax = S.cull2_all[si & (kMaxSpecies - 1)];
             sNc = S.nc, sReach = S.reach, sBase = S.bin_base, sOk = S.active && !S.by_species;
         }
@@ -681,8 +682,12 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         // walks its own offsets (the wave as long as its longest list) and queues
         // (molecule, cell) items, then the queued cells are scanned one item per lane
         const int nc = sNc, m = sReach;
-        const int ncc = nc * nc;
-        const int ix = cg / ncc, rem = cg - ix * ncc, iy = rem / nc, iz = rem - iy * nc;
+        // the molecule's cell, by the binning's own arithmetic on the same position
+        auto axis_cell = [&](float x) {
+            const int q = (int)floorf(__fmul_rn(__fadd_rn(x, sHL), sInvH));
+            return q > nc - 1 ? nc - 1 : (q < 0 ? 0 : q);
+        };
+        const int ix = axis_cell(pi.x), iy = axis_cell(pi.y), iz = axis_cell(pi.z);
         const bool full = nc < 2 * m + 1;  // the stencil covers each axis entirely
         const float h = sH, hL = sHL, eps = sEps;
         int xlo = 1, xhi = 0, ylo = 1, yhi = 0, zlo = 1, zhi = 0;  // empty for idle lanes
@@ -691,10 +696,11 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                 xlo = ylo = zlo = 0;
                 xhi = yhi = zhi = nc - 1;
             } else {
-                const float reach_d = sqrtf(cmax) + eps + 1e-3f * h;  // generous: the gap tests decide
-                stencil_range(pi.x, ix, h, hL, reach_d, m, xlo, xhi);
-                stencil_range(pi.y, iy, h, hL, reach_d, m, ylo, yhi);
-                stencil_range(pi.z, iz, h, hL, reach_d, m, zlo, zhi);
+                // generous (hardware root, quotients by a product): the gap tests decide
+                const float reach_d = __builtin_amdgcn_sqrtf(cmax) + eps + 1e-3f * h;
+                stencil_range(pi.x, ix, h, sInvH, hL, reach_d, m, xlo, xhi);
+                stencil_range(pi.y, iy, h, sInvH, hL, reach_d, m, ylo, yhi);
+                stencil_range(pi.z, iz, h, sInvH, hL, reach_d, m, zlo, zhi);
             }
         }
         const int nxr = xhi - xlo + 1, nyr = yhi - ylo + 1, nzr = zhi - zlo + 1;
@@ -714,7 +720,7 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                     const InstStep& Sm = P[mm >> 8];
                     float cm, Lm, hLm;
                     if ((mm >> 8) == home) {
-                        cm = hs_f[4 + sm], Lm = hs_f[0], hLm = hs_f[1];
+                        cm = hs_f[5 + sm], Lm = hs_f[0], hLm = hs_f[1];
                     } else {
                         cm = Sm.cull2_all[sm], Lm = Sm.L, hLm = Sm.halfL;
                     }
@@ -725,18 +731,24 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
             wave_sync_lds();
             qn = 0;
         };
+        int ox = xlo, oy = ylo, oz = zlo;  // this lane's item it, counted up without divisions
         for (int it = 0; it < witem; ++it) {
             bool need = false;
             int c2 = 0;
             if (it < nitem) {
-                const int oz = zlo + it % nzr, t2 = it / nzr;
-                const int oy = ylo + t2 % nyr, ox = xlo + t2 / nyr;
                 const int qx = wrap_cell(ix + ox, nc), qy = wrap_cell(iy + oy, nc), qz = wrap_cell(iz + oz, nc);
                 const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
                 const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
                 const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
                 c2 = (qx * nc + qy) * nc + qz;
                 need = !(gx * gx + gy * gy + gz * gz > cmax) && c2 > cg;
+                if (++oz > zhi) {
+                    oz = zlo;
+                    if (++oy > yhi) {
+                        oy = ylo;
+                        ++ox;
+                    }
+                }
             }
             const unsigned long long bal = __ballot(need);
             if (bal) {
