@@ -40,7 +40,7 @@ extern "C" {
 #define GSBS_ESTATE (-2)     /* call not valid now (e.g. time before the present) */
 #define GSBS_EMINIMAGE (-3)  /* reaction radius or cutoff too large for the cube */
 #define GSBS_ECAPACITY (-4)  /* molecule, pair or cell capacity exceeded */
-#define GSBS_EHIP (-5)       /* HIP runtime error */
+#define GSBS_EHIP (-5)       /* HIP runtime error, or a device-side stall (cell-scan look-back) */
 #define GSBS_ENOMEM (-6)     /* host or device allocation failed */
 
 #define GSBS_MAX_SPECIES 16

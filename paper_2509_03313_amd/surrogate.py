@@ -277,20 +277,25 @@ class Surrogate:
                     self.table[a, b] = float(np.quantile(err[m], 0.95))
         return err
 
-    def usable(self, log_dt: float, c_tot: float, x_norm: np.ndarray, tol: float = 0.01) -> bool:
+    def interval_error(self, log_dt: float, c_tot: float, x_norm: np.ndarray) -> float:
+        """Held-out error estimate (95th percentile of |dN_H2O2| / N_H2O2) for an
+        interval; infinity outside the table or the training inputs' range."""
         if self.table is None:
-            return False
+            return math.inf
         if log_dt < self.dt_edges[0] or log_dt > self.dt_edges[-1]:
-            return False
+            return math.inf
         lc = math.log10(c_tot)
         if lc < self.c_edges[0] or lc > self.c_edges[-1]:
-            return False
+            return math.inf
         span = self.hi - self.lo
         if np.any(x_norm < self.lo - 0.1 * span - 1e-3) or np.any(x_norm > self.hi + 0.1 * span + 1e-3):
-            return False
+            return math.inf
         a = int(np.clip(np.searchsorted(self.dt_edges, log_dt, side="right") - 1, 0, len(self.dt_edges) - 2))
         b = int(np.clip(np.searchsorted(self.c_edges, lc, side="right") - 1, 0, len(self.c_edges) - 2))
-        return bool(self.table[a, b] <= tol)
+        return float(self.table[a, b])
+
+    def usable(self, log_dt: float, c_tot: float, x_norm: np.ndarray, tol: float = 0.01) -> bool:
+        return self.interval_error(log_dt, c_tot, x_norm) <= tol
 
     def save(self, path: str):
         np.savez(path, w=self.net.get_weights(), mu=self.mu, sd=self.sd, mu_y=self.mu_y, sd_y=self.sd_y, lo=self.lo,
@@ -305,16 +310,24 @@ class Surrogate:
 
 
 # ------------------------------------------------------------ multi-pulse run ---
-def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01) -> dict:
+def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01,
+        budget: Optional[float] = None) -> dict:
     """Plain (surrogate None) or hybrid multi-pulse run of one cube.  Returns
     the H2O2 count and G(H2O2) at every pulse start after the first and at the
-    end, the wall time and the number of intervals the network took."""
+    end, the wall time and the number of intervals the network took.
+
+    An interval goes to the network when its held-out error estimate is at most
+    tol.  With a budget, the estimates of the intervals the network takes are
+    also summed over the run and must stay within it: errors of consecutive
+    intervals add up in the state (H2O2 is long-lived), so the per-interval
+    rule alone does not bound the error of the run."""
     import torch
     inj = plan.injections()
     e = _engine(plan.L, seed)
     for j in inj:
         e.inject(0, j.t, j.xyz, j.species, j.edep_ev)
     times, n_h2o2, g_h2o2, used, at_switch = [], [], [], [], []
+    spent = 0.0
     row = torch.empty((1, gsbs.N_FEATURES), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -332,7 +345,9 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
                                    out=row[0])
                 c_tot = float(np.sum(at_switch[-1])) / (NA * plan.L ** 3 * 1e-24)
                 x_norm = row[0].cpu().numpy()
-                if surrogate.usable(math.log10(t_next - ts), c_tot, x_norm, tol):
+                err = surrogate.interval_error(math.log10(t_next - ts), c_tot, x_norm)
+                if err <= tol and (budget is None or spent + err <= budget):
+                    spent += err
                     y = surrogate.net.forward(row)
                     gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_out(), surrogate.sd_y, C_FLOOR,
                                          relative=True)
@@ -355,4 +370,5 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     e.close()
     return dict(t=np.array(times), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
                 intervals_by_network=int(sum(used)), used=np.array(used), counts_at_switch=np.array(at_switch),
+                error_estimate_spent=spent,
                 steps=st["steps"], molecule_steps=st["molecule_steps"])
