@@ -251,14 +251,21 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scan(uint32_t* __restrict__ cnt,
     __shared__ uint32_t s_prefix;
     const int b = blockIdx.x;
     const int base = b * kScanTile + threadIdx.x * kScanItems;
+    const bool whole = base + kScanItems <= total;  // 16-byte vector accesses (the arrays are 256-byte aligned)
     uint32_t v[kScanItems];
     uint32_t sum = 0;
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int c = base + k;
-        v[k] = c < total ? cnt[c] : 0u;
-        sum += v[k];
+        for (int k = 0; k < kScanItems; k += 4) {
+            const uint4 q = *reinterpret_cast<const uint4*>(cnt + base + k);
+            v[k] = q.x, v[k + 1] = q.y, v[k + 2] = q.z, v[k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = base + k < total ? cnt[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
     uint32_t blk_total;
     const uint32_t excl = block_excl_scan(sum, &blk_total);
     if (threadIdx.x < 64) {
@@ -300,14 +307,31 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_scan(uint32_t* __restrict__ cnt,
     __syncthreads();
     const uint32_t tile_off = s_prefix;
     uint32_t run = tile_off + excl;
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int c = base + k;
-        if (c < total) {
-            start[c] = run;
-            cnt[c] = 0u;
+        for (int k = 0; k < kScanItems; k += 4) {
+            uint4 q;
+            q.x = run;
+            run += v[k];
+            q.y = run;
+            run += v[k + 1];
+            q.z = run;
+            run += v[k + 2];
+            q.w = run;
+            run += v[k + 3];
+            *reinterpret_cast<uint4*>(start + base + k) = q;
+            *reinterpret_cast<uint4*>(cnt + base + k) = make_uint4(0u, 0u, 0u, 0u);
         }
-        run += v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int c = base + k;
+            if (c < total) {
+                start[c] = run;
+                cnt[c] = 0u;
+            }
+            run += v[k];
+        }
     }
     if (b == gridDim.x - 1 && threadIdx.x == 0) {
         start[total] = tile_off + blk_total;

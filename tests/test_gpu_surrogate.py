@@ -153,3 +153,8 @@ def test_surrogate_pipeline(g):
     say("hybrid", hyb["intervals_by_network"], hyb["steps"], hyb["n_h2o2"].tolist(), "plain", plain["steps"],
         plain["n_h2o2"].tolist())
     assert hyb["intervals_by_network"] >= 1 and hyb["steps"] < plain["steps"]
+    # a budget on the summed error estimate: with 0.6 % per interval, 1 % admits one
+    s.table[:] = 0.006
+    hyb_b = SU.run(plan, s, tol=1.0, budget=0.01)
+    say("budgeted hybrid", hyb_b["intervals_by_network"], hyb_b["error_estimate_spent"])
+    assert hyb_b["intervals_by_network"] == 1 and abs(hyb_b["error_estimate_spent"] - 0.006) < 1e-12
