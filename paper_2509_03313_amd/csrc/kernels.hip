@@ -38,16 +38,12 @@ __device__ __forceinline__ float ln_u24(uint64_t w) {
 // above the midpoint x is folded to 2 - x so the sincospi argument stays exact.
 __device__ __forceinline__ void sincos_2pi_u24(uint64_t w, float* s, float* c) {
     const uint32_t k = (uint32_t)(w >> 40);
+    const bool lower = k < (1u << 23);  // selected, not branched: one call for the wave
+    const uint32_t m = lower ? 2u * k + 1u : (1u << 25) - 2u * k - 1u;
     float ss, cc;
-    if (k < (1u << 23)) {
-        sincospif((float)(2u * k + 1u) * 0x1p-24f, &ss, &cc);
-        *s = ss;
-        *c = cc;
-    } else {
-        sincospif((float)((1u << 25) - 2u * k - 1u) * 0x1p-24f, &ss, &cc);
-        *s = -ss;
-        *c = cc;
-    }
+    sincospif((float)m * 0x1p-24f, &ss, &cc);
+    *s = lower ? ss : -ss;
+    *c = cc;
 }
 
 // Position after this step's Brownian jump: Gaussian of variance 2 D dt per
