@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM counters")
+    ap.add_argument("--batched", type=int, default=0, metavar="N",
+                    help="the batched metric: N independent instances of uneven size stepped together")
+    ap.add_argument("--batched-t-end", type=float, default=100.0, help="end time (ns) of the batched runs")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -210,6 +213,110 @@ def cpu_baseline(wl, n_steps):
                        f"({ms} molecule-steps, {dt:.1f} s, 1 thread)")
 
 
+def roofline_of(prof, kernel=None, traffic_file=None):
+    """Roofline object of one kernel of a profile (by default the one with the
+    most time): HBM for the streaming kernels, FP32 vector for the species-bin
+    search."""
+    dom = kernel or max(prof, key=lambda k: prof[k][0])
+    tot_ms, launches, work, cand = prof[dom]
+    avg_s = tot_ms / 1e3 / max(launches, 1)
+    if dom in ALG_BYTES:
+        ach = ALG_BYTES[dom] * work / (tot_ms / 1e3) / 1e9
+        r = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=round(ach / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
+                 avg_launch_us=round(avg_s * 1e6, 3), alg_bytes_per_unit=ALG_BYTES[dom],
+                 units_per_launch=round(work / max(launches, 1), 1))
+    elif dom == "k_pairs_sp":
+        ach = ALG_FLOP_PER_CANDIDATE * cand / (tot_ms / 1e3) / 1e12
+        r = dict(bound="alu", achieved=round(ach, 4), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                 frac=round(ach / FP32_PEAK_TFLOPS, 6), traffic=None, kernel=dom,
+                 avg_launch_us=round(avg_s * 1e6, 3), alg_flop_per_candidate=ALG_FLOP_PER_CANDIDATE,
+                 candidates_per_launch=round(cand / max(launches, 1), 1))
+    else:
+        r = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                 kernel=dom, avg_launch_us=round(avg_s * 1e6, 3))
+    if traffic_file and os.path.exists(traffic_file):
+        t = json.load(open(traffic_file))
+        if t.get("kernels_hash") == kernels_hash() and dom in t.get("per_launch_bytes", {}):
+            r["traffic"] = t["per_launch_bytes"][dom]
+    return r
+
+
+def batched_bench(args):
+    """Batched instances: the first pulse of 64 independent cubes of uneven size
+    (edges 2-10 um, 0.1-2 Gy) stepped together from 1 ps to --batched-t-end."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import workload as W
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    insts = W.batched_first_pulses(args.seed, args.batched)
+    Ls = [L for L, _ in insts]
+    caps = [int(len(j.species) * 1.5) + 4096 for _, j in insts]
+    dev = [(torch.from_numpy(np.ascontiguousarray(j.xyz)).cuda(), torch.from_numpy(np.ascontiguousarray(j.species)).cuda())
+           for _, j in insts]
+    n_mol = sum(len(j.species) for _, j in insts)
+    t_end = args.batched_t_end
+    rec = np.concatenate([[0.0], W.log_times(W.DT0_NS, t_end, 20)])
+    rec[-1] = t_end
+    note(f"{len(insts)} instances, {n_mol} molecules, to {t_end:g} ns")
+
+    def engine(tune):
+        p = gsbs.gsbs_default_params()
+        p.autotune = 1 if tune else 0
+        return gsbs.Engine(Ls, 1000, W.D_CONFIG, W.REACTIONS, params=p, capacity=caps)
+
+    def run(e):
+        for i, (_, j) in enumerate(insts):
+            e.inject(i, 0.0, dev[i][0], dev[i][1], j.edep_ev)
+            e.set_records(i, rec)
+        e.advance_to([t_end] * len(insts))
+
+    for k in range(args.warmup):
+        e = engine(True)
+        t = time.perf_counter()
+        run(e)
+        torch.cuda.synchronize()
+        note(f"warmup {k}: {time.perf_counter() - t:.2f} s, stats {e.stats()}")
+        e.close()
+    engines = [engine(False) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in engines:
+        run(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = [e.stats() for e in engines]
+    for e in engines:
+        e.close()
+    msteps = sum(s_["molecule_steps"] for s_ in stats)
+    note(f"timed {args.steps} runs: {wall:.2f} s")
+    e = engine(False)
+    gsbs.gsbs_set_profiling(e.ctx, True)
+    run(e)
+    prof = gsbs.gsbs_get_profile(e.ctx)
+    e.close()
+    note(f"profile: {prof}")
+    line = {
+        "metric": "molecule-steps/s of SBS diffusion-reaction, batched instances",
+        "value": round(msteps / wall, 1), "unit": "molecule-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(insts)} batched instances (edges 2-10 um, first pulse of 0.1-2 Gy), "
+                               f"1 ps -> {t_end:g} ns", "instances": len(insts), "molecules": n_mol,
+                   "sbs_steps": stats[0]["steps"]},
+        "roofline": roofline_of(prof),
+        "roofline_streaming": {k: roofline_of(prof, k) for k in ("k_bin", "k_scatter") if k in prof},
+        "profile_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "profile_launches": {k: v[1] for k, v in prof.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -221,6 +328,9 @@ def main():
 
     if args.surrogate:
         surrogate_bench(args)
+        return
+    if args.batched:
+        batched_bench(args)
         return
 
     if args.calibrate_copy:
@@ -291,29 +401,7 @@ def main():
         pst = e.stats()
         note(f"profile: {prof}")
         e.close()
-        dom = max(prof, key=lambda k: prof[k][0])
-        tot_ms, launches, work, cand = prof[dom]
-        avg_s = tot_ms / 1e3 / max(launches, 1)
-        if dom in ALG_BYTES:
-            ach = ALG_BYTES[dom] * work / (tot_ms / 1e3) / 1e9
-            roofline = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=round(ach / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                            avg_launch_us=round(avg_s * 1e6, 3), alg_bytes_per_unit=ALG_BYTES[dom],
-                            units_per_launch=round(work / max(launches, 1), 1))
-        elif dom == "k_pairs_sp":
-            ach = ALG_FLOP_PER_CANDIDATE * cand / (tot_ms / 1e3) / 1e12
-            roofline = dict(bound="alu", achieved=round(ach, 4), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                            frac=round(ach / FP32_PEAK_TFLOPS, 6), traffic=None, kernel=dom,
-                            avg_launch_us=round(avg_s * 1e6, 3), alg_flop_per_candidate=ALG_FLOP_PER_CANDIDATE,
-                            candidates_per_launch=round(cand / max(launches, 1), 1))
-        else:
-            roofline = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                            kernel=dom, avg_launch_us=round(avg_s * 1e6, 3))
-        tr = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tr):
-            t = json.load(open(tr))
-            if t.get("kernels_hash") == kernels_hash() and dom in t.get("per_launch_bytes", {}):
-                roofline["traffic"] = t["per_launch_bytes"][dom]
+        roofline = roofline_of(prof, traffic_file=os.path.join(ROOT, "profiles", "traffic.json"))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -385,7 +385,8 @@ class Engine:
         self.records = [np.zeros(0)] * self.n_inst
         if stream is None and torch is not None and torch.cuda.is_available():
             stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-        self.ctx = gsbs_create([(x, capacity) for x in Ls], seed, stream)
+        caps = list(capacity) if np.ndim(capacity) else [capacity] * len(Ls)
+        self.ctx = gsbs_create([(x, int(c)) for x, c in zip(Ls, caps)], seed, stream)
         gsbs_set_species(self.ctx, D)
         if params is not None:
             gsbs_set_params(self.ctx, params)

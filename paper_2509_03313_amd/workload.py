@@ -275,3 +275,16 @@ def batched_instances(seed: int, n_instances: int = 64):
         dav = float(10.0 ** rng.uniform(-2.0, 5.0))
         out.append(dict(L=L, dose_per_pulse=dp, n_pulses=n_p, avg_rate=dav, seed=seed * 1000 + i))
     return out
+
+
+def batched_first_pulses(seed: int, n_instances: int = 64):
+    """The first pulse of every batched instance as one injection at t = 0
+    (z-parallel tracks of that instance's dose): [(L, Injection)]."""
+    out = []
+    for p in batched_instances(seed, n_instances):
+        rng = np.random.default_rng([p["seed"], 5])
+        L = p["L"]
+        n_tr = int(round(tracks_per_gray(L) * p["dose_per_pulse"]))
+        pos, sp = tracks_z(rng, L, n_tr)
+        out.append((L, Injection(0.0, _into_box(pos, L), sp, n_tr * L * LET_KEV_PER_UM)))
+    return out
