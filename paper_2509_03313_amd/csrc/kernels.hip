@@ -18,6 +18,8 @@
 // All molecules of all instances live in one array; the sort groups them by
 // instance (each instance owns a contiguous range of global cells).  Removed
 // molecules stay in the array, flagged, until the next sort drops them.
+#include <type_traits>
+
 #include "device_common.h"
 #include "engine.h"
 
@@ -489,9 +491,17 @@ __device__ __noinline__ void eval_candidate_call(int i, int j, float d2, const f
 }
 
 // Molecules [j0, j1) of one cell against molecule i, four loads in flight at a time.
+// The same without Eq. 2, for two molecules known to be less than L/2 apart
+// along every axis (Eq. 2 is then the identity): identical FP32 result.
+__device__ __forceinline__ float sep2(const float4& pj, const float4& pi) {
+    const float dx = __fsub_rn(pj.x, pi.x), dy = __fsub_rn(pj.y, pi.y), dz = __fsub_rn(pj.z, pi.z);
+    return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
 // Molecules j0 .. j1-1 of the sorted array against molecule i.  cpre bounds
 // every cutoff of i's species from above, so the per-partner cutoff lookups
 // (dependent loads) run only for the rare pairs that pass it.
+template <bool kEq2 = true>
 __device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1, float cpre, float L, float hL,
                                          const float4* __restrict__ pos, const float4* __restrict__ pos0,
                                          const uint64_t* __restrict__ uid, const InstStep& S, const int* row,
@@ -506,7 +516,7 @@ __device__ __forceinline__ void scan_run(int i, const float4& pi, int j0, int j1
         uint32_t m = 0u;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            d2v[u] = end_d2(q[u], pi, L, hL);
+            d2v[u] = kEq2 ? end_d2(q[u], pi, L, hL) : sep2(q[u], pi);
             rxv[u] = -1;
             if (j + u < j1 && d2v[u] < cpre) {
                 rxv[u] = row[__float_as_int(q[u].w) & 0xFF];
@@ -550,7 +560,7 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     __shared__ unsigned long long s_cand;
     __shared__ float4 wpos_all[GSBS_BLOCK / 64][kWin];
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
-    __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 6) | lane
+    __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 7) | (needs Eq. 2 << 6) | lane
     __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
     __shared__ float hs_f[5 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, 1/h, cull2_all[]
     __shared__ int hs_i[4];                            // home instance: nc, reach, bin_base, searched here
@@ -658,28 +668,46 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         const int ncyc = (run_lanes - 1) / 2 + (((run_lanes & 1) == 0 && rel < run_lanes / 2) ? 1 : 0);
         const int nown = ncyc + (run_end > 64 ? run_end - 64 : 0);
         auto own_partner = [&](int t) {
-            if (t >= ncyc) return 64 + (t - ncyc);
             const int q = rel + 1 + t;
-            return run_beg + (q >= run_lanes ? q - run_lanes : q);
+            const int kc = run_beg + (q >= run_lanes ? q - run_lanes : q);
+            return t >= ncyc ? 64 + (t - ncyc) : kc;
         };
         if (act) {
             // the largest cutoff of the species screens each partner before its own
             // cutoff is looked up
             if (inst == home) {
                 const float* rcrow = rc2s + si * kMaxSpecies;
-                const float Lh = sL, hLh = sHL;
-#pragma unroll 4
-                for (int t = 0; t < nown; ++t) {
-                    const int k = own_partner(t);
-                    const float4 pj = wpos[k];
-                    const float d2 = end_d2(pj, pi, Lh, hLh);
-                    if (!(d2 < cmax)) continue;
-                    const int sj = __float_as_int(pj.w) & 0xFF;
-                    if (!(d2 < rcrow[sj])) continue;
-                    ++ncand;
-                    eval_candidate_call(i, i0 + k, d2, pos0, uid, S, row[sj], contact_only, log_all, ctr, pairs,
-                                        pair_cap);
-                }
+                // Partners four at a time (their LDS reads in flight together).  Two
+                // molecules of one cell are less than a cell width apart, below L/2
+                // once an edge holds 3 cells: Eq. 2 then changes nothing and is skipped.
+                auto own_loop = [&](auto plain_tag) {
+                    constexpr bool kPlain = decltype(plain_tag)::value;
+                    for (int t0 = 0; t0 < nown; t0 += 4) {
+                        float4 pj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) pj[u] = wpos[own_partner(min(t0 + u, nown - 1))];
+                        float d2[4];
+                        uint32_t pass = 0u;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            d2[u] = kPlain ? sep2(pj[u], pi) : end_d2(pj[u], pi, sL, sHL);
+                            if (t0 + u < nown && d2[u] < cmax) pass |= 1u << u;
+                        }
+                        while (pass) {  // rare: the partner is read again
+                            const int u = __ffs(pass) - 1;
+                            pass &= pass - 1u;
+                            const float dd = u == 0 ? d2[0] : (u == 1 ? d2[1] : (u == 2 ? d2[2] : d2[3]));
+                            const int k = own_partner(t0 + u);
+                            const int sj = __float_as_int(wpos[k].w) & 0xFF;
+                            if (!(dd < rcrow[sj])) continue;
+                            ++ncand;
+                            eval_candidate_call(i, i0 + k, dd, pos0, uid, S, row[sj], contact_only, log_all, ctr,
+                                                pairs, pair_cap);
+                        }
+                    }
+                };
+                if (sNc >= 3) own_loop(std::true_type{});
+                else own_loop(std::false_type{});
             } else {
                 for (int t = 0; t < nown; ++t) {
                     const int k = own_partner(t);
@@ -694,8 +722,8 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                 }
             }
             if (run_end == kWin)  // the bin may continue past the window
-                scan_run(i, pi, i0 + kWin, (int)start[bi + 1], cmax, sL, sHL, pos, pos0, uid, S, row, contact_only,
-                         log_all, ctr, pairs, pair_cap, ncand);
+                scan_run<true>(i, pi, i0 + kWin, (int)start[bi + 1], cmax, sL, sHL, pos, pos0, uid, S, row,
+                               contact_only, log_all, ctr, pairs, pair_cap, ncand);
         }
         // stencil cells after the own cell in cell order: along each axis only the
         // offsets whose slab can lie within the species' largest cutoff; every lane
@@ -730,10 +758,14 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         auto drain = [&]() {
             wave_sync_lds();
             for (int e0 = 0; e0 < qn; e0 += 64) {
-                if (e0 + lane < qn) {
-                    const unsigned long long it = nq[e0 + lane];
+                const bool has = e0 + lane < qn;
+                const unsigned long long it = has ? nq[e0 + lane] : 0ull;
+                // Eq. 2 only where some item of the pass needs it (a wrapped cell, or a
+                // grid too small for neighbour cells to stay within L/2)
+                const bool eq2 = __ballot(has && ((it >> 6) & 1ull)) != 0ull;
+                if (has) {
                     const int ml = (int)(it & 63ull);
-                    const int b = (int)(it >> 6);
+                    const int b = (int)(it >> 7);
                     const float4 pm = wpos[ml];
                     const int mm = __float_as_int(pm.w);
                     const int sm = mm & (kMaxSpecies - 1);
@@ -744,19 +776,29 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                     } else {
                         cm = Sm.cull2_all[sm], Lm = Sm.L, hLm = Sm.halfL;
                     }
-                    scan_run(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid, Sm,
-                             rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap, ncand);
+                    if (eq2)
+                        scan_run<true>(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid,
+                                       Sm, rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
+                                       ncand);
+                    else
+                        scan_run<false>(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid,
+                                        Sm, rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
+                                        ncand);
                 }
             }
             wave_sync_lds();
             qn = 0;
         };
         int ox = xlo, oy = ylo, oz = zlo;  // this lane's item it, counted up without divisions
+        // neighbour cells that are not wrapped lie within (m + 1) cells along every
+        // axis: less than L/2 apart once an edge holds 2m + 3 cells
+        const bool near_ok = !full && nc >= 2 * m + 3;
         for (int it = 0; it < witem; ++it) {
-            bool need = false;
+            bool need = false, wrapped = false;
             int c2 = 0;
             if (it < nitem) {
                 const int qx = wrap_cell(ix + ox, nc), qy = wrap_cell(iy + oy, nc), qz = wrap_cell(iz + oz, nc);
+                wrapped = qx != ix + ox || qy != iy + oy || qz != iz + oz;
                 const float gx = full ? 0.0f : cell_gap(pi.x, ix, ox, h, hL, eps);
                 const float gy = full ? 0.0f : cell_gap(pi.y, iy, oy, h, hL, eps);
                 const float gz = full ? 0.0f : cell_gap(pi.z, iz, oz, h, hL, eps);
@@ -774,7 +816,8 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
             if (bal) {
                 if (need)
                     nq[qn + __popcll(bal & ((1ull << lane) - 1ull))] =
-                        ((unsigned long long)(uint32_t)(sBase + c2) << 6) | (unsigned long long)lane;
+                        ((unsigned long long)(uint32_t)(sBase + c2) << 7) |
+                        ((wrapped || !near_ok) ? 64ull : 0ull) | (unsigned long long)lane;
                 qn += __popcll(bal);
                 if (qn > kNbrQ - 64) drain();
             }
