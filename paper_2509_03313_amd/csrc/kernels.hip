@@ -1469,10 +1469,12 @@ __device__ __forceinline__ void apply_reaction(const PairRec& r, float4* __restr
 // Slot of molecule `mol` in the block's open-addressing table (inserted when
 // absent).  The table holds at most two molecules per pair and is at most
 // half full, so the probe ends.
-constexpr int kReactHash = 2048;
-constexpr int kReactFast = kReactHash / 4;  // pairs handled in LDS
+constexpr int kReactHashBits = 12;
+constexpr int kReactHash = 1 << kReactHashBits;
+constexpr int kReactFast = kReactHash / 4;  // pairs handled in LDS (one per thread)
+static_assert(kReactFast <= kReactBlock, "one pair per thread");
 __device__ __forceinline__ int react_slot(int* key, int mol) {
-    int h = (int)(((uint32_t)mol * 2654435761u) >> (32 - 11)) & (kReactHash - 1);
+    int h = (int)(((uint32_t)mol * 2654435761u) >> (32 - kReactHashBits));
     while (true) {
         const int prev = atomicCAS(&key[h], -1, mol);
         if (prev == -1 || prev == mol) return h;
