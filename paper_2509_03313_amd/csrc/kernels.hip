@@ -965,8 +965,9 @@ __device__ __forceinline__ void mask_push(uint32_t& m, float d2, float rc2) {
         : "vcc");
 }
 
-// Candidate mask of one stage: bit t set when staged B t lies within the
-// cutoff of this lane's A (end separation, FP32, fixed operation order).  The
+// Candidate mask of one stage: bit t set when staged B t may lie within the
+// cutoff of this lane's A (a superset: rc2 comes with a relative margin of
+// 2^-19 over the exact FP32 test, which the candidate stage applies).  The
 // tests run from t = 31 down so that doubling the mask lands bit t at t.
 template <bool kShift, bool kSame, bool kZero = false>
 __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
@@ -994,7 +995,10 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
                 dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
                 dz = minimg_f(__fsub_rn(p.z, pa.z), L, hL);
             }
-            float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+            // screening value with fused multiply-adds (3 operations instead of 5);
+            // rc2 carries a margin above the exact rounding differences, and the
+            // candidate stage repeats the exact test
+            float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __fmul_rn(dz, dz)));
             if (kSame) d2 = (__float_as_int(p.w) > ia) ? d2 : INFINITY;  // each pair once
             mask_push(m, d2, rc2);
         }
@@ -1015,7 +1019,6 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
                                                  int contact_only, int log_all, DevCounters* __restrict__ ctr,
                                                  PairRec* __restrict__ pairs, uint32_t pair_cap,
                                                  unsigned long long& ncand) {
-    ncand += (unsigned long long)(__popc(mlo) + __popc(mhi));
     while (__ballot((mlo | mhi) != 0u)) {
         const int have = __popc(mlo) + __popc(mhi);
         const int mine = have < kLaneQuota ? have : kLaneQuota;
@@ -1067,6 +1070,7 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
                 const float aexp = (r0a - R) * (r1a - R) * inv_s;
                 // (the end separation is tested again: padding, whose positions lie
                 // far outside the cube, never reaches the evaluation)
+                ncand += d2 < rc2 ? 1ull : 0ull;  // the exact test: candidates as the oracle counts them
                 need = d2 < rc2 &&
                        (log_all || contact_only || r0a <= 1.01f * R || r1a <= 1.01f * R || !(aexp > 18.01f));
                 r1 = d2;
@@ -1228,6 +1232,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                 const float c2 = S.cull2[rx];
                 const float rcu = sqrtf(c2);
                 const float rc2 = S.rc2[rx];
+                const float rc2m = rc2 * (1.0f + 0x1p-19f);
                 const float Rr = S.R[rx], inv_s = S.inv_s[rx];
                 const bool same = (sj == si);
                 int cx0, cx1, cy0, cy1, czl, czh;
@@ -1363,17 +1368,17 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                         uint32_t mlo, mhi;
                         if (exact) {
                             if (zero) {
-                                if (same) stage_mask<true, true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
-                                else stage_mask<true, false, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                                if (same) stage_mask<true, true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                                else stage_mask<true, false, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
                             } else {
-                                if (same) stage_mask<true, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
-                                else stage_mask<true, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                                if (same) stage_mask<true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                                else stage_mask<true, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
                             }
                             stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S, contact_only,
                                                    log_all, ctr, pairs, pair_cap, ncand);
                         } else {
-                            if (same) stage_mask<false, true>(w, pa, ia, rc2, L, hL, mlo, mhi);
-                            else stage_mask<false, false>(w, pa, ia, rc2, L, hL, mlo, mhi);
+                            if (same) stage_mask<false, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                            else stage_mask<false, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
                             stage_candidates<false>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S,
                                                     contact_only, log_all, ctr, pairs, pair_cap, ncand);
                         }
