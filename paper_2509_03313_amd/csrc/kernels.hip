@@ -1220,6 +1220,9 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
             wave_sync_lds();
             w.ap[lane] = pa;
             w.aq[lane] = qa;
+            // sorted index of the chunk's first molecule, the lowest of the chunk (rows
+            // and cells are listed in bin order)
+            const int ia_first = __builtin_amdgcn_readfirstlane(ia);
             // bounding box of the chunk's end positions (the box does not cross the cube faces)
             const float blx = wave_min_f(va ? pa.x : kFar), bhx = wave_max_f(va ? pa.x : -kFar);
             const float bly = wave_min_f(va ? pa.y : kFar), bhy = wave_max_f(va ? pa.y : -kFar);
@@ -1292,6 +1295,21 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                                 float gz;
                                 axis_shift(wl, wh, blz, bhz, h, hL, eps, szc, vz, gz);
                                 code2 = base_code | (szc << 4) | ((vxy && vz) ? 64 : 0);
+                            }
+                            if (same) {
+                                // a pair of one species is taken from its lower sorted
+                                // index: partners below the chunk's first molecule would
+                                // all be masked, so they are not streamed
+                                auto trim = [&](int& j, int& nn) {
+                                    const int e = j + nn;
+                                    if (e <= ia_first) nn = 0;
+                                    else if (j < ia_first) {
+                                        nn = e - ia_first;
+                                        j = ia_first;
+                                    }
+                                };
+                                trim(j1, n1);
+                                trim(j2, n2);
                             }
                         }
                     }
