@@ -861,10 +861,13 @@ constexpr int kListCap = 1024;  // candidates compacted per pass (16 per lane)
 constexpr int kLaneQuota = kListCap / 64;
 constexpr float kFar = 3.0e38f;
 
+// Shift of one axis from its code (0: none, 1: +L, 2: -L).
+__device__ __forceinline__ float shift_of(int code, float L) { return code == 1 ? L : (code == 2 ? -L : 0.0f); }
+
 struct SpWave {
     float4 bp[64];   // staged B end position, .w = bits of the sorted index (-1: padding)
-    float4 bs[64];   // staged B shift per axis, .w = 1 when the shift is exact
-    float4 bq[64];   // staged B start position
+    float4 bs[64];   // staged B end position moved by its shift (screening only), .w = sorted index
+    float4 bq[64];   // staged B start position, .w = bits of its shift code
     float4 ap[64];   // A end position, .w = bits of the sorted index
     float4 aq[64];   // A start position
     int32_t seg_j0[kSegCap];
@@ -969,7 +972,7 @@ __device__ __forceinline__ void mask_push(uint32_t& m, float d2, float rc2) {
 // cutoff of this lane's A (a superset: rc2 comes with a relative margin of
 // 2^-19 over the exact FP32 test, which the candidate stage applies).  The
 // tests run from t = 31 down so that doubling the mask lands bit t at t.
-template <bool kShift, bool kSame, bool kZero = false>
+template <bool kShift, bool kSame>
 __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
                                            uint32_t& mlo, uint32_t& mhi) {
     uint32_t half[2];
@@ -979,17 +982,14 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
 #pragma unroll 8
         for (int kk = 0; kk < 32; ++kk) {
             const int t = 32 * g + 31 - kk;
-            const float4 p = w.bp[t];
             float dx, dy, dz;
-            if (kZero) {  // every shift of the stage is 0: adding it would change nothing
+            // a stage whose shifts are exact screens the staged positions moved by
+            // their shift (equal to the unmoved ones where the shift is 0)
+            const float4 p = kShift ? w.bs[t] : w.bp[t];
+            if (kShift) {
                 dx = __fsub_rn(p.x, pa.x);
                 dy = __fsub_rn(p.y, pa.y);
                 dz = __fsub_rn(p.z, pa.z);
-            } else if (kShift) {
-                const float4 sh = w.bs[t];
-                dx = __fadd_rn(__fsub_rn(p.x, pa.x), sh.x);
-                dy = __fadd_rn(__fsub_rn(p.y, pa.y), sh.y);
-                dz = __fadd_rn(__fsub_rn(p.z, pa.z), sh.z);
             } else {
                 dx = minimg_f(__fsub_rn(p.x, pa.x), L, hL);
                 dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
@@ -1048,10 +1048,10 @@ __device__ __forceinline__ void stage_candidates(SpWave& w, uint32_t mlo, uint32
                 const float4 p = w.bp[t], q = w.bq[t];
                 float dx, dy, dz;
                 if (kShift) {
-                    const float4 sh = w.bs[t];
-                    dx = __fadd_rn(__fsub_rn(p.x, pa.x), sh.x);
-                    dy = __fadd_rn(__fsub_rn(p.y, pa.y), sh.y);
-                    dz = __fadd_rn(__fsub_rn(p.z, pa.z), sh.z);
+                    const int sc = __float_as_int(q.w);  // shift code of the staged molecule
+                    dx = __fadd_rn(__fsub_rn(p.x, pa.x), shift_of(sc & 3, L));
+                    dy = __fadd_rn(__fsub_rn(p.y, pa.y), shift_of((sc >> 2) & 3, L));
+                    dz = __fadd_rn(__fsub_rn(p.z, pa.z), shift_of((sc >> 4) & 3, L));
                 } else {
                     dx = minimg_f(__fsub_rn(p.x, pa.x), L, hL);
                     dy = minimg_f(__fsub_rn(p.y, pa.y), L, hL);
@@ -1122,7 +1122,6 @@ __device__ __forceinline__ void axis_shift(int qlo, int qhi, float blo, float bh
     gap = valid ? fmaxf(0.0f, fmaxf(a, -b)) : 0.0f;
 }
 
-__device__ __forceinline__ float shift_of(int code, float L) { return code == 1 ? L : (code == 2 ? -L : 0.0f); }
 
 __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restrict__ pos,
                                                        const float4* __restrict__ pos0,
@@ -1235,7 +1234,10 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                 const float c2 = S.cull2[rx];
                 const float rcu = sqrtf(c2);
                 const float rc2 = S.rc2[rx];
-                const float rc2m = rc2 * (1.0f + 0x1p-19f);
+                // screening cutoff: a relative margin for the fused arithmetic and an
+                // absolute one for the rounding of a position moved by +-L
+                const float rcs = __builtin_amdgcn_sqrtf(rc2) * (1.0f + 0x1p-19f) + 1e-6f * L;
+                const float rc2m = rcs * rcs;
                 const float Rr = S.R[rx], inv_s = S.inv_s[rx];
                 const bool same = (sj == si);
                 int cx0, cx1, cy0, cy1, czl, czh;
@@ -1314,7 +1316,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                         }
                     }
                     // segments whose exact shift is 0 on every axis go first in the
-                    // stream, so that most stages need no shift at all
+                    // stream (stages of one kind)
                     const bool z1 = n1 > 0 && (code1 & 127) == 64, z2 = n2 > 0 && (code2 & 127) == 64;
                     const int nz_l = (z1 ? 1 : 0) + (z2 ? 1 : 0);
                     const int no_l = (n1 > 0 ? 1 : 0) + (n2 > 0 ? 1 : 0) - nz_l;
@@ -1376,22 +1378,16 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                     for (int b = p0; b < p1; b += 64) {
                         wave_sync_lds();
                         w.bp[lane] = make_float4(fp.x, fp.y, fp.z, __int_as_float(fj));
-                        w.bq[lane] = fq;
-                        w.bs[lane] = make_float4(shift_of(fc & 3, L), shift_of((fc >> 2) & 3, L),
-                                                 shift_of((fc >> 4) & 3, L), 0.f);
+                        w.bq[lane] = make_float4(fq.x, fq.y, fq.z, __int_as_float(fc & 63));
+                        w.bs[lane] = make_float4(fp.x + shift_of(fc & 3, L), fp.y + shift_of((fc >> 2) & 3, L),
+                                                 fp.z + shift_of((fc >> 4) & 3, L), __int_as_float(fj));
                         const bool exact = __ballot((fc & 64) == 0) == 0ull;
-                        const bool zero = __ballot((fc & 63) != 0) == 0ull;
                         wave_sync_lds();
                         if (b + 64 < p1) fetch(b + 64, fp, fq, fj, fc);
                         uint32_t mlo, mhi;
                         if (exact) {
-                            if (zero) {
-                                if (same) stage_mask<true, true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                                else stage_mask<true, false, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                            } else {
-                                if (same) stage_mask<true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                                else stage_mask<true, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                            }
+                            if (same) stage_mask<true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                            else stage_mask<true, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
                             stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S, contact_only,
                                                    log_all, ctr, pairs, pair_cap, ncand);
                         } else {
