@@ -195,6 +195,37 @@ def test_candidates_independent_of_search_shape(g, orc, dt, nc):
             e.close()
 
 
+@pytest.mark.parametrize("dt", [20.0, 500.0])
+def test_filtered_search_reacts_like_logged_search(g, dt):
+    """Without logging, the species-bin search screens with fused arithmetic and
+    skips the evaluation of pairs whose bridge exponent bound exceeds 18
+    (P < e^-18 < 2^-25, never accepted), and few accepted pairs are matched in
+    LDS; with every candidate logged, every pair is evaluated and matched
+    through the global tables.  Both steps must react the same pairs into the
+    same state."""
+    L = 2000.0
+    n = 20000
+    rng = np.random.default_rng(int(dt))
+    x = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    x[: n // 4] = rng.uniform(-L / 2, L / 2, size=(n // 40, 3)).repeat(10, axis=0) + rng.normal(0, 5.0, size=(n // 4, 3))
+    x = ((x + L / 2) % L - L / 2).astype(np.float32)
+    sp = rng.integers(0, 7, size=n).astype(np.uint8)
+    uid = np.arange(n, dtype=np.uint64)
+    outs = []
+    for flags in (0, g.DEBUG_LOG_ALL):
+        say("filtered vs logged", dt, flags)
+        e = make_engine(g, L, 11)
+        g.gsbs_debug_set_state(e.ctx, x, sp, uid, step=7, next_uid=n)
+        g.gsbs_debug_step(e.ctx, dt, flags | MODES["species"])
+        outs.append(g.gsbs_debug_get_state(e.ctx, 0))
+        e.close()
+    (xa, sa, ua), (xb, sb, ub) = outs
+    ia, ib = np.argsort(ua), np.argsort(ub)
+    assert not np.array_equal(np.sort(ua), uid)  # something reacted
+    assert np.array_equal(ua[ia], ub[ib]) and np.array_equal(sa[ia], sb[ib])
+    assert np.array_equal(xa[ia], xb[ib])
+
+
 # ------------------------------------------------ short trajectory parity ---
 def test_first_steps_match_oracle(g, orc):
     """Same initial spurs, same Philox streams: the GPU and the oracle follow
