@@ -1,0 +1,74 @@
+"""Pins of the rate-equation oracle (CPU only).
+
+  * A + A with the printed 2k: 1/[A](t) = 1/[A]0 + k t, the product at half
+    the consumed amount (closed form of the paper's self-recombination law);
+  * A + B with unequal starts: ln([B][A]0 / ([A][B]0)) = ([B]0 - [A]0) k t;
+  * the Jacobian equals central finite differences of the right-hand side;
+  * the full water scheme conserves charge (H3O+ - e_aq - OH-) and the redox
+    balance (OH + 2 H2O2 - e_aq - H - 2 H2) to rounding;
+  * a test-only sink (keep_b) decays A exponentially at k [B].
+"""
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from oracle import numodes_oracle as N  # noqa: E402
+from paper_2509_03313_amd import workload as W  # noqa: E402
+
+
+def test_self_recombination_closed_form():
+    r = [W.Reaction("X", 0, 0, 0.95, (1,))]
+    a0 = 3e-6
+    for t in (1e2, 1e4, 1e6):
+        c = N.integrate([a0, 0.0], t, r)
+        a = 1.0 / (1.0 / a0 + 10.0 * 0.95 * t)
+        assert abs(c[0] - a) <= 1e-8 * a, (t, c[0], a)
+        assert abs(c[1] - (a0 - a) / 2) <= 1e-8 * a0
+
+
+def test_a_plus_b_closed_form():
+    r = [W.Reaction("Y", 0, 1, 3.0, ())]
+    a0, b0 = 2e-6, 5e-6
+    k = 30.0
+    for t in (1e3, 1e4, 1e5):
+        c = N.integrate([a0, b0], t, r)
+        lhs = math.log(c[1] * a0 / (c[0] * b0))
+        assert abs(lhs - (b0 - a0) * k * t) <= 1e-7 * max(1.0, lhs), (t, lhs)
+        assert abs((b0 - c[1]) - (a0 - c[0])) <= 1e-9 * b0
+
+
+def test_jacobian_is_derivative_of_rhs():
+    rng = np.random.default_rng(0)
+    c = 10.0 ** rng.uniform(-8, -5, size=7)
+    J = N.jacobian(c, W.REACTIONS)
+    for j in range(7):
+        h = 1e-6 * c[j]
+        cp, cm = c.copy(), c.copy()
+        cp[j] += h
+        cm[j] -= h
+        fd = (N.rhs(cp, W.REACTIONS) - N.rhs(cm, W.REACTIONS)) / (2 * h)
+        assert np.allclose(fd, J[:, j], rtol=1e-6, atol=1e-12 * np.abs(J).max())
+
+
+def test_water_scheme_conserves_charge_and_redox():
+    rng = np.random.default_rng(1)
+    c0 = 10.0 ** rng.uniform(-7, -5, size=7)
+    c = N.integrate(c0, 1e6, W.REACTIONS)
+    Q = lambda x: x[W.H3O] - x[W.E_AQ] - x[W.OHM]  # noqa: E731
+    R = lambda x: x[W.OH] + 2 * x[W.H2O2] - x[W.E_AQ] - x[W.H] - 2 * x[W.H2]  # noqa: E731
+    scale = c0.sum()
+    assert abs(Q(c) - Q(c0)) <= 1e-9 * scale and abs(R(c) - R(c0)) <= 1e-9 * scale
+    assert np.all(c >= -1e-15 * scale)
+
+
+def test_sink_decays_exponentially():
+    r = [W.Reaction("S", 0, 1, 2.0, (), keep_b=True)]
+    a0, b = 1e-7, 4e-6
+    t = 2e4
+    c = N.integrate([a0, b], t, r)
+    assert abs(c[0] - a0 * math.exp(-20.0 * b * t)) <= 1e-8 * a0 and c[1] == b
