@@ -1338,6 +1338,57 @@ int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, in
     return check_device_errors(c);
 }
 
+int gsbs_numodes(gsbs_ctx* c, int32_t n, const double* c0, const double* dt_ns, double* c1, double rtol,
+                 int32_t* steps, int32_t on_device) {
+    if (!c || n < 0 || (n > 0 && (!c0 || !dt_ns || !c1)) || !(rtol > 0.0) || rtol > 0.1)
+        return fail(GSBS_EINVAL, "bad rate-equation arguments");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    if (n == 0) return GSBS_OK;
+    OdeTable tb{};
+    tb.ns = c->ns;
+    tb.nr = (int32_t)c->rx.size();
+    for (int r = 0; r < tb.nr; ++r) {
+        const gsbs_reaction& q = c->rx[r];
+        tb.ra[r] = q.a;
+        tb.rb[r] = q.b;
+        tb.keep_b[r] = q.keep_b ? 1 : 0;
+        tb.nprod[r] = q.n_products;
+        for (int k = 0; k < 3; ++k) tb.prod[r][k] = k < q.n_products ? q.products[k] : -1;
+        tb.k[r] = 10.0 * q.k_in;  // 1e10 L/mol/s -> L/mol/ns
+    }
+    const size_t nc = (size_t)n * (size_t)c->ns;
+    double *d0 = nullptr, *dd = nullptr, *d1 = nullptr;
+    int32_t* dsteps = nullptr;
+    const double* pc0 = c0;
+    const double* pdt = dt_ns;
+    double* pc1 = c1;
+    CHK(dalloc(&dsteps, (size_t)n));
+    if (!on_device) {
+        CHK(dalloc(&d0, nc));
+        CHK(dalloc(&dd, (size_t)n));
+        CHK(dalloc(&d1, nc));
+        HIPCHK(hipMemcpyAsync(d0, c0, sizeof(double) * nc, hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(dd, dt_ns, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+        pc0 = d0;
+        pdt = dd;
+        pc1 = d1;
+    }
+    launch_numodes(c->st, pc0, pdt, pc1, dsteps, n, tb, rtol, 1e-10 * rtol, 200000);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> hs((size_t)n);
+    HIPCHK(hipMemcpyAsync(hs.data(), dsteps, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->st));
+    if (!on_device) HIPCHK(hipMemcpyAsync(c1, d1, sizeof(double) * nc, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    dfree(dsteps);
+    dfree(d0);
+    dfree(dd);
+    dfree(d1);
+    if (steps) std::copy(hs.begin(), hs.end(), steps);
+    for (int32_t m = 0; m < n; ++m)
+        if (hs[(size_t)m] < 0) return fail(GSBS_ESTATE, "rate equations: step limit reached");
+    return GSBS_OK;
+}
+
 int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_t y_is_device, const float* mu_y,
                     const float* sd_y, double c_floor_M, int32_t relative) {
     if (!c || !y || !mu_y || !sd_y || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");

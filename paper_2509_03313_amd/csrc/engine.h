@@ -14,6 +14,15 @@ constexpr int kDead = 0xFF;          // species byte of a removed molecule
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 
 // Chemistry tables (constant during a run).
+// Reaction table of the rate equations (passed by value to the integrator):
+// event rate k [a][b] (k [a]^2 / 2 when a == b), k in L/mol/ns.
+struct OdeTable {
+    int32_t ns, nr;
+    int32_t ra[kMaxReactions], rb[kMaxReactions], keep_b[kMaxReactions], nprod[kMaxReactions];
+    int32_t prod[kMaxReactions][3];
+    double k[kMaxReactions];
+};
+
 struct ChemDev {
     int32_t rmap[kMaxSpecies][kMaxSpecies];  // reaction index of a species pair or -1
     float D[kMaxSpecies];                    // nm^2/ns
@@ -156,6 +165,9 @@ void launch_features(hipStream_t st, const long long* counts, int inst, int ns, 
 void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const float* sd, int ns, double c_floor,
                          double vol_litre, uint64_t seed, int inst, uint64_t step, int relative,
                          const long long* counts, long long* out);
+// Rate equations of n mixtures (c0, c1: [n][tb.ns] mol/L, dt: [n] ns, device).
+void launch_numodes(hipStream_t st, const double* c0, const double* dt, double* c1, int32_t* steps, int32_t n,
+                    const OdeTable& tb, double rtol, double atol, int32_t max_steps);
 void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,
                   int n_new, int inst, uint64_t uid_base, uint64_t seed, uint64_t step, float L, int cap,
                   long long* counts, int grid);
