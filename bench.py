@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="the batched metric: N independent instances of uneven size stepped together")
     ap.add_argument("--batched-t-end", type=float, default=100.0, help="end time (ns) of the batched runs")
+    ap.add_argument("--numodes", type=int, default=0, metavar="N",
+                    help="the rate equations: N batched mixtures, then 20-pulse SBS + rate-equation runs")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -134,7 +136,7 @@ def surrogate_bench(args):
          f"table {np.round(s.table, 4).tolist()} over log10 dt edges {np.round(s.dt_edges, 2).tolist()}, "
          f"log10 C_tot edges {np.round(s.c_edges, 2).tolist()}")
     runs = []
-    for rate in [float(r) for r in args.sur_rates.split(",")]:
+    for rate in [float(r) for r in args.sur_rates.split(",") if r]:
         plan = SU.PulsePlan(args.sur_L, args.seed + 77, 20, 1.0, 1e6, rate)
         SU.run(SU.PulsePlan(args.sur_L, 5, 2, 1.0, 1e6, rate), None)  # warm the grid tuner
         plain = SU.run(plan, None)
@@ -166,7 +168,7 @@ def surrogate_bench(args):
                                           end_rel_dG_h2o2=round(float(rel_b[-1]), 5))))
     line = {
         "metric": "20-pulse wall time, plain SBS / SBS with the inter-pulse network",
-        "value": runs[0]["speedup"], "unit": "x", "higher_is_better": True, "n_gpus": 1,
+        "value": runs[0]["speedup"] if runs else None, "unit": "x", "higher_is_better": True, "n_gpus": 1,
         "dtype": "f32 SBS, bf16 network with f32 accumulation", "data": "synthetic",
         "config": {"workload": f"20 pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate 1e6 Gy/s, "
                                f"2 batches per pulse", "train_runs": len(plans), "train_L_nm": args.sur_train_L,
@@ -317,6 +319,72 @@ def batched_bench(args):
     print(json.dumps(line), flush=True)
 
 
+# Algorithmic FP64 operations of one accepted step of the rate-equation integrator
+# (four-stage Rosenbrock) for the 7-species, 9-reaction scheme: three right-hand
+# sides (~63 each), the Jacobian (~108), the stage matrix (~50), the 7 x 7 LU
+# (203), four triangular solve pairs (91 each), stage and error vectors (~126).
+ALG_FLOP_PER_ODE_STEP = 1040
+FP64_PEAK_TFLOPS = 78.6
+
+
+def numodes_bench(args):
+    """The rate equations of the beam-off stage: batched throughput on the
+    device, and 20-pulse runs alternating SBS with them (the paper's scheme)
+    against plain SBS on the same pulses and seeds."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import surrogate as SU
+    from paper_2509_03313_amd import workload as W
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    rng = np.random.default_rng(args.seed + 9)
+    n = args.numodes
+    c0 = torch.as_tensor(10.0 ** rng.uniform(-8, -5, size=(n, 7)), device="cuda")
+    dt = torch.full((n,), 1e6, dtype=torch.float64, device="cuda")
+    e = gsbs.Engine(1000.0, 1, W.D_CONFIG, W.REACTIONS)
+    gsbs.gsbs_numodes(e.ctx, c0[:64], dt[:64])  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c1, steps = gsbs.gsbs_numodes(e.ctx, c0, dt, rtol=1e-6)
+    wall_ode = time.perf_counter() - t0
+    e.close()
+    tot_steps = int(np.sum(steps))
+    ach = ALG_FLOP_PER_ODE_STEP * tot_steps / wall_ode / 1e12
+    note(f"{n} mixtures over 1 ms: {wall_ode * 1e3:.1f} ms, {tot_steps} steps ({np.mean(steps):.0f} per mixture)")
+    runs = []
+    for rate in [float(r) for r in args.sur_rates.split(",") if r]:
+        plan = SU.PulsePlan(args.sur_L, args.seed + 77, 20, 1.0, 1e6, rate)
+        SU.run(SU.PulsePlan(args.sur_L, 5, 2, 1.0, 1e6, rate), None)  # warm the grid tuner
+        plain = SU.run(plan, None)
+        hyb = SU.run(plan, None, numodes_rtol=1e-6)
+        rel = np.abs(hyb["g_h2o2"] - plain["g_h2o2"]) / plain["g_h2o2"]
+        note(f"rate {rate:g}: plain {plain['wall']:.2f} s, SBS + rate equations {hyb['wall']:.2f} s, "
+             f"max |dG(H2O2)|/G {rel.max():.4f}, end {rel[-1]:.4f}")
+        runs.append(dict(avg_rate_gy_s=rate, wall_plain_s=round(plain["wall"], 3), wall_numodes_s=round(hyb["wall"], 3),
+                         speedup=round(plain["wall"] / hyb["wall"], 3),
+                         g_h2o2_plain=[round(float(x), 5) for x in plain["g_h2o2"]],
+                         g_h2o2_numodes=[round(float(x), 5) for x in hyb["g_h2o2"]],
+                         max_rel_dG_h2o2=round(float(rel.max()), 5), end_rel_dG_h2o2=round(float(rel[-1]), 5)))
+    line = {
+        "metric": "20-pulse wall time, plain SBS / SBS with the rate equations between pulses",
+        "value": runs[0]["speedup"] if runs else None, "unit": "x", "higher_is_better": True, "n_gpus": 1,
+        "dtype": "f32 SBS, f64 rate equations", "data": "synthetic",
+        "config": {"workload": f"20 pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate 1e6 Gy/s, "
+                               f"2 batches per pulse; rate equations at rtol 1e-6"},
+        "batched_rate_equations": {"mixtures": n, "interval_ns": 1e6, "wall_ms": round(wall_ode * 1e3, 3),
+                                   "mixtures_per_s": round(n / wall_ode, 1), "steps": tot_steps,
+                                   "roofline": dict(bound="alu", achieved=round(ach, 4), peak=FP64_PEAK_TFLOPS,
+                                                    unit="TFLOP/s", frac=round(ach / FP64_PEAK_TFLOPS, 5),
+                                                    kernel="k_numodes", alg_flop_per_step=ALG_FLOP_PER_ODE_STEP)},
+        "runs": runs,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,6 +399,9 @@ def main():
         return
     if args.batched:
         batched_bench(args)
+        return
+    if args.numodes:
+        numodes_bench(args)
         return
 
     if args.calibrate_copy:

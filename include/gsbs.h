@@ -298,17 +298,21 @@ int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y
  * self-recombinations, so that d[a]/dt = -k [a]^2, the paper's equation for the
  * OH recombination), k = 10 * k_in L/mol/ns; each event removes its reactants
  * (not b when keep_b) and adds its products.  c0 and c1 are [n][n_species]
- * concentrations in mol/L (row-major), dt_ns[n] the time of each solution;
- * c1 receives the concentrations after dt_ns.  Integration: FP64, two-stage
- * L-stable Rosenbrock (ROS2) with step control, relative tolerance rtol
+ * concentrations in mol/L (row-major; n_species must equal the table's
+ * species count, else GSBS_EINVAL), dt_ns[n] the time of each solution;
+ * c1 receives the concentrations after dt_ns (negative entries of c0 are
+ * taken as 0; a dt_ns of 0 or below returns them so).  Integration: FP64, the
+ * four-stage third-order stiffly accurate Rosenbrock method RODAS3 with step
+ * control by its embedded second-order solution, relative tolerance rtol
  * (0 < rtol <= 0.1) and absolute tolerance 1e-10 * rtol mol/L; one device
  * thread per solution.  on_device = 1: c0, dt_ns, c1 are device pointers;
  * 0: host arrays.  steps (host, may be NULL) receives the accepted steps of
  * every solution.  Returns after c1 is written.  Fails with GSBS_ESTATE before
  * the reaction table is set or when a solution needs more than 200000 steps
- * (its steps entry is then -1). */
-int gsbs_numodes(gsbs_ctx* ctx, int32_t n, const double* c0, const double* dt_ns, double* c1, double rtol,
-                 int32_t* steps, int32_t on_device);
+ * (its steps entry is then -1), and with GSBS_EINVAL when the table has more
+ * than 8 species (a mixture's state is held in registers). */
+int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
+                 double rtol, int32_t* steps, int32_t on_device);
 
 /* ------------------------------------------- inter-pulse surrogate MLP --- */
 /* A perceptron that maps the state at the end of a pulse's SBS segment

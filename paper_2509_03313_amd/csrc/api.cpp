@@ -1338,11 +1338,13 @@ int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, in
     return check_device_errors(c);
 }
 
-int gsbs_numodes(gsbs_ctx* c, int32_t n, const double* c0, const double* dt_ns, double* c1, double rtol,
-                 int32_t* steps, int32_t on_device) {
+int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
+                 double rtol, int32_t* steps, int32_t on_device) {
     if (!c || n < 0 || (n > 0 && (!c0 || !dt_ns || !c1)) || !(rtol > 0.0) || rtol > 0.1)
         return fail(GSBS_EINVAL, "bad rate-equation arguments");
     if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    if (n_species != c->ns) return fail(GSBS_EINVAL, "rate equations: n_species is not the table's");
+    if (c->ns > kOdeMaxSpecies) return fail(GSBS_EINVAL, "the rate equations take at most 8 species");
     if (n == 0) return GSBS_OK;
     OdeTable tb{};
     tb.ns = c->ns;
@@ -1359,6 +1361,16 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, const double* c0, const double* dt_ns, 
     const size_t nc = (size_t)n * (size_t)c->ns;
     double *d0 = nullptr, *dd = nullptr, *d1 = nullptr;
     int32_t* dsteps = nullptr;
+    struct Release {
+        double **a, **b, **d;
+        int32_t** s;
+        ~Release() {
+            dfree(*a);
+            dfree(*b);
+            dfree(*d);
+            dfree(*s);
+        }
+    } release{&d0, &dd, &d1, &dsteps};
     const double* pc0 = c0;
     const double* pdt = dt_ns;
     double* pc1 = c1;
@@ -1379,10 +1391,6 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, const double* c0, const double* dt_ns, 
     HIPCHK(hipMemcpyAsync(hs.data(), dsteps, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->st));
     if (!on_device) HIPCHK(hipMemcpyAsync(c1, d1, sizeof(double) * nc, hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    dfree(dsteps);
-    dfree(d0);
-    dfree(dd);
-    dfree(d1);
     if (steps) std::copy(hs.begin(), hs.end(), steps);
     for (int32_t m = 0; m < n; ++m)
         if (hs[(size_t)m] < 0) return fail(GSBS_ESTATE, "rate equations: step limit reached");

@@ -15,7 +15,9 @@ constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 
 // Chemistry tables (constant during a run).
 // Reaction table of the rate equations (passed by value to the integrator):
-// event rate k [a][b] (k [a]^2 / 2 when a == b), k in L/mol/ns.
+// event rate k [a][b] (k [a]^2 / 2 when a == b), k in L/mol/ns.  The
+// integrator keeps a mixture's state in registers: at most kOdeMaxSpecies.
+constexpr int kOdeMaxSpecies = 8;
 struct OdeTable {
     int32_t ns, nr;
     int32_t ra[kMaxReactions], rb[kMaxReactions], keep_b[kMaxReactions], nprod[kMaxReactions];

@@ -95,7 +95,7 @@ _SIGS = {
     "gsbs_debug_get_cells": [_vp, _i64, _P(_i32), _P(_u64), _P(_i32), _P(_i64)],
     "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
     "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
-    "gsbs_numodes": [_vp, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
+    "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
     "gsbs_mlp_destroy": [_vp],
@@ -495,19 +495,29 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     float64 tensors).  Returns (c1, steps) -- c1 of the same kind as c0."""
     if hasattr(c0, "data_ptr"):
         import torch
-        n = int(c0.shape[0])
+        if c0.dim() != 2 or c0.dtype != torch.float64 or not c0.is_cuda or not c0.is_contiguous():
+            raise ValueError("c0: a contiguous [n][n_species] float64 device tensor")
+        n, ns = int(c0.shape[0]), int(c0.shape[1])
         c1 = torch.empty_like(c0)
-        dtt = dt_ns if hasattr(dt_ns, "data_ptr") else torch.as_tensor(np.asarray(dt_ns, np.float64), device=c0.device)
+        if hasattr(dt_ns, "data_ptr"):
+            dtt = dt_ns
+        else:
+            dtt = torch.as_tensor(np.broadcast_to(np.asarray(dt_ns, np.float64), (n,)).copy(), device=c0.device)
+        if (dtt.shape != (n,) or dtt.dtype != torch.float64 or dtt.device != c0.device
+                or not dtt.is_contiguous()):
+            raise ValueError("dt_ns: a contiguous [n] float64 tensor on c0's device")
         steps = np.zeros(max(n, 1), dtype=np.int32)
-        _chk(_lib.gsbs_numodes(ctx, n, C.c_void_p(c0.data_ptr()), C.c_void_p(dtt.data_ptr()),
+        _chk(_lib.gsbs_numodes(ctx, n, ns, C.c_void_p(c0.data_ptr()), C.c_void_p(dtt.data_ptr()),
                                C.c_void_p(c1.data_ptr()), float(rtol), _ptr(steps, _i32), 1))
         return c1, steps[:n]
     c0h = np.ascontiguousarray(c0, dtype=np.float64)
-    n = c0h.shape[0]
+    if c0h.ndim != 2:
+        raise ValueError("c0: [n][n_species]")
+    n, ns = c0h.shape
     dth = np.ascontiguousarray(np.broadcast_to(np.asarray(dt_ns, np.float64), (n,)))
     c1 = np.empty_like(c0h)
     steps = np.zeros(max(n, 1), dtype=np.int32)
-    _chk(_lib.gsbs_numodes(ctx, n, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
+    _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
 

@@ -311,10 +311,15 @@ class Surrogate:
 
 # ------------------------------------------------------------ multi-pulse run ---
 def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01,
-        budget: Optional[float] = None) -> dict:
+        budget: Optional[float] = None, numodes_rtol: Optional[float] = None) -> dict:
     """Plain (surrogate None) or hybrid multi-pulse run of one cube.  Returns
     the H2O2 count and G(H2O2) at every pulse start after the first and at the
     end, the wall time and the number of intervals the network took.
+
+    With numodes_rtol (and no surrogate) every interval goes to the rate
+    equations instead (the paper's SBS + NumODEs alternation): the counts at
+    the switch time become concentrations, gsbs_numodes carries them to the
+    next pulse start and the cube is re-populated homogeneously.
 
     An interval goes to the network when its held-out error estimate is at most
     tol.  With a budget, the estimates of the intervals the network takes are
@@ -340,6 +345,13 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
             ts = plan.switch(p)
             e.advance_to(ts)
             at_switch.append(e.current_counts(0))
+            if surrogate is None and numodes_rtol is not None:
+                conc = at_switch[-1].astype(np.float64) / (NA * plan.L ** 3 * 1e-24)
+                c1, _ = gsbs.gsbs_numodes(e.ctx, conc[None, :], [t_next - ts], rtol=numodes_rtol)
+                y = np.log10(np.maximum(c1[0], 0.0) + C_FLOOR).astype(np.float32)
+                gsbs.gsbs_repopulate(e.ctx, 0, t_next, y, np.zeros(len(y), np.float32),
+                                     np.ones(len(y), np.float32), C_FLOOR, relative=False)
+                took = True
             if surrogate is not None:
                 gsbs.gsbs_features(e.ctx, 0, t_next - ts, R_MAX, N_REF, C_FLOOR, surrogate.mu, surrogate.sd,
                                    out=row[0])
