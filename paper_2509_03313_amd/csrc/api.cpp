@@ -1353,10 +1353,11 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
         const gsbs_reaction& q = c->rx[r];
         tb.ra[r] = q.a;
         tb.rb[r] = q.b;
-        tb.keep_b[r] = q.keep_b ? 1 : 0;
-        tb.nprod[r] = q.n_products;
-        for (int k = 0; k < 3; ++k) tb.prod[r][k] = k < q.n_products ? q.products[k] : -1;
-        tb.k[r] = 10.0 * q.k_in;  // 1e10 L/mol/s -> L/mol/ns
+        // 1e10 L/mol/s -> L/mol/ns; the printed k of a self-recombination is 2k
+        tb.kr[r] = 10.0 * q.k_in * (q.a == q.b ? 0.5 : 1.0);
+        tb.nu[r][q.a] -= 1.0;
+        if (!q.keep_b) tb.nu[r][q.b] -= 1.0;
+        for (int k = 0; k < q.n_products; ++k) tb.nu[r][q.products[k]] += 1.0;
     }
     const size_t nc = (size_t)n * (size_t)c->ns;
     double *d0 = nullptr, *dd = nullptr, *d1 = nullptr;

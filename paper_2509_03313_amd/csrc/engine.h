@@ -15,14 +15,15 @@ constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 
 // Chemistry tables (constant during a run).
 // Reaction table of the rate equations (passed by value to the integrator):
-// event rate k [a][b] (k [a]^2 / 2 when a == b), k in L/mol/ns.  The
+// reaction r runs at the event rate kr[r] [a][b] (kr = k for a != b, k / 2 for
+// a == b; k in L/mol/ns) and changes species s by nu[r][s] per event.  The
 // integrator keeps a mixture's state in registers: at most kOdeMaxSpecies.
 constexpr int kOdeMaxSpecies = 8;
 struct OdeTable {
     int32_t ns, nr;
-    int32_t ra[kMaxReactions], rb[kMaxReactions], keep_b[kMaxReactions], nprod[kMaxReactions];
-    int32_t prod[kMaxReactions][3];
-    double k[kMaxReactions];
+    int32_t ra[kMaxReactions], rb[kMaxReactions];
+    double kr[kMaxReactions];
+    double nu[kMaxReactions][kOdeMaxSpecies];
 };
 
 struct ChemDev {

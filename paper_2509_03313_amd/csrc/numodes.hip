@@ -16,111 +16,119 @@
 //
 // Event rate of reaction r between a and b: k_r [a][b] (a != b), k_r [a]^2 / 2
 // (a == b; the table prints 2k for self-recombinations), k_r in L/mol/ns;
-// d[X]/dt = sum_r rate_r (products X - reactants X).  The stage matrix is factored in registers with
-// partial pivoting done by selects.
+// d[X]/dt = sum_r nu_rX rate_r with nu_rX the net change of X per event
+// (products minus reactants).  The stage matrix is factored in registers.
 #include "engine.h"
 
 namespace gsbs {
 
 namespace {
 
+// The table's species indices are the same for every lane, so the gathers of
+// y[a], y[b] and the column updates below are uniform (scalar) selections.
+template <int S>
+__device__ __forceinline__ void gather2(const double* y, int a, int b, double& ya, double& yb) {
+    ya = 0.0;
+    yb = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        ya = s == a ? y[s] : ya;
+        yb = s == b ? y[s] : yb;
+    }
+}
+
 template <int S>
 __device__ __forceinline__ void ode_rhs(const double* y, const OdeTable& tb, double* f) {
 #pragma unroll
     for (int s = 0; s < S; ++s) f[s] = 0.0;
+#pragma unroll 3
     for (int r = 0; r < tb.nr; ++r) {
-        const int a = tb.ra[r], b = tb.rb[r];
-        double ya = 0.0, yb = 0.0;
+        double ya, yb;
+        gather2<S>(y, tb.ra[r], tb.rb[r], ya, yb);
+        const double rho = tb.kr[r] * ya * yb;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            ya = s == a ? y[s] : ya;
-            yb = s == b ? y[s] : yb;
-        }
-        const double rho = (a == b ? 0.5 : 1.0) * tb.k[r] * ya * yb;
-        const double da = -rho, db = tb.keep_b[r] ? 0.0 : -rho;
-        const int p0 = tb.nprod[r] > 0 ? tb.prod[r][0] : -1;
-        const int p1 = tb.nprod[r] > 1 ? tb.prod[r][1] : -1;
-        const int p2 = tb.nprod[r] > 2 ? tb.prod[r][2] : -1;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            double d = (s == a ? da : 0.0) + (s == b ? db : 0.0);
-            d += (s == p0 ? rho : 0.0) + (s == p1 ? rho : 0.0) + (s == p2 ? rho : 0.0);
-            f[s] += d;
-        }
+        for (int s = 0; s < S; ++s) f[s] = fma(tb.nu[r][s], rho, f[s]);
     }
 }
 
-// J[i][j] = d f_i / d y_j
+// J[i][j] = d f_i / d y_j = sum_r nu[r][i] d rate_r / d y_j; the rate of r
+// depends on y_a and y_b only: kr y_b and kr y_a, or 2 kr y_a when a == b.
 template <int S>
 __device__ __forceinline__ void ode_jac(const double* y, const OdeTable& tb, double (*J)[S]) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
         for (int j = 0; j < S; ++j) J[i][j] = 0.0;
+#pragma unroll 3
     for (int r = 0; r < tb.nr; ++r) {
         const int a = tb.ra[r], b = tb.rb[r];
-        double ya = 0.0, yb = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            ya = s == a ? y[s] : ya;
-            yb = s == b ? y[s] : yb;
-        }
-        // d rate / d y_j: k y_a (j = a, a == b); k y_b (j = a), k y_a (j = b)
-        double g[S];
+        double ya, yb;
+        gather2<S>(y, a, b, ya, yb);
+        const double ga = (a == b ? 2.0 : 1.0) * tb.kr[r] * yb, gb = tb.kr[r] * ya;
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            g[j] = a == b ? (j == a ? tb.k[r] * ya : 0.0)
-                          : ((j == a ? tb.k[r] * yb : 0.0) + (j == b ? tb.k[r] * ya : 0.0));
-        }
-        const int p0 = tb.nprod[r] > 0 ? tb.prod[r][0] : -1;
-        const int p1 = tb.nprod[r] > 1 ? tb.prod[r][1] : -1;
-        const int p2 = tb.nprod[r] > 2 ? tb.prod[r][2] : -1;
-        const bool kb = tb.keep_b[r] != 0;
+            if (j == a || j == b) {
+                const double g = j == a ? ga : gb;
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const double w = (i == a ? -1.0 : 0.0) + (i == b && !kb ? -1.0 : 0.0) + (i == p0 ? 1.0 : 0.0) +
-                             (i == p1 ? 1.0 : 0.0) + (i == p2 ? 1.0 : 0.0);
-            if (w != 0.0) {
-#pragma unroll
-                for (int j = 0; j < S; ++j) J[i][j] += w * g[j];
+                for (int i = 0; i < S; ++i) J[i][j] = fma(tb.nu[r][i], g, J[i][j]);
             }
         }
     }
 }
 
-// In-place LU of M with partial pivoting; the row exchanges are applied to
-// the right-hand sides by solve_lu through perm.
-template <int S>
-__device__ __forceinline__ void factor(double (*M)[S], int* perm) {
+// 1/x from the hardware estimate refined by two Newton steps (each squares
+// the relative error), for x normal and finite.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// In-place LU of M.  kPivot: partial pivoting, rows exchanged by selects and
+// recorded in perm for solve_lu.  Without it the diagonal is taken as the
+// pivot, and the result says whether every pivot was at least a tenth of the
+// largest entry below it (threshold pivoting; for mass-action stage matrices
+// the diagonal, 1/(gamma h) plus the species' own loss rate, is normally the
+// largest).  The diagonal receives the pivots' reciprocals.
+template <int S, bool kPivot>
+__device__ __forceinline__ bool factor(double (*M)[S], int* perm) {
+    bool ok = true;
+    if (kPivot) {
 #pragma unroll
-    for (int i = 0; i < S; ++i) perm[i] = i;
+        for (int i = 0; i < S; ++i) perm[i] = i;
+    }
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        // pivot: the largest |M[i][k]|, i >= k; rows exchanged by selects
         int p = k;
-        double best = fabs(M[k][k]);
+        double best = fabs(M[k][k]), below = 0.0;
 #pragma unroll
         for (int i = k + 1; i < S; ++i) {
             const double v = fabs(M[i][k]);
-            if (v > best) {
+            below = fmax(below, v);
+            if (kPivot && v > best) {
                 best = v;
                 p = i;
             }
         }
+        if (kPivot) {
 #pragma unroll
-        for (int i = k + 1; i < S; ++i) {
-            const bool sw = i == p;
+            for (int i = k + 1; i < S; ++i) {
+                const bool sw = i == p;
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const double a = M[k][j], b = M[i][j];
-                M[k][j] = sw ? b : a;
-                M[i][j] = sw ? a : b;
+                for (int j = 0; j < S; ++j) {
+                    const double a = M[k][j], b = M[i][j];
+                    M[k][j] = sw ? b : a;
+                    M[i][j] = sw ? a : b;
+                }
+                const int pa = perm[k], pb = perm[i];
+                perm[k] = sw ? pb : pa;
+                perm[i] = sw ? pa : pb;
             }
-            const int pa = perm[k], pb = perm[i];
-            perm[k] = sw ? pb : pa;
-            perm[i] = sw ? pa : pb;
+        } else {
+            ok = ok && best >= 0.1 * below && best > 0.0;
         }
-        const double inv = 1.0 / M[k][k];
+        const double inv = recip(M[k][k]);
+        M[k][k] = inv;
 #pragma unroll
         for (int i = k + 1; i < S; ++i) {
             const double l = M[i][k] * inv;
@@ -129,16 +137,19 @@ __device__ __forceinline__ void factor(double (*M)[S], int* perm) {
             for (int j = k + 1; j < S; ++j) M[i][j] -= l * M[k][j];
         }
     }
+    return ok;
 }
 
-template <int S>
+template <int S, bool kPivot>
 __device__ __forceinline__ void solve_lu(const double (*M)[S], const int* perm, const double* b, double* x) {
     double z[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        double v = 0.0;
+        double v = b[i];
+        if (kPivot) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) v = perm[i] == s ? b[s] : v;
+            for (int s = 0; s < S; ++s) v = perm[i] == s ? b[s] : v;
+        }
         z[i] = v;
     }
 #pragma unroll
@@ -149,10 +160,20 @@ __device__ __forceinline__ void solve_lu(const double (*M)[S], const int* perm, 
     for (int i = S - 1; i >= 0; --i) {
 #pragma unroll
         for (int j = i + 1; j < S; ++j) z[i] -= M[i][j] * z[j];
-        z[i] /= M[i][i];
+        z[i] *= M[i][i];
     }
 #pragma unroll
     for (int i = 0; i < S; ++i) x[i] = z[i];
+}
+
+// W = I / (gamma h) - J at y
+template <int S>
+__device__ __forceinline__ void stage_matrix(const double* y, const OdeTable& tb, double dg, double (*M)[S]) {
+    ode_jac<S>(y, tb, M);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j < S; ++j) M[i][j] = (i == j ? dg : 0.0) - M[i][j];
 }
 
 template <int S>
@@ -185,19 +206,26 @@ __global__ __launch_bounds__(64) void k_numodes(const double* __restrict__ c0, c
         h = fmin(h, T - t);
         const double ih = 1.0 / h;
         double M[S][S];
-        ode_jac<S>(y, tb, M);
-        const double dg = 1.0 / (gam * h);
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-#pragma unroll
-            for (int j = 0; j < S; ++j) M[i][j] = (i == j ? dg : 0.0) - M[i][j];
         int perm[S];
-        factor<S>(M, perm);
+        stage_matrix<S>(y, tb, ih / gam, M);
+        // threshold-pivoted LU; a wave with any lane below the threshold
+        // refactors with partial pivoting (wave-uniform branch)
+        const bool piv = __builtin_amdgcn_ballot_w64(!factor<S, false>(M, perm)) != 0;
+        if (piv) {
+            stage_matrix<S>(y, tb, ih / gam, M);
+            factor<S, true>(M, perm);
+        }
+        auto solve = [&](const double* rhs_, double* x_) {
+            if (piv)
+                solve_lu<S, true>(M, perm, rhs_, x_);
+            else
+                solve_lu<S, false>(M, perm, rhs_, x_);
+        };
         double k1[S], d[S], k3[S], k4[S], r[S], ys[S], fs[S];
-        solve_lu<S>(M, perm, f, k1);
+        solve(f, k1);
 #pragma unroll
         for (int s = 0; s < S; ++s) r[s] = f[s] + 4.0 * ih * k1[s];
-        solve_lu<S>(M, perm, r, d);  // K2
+        solve(r, d);  // K2
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             d[s] = k1[s] - d[s];  // K1 - K2
@@ -206,18 +234,19 @@ __global__ __launch_bounds__(64) void k_numodes(const double* __restrict__ c0, c
         ode_rhs<S>(ys, tb, fs);
 #pragma unroll
         for (int s = 0; s < S; ++s) r[s] = fs[s] + ih * d[s];
-        solve_lu<S>(M, perm, r, k3);
+        solve(r, k3);
 #pragma unroll
         for (int s = 0; s < S; ++s) ys[s] += k3[s];
         ode_rhs<S>(ys, tb, fs);
 #pragma unroll
         for (int s = 0; s < S; ++s) r[s] = fs[s] + ih * (d[s] - (8.0 / 3.0) * k3[s]);
-        solve_lu<S>(M, perm, r, k4);
+        solve(r, k4);
         double err = 0.0, yn[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             yn[s] = ys[s] + k4[s];
-            err = fmax(err, fabs(k4[s]) / (atol + rtol * fmax(fabs(y[s]), fabs(yn[s]))));
+            const double e = fabs(k4[s]) * recip(atol + rtol * fmax(fabs(y[s]), fabs(yn[s])));
+            err = (e > err || isnan(e)) ? e : err;  // a NaN stays and rejects the step
         }
         if (err <= 1.0 && isfinite(err)) {
             t += h;
