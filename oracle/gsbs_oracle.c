@@ -790,3 +790,90 @@ int64_t orc_cand_f32(int64_t n, const float* xyz, const int32_t* sp, float L, co
         }
     return cnt;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Homogeneous stochastic kinetics: Gillespie's direct method (Gillespie,    */
+/* J. Phys. Chem. 81, 1977), the algorithm of the stochastic reference the   */
+/* paper compares SBS + PBCs and its rate equations against (Sec. "Setup for  */
+/* verification of periodic boundary conditions" and the discussion of the   */
+/* PBC figure): the next reaction and the waiting time to it are drawn from   */
+/* reaction probabilities built from the k list.                             */
+/*                                                                          */
+/* One well-mixed volume V (litres) holding integer counts n.  Reaction r    */
+/* between species a and b has the stochastic constant c_r = k_r / (N_A V),  */
+/* k_r = 10 k_in L/mol/ns (the printed value: 2k for a self-recombination),  */
+/* and the propensity a_r = c_r h_r with h_r = n_a n_b (a != b) or           */
+/* n_a (n_a - 1) / 2 (a == b), the number of distinct reactant pairs; this   */
+/* is the stochastic form of the rate equations (event rate k[a][b], or      */
+/* k[a]^2 / 2).  Each step: a_0 = sum of a_r in table order, waiting time    */
+/* tau = -ln(u1) / a_0, reaction mu = the first r whose running sum of a_r   */
+/* exceeds u2 a_0 (if rounding leaves none, the last r with a_r > 0), then   */
+/* the reactants are removed (not b when keep_b) and the products added.     */
+/*                                                                          */
+/* Random numbers: Philox4x64-10 with key (seed, 0x4753534153534131) and     */
+/* counter (stream, event index, 0, 0); u1 from word 0 and u2 from word 1,   */
+/* u = (top 53 bits + 1/2) 2^-53, in (0, 1).                                 */
+/*                                                                          */
+/* out[k][s] = the counts after every event at a time <= t_rec[k] (t_rec     */
+/* ascending, times in ns from the start).  The run stops once the last      */
+/* record is taken or no reaction can happen.  Returns the number of events, */
+/* or -1 when max_events were taken before the last record.  ev_t / ev_r     */
+/* (may be NULL) receive the time and reaction of the first ev_cap events.   */
+/* ------------------------------------------------------------------------ */
+static double orc_u53(uint64_t w)
+{
+    return ((double)(w >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n_rec, const double* t_rec,
+                uint64_t seed, uint64_t stream, int64_t max_events, int64_t* out, double* ev_t, int32_t* ev_r,
+                int64_t ev_cap)
+{
+    const double NA = 6.02214076e23;
+    int64_t n[ORC_MAX_SPECIES];
+    double cr[ORC_MAX_REACT], a[ORC_MAX_REACT];
+    for (int s = 0; s < c->ns; ++s) n[s] = n0[s];
+    for (int r = 0; r < c->nr; ++r) cr[r] = (10.0 * c->k_in[r]) / (NA * volume_L);
+    const uint64_t key[2] = {seed, 0x4753534153534131ULL};
+    double t = 0.0;
+    int64_t j = 0;
+    int32_t rec = 0;
+    for (;;) {
+        double a0 = 0.0;
+        for (int r = 0; r < c->nr; ++r) {
+            const int64_t na = n[c->ra[r]], nb = n[c->rb[r]];
+            const int64_t h = c->ra[r] == c->rb[r] ? na * (na - 1) / 2 : na * nb;
+            a[r] = cr[r] * (double)h;
+            a0 += a[r];
+        }
+        double t_next = INFINITY, u2 = 0.0;
+        if (a0 > 0.0) {
+            const uint64_t ctr[4] = {stream, (uint64_t)j, 0, 0};
+            uint64_t w[4];
+            orc_philox4x64_10(ctr, key, w);
+            t_next = t + (-log(orc_u53(w[0])) / a0);
+            u2 = orc_u53(w[1]);
+        }
+        while (rec < n_rec && t_rec[rec] < t_next) {
+            for (int s = 0; s < c->ns; ++s) out[(int64_t)rec * c->ns + s] = n[s];
+            ++rec;
+        }
+        if (rec == n_rec) return j;
+        if (j == max_events) return -1;
+        const double target = u2 * a0;
+        double cum = 0.0;
+        int mu = -1, last = -1;
+        for (int r = 0; r < c->nr; ++r) {
+            cum += a[r];
+            if (a[r] > 0.0) last = r;
+            if (target < cum) { mu = r; break; }
+        }
+        if (mu < 0) mu = last;
+        n[c->ra[mu]] -= 1;
+        if (!c->keep_b[mu]) n[c->rb[mu]] -= 1;
+        for (int k = 0; k < c->nprod[mu]; ++k) n[c->prod[mu][k]] += 1;
+        if (ev_t && j < ev_cap) { ev_t[j] = t_next; ev_r[j] = mu; }
+        t = t_next;
+        ++j;
+    }
+}
