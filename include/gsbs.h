@@ -314,6 +314,38 @@ int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y
 int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
                  double rtol, int32_t* steps, int32_t on_device);
 
+/* --------------------------------------------- stochastic kinetics --- */
+/* Homogeneous stochastic kinetics of the context's reaction table in n
+ * independent well-mixed volumes: Gillespie's direct method (Gillespie 1977),
+ * the stochastic reference the paper checks SBS + PBCs and its rate
+ * equations against (section on the verification of periodic boundary
+ * conditions).  Volume m (volume_L[m] litres) starts from the counts
+ * n0[m][n_species] (n_species must equal the table's species count).
+ * Reaction r between a and b has the propensity c_r h_r, c_r = k_r / (N_A V)
+ * (k_r = 10 * k_in L/mol/ns, the printed constant: 2k for a
+ * self-recombination), h_r = n_a n_b or n_a (n_a - 1) / 2 when a == b; each
+ * event removes the reactants (not b when keep_b) and adds the products.
+ * Random numbers: Philox4x64-10, key (seed, 0x4753534153534131), counter
+ * (stream0 + m, event index, 0, 0); waiting time -ln(u1) / a_0, reaction =
+ * first r whose running sum of propensities (table order) exceeds u2 a_0,
+ * u = (top 53 bits of words 0 and 1 + 1/2) 2^-53.  A stream's event sequence
+ * is therefore fixed bit for bit; event times carry the rounding of ln.
+ * t_rec_ns[n_rec] (host, finite, >= 0, ascending) are the record times:
+ * out[m][k][s] receives the counts after every event at a time <= t_rec_ns[k].
+ * A volume stops once its last record is taken or no reaction can happen.
+ * events (host, may be NULL) receives the number of events of each volume.
+ * on_device = 1: n0, volume_L and out are device pointers (volumes and counts
+ * are then not checked); 0: host arrays.  Returns after out is written.
+ * Fails with GSBS_EINVAL for bad arguments, a table beyond 8 species or 16
+ * reactions, a volume <= 0 or a negative count (host arrays); GSBS_ESTATE
+ * before the reaction table is set or when a volume needs more than
+ * max_events events before its last record (its events entry is then -1).
+ * One device thread per volume; its run time grows with the event count, so
+ * callers bound max_events. */
+int gsbs_ssa(gsbs_ctx* ctx, int32_t n, int32_t n_species, const int32_t* n0, const double* volume_L, int32_t n_rec,
+             const double* t_rec_ns, uint64_t seed, uint64_t stream0, int64_t max_events, int32_t* out,
+             int64_t* events, int32_t on_device);
+
 /* ------------------------------------------- inter-pulse surrogate MLP --- */
 /* A perceptron that maps the state at the end of a pulse's SBS segment
  * (species concentrations, binned pair-correlation features, log of the time

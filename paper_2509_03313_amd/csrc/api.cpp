@@ -1398,6 +1398,86 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
     return GSBS_OK;
 }
 
+int gsbs_ssa(gsbs_ctx* c, int32_t n, int32_t n_species, const int32_t* n0, const double* volume_L, int32_t n_rec,
+             const double* t_rec_ns, uint64_t seed, uint64_t stream0, int64_t max_events, int32_t* out,
+             int64_t* events, int32_t on_device) {
+    if (!c || n < 0 || n_rec < 1 || !t_rec_ns || max_events < 0 || (n > 0 && (!n0 || !volume_L || !out)))
+        return fail(GSBS_EINVAL, "bad stochastic-kinetics arguments");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    if (n_species != c->ns) return fail(GSBS_EINVAL, "stochastic kinetics: n_species is not the table's");
+    if (c->ns > kOdeMaxSpecies || (int)c->rx.size() > kSsaMaxReactions)
+        return fail(GSBS_EINVAL, "stochastic kinetics take at most 8 species and 16 reactions");
+    for (int32_t k = 0; k < n_rec; ++k)
+        if (!(t_rec_ns[k] >= 0.0) || !std::isfinite(t_rec_ns[k]) || (k > 0 && t_rec_ns[k] < t_rec_ns[k - 1]))
+            return fail(GSBS_EINVAL, "record times must be finite, >= 0 and ascending");
+    if (!on_device)
+        for (int32_t m = 0; m < n; ++m) {
+            if (!(volume_L[m] > 0.0) || !std::isfinite(volume_L[m])) return fail(GSBS_EINVAL, "bad volume");
+            for (int s = 0; s < c->ns; ++s)
+                if (n0[(size_t)m * c->ns + s] < 0) return fail(GSBS_EINVAL, "negative initial count");
+        }
+    if (n == 0) return GSBS_OK;
+    SsaTable tb{};
+    tb.ns = c->ns;
+    tb.nr = (int32_t)c->rx.size();
+    for (int r = 0; r < tb.nr; ++r) {
+        const gsbs_reaction& q = c->rx[r];
+        int nu[kOdeMaxSpecies] = {};
+        nu[q.a] -= 1;
+        if (!q.keep_b) nu[q.b] -= 1;
+        for (int k = 0; k < q.n_products; ++k) nu[q.products[k]] += 1;
+        tb.ra[r] = q.a;
+        tb.rb[r] = q.b;
+        tb.k10[r] = 10.0 * q.k_in;  // 1e10 L/mol/s -> L/mol/ns
+        uint64_t d = 0;
+        for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
+        tb.dn[r] = d;
+    }
+    const size_t nc = (size_t)n * (size_t)c->ns, no = (size_t)n * (size_t)n_rec * (size_t)c->ns;
+    int32_t *d0 = nullptr, *dout = nullptr;
+    double *dvol = nullptr, *drec = nullptr;
+    long long* dev = nullptr;
+    struct Release {
+        int32_t **a, **b;
+        double **v, **r;
+        long long** e;
+        ~Release() {
+            dfree(*a);
+            dfree(*b);
+            dfree(*v);
+            dfree(*r);
+            dfree(*e);
+        }
+    } release{&d0, &dout, &dvol, &drec, &dev};
+    const int32_t* p0 = n0;
+    const double* pv = volume_L;
+    int32_t* po = out;
+    CHK(dalloc(&drec, (size_t)n_rec));
+    CHK(dalloc(&dev, (size_t)n));
+    HIPCHK(hipMemcpyAsync(drec, t_rec_ns, sizeof(double) * n_rec, hipMemcpyHostToDevice, c->st));
+    if (!on_device) {
+        CHK(dalloc(&d0, nc));
+        CHK(dalloc(&dvol, (size_t)n));
+        CHK(dalloc(&dout, no));
+        HIPCHK(hipMemcpyAsync(d0, n0, sizeof(int32_t) * nc, hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(dvol, volume_L, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+        p0 = d0;
+        pv = dvol;
+        po = dout;
+    }
+    launch_ssa(c->st, p0, pv, drec, n_rec, po, dev, n, tb, seed, stream0, (long long)max_events);
+    HIPCHK(hipGetLastError());
+    std::vector<long long> he((size_t)n);
+    HIPCHK(hipMemcpyAsync(he.data(), dev, sizeof(long long) * n, hipMemcpyDeviceToHost, c->st));
+    if (!on_device) HIPCHK(hipMemcpyAsync(out, dout, sizeof(int32_t) * no, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (events)
+        for (int32_t m = 0; m < n; ++m) events[m] = (int64_t)he[(size_t)m];
+    for (int32_t m = 0; m < n; ++m)
+        if (he[(size_t)m] < 0) return fail(GSBS_ESTATE, "stochastic kinetics: event limit reached");
+    return GSBS_OK;
+}
+
 int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_t y_is_device, const float* mu_y,
                     const float* sd_y, double c_floor_M, int32_t relative) {
     if (!c || !y || !mu_y || !sd_y || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");

@@ -26,6 +26,18 @@ struct OdeTable {
     double nu[kMaxReactions][kOdeMaxSpecies];
 };
 
+// Reaction table of the stochastic kinetics (Gillespie's direct method):
+// reaction r between ra and rb has the macroscopic constant k10[r] L/mol/ns
+// (the printed value, 2k for a self-recombination) and changes species s by
+// the signed byte s of dn[r] per event.
+constexpr int kSsaMaxReactions = 16;
+struct SsaTable {
+    int32_t ns, nr;
+    int32_t ra[kSsaMaxReactions], rb[kSsaMaxReactions];
+    uint64_t dn[kSsaMaxReactions];
+    double k10[kSsaMaxReactions];
+};
+
 struct ChemDev {
     int32_t rmap[kMaxSpecies][kMaxSpecies];  // reaction index of a species pair or -1
     float D[kMaxSpecies];                    // nm^2/ns
@@ -169,6 +181,9 @@ void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const 
                          double vol_litre, uint64_t seed, int inst, uint64_t step, int relative,
                          const long long* counts, long long* out);
 // Rate equations of n mixtures (c0, c1: [n][tb.ns] mol/L, dt: [n] ns, device).
+void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const double* t_rec, int32_t n_rec,
+                int32_t* out, long long* events, int32_t n, const SsaTable& tb, uint64_t seed, uint64_t stream0,
+                long long max_events);
 void launch_numodes(hipStream_t st, const double* c0, const double* dt, double* c1, int32_t* steps, int32_t n,
                     const OdeTable& tb, double rtol, double atol, int32_t max_steps);
 void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,

@@ -1,0 +1,142 @@
+// ssa.hip -- homogeneous stochastic kinetics for many independent well-mixed
+// volumes at once: Gillespie's direct method (Gillespie, J. Phys. Chem. 81,
+// 1977), the stochastic reference against which the paper checks SBS + PBCs
+// and its rate equations (section on the verification of periodic boundary
+// conditions, and the discussion of its figure).  One lane per volume; the
+// counts, constants and propensities live in registers.
+//
+// Propensity of reaction r: a_r = c_r h_r, c_r = k_r / (N_A V) with k_r the
+// printed constant in L/mol/ns, h_r = n_a n_b (a != b) or n_a (n_a - 1) / 2
+// (a == b), the number of distinct reactant pairs.  A step draws u1, u2 from
+// Philox4x64-10 (key (seed, 0x4753534153534131), counter (stream, event, 0,
+// 0), words 0 and 1, u = (top 53 bits + 1/2) 2^-53), waits -ln(u1) / a_0
+// (a_0 summed in table order) and fires the first reaction whose running sum
+// of propensities exceeds u2 a_0 (the last one with a_r > 0 if rounding leaves
+// none).  The reaction choice is exact integer-derived FP64 arithmetic in a
+// fixed order, so the event sequence of a stream is reproducible bit for bit.
+#include "device_common.h"
+#include "engine.h"
+
+namespace gsbs {
+
+namespace {
+
+constexpr double kNA = 6.02214076e23;
+constexpr uint64_t kSsaKey = 0x4753534153534131ull;
+
+__device__ __forceinline__ double u53(uint64_t w) {
+    return ((double)(w >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// counts of reactants a and b (indices uniform across the wave)
+template <int S>
+__device__ __forceinline__ void gather_n(const int32_t* n, int a, int b, int32_t& na, int32_t& nb) {
+    na = 0;
+    nb = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        na = s == a ? n[s] : na;
+        nb = s == b ? n[s] : nb;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, const double* __restrict__ vol,
+                                            const double* __restrict__ t_rec, int32_t n_rec,
+                                            int32_t* __restrict__ out, long long* __restrict__ events, int32_t n,
+                                            SsaTable tb, uint64_t seed, uint64_t stream0, long long max_events) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int ns = tb.ns, nr = tb.nr;
+    int32_t cnt[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) cnt[s] = s < ns ? n0[(size_t)m * ns + s] : 0;
+    const double nav = kNA * vol[m];
+    double c[kSsaMaxReactions];
+#pragma unroll
+    for (int r = 0; r < kSsaMaxReactions; ++r) c[r] = r < nr ? tb.k10[r] / nav : 0.0;
+    const uint64_t stream = stream0 + (uint64_t)m;
+    int32_t* o = out + (size_t)m * n_rec * ns;
+    double t = 0.0;
+    long long j = 0;
+    int rec = 0;
+    double t_r = t_rec[0];
+    for (;;) {
+        double a[kSsaMaxReactions];
+        double a0 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kSsaMaxReactions; ++r) {
+            if (r < nr) {
+                int32_t na, nb;
+                gather_n<S>(cnt, tb.ra[r], tb.rb[r], na, nb);
+                const double h = tb.ra[r] == tb.rb[r] ? (double)na * (double)(na - 1) * 0.5
+                                                      : (double)na * (double)nb;
+                a[r] = c[r] * h;
+                a0 += a[r];
+            } else {
+                a[r] = 0.0;
+            }
+        }
+        double t_next = __builtin_huge_val(), u2 = 0.0;
+        if (a0 > 0.0) {
+            uint64_t w[4];
+            philox(stream, (uint64_t)j, 0, 0, seed, kSsaKey, w);
+            t_next = t + (-log(u53(w[0])) / a0);
+            u2 = u53(w[1]);
+        }
+        while (rec < n_rec && t_r < t_next) {
+            int32_t* orow = o + (size_t)rec * ns;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (s < ns) orow[s] = cnt[s];
+            ++rec;
+            t_r = rec < n_rec ? t_rec[rec] : 0.0;
+        }
+        if (rec == n_rec) break;
+        if (j == max_events) {
+            j = -1;
+            break;
+        }
+        const double target = u2 * a0;
+        double cum = 0.0;
+        int mu = -1, last = -1;
+#pragma unroll
+        for (int r = 0; r < kSsaMaxReactions; ++r) {
+            if (r < nr) {
+                cum += a[r];
+                last = (mu < 0 && a[r] > 0.0) ? r : last;
+                mu = (mu < 0 && target < cum) ? r : mu;
+            }
+        }
+        mu = mu < 0 ? last : mu;
+        uint64_t d = 0;
+#pragma unroll
+        for (int r = 0; r < kSsaMaxReactions; ++r)
+            if (r < nr) d = r == mu ? tb.dn[r] : d;
+#pragma unroll
+        for (int s = 0; s < S; ++s) cnt[s] += (int32_t)(int8_t)(uint8_t)(d >> (8 * s));
+        t = t_next;
+        ++j;
+    }
+    events[m] = j;
+}
+
+}  // namespace
+
+void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const double* t_rec, int32_t n_rec,
+                int32_t* out, long long* events, int32_t n, const SsaTable& tb, uint64_t seed, uint64_t stream0,
+                long long max_events) {
+    if (n <= 0 || n_rec <= 0 || tb.ns > kOdeMaxSpecies || tb.nr > kSsaMaxReactions) return;
+    const dim3 grid((n + 63) / 64), block(64);
+    if (tb.ns <= 4)
+        hipLaunchKernelGGL(k_ssa<4>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb, seed, stream0,
+                           max_events);
+    else if (tb.ns <= 7)
+        hipLaunchKernelGGL(k_ssa<7>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb, seed, stream0,
+                           max_events);
+    else
+        hipLaunchKernelGGL(k_ssa<kOdeMaxSpecies>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb,
+                           seed, stream0, max_events);
+}
+
+}  // namespace gsbs

@@ -96,6 +96,7 @@ _SIGS = {
     "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
     "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
     "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
+    "gsbs_ssa": [_vp, _i32, _i32, _vp, _vp, _i32, _P(_d), _u64, _u64, _i64, _vp, _P(_i64), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
     "gsbs_mlp_destroy": [_vp],
@@ -520,6 +521,41 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_ssa(ctx, n0, volume_L, t_rec_ns, seed, stream0=0, max_events=1 << 32):
+    """Gillespie runs of the context's reaction table in n volumes: n0
+    [n][n_species] int32 counts and volume_L [n] litres (host arrays, or
+    int32 / float64 device tensors), t_rec_ns the record times.  Returns
+    (out [n][n_rec][n_species] of the kind of n0, events [n])."""
+    t_rec = np.ascontiguousarray(np.atleast_1d(np.asarray(t_rec_ns, np.float64)))
+    if hasattr(n0, "data_ptr"):
+        import torch
+        if n0.dim() != 2 or n0.dtype != torch.int32 or not n0.is_cuda or not n0.is_contiguous():
+            raise ValueError("n0: a contiguous [n][n_species] int32 device tensor")
+        n, ns = int(n0.shape[0]), int(n0.shape[1])
+        if hasattr(volume_L, "data_ptr"):
+            vol = volume_L
+        else:
+            vol = torch.as_tensor(np.broadcast_to(np.asarray(volume_L, np.float64), (n,)).copy(), device=n0.device)
+        if vol.shape != (n,) or vol.dtype != torch.float64 or vol.device != n0.device or not vol.is_contiguous():
+            raise ValueError("volume_L: a contiguous [n] float64 tensor on n0's device")
+        out = torch.empty((n, len(t_rec), ns), dtype=torch.int32, device=n0.device)
+        ev = np.zeros(max(n, 1), dtype=np.int64)
+        _chk(_lib.gsbs_ssa(ctx, n, ns, C.c_void_p(n0.data_ptr()), C.c_void_p(vol.data_ptr()), len(t_rec),
+                           _ptr(t_rec, _d), int(seed), int(stream0), int(max_events), C.c_void_p(out.data_ptr()),
+                           _ptr(ev, _i64), 1))
+        return out, ev[:n]
+    n0h = np.ascontiguousarray(n0, dtype=np.int32)
+    if n0h.ndim != 2:
+        raise ValueError("n0: [n][n_species]")
+    n, ns = n0h.shape
+    volh = np.ascontiguousarray(np.broadcast_to(np.asarray(volume_L, np.float64), (n,)))
+    out = np.zeros((n, len(t_rec), ns), dtype=np.int32)
+    ev = np.zeros(max(n, 1), dtype=np.int64)
+    _chk(_lib.gsbs_ssa(ctx, n, ns, n0h.ctypes.data_as(_vp), volh.ctypes.data_as(_vp), len(t_rec), _ptr(t_rec, _d),
+                       int(seed), int(stream0), int(max_events), out.ctypes.data_as(_vp), _ptr(ev, _i64), 0))
+    return out, ev[:n]
 
 
 # ------------------------------------------------------------- surrogate MLP ---

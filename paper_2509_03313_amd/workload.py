@@ -262,6 +262,33 @@ def homogeneous(seed: int, L: float, conc_per_nm3: dict, t_end: float, n_records
                     reactions=list(reactions) if reactions is not None else list(REACTIONS))
 
 
+# Volume-scaling mixture: the species fractions of the spur model at a total
+# of 2.5e5 molecules per um^3 (4.15e-4 mol/L), dense enough that a 0.2 um cube
+# still holds 2000 molecules; the paper scales the single-pulse yields up in
+# the same way so that its smallest cube is populated.
+VOLUME_SCALING_TOTAL_PER_NM3 = 2.5e-4
+VOLUME_SCALING_EDGES_NM = (200.0, 500.0, 1000.0)
+
+
+def volume_scaling_conc() -> dict:
+    """Species -> molecules per nm^3 of the volume-scaling mixture."""
+    return {s: VOLUME_SCALING_TOTAL_PER_NM3 * f for s, f in enumerate(SPUR_FRACTIONS) if f > 0}
+
+
+def volume_scaling(seed: int, L: float, t_end: float = 1e4, n_records: int = 40) -> Workload:
+    """The homogeneous volume-scaling mixture in a cube of edge L nm."""
+    return homogeneous(seed, L, volume_scaling_conc(), t_end, n_records=n_records)
+
+
+def volume_scaling_counts(L: float) -> np.ndarray:
+    """Initial counts of the volume-scaling mixture in a cube of edge L nm
+    (the same rounding as volume_scaling)."""
+    n = np.zeros(len(SPECIES), dtype=np.int64)
+    for s, c in volume_scaling_conc().items():
+        n[s] = int(round(c * L ** 3))
+    return n
+
+
 def batched_instances(seed: int, n_instances: int = 64):
     """Independent instances of uneven size for batched runs: box edge U(2,10) um,
     dose per pulse U(0.1, 2) Gy, 1-20 pulses, average dose rate log-uniform in
