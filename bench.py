@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--batched-t-end", type=float, default=100.0, help="end time (ns) of the batched runs")
     ap.add_argument("--numodes", type=int, default=0, metavar="N",
                     help="the rate equations: N batched mixtures, then 20-pulse SBS + rate-equation runs")
+    ap.add_argument("--volume-scaling", action="store_true",
+                    help="SBS + PBCs, Gillespie runs and the rate equations of one homogeneous mixture in "
+                         "0.2, 0.5 and 1 um cubes")
+    ap.add_argument("--ssa-realisations", type=int, default=4096, help="Gillespie runs per cube edge")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -385,6 +389,107 @@ def numodes_bench(args):
     print(json.dumps(line), flush=True)
 
 
+# Algorithmic FP64 operations of one Gillespie event of the 9-reaction scheme:
+# nine propensities (pair count and product, ~3 each), their sum (9), the
+# running sum of the choice (~5 on average), the waiting time (ln ~20, a
+# division and an add) and the uniforms (4).
+ALG_FLOP_PER_SSA_EVENT = 70
+
+
+def volume_scaling_bench(args):
+    """The paper's volume-scaling check: one homogeneous mixture in cubes of
+    0.2, 0.5 and 1 um; SBS + PBCs (several cubes per edge), Gillespie runs in
+    the same volumes and the rate equations, compared species by species."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import workload as W
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    NA = 6.02214076e23
+    t_end = 1e4
+    rec = np.concatenate([[0.0], W.log_times(1e-3, t_end, 40)])
+    rec[-1] = t_end
+    n_sbs = {200.0: 32, 500.0: 8, 1000.0: 2}
+    out = []
+    ssa_rate = None
+    for L in W.VOLUME_SCALING_EDGES_NM:
+        V = L ** 3 * 1e-24  # nm^3 -> litres
+        n0 = W.volume_scaling_counts(L)
+        # SBS + PBCs: independent cubes stepped together
+        k = n_sbs[L]
+        wls = [W.volume_scaling(args.seed * 100 + i, L, t_end=t_end) for i in range(k)]
+        e = gsbs.Engine([L] * k, args.seed + 7, W.D_CONFIG, W.REACTIONS)
+        for i, wl in enumerate(wls):
+            e.inject(i, 0.0, wl.injections[0].xyz, wl.injections[0].species)
+            e.set_records(i, rec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.advance_to(t_end)
+        torch.cuda.synchronize()
+        wall_sbs = time.perf_counter() - t0
+        msteps = e.stats()["molecule_steps"]
+        sbs = np.stack([e.counts(i) for i in range(k)]).astype(np.float64)
+        e.close()
+        # Gillespie runs in the same volume
+        e = gsbs.Engine(L, 1, W.D_CONFIG, W.REACTIONS)
+        n_r = args.ssa_realisations
+        n0d = torch.as_tensor(np.tile(n0.astype(np.int32), (n_r, 1)), device="cuda")
+        vol = torch.full((n_r,), V, dtype=torch.float64, device="cuda")
+        gsbs.gsbs_ssa(e.ctx, n0d[:64], vol[:64], rec, seed=args.seed)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ssa_d, ev = gsbs.gsbs_ssa(e.ctx, n0d, vol, rec, seed=args.seed + 1)
+        wall_ssa = time.perf_counter() - t0
+        ssa = ssa_d.cpu().numpy().astype(np.float64)
+        # the rate equations from the same start, to every record time
+        c0 = np.tile(n0 / (NA * V), (len(rec), 1))
+        t0 = time.perf_counter()
+        ode, _ = gsbs.gsbs_numodes(e.ctx, c0, rec, rtol=1e-8)
+        wall_ode = time.perf_counter() - t0
+        e.close()
+        ode *= NA * V
+        m_sbs, m_ssa = sbs.mean(axis=0), ssa.mean(axis=0)
+        row = dict(L_nm=L, molecules=int(n0.sum()), sbs_cubes=k, ssa_realisations=n_r,
+                   wall_sbs_s=round(wall_sbs, 3), wall_ssa_s=round(wall_ssa, 4), wall_ode_s=round(wall_ode, 4),
+                   sbs_molecule_steps=int(msteps), ssa_events=int(ev.sum()), species={})
+        for sp in range(7):
+            ok = m_ssa[:, sp] >= 20
+            if not ok.any():
+                continue
+            r_ode = ode[ok, sp] / m_ssa[ok, sp]
+            r_sbs = m_sbs[ok, sp] / m_ssa[ok, sp]
+            row["species"][W.SPECIES[sp]] = dict(
+                max_abs_ode_over_ssa_minus_1=round(float(np.max(np.abs(r_ode - 1))), 5),
+                sbs_over_ssa_min=round(float(r_sbs.min()), 4), sbs_over_ssa_max=round(float(r_sbs.max()), 4),
+                sbs_over_ssa_end=round(float(r_sbs[-1]), 4))
+        note(f"L {L:g} nm: {n0.sum()} molecules; SBS {k} cubes {wall_sbs:.2f} s, Gillespie {n_r} runs "
+             f"{wall_ssa * 1e3:.1f} ms ({ev.sum()} events), rate equations {wall_ode * 1e3:.1f} ms")
+        for name, v in row["species"].items():
+            note(f"   {name:5s} |ODE/SSA-1| max {v['max_abs_ode_over_ssa_minus_1']:.4f}   SBS/SSA "
+                 f"{v['sbs_over_ssa_min']:.3f}..{v['sbs_over_ssa_max']:.3f} (end {v['sbs_over_ssa_end']:.3f})")
+        out.append(row)
+        if L == W.VOLUME_SCALING_EDGES_NM[-1]:
+            ssa_rate = ev.sum() / wall_ssa
+            ach = ALG_FLOP_PER_SSA_EVENT * ssa_rate / 1e12
+            ssa_roof = dict(bound="alu", achieved=round(ach, 5), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=round(ach / FP64_PEAK_TFLOPS, 6), kernel="k_ssa",
+                            alg_flop_per_event=ALG_FLOP_PER_SSA_EVENT)
+    line = {
+        "metric": "Gillespie events/s, volume-scaling mixture in a 1 um cube",
+        "value": round(float(ssa_rate), 1), "unit": "events/s", "higher_is_better": True, "n_gpus": 1,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "homogeneous mixture at 2.5e5 molecules/um^3 (spur-model fractions), "
+                               "cubes of 0.2, 0.5 and 1 um, 0 to 10 us"},
+        "roofline": ssa_roof,
+        "volume_scaling": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -402,6 +507,9 @@ def main():
         return
     if args.numodes:
         numodes_bench(args)
+        return
+    if args.volume_scaling:
+        volume_scaling_bench(args)
         return
 
     if args.calibrate_copy:
