@@ -326,9 +326,10 @@ int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, 
  * self-recombination), h_r = n_a n_b or n_a (n_a - 1) / 2 when a == b; each
  * event removes the reactants (not b when keep_b) and adds the products.
  * Random numbers: Philox4x64-10, key (seed, 0x4753534153534131), counter
- * (stream0 + m, event index, 0, 0); waiting time -ln(u1) / a_0, reaction =
- * first r whose running sum of propensities (table order) exceeds u2 a_0,
- * u = (top 53 bits of words 0 and 1 + 1/2) 2^-53.  A stream's event sequence
+ * (stream0 + m, j / 2, 0, 0) for events j (even; words 0, 1) and j + 1
+ * (words 2, 3); waiting time -ln(u1) / a_0, reaction = first r whose running
+ * sum of propensities (table order) exceeds u2 a_0, u = (top 53 bits of the
+ * word + 1/2) 2^-53.  A stream's event sequence
  * is therefore fixed bit for bit; event times carry the rounding of ln.
  * t_rec_ns[n_rec] (host, finite, >= 0, ascending) are the record times:
  * out[m][k][s] receives the counts after every event at a time <= t_rec_ns[k].

@@ -811,7 +811,8 @@ int64_t orc_cand_f32(int64_t n, const float* xyz, const int32_t* sp, float L, co
 /* the reactants are removed (not b when keep_b) and the products added.     */
 /*                                                                          */
 /* Random numbers: Philox4x64-10 with key (seed, 0x4753534153534131) and     */
-/* counter (stream, event index, 0, 0); u1 from word 0 and u2 from word 1,   */
+/* counter (stream, j / 2, 0, 0) serve events j and j + 1 (j even): event j  */
+/* takes u1, u2 from words 0 and 1, event j + 1 from words 2 and 3;          */
 /* u = (top 53 bits + 1/2) 2^-53, in (0, 1).                                 */
 /*                                                                          */
 /* out[k][s] = the counts after every event at a time <= t_rec[k] (t_rec     */
@@ -838,6 +839,7 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
     double t = 0.0;
     int64_t j = 0;
     int32_t rec = 0;
+    uint64_t w[4] = {0, 0, 0, 0};
     for (;;) {
         double a0 = 0.0;
         for (int r = 0; r < c->nr; ++r) {
@@ -848,11 +850,13 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
         }
         double t_next = INFINITY, u2 = 0.0;
         if (a0 > 0.0) {
-            const uint64_t ctr[4] = {stream, (uint64_t)j, 0, 0};
-            uint64_t w[4];
-            orc_philox4x64_10(ctr, key, w);
-            t_next = t + (-log(orc_u53(w[0])) / a0);
-            u2 = orc_u53(w[1]);
+            if ((j & 1) == 0) {
+                const uint64_t ctr[4] = {stream, (uint64_t)j >> 1, 0, 0};
+                orc_philox4x64_10(ctr, key, w);
+            }
+            const uint64_t* wj = w + 2 * (j & 1);
+            t_next = t + (-log(orc_u53(wj[0])) / a0);
+            u2 = orc_u53(wj[1]);
         }
         while (rec < n_rec && t_rec[rec] < t_next) {
             for (int s = 0; s < c->ns; ++s) out[(int64_t)rec * c->ns + s] = n[s];

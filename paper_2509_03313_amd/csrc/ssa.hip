@@ -3,13 +3,14 @@
 // 1977), the stochastic reference against which the paper checks SBS + PBCs
 // and its rate equations (section on the verification of periodic boundary
 // conditions, and the discussion of its figure).  One lane per volume; the
-// counts, constants and propensities live in registers.
+// constants and propensities live in registers, the counts in LDS.
 //
 // Propensity of reaction r: a_r = c_r h_r, c_r = k_r / (N_A V) with k_r the
 // printed constant in L/mol/ns, h_r = n_a n_b (a != b) or n_a (n_a - 1) / 2
 // (a == b), the number of distinct reactant pairs.  A step draws u1, u2 from
-// Philox4x64-10 (key (seed, 0x4753534153534131), counter (stream, event, 0,
-// 0), words 0 and 1, u = (top 53 bits + 1/2) 2^-53), waits -ln(u1) / a_0
+// Philox4x64-10 (key (seed, 0x4753534153534131), counter (stream, j / 2, 0,
+// 0): words 0 and 1 for an even event j, 2 and 3 for the odd one after it;
+// u = (top 53 bits + 1/2) 2^-53), waits -ln(u1) / a_0
 // (a_0 summed in table order) and fires the first reaction whose running sum
 // of propensities exceeds u2 a_0 (the last one with a_r > 0 if rounding leaves
 // none).  The reaction choice is exact integer-derived FP64 arithmetic in a
@@ -28,18 +29,6 @@ __device__ __forceinline__ double u53(uint64_t w) {
     return ((double)(w >> 11) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-// counts of reactants a and b (indices uniform across the wave)
-template <int S>
-__device__ __forceinline__ void gather_n(const int32_t* n, int a, int b, int32_t& na, int32_t& nb) {
-    na = 0;
-    nb = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        na = s == a ? n[s] : na;
-        nb = s == b ? n[s] : nb;
-    }
-}
-
 template <int S>
 __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, const double* __restrict__ vol,
                                             const double* __restrict__ t_rec, int32_t n_rec,
@@ -48,9 +37,12 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
     const int ns = tb.ns, nr = tb.nr;
-    int32_t cnt[S];
+    // the counts live in LDS, one column per lane: a reactant's count is read
+    // at an offset that is the same for every lane
+    __shared__ int32_t cnt_lds[S][64];
+    const int lane = threadIdx.x;
 #pragma unroll
-    for (int s = 0; s < S; ++s) cnt[s] = s < ns ? n0[(size_t)m * ns + s] : 0;
+    for (int s = 0; s < S; ++s) cnt_lds[s][lane] = s < ns ? n0[(size_t)m * ns + s] : 0;
     const double nav = kNA * vol[m];
     double c[kSsaMaxReactions];
 #pragma unroll
@@ -61,14 +53,14 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
     long long j = 0;
     int rec = 0;
     double t_r = t_rec[0];
+    uint64_t w[4] = {0, 0, 0, 0};
     for (;;) {
         double a[kSsaMaxReactions];
         double a0 = 0.0;
 #pragma unroll
         for (int r = 0; r < kSsaMaxReactions; ++r) {
             if (r < nr) {
-                int32_t na, nb;
-                gather_n<S>(cnt, tb.ra[r], tb.rb[r], na, nb);
+                const int32_t na = cnt_lds[tb.ra[r]][lane], nb = cnt_lds[tb.rb[r]][lane];
                 const double h = tb.ra[r] == tb.rb[r] ? (double)na * (double)(na - 1) * 0.5
                                                       : (double)na * (double)nb;
                 a[r] = c[r] * h;
@@ -79,16 +71,17 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         }
         double t_next = __builtin_huge_val(), u2 = 0.0;
         if (a0 > 0.0) {
-            uint64_t w[4];
-            philox(stream, (uint64_t)j, 0, 0, seed, kSsaKey, w);
-            t_next = t + (-log(u53(w[0])) / a0);
-            u2 = u53(w[1]);
+            // every live lane is at the same event index, so this branch is uniform
+            if ((j & 1) == 0) philox(stream, (uint64_t)j >> 1, 0, 0, seed, kSsaKey, w);
+            const bool odd = (j & 1) != 0;
+            t_next = t + (-log(u53(odd ? w[2] : w[0])) / a0);
+            u2 = u53(odd ? w[3] : w[1]);
         }
         while (rec < n_rec && t_r < t_next) {
             int32_t* orow = o + (size_t)rec * ns;
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                if (s < ns) orow[s] = cnt[s];
+                if (s < ns) orow[s] = cnt_lds[s][lane];
             ++rec;
             t_r = rec < n_rec ? t_rec[rec] : 0.0;
         }
@@ -114,7 +107,7 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         for (int r = 0; r < kSsaMaxReactions; ++r)
             if (r < nr) d = r == mu ? tb.dn[r] : d;
 #pragma unroll
-        for (int s = 0; s < S; ++s) cnt[s] += (int32_t)(int8_t)(uint8_t)(d >> (8 * s));
+        for (int s = 0; s < S; ++s) cnt_lds[s][lane] += (int32_t)(int8_t)(uint8_t)(d >> (8 * s));
         t = t_next;
         ++j;
     }
