@@ -67,6 +67,8 @@ def parse():
                     help="SBS + PBCs, Gillespie runs and the rate equations of one homogeneous mixture in "
                          "0.2, 0.5 and 1 um cubes")
     ap.add_argument("--ssa-realisations", type=int, default=4096, help="Gillespie runs per cube edge")
+    ap.add_argument("--ssa-throughput", type=int, default=131072, metavar="N",
+                    help="Gillespie runs of the 0.5 um volume-scaling cube timed for the event rate")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -415,7 +417,6 @@ def volume_scaling_bench(args):
     rec[-1] = t_end
     n_sbs = {200.0: 32, 500.0: 8, 1000.0: 2}
     out = []
-    ssa_rate = None
     for L in W.VOLUME_SCALING_EDGES_NM:
         V = L ** 3 * 1e-24  # nm^3 -> litres
         n0 = W.volume_scaling_counts(L)
@@ -472,19 +473,43 @@ def volume_scaling_bench(args):
             note(f"   {name:5s} |ODE/SSA-1| max {v['max_abs_ode_over_ssa_minus_1']:.4f}   SBS/SSA "
                  f"{v['sbs_over_ssa_min']:.3f}..{v['sbs_over_ssa_max']:.3f} (end {v['sbs_over_ssa_end']:.3f})")
         out.append(row)
-        if L == W.VOLUME_SCALING_EDGES_NM[-1]:
-            ssa_rate = ev.sum() / wall_ssa
-            ach = ALG_FLOP_PER_SSA_EVENT * ssa_rate / 1e12
-            ssa_roof = dict(bound="alu", achieved=round(ach, 5), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                            frac=round(ach / FP64_PEAK_TFLOPS, 6), kernel="k_ssa",
-                            alg_flop_per_event=ALG_FLOP_PER_SSA_EVENT)
+    # event rate with the device full: many runs of the 0.5 um cube
+    L = 500.0
+    V = L ** 3 * 1e-24
+    n_r = args.ssa_throughput
+    e = gsbs.Engine(L, 1, W.D_CONFIG, W.REACTIONS)
+    n0d = torch.as_tensor(np.tile(W.volume_scaling_counts(L).astype(np.int32), (n_r, 1)), device="cuda")
+    vol = torch.full((n_r,), V, dtype=torch.float64, device="cuda")
+    gsbs.gsbs_ssa(e.ctx, n0d[:64], vol[:64], rec, seed=args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ev = gsbs.gsbs_ssa(e.ctx, n0d, vol, rec, seed=args.seed + 2)
+    wall = time.perf_counter() - t0
+    e.close()
+    ssa_rate = ev.sum() / wall
+    ach = ALG_FLOP_PER_SSA_EVENT * ssa_rate / 1e12
+    ssa_roof = dict(bound="alu", achieved=round(ach, 5), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP64_PEAK_TFLOPS, 6), kernel="k_ssa", alg_flop_per_event=ALG_FLOP_PER_SSA_EVENT)
+    note(f"throughput: {n_r} Gillespie runs of the {L:g} nm cube, {ev.sum()} events in {wall * 1e3:.1f} ms "
+         f"= {ssa_rate:.3e} events/s")
+    # the oracle's direct method on a bounded sample of the same runs, one thread
+    from oracle import ssa_oracle as SO
+    n_cpu = 4096
+    n0h = W.volume_scaling_counts(L)
+    t0 = time.perf_counter()
+    ev_cpu = sum(SO.ssa(W.REACTIONS, 7, n0h, V, rec, args.seed + 2, m)[1] for m in range(n_cpu))
+    dt_cpu = time.perf_counter() - t0
+    cpu = dict(value=round(ev_cpu / dt_cpu, 1), unit="events/s", cores=1, kind="oracle",
+               sample=f"{n_cpu} of the {n_r} runs ({ev_cpu} events, {dt_cpu:.1f} s, 1 thread)")
+    note(f"oracle: {cpu['sample']}")
     line = {
-        "metric": "Gillespie events/s, volume-scaling mixture in a 1 um cube",
+        "metric": "Gillespie events/s, volume-scaling mixture in a 0.5 um cube",
         "value": round(float(ssa_rate), 1), "unit": "events/s", "higher_is_better": True, "n_gpus": 1,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "homogeneous mixture at 2.5e5 molecules/um^3 (spur-model fractions), "
-                               "cubes of 0.2, 0.5 and 1 um, 0 to 10 us"},
+        "config": {"workload": f"{n_r} runs of the homogeneous mixture at 2.5e5 molecules/um^3 (spur-model "
+                               f"fractions) in a 0.5 um cube, 0 to 10 us; comparisons in 0.2, 0.5 and 1 um cubes"},
         "roofline": ssa_roof,
+        "cpu_baseline": cpu,
         "volume_scaling": out,
     }
     print(json.dumps(line), flush=True)
