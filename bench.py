@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--ssa-realisations", type=int, default=4096, help="Gillespie runs per cube edge")
     ap.add_argument("--ssa-throughput", type=int, default=131072, metavar="N",
                     help="Gillespie runs of the 0.5 um volume-scaling cube timed for the event rate")
+    ap.add_argument("--dose-rate", action="store_true",
+                    help="the paper's dose-rate study: 1 us pulse trains at 2e5 and 1e6 Gy/s to 20 Gy, "
+                         "average dose rates 0.01-1e5 Gy/s, 2 um cube, SBS + rate equations")
+    ap.add_argument("--dose-rate-seeds", type=int, default=3, help="pulse trains per grid point")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -515,6 +519,44 @@ def volume_scaling_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def dose_rate_bench(args):
+    """The paper's dose-rate grid as one batched run (one instance per pulse
+    train): H2O2 yield and radical build-up against the average dose rate for
+    the two pulse dose rates."""
+    import numpy as np
+
+    from paper_2509_03313_amd import dose_rate as DR
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    trains = DR.paper_trains(seeds=tuple(range(1, args.dose_rate_seeds + 1)))
+    note(f"{len(trains)} pulse trains, {sum(t.n_pulses for t in trains)} pulses")
+    r = DR.run(trains, seed=args.seed)
+    note(f"wall {r['wall']:.1f} s, {r['steps']} steps, {r['molecule_steps']} molecule-steps, "
+         f"{r['ode_steps']} rate-equation steps")
+    grid = []
+    for dp in sorted({t.pulse_rate for t in trains}):
+        for rate in sorted({t.avg_rate for t in trains}):
+            idx = [k for k, t in enumerate(trains) if t.pulse_rate == dp and t.avg_rate == rate]
+            g = np.array([r["g_h2o2"][k] for k in idx])
+            b = np.array([DR.build_up(trains[k], r["counts"][k]) for k in idx])
+            grid.append(dict(pulse_rate_gy_s=dp, avg_rate_gy_s=rate, g_h2o2=round(float(g.mean()), 4),
+                             g_h2o2_sem=round(float(g.std(ddof=1) / np.sqrt(len(g))) if len(g) > 1 else 0.0, 4),
+                             radical_build_up=round(float(b.mean()), 4)))
+            note(f"Dp {dp:g} Gy/s  Dav {rate:>8g} Gy/s: G(H2O2) {g.mean():.4f} +- {grid[-1]['g_h2o2_sem']:.4f}"
+                 f"  radicals standing / per pulse {b.mean():.3f}")
+    line = {
+        "metric": "molecule-steps/s of the dose-rate grid (SBS + rate equations, batched pulse trains)",
+        "value": round(r["molecule_steps"] / r["wall"], 1), "unit": "molecule-steps/s", "higher_is_better": True,
+        "n_gpus": 1, "dtype": "f32 SBS, f64 rate equations", "data": "synthetic",
+        "config": {"workload": f"{len(trains)} trains of 1 us pulses at 2e5 / 1e6 Gy/s to 20 Gy, average "
+                               f"0.01-1e5 Gy/s, 2 um cube, hand-over 1 us after each pulse"},
+        "wall_s": round(r["wall"], 2), "grid": grid,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -535,6 +577,9 @@ def main():
         return
     if args.volume_scaling:
         volume_scaling_bench(args)
+        return
+    if args.dose_rate:
+        dose_rate_bench(args)
         return
 
     if args.calibrate_copy:
