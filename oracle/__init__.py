@@ -95,7 +95,8 @@ def lib():
                 "orc_bin_f32": (None, [i64, P(f32), f32, i32, P(i32)]),
                 "orc_rc2_f32": (None, [P(Chem), d, P(f32)]),
                 "orc_cand_f32": (i64, [i64, P(f32), P(i32), f32, P(Chem), d, P(i64), i64]),
-                "orc_ssa": (i64, [P(Chem), d, P(i64), i32, P(d), u64, u64, i64, P(i64), P(d), P(i32), i64]),
+                "orc_ssa": (i64, [P(Chem), d, P(i64), i32, P(d), u64, u64, i64, P(i64), P(d), P(i32), i64,
+                                  i32, P(d), P(i32), P(i32)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)

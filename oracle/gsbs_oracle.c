@@ -809,6 +809,9 @@ int64_t orc_cand_f32(int64_t n, const float* xyz, const int32_t* sp, float L, co
 /* tau = -ln(u1) / a_0, reaction mu = the first r whose running sum of a_r   */
 /* exceeds u2 a_0 (if rounding leaves none, the last r with a_r > 0), then   */
 /* the reactants are removed (not b when keep_b) and the products added.     */
+/* Zero-order sources (an extension: R9's reverse, the water autoionisation) */
+/* follow the reactions in the propensity list with a_q = rate_q N_A V       */
+/* (rate in mol/L/ns) and add their products.                               */
 /*                                                                          */
 /* Random numbers: Philox4x64-10 with key (seed, 0x4753534153534131) and     */
 /* counter (stream, j / 2, 0, 0) serve events j and j + 1 (j even): event j  */
@@ -828,13 +831,15 @@ static double orc_u53(uint64_t w)
 
 int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n_rec, const double* t_rec,
                 uint64_t seed, uint64_t stream, int64_t max_events, int64_t* out, double* ev_t, int32_t* ev_r,
-                int64_t ev_cap)
+                int64_t ev_cap, int32_t n_src, const double* src_rate, const int32_t* src_nprod,
+                const int32_t* src_prod)
 {
     const double NA = 6.02214076e23;
     int64_t n[ORC_MAX_SPECIES];
-    double cr[ORC_MAX_REACT], a[ORC_MAX_REACT];
+    double cr[ORC_MAX_REACT], a[ORC_MAX_REACT + 8];
     for (int s = 0; s < c->ns; ++s) n[s] = n0[s];
     for (int r = 0; r < c->nr; ++r) cr[r] = (10.0 * c->k_in[r]) / (NA * volume_L);
+    if (n_src > 8) return -2;
     const uint64_t key[2] = {seed, 0x4753534153534131ULL};
     double t = 0.0;
     int64_t j = 0;
@@ -847,6 +852,10 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
             const int64_t h = c->ra[r] == c->rb[r] ? na * (na - 1) / 2 : na * nb;
             a[r] = cr[r] * (double)h;
             a0 += a[r];
+        }
+        for (int q = 0; q < n_src; ++q) {
+            a[c->nr + q] = src_rate[q] * (NA * volume_L);
+            a0 += a[c->nr + q];
         }
         double t_next = INFINITY, u2 = 0.0;
         if (a0 > 0.0) {
@@ -867,15 +876,20 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
         const double target = u2 * a0;
         double cum = 0.0;
         int mu = -1, last = -1;
-        for (int r = 0; r < c->nr; ++r) {
+        for (int r = 0; r < c->nr + n_src; ++r) {
             cum += a[r];
             if (a[r] > 0.0) last = r;
             if (target < cum) { mu = r; break; }
         }
         if (mu < 0) mu = last;
-        n[c->ra[mu]] -= 1;
-        if (!c->keep_b[mu]) n[c->rb[mu]] -= 1;
-        for (int k = 0; k < c->nprod[mu]; ++k) n[c->prod[mu][k]] += 1;
+        if (mu < c->nr) {
+            n[c->ra[mu]] -= 1;
+            if (!c->keep_b[mu]) n[c->rb[mu]] -= 1;
+            for (int k = 0; k < c->nprod[mu]; ++k) n[c->prod[mu][k]] += 1;
+        } else {
+            const int q = mu - c->nr;
+            for (int k = 0; k < src_nprod[q]; ++k) n[src_prod[3 * q + k]] += 1;
+        }
         if (ev_t && j < ev_cap) { ev_t[j] = t_next; ev_r[j] = mu; }
         t = t_next;
         ++j;

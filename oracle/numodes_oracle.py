@@ -19,6 +19,11 @@ X), with k_r in L/mol/ns (the table's 1e10 L/mol/s times 10 / 1e9 ns) and
 concentrations in mol/L.  A reaction flagged keep_b consumes only a.  The
 integration uses SciPy's Radau (implicit Runge-Kutta, order 5) with the
 analytic Jacobian and tight tolerances: a library routine as one step.
+
+Extension (the paper prints R9 as an equilibrium and leaves its reverse and
+the pH background aside): zero-order sources, each producing its products at
+a constant rate in mol/L/ns -- with R9's reverse, the water autoionisation at
+k9 Kw, [H3O+][OH-] relaxes to Kw.
 """
 from __future__ import annotations
 
@@ -41,10 +46,15 @@ def event_rates(c, ra, rb, k):
     return np.where(same, 0.5 * k * c[ra] * c[ra], k * c[ra] * c[rb])
 
 
-def rhs(c, reactions):
+def rhs(c, reactions, sources=()):
+    """d[X]/dt.  sources: zero-order reactions (rate in mol/L/ns, products),
+    each adding its rate to every product."""
     ra, rb, k, prods, keep = table(reactions)
     rho = event_rates(c, ra, rb, k)
     d = np.zeros(len(c))
+    for src in sources:
+        for p in src.products:
+            d[p] += src.rate
     for r in range(len(ra)):
         d[ra[r]] -= rho[r]
         if not keep[r]:
@@ -75,13 +85,14 @@ def jacobian(c, reactions):
     return J
 
 
-def integrate(c0, dt, reactions, rtol=1e-11, atol=1e-24):
-    """Concentrations (mol/L) after dt ns from c0."""
+def integrate(c0, dt, reactions, rtol=1e-11, atol=1e-24, sources=()):
+    """Concentrations (mol/L) after dt ns from c0 (a zero-order source adds a
+    constant to the right-hand side and nothing to the Jacobian)."""
     from scipy.integrate import solve_ivp
     c0 = np.asarray(c0, dtype=np.float64)
     if dt <= 0:
         return c0.copy()
-    sol = solve_ivp(lambda t, y: rhs(y, reactions), (0.0, float(dt)), c0, method="Radau",
+    sol = solve_ivp(lambda t, y: rhs(y, reactions, sources), (0.0, float(dt)), c0, method="Radau",
                     jac=lambda t, y: jacobian(y, reactions), rtol=rtol, atol=atol)
     assert sol.success, sol.message
     return sol.y[:, -1]

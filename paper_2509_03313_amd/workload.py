@@ -53,6 +53,15 @@ class Reaction:
     keep_b: bool = False     # test-only sink: reactant b survives unchanged
 
 
+@dataclasses.dataclass(frozen=True)
+class Source:
+    """A zero-order reaction (no reactants): products appear at a constant
+    rate, mol/L/ns, anywhere in the volume."""
+    name: str
+    rate: float              # mol/L/ns
+    products: tuple          # species indices, at most three
+
+
 # Table 1; H2O is not tracked, R9 is taken in the forward direction only.
 REACTIONS = [
     Reaction("R1", E_AQ, E_AQ, 1.3, (H2, OHM, OHM)),
@@ -65,6 +74,14 @@ REACTIONS = [
     Reaction("R8", H, H, 1.1, (H2,)),
     Reaction("R9", H3O, OHM, 11.0, ()),
 ]
+
+# Chemistry extension: pH 7 water.  R9 made reversible by its reverse, the
+# autoionisation H2O -> H3O+ + OH-, at k9 * Kw (Kw = 1e-14 M^2 at 25 C), so that
+# [H3O+][OH-] relaxes to Kw; the background starts at 1e-7 mol/L of each.
+KW_M2 = 1e-14
+PH7_BACKGROUND_M = 1e-7
+SOURCES_PH7 = [Source("R9 reverse", 10.0 * 11.0 * KW_M2, (H3O, OHM))]  # 1e10 /M/s * 10 = /M/ns
+
 
 # synthetic spur composition, molecules per 100 (charge and redox balance to 0)
 SPUR_FRACTIONS = np.array([29, 35, 4, 30, 1, 0, 1], dtype=np.float64) / 100.0

@@ -6,7 +6,9 @@
   * the Jacobian equals central finite differences of the right-hand side;
   * the full water scheme conserves charge (H3O+ - e_aq - OH-) and the redox
     balance (OH + 2 H2O2 - e_aq - H - 2 H2) to rounding;
-  * a test-only sink (keep_b) decays A exponentially at k [B].
+  * a test-only sink (keep_b) decays A exponentially at k [B];
+  * a zero-order source alone grows its products linearly, and with R9 the
+    ion concentration relaxes along the tanh / coth closed form to sqrt(Kw).
 """
 import math
 import os
@@ -72,3 +74,31 @@ def test_sink_decays_exponentially():
     t = 2e4
     c = N.integrate([a0, b], t, r)
     assert abs(c[0] - a0 * math.exp(-20.0 * b * t)) <= 1e-8 * a0 and c[1] == b
+
+
+def test_source_alone_is_linear():
+    src = [W.Source("S", 2e-12, (0, 1))]
+    c = N.integrate([1e-7, 0.0], 1e5, [], sources=src)
+    assert np.allclose(c, [1e-7 + 2e-7, 2e-7], rtol=1e-10, atol=0)
+
+
+def test_autoionisation_relaxes_along_tanh():
+    # d c/dt = kb - kf c^2 for [H3O+] = [OH-] = c: c = ceq tanh(sqrt(kb kf) t + atanh(c0/ceq))
+    # (coth and acoth above ceq), ceq = sqrt(Kw)
+    r9 = [W.Reaction("R9", 0, 1, 11.0, ())]
+    src = [W.Source("R9 reverse", W.SOURCES_PH7[0].rate, (0, 1))]
+    kf = 110.0
+    kb = src[0].rate
+    ceq = math.sqrt(kb / kf)
+    assert abs(ceq - 1e-7) <= 1e-15
+    w = math.sqrt(kb * kf)
+    for t in (1e3, 3e4, 1e5, 1e6):
+        c = N.integrate([0.0, 0.0], t, r9, sources=src)
+        want = ceq * math.tanh(w * t)
+        assert abs(c[0] - want) <= 1e-8 * ceq and abs(c[1] - want) <= 1e-8 * ceq, (t, c, want)
+        c = N.integrate([3e-7, 3e-7], t, r9, sources=src)
+        want = ceq / math.tanh(w * t + math.atanh(ceq / 3e-7))
+        assert abs(c[0] - want) <= 1e-8 * ceq, (t, c, want)
+    # unequal starts: the ion product settles at Kw
+    c = N.integrate([5e-7, 1e-8], 1e8, r9, sources=src)
+    assert abs(c[0] * c[1] - W.KW_M2) <= 1e-6 * W.KW_M2

@@ -10,6 +10,8 @@
     equations (the paper finds its rate equations and the Gillespie reference
     within 1 % of each other for such a mixture);
   * charge and redox balance conserved exactly in every realisation;
+  * zero-order sources: Poisson counts alone, and with R9 the pH 7 background
+    held at its equilibrium;
   * edge cases: records before the first event, no possible reaction, the
     event limit, and determinism of the counter-based random numbers.
 """
@@ -136,3 +138,32 @@ def test_edges_and_determinism():
     ev_t = a[2][0]
     assert np.all(np.diff(ev_t) > 0)
     assert a[0][0][2] == np.sum(ev_t <= 1e3)
+
+
+def test_source_alone_is_poisson():
+    src = [W.Source("S", 1e-12, (0, 1))]
+    V = 1e-16
+    lam = 1e-12 * NA * V  # per ns
+    t = np.array([50.0, 200.0])
+    ens = S.ensemble([], 2, [0, 3], V, t, seed=15, n_real=3000, sources=src)
+    assert np.all(ens[:, :, 1] - ens[:, :, 0] == 3)
+    for k, tk in enumerate(t):
+        mu = lam * tk
+        states = list(range(0, int(mu + 8 * math.sqrt(mu) + 10)))
+        pk = [math.exp(-mu) * mu ** s / math.factorial(s) for s in states]
+        _check_hist(ens[:, k, 0], states, pk, len(ens))
+
+
+def test_autoionisation_holds_the_background():
+    # pH 7 background with R9 and its reverse: the mean ion count stays at
+    # 1e-7 mol/L (up to the O(1/N) stochastic correction)
+    r9 = [W.Reaction("R9", 0, 1, 11.0, ())]
+    V = 1e-14  # 602 ions of each kind
+    n_eq = 1e-7 * NA * V
+    n0 = [int(round(n_eq))] * 2
+    t = np.array([1e5, 1e6])
+    src = [W.Source("R9 reverse", W.SOURCES_PH7[0].rate, (0, 1))]
+    ens = S.ensemble(r9, 2, n0, V, t, seed=16, n_real=64, sources=src)
+    assert np.all(ens[:, :, 0] == ens[:, :, 1])
+    m = ens[:, :, 0].mean()
+    assert abs(m - n_eq) <= 0.02 * n_eq, (m, n_eq)
