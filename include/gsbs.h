@@ -122,6 +122,23 @@ int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
  * 2R >= L for some cube (PBC 2). */
 int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
 
+/* A zero-order reaction: its products appear at rate_M_per_ns mol/L/ns
+ * anywhere in the volume.  Extension of Table 1, which prints R9 as an
+ * equilibrium: R9's reverse, the water autoionisation H2O -> H3O+ + OH- at
+ * k9 Kw, keeps [H3O+][OH-] at Kw (pH 7 water). */
+typedef struct {
+    double rate_M_per_ns;
+    int32_t n_products; /* 1..3 */
+    int32_t products[3];
+} gsbs_source;
+
+/* Replace the zero-order sources (n <= 4; 0 clears them).  They act in the
+ * homogeneous solvers (gsbs_numodes, gsbs_ssa); the SBS steps of
+ * gsbs_advance_to do not create molecules from them.  Fails with GSBS_EINVAL
+ * for a negative or non-finite rate or a product outside the species table,
+ * GSBS_ESTATE before gsbs_set_species. */
+int gsbs_set_sources(gsbs_ctx* ctx, int32_t n, const gsbs_source* src);
+
 /* Replace the method parameters.  The search fields (grid_config, autotune,
  * search_split, search_box) and step_graph change only speed, never a result,
  * and may change between advances; the others before the first one. */
@@ -297,7 +314,8 @@ int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y
  * at the event rate k [a][b] (k [a]^2 / 2 when a == b: the table prints 2k for
  * self-recombinations, so that d[a]/dt = -k [a]^2, the paper's equation for the
  * OH recombination), k = 10 * k_in L/mol/ns; each event removes its reactants
- * (not b when keep_b) and adds its products.  c0 and c1 are [n][n_species]
+ * (not b when keep_b) and adds its products; each zero-order source of
+ * gsbs_set_sources adds its rate to its products.  c0 and c1 are [n][n_species]
  * concentrations in mol/L (row-major; n_species must equal the table's
  * species count, else GSBS_EINVAL), dt_ns[n] the time of each solution;
  * c1 receives the concentrations after dt_ns (negative entries of c0 are
@@ -324,7 +342,9 @@ int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, 
  * Reaction r between a and b has the propensity c_r h_r, c_r = k_r / (N_A V)
  * (k_r = 10 * k_in L/mol/ns, the printed constant: 2k for a
  * self-recombination), h_r = n_a n_b or n_a (n_a - 1) / 2 when a == b; each
- * event removes the reactants (not b when keep_b) and adds the products.
+ * event removes the reactants (not b when keep_b) and adds the products.  The
+ * zero-order sources of gsbs_set_sources follow the reactions in the
+ * propensity list with a_q = rate_q N_A V and add their products.
  * Random numbers: Philox4x64-10, key (seed, 0x4753534153534131), counter
  * (stream0 + m, j / 2, 0, 0) for events j (even; words 0, 1) and j + 1
  * (words 2, 3); waiting time -ln(u1) / a_0, reaction = first r whose running

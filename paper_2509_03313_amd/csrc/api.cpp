@@ -152,6 +152,7 @@ struct gsbs_ctx {
     int ns = 0;
     std::vector<double> D;
     std::vector<gsbs_reaction> rx;
+    std::vector<gsbs_source> src;  // zero-order sources (homogeneous solvers)
     std::vector<double> R;
     bool chem_ready = false;
     ChemDev chem_h{};
@@ -904,6 +905,20 @@ int gsbs_set_reactions(gsbs_ctx* c, int32_t n, const gsbs_reaction* r) {
     return GSBS_OK;
 }
 
+int gsbs_set_sources(gsbs_ctx* c, int32_t n, const gsbs_source* src) {
+    if (!c || n < 0 || n > kMaxSources || (n > 0 && !src)) return fail(GSBS_EINVAL, "sources: 0..4");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    for (int q = 0; q < n; ++q) {
+        if (!(src[q].rate_M_per_ns >= 0.0) || !std::isfinite(src[q].rate_M_per_ns))
+            return fail(GSBS_EINVAL, "source rate must be finite and >= 0");
+        if (src[q].n_products < 1 || src[q].n_products > 3) return fail(GSBS_EINVAL, "1..3 source products");
+        for (int k = 0; k < src[q].n_products; ++k)
+            if (src[q].products[k] < 0 || src[q].products[k] >= c->ns) return fail(GSBS_EINVAL, "product species");
+    }
+    c->src.assign(src, src + n);
+    return GSBS_OK;
+}
+
 int gsbs_set_params(gsbs_ctx* c, const gsbs_params* p) {
     if (!c || !p) return fail(GSBS_EINVAL, "null");
     if (!(p->c_cut > 0) || p->rounds < 1 || !(p->dt0_ns > 0) || !(p->ratio > 1.0) || p->dt_max_ns < 0 ||
@@ -1359,6 +1374,8 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
         if (!q.keep_b) tb.nu[r][q.b] -= 1.0;
         for (int k = 0; k < q.n_products; ++k) tb.nu[r][q.products[k]] += 1.0;
     }
+    for (const gsbs_source& q : c->src)
+        for (int k = 0; k < q.n_products; ++k) tb.src[q.products[k]] += q.rate_M_per_ns;
     const size_t nc = (size_t)n * (size_t)c->ns;
     double *d0 = nullptr, *dd = nullptr, *d1 = nullptr;
     int32_t* dsteps = nullptr;
@@ -1432,6 +1449,15 @@ int gsbs_ssa(gsbs_ctx* c, int32_t n, int32_t n_species, const int32_t* n0, const
         uint64_t d = 0;
         for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
         tb.dn[r] = d;
+    }
+    tb.nsrc = (int32_t)c->src.size();
+    for (int q = 0; q < tb.nsrc; ++q) {
+        int nu[kOdeMaxSpecies] = {};
+        for (int k = 0; k < c->src[q].n_products; ++k) nu[c->src[q].products[k]] += 1;
+        uint64_t d = 0;
+        for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
+        tb.src_rate[q] = c->src[q].rate_M_per_ns;
+        tb.dn[kSsaMaxReactions + q] = d;
     }
     const size_t nc = (size_t)n * (size_t)c->ns, no = (size_t)n * (size_t)n_rec * (size_t)c->ns;
     int32_t *d0 = nullptr, *dout = nullptr;

@@ -24,6 +24,7 @@ struct OdeTable {
     int32_t ra[kMaxReactions], rb[kMaxReactions];
     double kr[kMaxReactions];
     double nu[kMaxReactions][kOdeMaxSpecies];
+    double src[kOdeMaxSpecies];  // zero-order production, mol/L/ns per species
 };
 
 // Reaction table of the stochastic kinetics (Gillespie's direct method):
@@ -31,11 +32,13 @@ struct OdeTable {
 // (the printed value, 2k for a self-recombination) and changes species s by
 // the signed byte s of dn[r] per event.
 constexpr int kSsaMaxReactions = 16;
+constexpr int kMaxSources = 4;
 struct SsaTable {
-    int32_t ns, nr;
+    int32_t ns, nr, nsrc;
     int32_t ra[kSsaMaxReactions], rb[kSsaMaxReactions];
-    uint64_t dn[kSsaMaxReactions];
+    uint64_t dn[kSsaMaxReactions + kMaxSources];  // reactions, then sources
     double k10[kSsaMaxReactions];
+    double src_rate[kMaxSources];                  // zero-order sources, mol/L/ns
 };
 
 struct ChemDev {

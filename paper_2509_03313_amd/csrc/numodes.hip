@@ -40,7 +40,7 @@ __device__ __forceinline__ void gather2(const double* y, int a, int b, double& y
 template <int S>
 __device__ __forceinline__ void ode_rhs(const double* y, const OdeTable& tb, double* f) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) f[s] = 0.0;
+    for (int s = 0; s < S; ++s) f[s] = tb.src[s];  // zero-order sources
 #pragma unroll 3
     for (int r = 0; r < tb.nr; ++r) {
         double ya, yb;

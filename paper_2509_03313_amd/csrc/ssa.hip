@@ -15,6 +15,8 @@
 // of propensities exceeds u2 a_0 (the last one with a_r > 0 if rounding leaves
 // none).  The reaction choice is exact integer-derived FP64 arithmetic in a
 // fixed order, so the event sequence of a stream is reproducible bit for bit.
+// Zero-order sources (rate q in mol/L/ns) follow the reactions in the
+// propensity list with a_q = rate_q N_A V.
 #include "device_common.h"
 #include "engine.h"
 
@@ -44,6 +46,7 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
 #pragma unroll
     for (int s = 0; s < S; ++s) cnt_lds[s][lane] = s < ns ? n0[(size_t)m * ns + s] : 0;
     const double nav = kNA * vol[m];
+    constexpr int kA = kSsaMaxReactions + kMaxSources;  // reactions, then sources
     double c[kSsaMaxReactions];
 #pragma unroll
     for (int r = 0; r < kSsaMaxReactions; ++r) c[r] = r < nr ? tb.k10[r] / nav : 0.0;
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
     double t_r = t_rec[0];
     uint64_t w[4] = {0, 0, 0, 0};
     for (;;) {
-        double a[kSsaMaxReactions];
+        double a[kA];
         double a0 = 0.0;
 #pragma unroll
         for (int r = 0; r < kSsaMaxReactions; ++r) {
@@ -68,6 +71,11 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
             } else {
                 a[r] = 0.0;
             }
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxSources; ++q) {
+            a[kSsaMaxReactions + q] = q < tb.nsrc ? tb.src_rate[q] * nav : 0.0;
+            if (q < tb.nsrc) a0 += a[kSsaMaxReactions + q];
         }
         double t_next = __builtin_huge_val(), u2 = 0.0;
         if (a0 > 0.0) {
@@ -94,8 +102,8 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         double cum = 0.0;
         int mu = -1, last = -1;
 #pragma unroll
-        for (int r = 0; r < kSsaMaxReactions; ++r) {
-            if (r < nr) {
+        for (int r = 0; r < kA; ++r) {
+            if (r < nr || (r >= kSsaMaxReactions && r - kSsaMaxReactions < tb.nsrc)) {
                 cum += a[r];
                 last = (mu < 0 && a[r] > 0.0) ? r : last;
                 mu = (mu < 0 && target < cum) ? r : mu;
@@ -104,8 +112,8 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         mu = mu < 0 ? last : mu;
         uint64_t d = 0;
 #pragma unroll
-        for (int r = 0; r < kSsaMaxReactions; ++r)
-            if (r < nr) d = r == mu ? tb.dn[r] : d;
+        for (int r = 0; r < kA; ++r)
+            if (r < nr || (r >= kSsaMaxReactions && r - kSsaMaxReactions < tb.nsrc)) d = r == mu ? tb.dn[r] : d;
 #pragma unroll
         for (int s = 0; s < S; ++s) cnt_lds[s][lane] += (int32_t)(int8_t)(uint8_t)(d >> (8 * s));
         t = t_next;

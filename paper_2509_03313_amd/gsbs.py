@@ -48,6 +48,10 @@ class gsbs_reaction(C.Structure):
                 ("products", C.c_int32 * 3), ("keep_b", C.c_int32)]
 
 
+class gsbs_source(C.Structure):
+    _fields_ = [("rate_M_per_ns", C.c_double), ("n_products", C.c_int32), ("products", C.c_int32 * 3)]
+
+
 class gsbs_params(C.Structure):
     _fields_ = [("c_cut", C.c_double), ("rounds", C.c_int32), ("contact_only", C.c_int32),
                 ("dt0_ns", C.c_double), ("ratio", C.c_double), ("dt_max_ns", C.c_double),
@@ -96,6 +100,7 @@ _SIGS = {
     "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
     "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
     "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
+    "gsbs_set_sources": [_vp, _i32, _vp],
     "gsbs_ssa": [_vp, _i32, _i32, _vp, _vp, _i32, _P(_d), _u64, _u64, _i64, _vp, _P(_i64), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
@@ -521,6 +526,18 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_set_sources(ctx, sources):
+    """Zero-order sources: objects with rate (mol/L/ns) and products (see
+    workload.Source); used by gsbs_numodes and gsbs_ssa."""
+    arr = (gsbs_source * max(len(sources), 1))()
+    for k, q in enumerate(sources):
+        arr[k].rate_M_per_ns = float(q.rate)
+        arr[k].n_products = len(q.products)
+        for j, p in enumerate(q.products):
+            arr[k].products[j] = int(p)
+    _chk(_lib.gsbs_set_sources(ctx, len(sources), C.cast(arr, _vp)))
 
 
 def gsbs_ssa(ctx, n0, volume_L, t_rec_ns, seed, stream0=0, max_events=1 << 32):

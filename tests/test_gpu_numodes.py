@@ -142,3 +142,33 @@ def test_sbs_with_rate_equations_between_pulses(g):
     # ~600 H2O2 per pulse in 1 um^3: a few sigma of Poisson noise on the totals
     n_h, n_p = hyb["n_h2o2"][-1], plain["n_h2o2"][-1]
     assert abs(n_h - n_p) <= 5 * np.sqrt(n_p) + 0.1 * n_p
+
+
+def test_zero_order_sources(g):
+    """R9 with its reverse (the water autoionisation) on the device against the
+    oracle: the pH 7 background relaxes to sqrt(Kw); the full scheme with the
+    source and a radiolytic mixture matches the oracle."""
+    r9 = [W.Reaction("R9", 0, 1, 11.0, ())]
+    src2 = [W.Source("R9 reverse", W.SOURCES_PH7[0].rate, (0, 1))]
+    e = g.Engine(1000.0, 1, [1.0, 1.0], r9)
+    g.gsbs_set_sources(e.ctx, src2)
+    c0 = np.array([[0.0, 0.0], [3e-7, 3e-7], [5e-7, 1e-8]])
+    t = np.array([3e4, 1e5, 1e8])
+    c1, _ = g.gsbs_numodes(e.ctx, c0, t, rtol=1e-7)
+    for m in range(3):
+        ref = N.integrate(c0[m], t[m], r9, sources=src2)
+        assert np.all(np.abs(c1[m] - ref) <= 5e-5 * ref), (m, c1[m], ref)
+    with pytest.raises(g.GsbsError):
+        g.gsbs_set_sources(e.ctx, [W.Source("bad", -1.0, (0,))])
+    e.close()
+    e = g.Engine(1000.0, 1, W.D_CONFIG, W.REACTIONS)
+    g.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
+    rng = np.random.default_rng(8)
+    c0 = 10.0 ** rng.uniform(-8, -6, size=(8, 7))
+    t = np.array([1e3, 1e5, 1e7, 1e9] * 2)
+    c1, _ = g.gsbs_numodes(e.ctx, c0, t, rtol=1e-7)
+    e.close()
+    for m in range(8):
+        ref = N.integrate(c0[m], t[m], W.REACTIONS, sources=W.SOURCES_PH7)
+        big = ref > 1e-13
+        assert np.all(np.abs(c1[m] - ref)[big] <= 5e-5 * ref[big]), (m, c1[m], ref)

@@ -173,3 +173,30 @@ def test_rate_equations_match_ensemble_mean(g):
     say("events per realisation", ev.min(), ev.max())
     ok = mean >= 200
     assert np.all(np.abs(mean - ode)[ok] <= 0.01 * ode[ok] + 3 * se[ok])
+
+
+def test_sources_event_for_event(g):
+    """The water scheme with R9's reverse (a zero-order source) and the pH 7
+    background, event for event against the oracle."""
+    n = 40
+    V = 1e-17
+    n0 = S.counts_from_conc([2e-6, 2e-6, 3e-7, 2e-6 + 1e-7, 1e-7, 1e-7, 1e-7], V)
+    n0 = np.tile(n0.astype(np.int32), (n, 1))
+    t_rec = np.concatenate([[0.0], np.geomspace(1.0, 1e7, 20)])
+    e = g.Engine(1000.0, 1, W.D_CONFIG, W.REACTIONS)
+    g.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
+    out, ev = g.gsbs_ssa(e.ctx, n0, np.full(n, V), t_rec, seed=31)
+    e.close()
+    say("events", ev.min(), ev.max())
+    fired = 0
+    for m in range(n):
+        ref, ne, (ev_t, ev_r) = S.ssa(W.REACTIONS, 7, n0[m], V, t_rec, 31, m, log_events=1 << 22,
+                                      sources=W.SOURCES_PH7)
+        assert ne >= 0
+        fired += int(np.sum(ev_r == len(W.REACTIONS)))
+        for k, tk in enumerate(t_rec):
+            if not np.array_equal(out[m, k], ref[k]):
+                assert np.any(np.abs(ev_t - tk) <= 1e-9 * tk), (m, k, out[m, k], ref[k])
+    # the source took part: its events are in the compared sequences
+    say("source events", fired)
+    assert fired > 0
