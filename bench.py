@@ -73,6 +73,8 @@ def parse():
                     help="the paper's dose-rate study: 1 us pulse trains at 2e5 and 1e6 Gy/s to 20 Gy, "
                          "average dose rates 0.01-1e5 Gy/s, 2 um cube, SBS + rate equations")
     ap.add_argument("--dose-rate-seeds", type=int, default=3, help="pulse trains per grid point")
+    ap.add_argument("--ph7", action="store_true", help="dose-rate study in pH 7 water (background ions and "
+                                                        "R9's reverse in the rate equations)")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -532,7 +534,7 @@ def dose_rate_bench(args):
 
     trains = DR.paper_trains(seeds=tuple(range(1, args.dose_rate_seeds + 1)))
     note(f"{len(trains)} pulse trains, {sum(t.n_pulses for t in trains)} pulses")
-    r = DR.run(trains, seed=args.seed)
+    r = DR.run(trains, seed=args.seed, ph7=args.ph7)
     note(f"wall {r['wall']:.1f} s, {r['steps']} steps, {r['molecule_steps']} molecule-steps, "
          f"{r['ode_steps']} rate-equation steps")
     grid = []
@@ -551,7 +553,8 @@ def dose_rate_bench(args):
         "value": round(r["molecule_steps"] / r["wall"], 1), "unit": "molecule-steps/s", "higher_is_better": True,
         "n_gpus": 1, "dtype": "f32 SBS, f64 rate equations", "data": "synthetic",
         "config": {"workload": f"{len(trains)} trains of 1 us pulses at 2e5 / 1e6 Gy/s to 20 Gy, average "
-                               f"0.01-1e5 Gy/s, 2 um cube, hand-over 1 us after each pulse"},
+                               f"0.01-1e5 Gy/s, 2 um cube, hand-over 1 us after each pulse"
+                               + ("; pH 7 water" if args.ph7 else "")},
         "wall_s": round(r["wall"], 2), "grid": grid,
     }
     print(json.dumps(line), flush=True)

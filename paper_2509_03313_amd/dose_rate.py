@@ -84,17 +84,32 @@ def paper_trains(seeds=(1, 2), avg_rates=(0.01, 1.0, 10.0, 100.0, 1e3, 1e4, 1e5)
     return out
 
 
-def run(trains: List[Train], L: float = 2000.0, seed: int = 1, numodes_rtol: float = 1e-6) -> dict:
+def run(trains: List[Train], L: float = 2000.0, seed: int = 1, numodes_rtol: float = 1e-6,
+        ph7: bool = False) -> dict:
     """Run the trains as instances of one engine.  Returns, per train, the
     species counts, the H2O2 count and the deposited energy just before every
     pulse after the first and one period after the last, the H2O2 yield (slope
     of count against energy, molecules per 100 eV) and the wall time of the
-    whole batch."""
+    whole batch.
+
+    ph7: pH 7 water (a chemistry extension): every cube starts with the
+    1e-7 mol/L H3O+ / OH- background at uniform positions, and the rate
+    equations carry R9's reverse (the water autoionisation) as a zero-order
+    source.  The SBS stages (about 2 us per pulse) do not create ions; the
+    background's turnover time, 1 / (k9 sqrt(Kw)) ~ 90 us, is much longer."""
     import torch
     n = len(trains)
     V = L ** 3 * 1e-24
     e = gsbs.Engine([L] * n, seed, W.D_CONFIG, W.REACTIONS)
     inj = [t.injections(L) for t in trains]
+    if ph7:
+        gsbs.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
+        n_bg = int(round(W.PH7_BACKGROUND_M * NA * V))
+        for i, t in enumerate(trains):
+            rng = np.random.default_rng([t.seed, 12])
+            xyz = rng.uniform(-L / 2, L / 2, size=(2 * n_bg, 3))
+            sp = np.repeat(np.array([W.H3O, W.OHM], dtype=np.uint8), n_bg)
+            inj[i] = [W.Injection(0.0, W._into_box(xyz, L), sp, 0.0)] + inj[i]
     for i, js in enumerate(inj):
         for j in js:
             e.inject(i, j.t, j.xyz, j.species, j.edep_ev)
