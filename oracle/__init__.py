@@ -47,6 +47,8 @@ class Chem(C.Structure):
         ("keep_b", C.c_int32 * MAX_REACT),
         ("c_cut", C.c_double),
         ("rounds", C.c_int32), ("contact_only", C.c_int32), ("brute", C.c_int32),
+        ("fo_k", C.c_double * MAX_SPECIES), ("fo_nprod", C.c_int32 * MAX_SPECIES),
+        ("fo_prod", (C.c_int32 * 2) * MAX_SPECIES),
     ]
 
 
@@ -108,8 +110,10 @@ def lib():
 
 # ------------------------------------------------------------ chemistry ---
 def make_chem(D, reactions, c_cut: float = 5.0, rounds: int = 4, contact_only: bool = False,
-              brute: bool = False) -> Chem:
-    """reactions: objects with a, b, k_in, products, keep_b (see workload.Reaction)."""
+              brute: bool = False, first_order=()) -> Chem:
+    """reactions: objects with a, b, k_in, products, keep_b (see
+    workload.Reaction); first_order: objects with a, k (per ns) and products
+    (at most two; see workload.FirstOrder), one per species."""
     c = Chem()
     c.ns = len(D)
     c.nr = len(reactions)
@@ -127,6 +131,12 @@ def make_chem(D, reactions, c_cut: float = 5.0, rounds: int = 4, contact_only: b
     c.rounds = rounds
     c.contact_only = 1 if contact_only else 0
     c.brute = 1 if brute else 0
+    for f in first_order:
+        assert c.fo_k[f.a] == 0.0 and len(f.products) <= 2
+        c.fo_k[f.a] = f.k
+        c.fo_nprod[f.a] = len(f.products)
+        for k, p in enumerate(f.products):
+            c.fo_prod[f.a][k] = p
     return c
 
 

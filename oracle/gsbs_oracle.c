@@ -59,6 +59,12 @@ typedef struct {
     int32_t rounds;                /* rounds of mutual-best matching per step */
     int32_t contact_only;          /* 1: react only if the pair is within R at the start or end */
     int32_t brute;                 /* 1: all-pairs candidate search instead of the cell list */
+    /* First-order (pseudo-first-order scavenging) channels, an extension: a
+     * molecule of species s turns into fo_prod[s][0] (plus fo_prod[s][1]
+     * when fo_nprod[s] == 2; removed when 0) at rate fo_k[s] per ns. */
+    double fo_k[ORC_MAX_SPECIES];
+    int32_t fo_nprod[ORC_MAX_SPECIES];
+    int32_t fo_prod[ORC_MAX_SPECIES][2];
 } orc_chem;
 
 /* ------------------------------------------------------------------------ */
@@ -647,6 +653,59 @@ int64_t orc_step(orc_inst* s, const orc_chem* c, double dt)
         ++w;
     }
     s->n = w;
+
+    /* 5. First-order channels (extension).  Every molecule that survived the
+     *    step's pair reactions (not this step's products) converts with
+     *    probability p = 1 - exp(-k dt), decided by the top 24 bits k24 of
+     *    word 0 of the Philox block at counter (uid, step, 3, 0): converts iff
+     *    (2 k24 + 1) 2^-25 < p.  Product 1 takes the molecule's place and uid,
+     *    product 2 appears at the same point (x0 = x) with uid = word 1 with
+     *    the top bit set; no product removes the molecule. */
+    int64_t n_fo2 = 0;
+    for (int64_t i = 0; i < w; ++i) if (c->fo_k[s->sp[i]] > 0.0 && c->fo_nprod[s->sp[i]] == 2) ++n_fo2;
+    double* fx = (double*)malloc(sizeof(double) * 3 * (n_fo2 ? n_fo2 : 1));
+    int32_t* fsp = (int32_t*)malloc(sizeof(int32_t) * (n_fo2 ? n_fo2 : 1));
+    uint64_t* fuid = (uint64_t*)malloc(sizeof(uint64_t) * (n_fo2 ? n_fo2 : 1));
+    int64_t nf = 0;
+    char* gone = (char*)calloc((size_t)(w ? w : 1), 1);
+    for (int64_t i = 0; i < w; ++i) {
+        const int32_t sp = s->sp[i];
+        if (!(c->fo_k[sp] > 0.0)) continue;
+        const double pc = -expm1(-c->fo_k[sp] * dt);
+        uint64_t ctr[4] = {s->uid[i], (uint64_t)s->step, 3, 0}, wd[4];
+        orc_philox4x64_10(ctr, s->key, wd);
+        const double u = (double)(2 * (wd[0] >> 40) + 1) * (1.0 / 33554432.0);
+        if (!(u < pc)) continue;
+        if (c->fo_nprod[sp] == 0) { gone[i] = 1; continue; }
+        s->sp[i] = c->fo_prod[sp][0];
+        if (c->fo_nprod[sp] == 2) {
+            for (int e = 0; e < 3; ++e) fx[3 * nf + e] = s->x[3 * i + e];
+            fsp[nf] = c->fo_prod[sp][1];
+            fuid[nf] = wd[1] | 0x8000000000000000ULL;
+            ++nf;
+        }
+    }
+    int64_t w2 = 0;
+    for (int64_t i = 0; i < w; ++i) {
+        if (gone[i]) continue;
+        if (w2 != i) {
+            for (int e = 0; e < 3; ++e) { s->x[3 * w2 + e] = s->x[3 * i + e]; s->x0[3 * w2 + e] = s->x0[3 * i + e]; }
+            s->sp[w2] = s->sp[i];
+            s->uid[w2] = s->uid[i];
+        }
+        ++w2;
+    }
+    w = w2;
+    s->n = w;
+    orc_reserve(s, w + nf);
+    for (int64_t k = 0; k < nf; ++k) {
+        for (int e = 0; e < 3; ++e) { s->x[3 * (w + k) + e] = fx[3 * k + e]; s->x0[3 * (w + k) + e] = fx[3 * k + e]; }
+        s->sp[w + k] = fsp[k];
+        s->uid[w + k] = fuid[k];
+    }
+    w += nf;
+    s->n = w;
+    free(fx); free(fsp); free(fuid); free(gone);
     orc_reserve(s, w + np);
     for (int64_t k = 0; k < np; ++k) {
         for (int e = 0; e < 3; ++e) { s->x[3 * (w + k) + e] = px[3 * k + e]; s->x0[3 * (w + k) + e] = px[3 * k + e]; }
@@ -809,9 +868,10 @@ int64_t orc_cand_f32(int64_t n, const float* xyz, const int32_t* sp, float L, co
 /* tau = -ln(u1) / a_0, reaction mu = the first r whose running sum of a_r   */
 /* exceeds u2 a_0 (if rounding leaves none, the last r with a_r > 0), then   */
 /* the reactants are removed (not b when keep_b) and the products added.     */
-/* Zero-order sources (an extension: R9's reverse, the water autoionisation) */
-/* follow the reactions in the propensity list with a_q = rate_q N_A V       */
-/* (rate in mol/L/ns) and add their products.                               */
+/* Extensions: the first-order channels of the chemistry (species order,    */
+/* a = fo_k[s] n_s) and then the zero-order sources (R9's reverse, the water */
+/* autoionisation; a_q = rate_q N_A V, rate in mol/L/ns) follow the          */
+/* reactions in the propensity list.                                         */
 /*                                                                          */
 /* Random numbers: Philox4x64-10 with key (seed, 0x4753534153534131) and     */
 /* counter (stream, j / 2, 0, 0) serve events j and j + 1 (j even): event j  */
@@ -836,7 +896,11 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
 {
     const double NA = 6.02214076e23;
     int64_t n[ORC_MAX_SPECIES];
-    double cr[ORC_MAX_REACT], a[ORC_MAX_REACT + 8];
+    double cr[ORC_MAX_REACT], a[ORC_MAX_REACT + ORC_MAX_SPECIES + 8];
+    int32_t fo_sp[ORC_MAX_SPECIES];
+    int nfo = 0;
+    for (int sp = 0; sp < c->ns; ++sp)
+        if (c->fo_k[sp] > 0.0) fo_sp[nfo++] = sp;
     for (int s = 0; s < c->ns; ++s) n[s] = n0[s];
     for (int r = 0; r < c->nr; ++r) cr[r] = (10.0 * c->k_in[r]) / (NA * volume_L);
     if (n_src > 8) return -2;
@@ -853,9 +917,13 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
             a[r] = cr[r] * (double)h;
             a0 += a[r];
         }
-        for (int q = 0; q < n_src; ++q) {
-            a[c->nr + q] = src_rate[q] * (NA * volume_L);
+        for (int q = 0; q < nfo; ++q) {
+            a[c->nr + q] = c->fo_k[fo_sp[q]] * (double)n[fo_sp[q]];
             a0 += a[c->nr + q];
+        }
+        for (int q = 0; q < n_src; ++q) {
+            a[c->nr + nfo + q] = src_rate[q] * (NA * volume_L);
+            a0 += a[c->nr + nfo + q];
         }
         double t_next = INFINITY, u2 = 0.0;
         if (a0 > 0.0) {
@@ -876,7 +944,7 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
         const double target = u2 * a0;
         double cum = 0.0;
         int mu = -1, last = -1;
-        for (int r = 0; r < c->nr + n_src; ++r) {
+        for (int r = 0; r < c->nr + nfo + n_src; ++r) {
             cum += a[r];
             if (a[r] > 0.0) last = r;
             if (target < cum) { mu = r; break; }
@@ -886,8 +954,12 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
             n[c->ra[mu]] -= 1;
             if (!c->keep_b[mu]) n[c->rb[mu]] -= 1;
             for (int k = 0; k < c->nprod[mu]; ++k) n[c->prod[mu][k]] += 1;
+        } else if (mu < c->nr + nfo) {
+            const int sp = fo_sp[mu - c->nr];
+            n[sp] -= 1;
+            for (int k = 0; k < c->fo_nprod[sp]; ++k) n[c->fo_prod[sp][k]] += 1;
         } else {
-            const int q = mu - c->nr;
+            const int q = mu - c->nr - nfo;
             for (int k = 0; k < src_nprod[q]; ++k) n[src_prod[3 * q + k]] += 1;
         }
         if (ev_t && j < ev_cap) { ev_t[j] = t_next; ev_r[j] = mu; }

@@ -23,7 +23,8 @@ analytic Jacobian and tight tolerances: a library routine as one step.
 Extension (the paper prints R9 as an equilibrium and leaves its reverse and
 the pH background aside): zero-order sources, each producing its products at
 a constant rate in mol/L/ns -- with R9's reverse, the water autoionisation at
-k9 Kw, [H3O+][OH-] relaxes to Kw.
+k9 Kw, [H3O+][OH-] relaxes to Kw; and first-order channels a -> products at
+k [a] (scavenging by a solute at a fixed concentration, e.g. O2).
 """
 from __future__ import annotations
 
@@ -46,12 +47,18 @@ def event_rates(c, ra, rb, k):
     return np.where(same, 0.5 * k * c[ra] * c[ra], k * c[ra] * c[rb])
 
 
-def rhs(c, reactions, sources=()):
+def rhs(c, reactions, sources=(), first_order=()):
     """d[X]/dt.  sources: zero-order reactions (rate in mol/L/ns, products),
-    each adding its rate to every product."""
+    each adding its rate to every product; first_order: channels a -> products
+    at k [a] (k per ns)."""
     ra, rb, k, prods, keep = table(reactions)
     rho = event_rates(c, ra, rb, k)
     d = np.zeros(len(c))
+    for f in first_order:
+        r1 = f.k * c[f.a]
+        d[f.a] -= r1
+        for p in f.products:
+            d[p] += r1
     for src in sources:
         for p in src.products:
             d[p] += src.rate
@@ -64,10 +71,14 @@ def rhs(c, reactions, sources=()):
     return d
 
 
-def jacobian(c, reactions):
+def jacobian(c, reactions, first_order=()):
     ra, rb, k, prods, keep = table(reactions)
     c = np.asarray(c, dtype=np.float64)
     J = np.zeros((len(c), len(c)))
+    for f in first_order:
+        J[f.a, f.a] -= f.k
+        for p in f.products:
+            J[p, f.a] += f.k
     for r in range(len(ra)):
         a, b = ra[r], rb[r]
         # d rho / d c
@@ -85,14 +96,14 @@ def jacobian(c, reactions):
     return J
 
 
-def integrate(c0, dt, reactions, rtol=1e-11, atol=1e-24, sources=()):
+def integrate(c0, dt, reactions, rtol=1e-11, atol=1e-24, sources=(), first_order=()):
     """Concentrations (mol/L) after dt ns from c0 (a zero-order source adds a
     constant to the right-hand side and nothing to the Jacobian)."""
     from scipy.integrate import solve_ivp
     c0 = np.asarray(c0, dtype=np.float64)
     if dt <= 0:
         return c0.copy()
-    sol = solve_ivp(lambda t, y: rhs(y, reactions, sources), (0.0, float(dt)), c0, method="Radau",
-                    jac=lambda t, y: jacobian(y, reactions), rtol=rtol, atol=atol)
+    sol = solve_ivp(lambda t, y: rhs(y, reactions, sources, first_order), (0.0, float(dt)), c0, method="Radau",
+                    jac=lambda t, y: jacobian(y, reactions, first_order), rtol=rtol, atol=atol)
     assert sol.success, sol.message
     return sol.y[:, -1]

@@ -18,17 +18,19 @@ import ctypes as C
 NA = 6.02214076e23
 
 
-def ssa(reactions, ns, n0, volume_L, t_rec, seed, stream, max_events=1 << 40, log_events=0, sources=()):
+def ssa(reactions, ns, n0, volume_L, t_rec, seed, stream, max_events=1 << 40, log_events=0, sources=(),
+        first_order=()):
     """One realisation.  Returns (counts [n_rec][ns] int64, events, (ev_t, ev_r))
     with events = -1 when max_events ran out before the last record.  sources:
     zero-order reactions (rate mol/L/ns, products), after the reactions in the
-    propensity list."""
+    propensity list; first_order: first-order channels (species order, between
+    the reactions and the sources)."""
     src_rate = np.array([q.rate for q in sources] + [0.0], dtype=np.float64)
     src_np = np.array([len(q.products) for q in sources] + [0], dtype=np.int32)
     src_p = np.zeros(3 * (len(sources) + 1), dtype=np.int32)
     for k, q in enumerate(sources):
         src_p[3 * k:3 * k + len(q.products)] = q.products
-    chem = make_chem([1.0] * ns, reactions)
+    chem = make_chem([1.0] * ns, reactions, first_order=first_order)
     n0 = np.ascontiguousarray(n0, dtype=np.int64)
     assert n0.shape == (ns,)
     t_rec = np.ascontiguousarray(t_rec, dtype=np.float64)
@@ -44,11 +46,12 @@ def ssa(reactions, ns, n0, volume_L, t_rec, seed, stream, max_events=1 << 40, lo
     return out, int(ne), (ev_t[:k], ev_r[:k])
 
 
-def ensemble(reactions, ns, n0, volume_L, t_rec, seed, n_real, stream0=0, sources=()):
+def ensemble(reactions, ns, n0, volume_L, t_rec, seed, n_real, stream0=0, sources=(), first_order=()):
     """n_real realisations (streams stream0 ...).  Returns counts [n_real][n_rec][ns]."""
     res = np.zeros((n_real, len(t_rec), ns), dtype=np.int64)
     for m in range(n_real):
-        out, ne, _ = ssa(reactions, ns, n0, volume_L, t_rec, seed, stream0 + m, sources=sources)
+        out, ne, _ = ssa(reactions, ns, n0, volume_L, t_rec, seed, stream0 + m, sources=sources,
+                         first_order=first_order)
         assert ne >= 0
         res[m] = out
     return res

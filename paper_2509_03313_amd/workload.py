@@ -62,6 +62,17 @@ class Source:
     products: tuple          # species indices, at most three
 
 
+@dataclasses.dataclass(frozen=True)
+class FirstOrder:
+    """A first-order channel: a molecule of species a turns into its products
+    (at most two, the first in its place) at rate k per ns -- e.g. scavenging
+    by a solute held at a fixed concentration (pseudo-first order)."""
+    name: str
+    a: int
+    k: float                 # per ns
+    products: tuple
+
+
 # Table 1; H2O is not tracked, R9 is taken in the forward direction only.
 REACTIONS = [
     Reaction("R1", E_AQ, E_AQ, 1.3, (H2, OHM, OHM)),
@@ -81,6 +92,28 @@ REACTIONS = [
 KW_M2 = 1e-14
 PH7_BACKGROUND_M = 1e-7
 SOURCES_PH7 = [Source("R9 reverse", 10.0 * 11.0 * KW_M2, (H3O, OHM))]  # 1e10 /M/s * 10 = /M/ns
+
+
+# Chemistry extension: aerated water.  O2 at a fixed 2.5e-4 mol/L scavenges
+# e_aq and H (pseudo-first order); superoxide is one species (O2- and HO2,
+# pKa 4.8, lumped as O2- at pH 7: H + O2 -> HO2 -> O2- + H3O+).  Rate constants
+# (1e10 L/mol/s) from the compilation of Buxton, Greenstock, Helman and Ross,
+# J. Phys. Chem. Ref. Data 17 (1988) and Bielski et al., J. Phys. Chem. Ref.
+# Data 14 (1985); superoxide dismutation (~1e5-1e6 L/mol/s at pH 7) is left
+# out.  D(O2-) = 1.75 nm^2/ns.
+O2M = 7
+SPECIES_O2 = SPECIES + ["O2-"]
+D_CONFIG_O2 = D_CONFIG + [1.75]
+O2_AERATED_M = 2.5e-4
+REACTIONS_O2 = REACTIONS + [
+    Reaction("O2- + OH", O2M, OH, 1.0, (OHM,)),
+    Reaction("O2- + e_aq", O2M, E_AQ, 1.3, (H2O2, OHM, OHM)),
+    Reaction("O2- + H", O2M, H, 2.0, (H2O2, OHM)),
+]
+FIRST_ORDER_O2 = [
+    FirstOrder("e_aq + O2", E_AQ, 1.9e10 * O2_AERATED_M * 1e-9, (O2M,)),
+    FirstOrder("H + O2", H, 2.1e10 * O2_AERATED_M * 1e-9, (O2M, H3O)),
+]
 
 
 # synthetic spur composition, molecules per 100 (charge and redox balance to 0)

@@ -102,3 +102,25 @@ def test_autoionisation_relaxes_along_tanh():
     # unequal starts: the ion product settles at Kw
     c = N.integrate([5e-7, 1e-8], 1e8, r9, sources=src)
     assert abs(c[0] * c[1] - W.KW_M2) <= 1e-6 * W.KW_M2
+
+
+def test_first_order_channel_closed_form():
+    # a -> p0 + p1 at k: a = a0 exp(-k t), each product a0 (1 - exp(-k t))
+    fo = [W.FirstOrder("A", 0, 3e-3, (1, 2))]
+    a0 = 2e-6
+    for t in (10.0, 300.0, 3000.0):
+        c = N.integrate([a0, 0.0, 0.0], t, [], first_order=fo)
+        e = math.exp(-3e-3 * t)
+        assert abs(c[0] - a0 * e) <= 1e-9 * a0 and abs(c[1] - a0 * (1 - e)) <= 1e-9 * a0
+        assert abs(c[2] - c[1]) <= 1e-12 * a0
+    # the Jacobian of the aerated scheme equals finite differences
+    rng = np.random.default_rng(6)
+    c = 10.0 ** rng.uniform(-8, -5, size=8)
+    J = N.jacobian(c, W.REACTIONS_O2, W.FIRST_ORDER_O2)
+    for j in range(8):
+        h = 1e-6 * c[j]
+        dp = c.copy(); dp[j] += h
+        dm = c.copy(); dm[j] -= h
+        fd = (N.rhs(dp, W.REACTIONS_O2, first_order=W.FIRST_ORDER_O2)
+              - N.rhs(dm, W.REACTIONS_O2, first_order=W.FIRST_ORDER_O2)) / (2 * h)
+        assert np.allclose(J[:, j], fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())

@@ -509,3 +509,57 @@ def test_cand_f32_matches_numpy_float32(orc):
             if r is not None and d2[k] < rc2[r]:
                 ref.add((i, j))
     assert got == ref and len(ref) > 100
+
+
+# ----------------------------------------------------- first-order channels ---
+def test_first_order_decisions_follow_numpy_philox(orc):
+    """Extension: a first-order channel a -> p0 + p1 at k per ns.  Each molecule
+    converts iff (2 k24 + 1) 2^-25 < 1 - exp(-k dt), k24 the top 24 bits of
+    word 0 of the Philox block (uid, step, 3, 0) (recomputed here with numpy);
+    p0 keeps the uid in place, p1 appears at the end position with uid =
+    word 1 | 2^63."""
+    L, seed, inst, dt, step = 2000.0, 5, 1, 40.0, 3
+    fo = [W.FirstOrder("A", 0, 0.01, (1, 2))]
+    chem = orc.make_chem([1.0, 1.0, 1.0], [], first_order=fo)
+    rng = np.random.default_rng(2)
+    n = 400
+    x = rng.uniform(-900, 900, size=(n, 3))
+    uid = np.arange(10, 10 + n, dtype=np.uint64)
+    s = orc.Instance(L, seed, inst)
+    s.set_state(x, [0] * n, uid, step=step)
+    s.step(chem, dt)
+    xn, _, sp, u = s.state()
+    p = -math.expm1(-0.01 * dt)
+    want_conv = {}
+    for i in range(n):
+        w = _numpy_philox([int(uid[i]), step, 3, 0], [seed, inst])
+        conv = (2 * (int(w[0]) >> 40) + 1) / 2 ** 25 < p
+        want_conv[int(uid[i])] = (conv, int(w[1]) | (1 << 63))
+    by_uid = {int(uu): (int(ss), xn[k]) for k, (uu, ss) in enumerate(zip(u, sp))}
+    n_conv = 0
+    for uu, (conv, u2) in want_conv.items():
+        assert by_uid[uu][0] == (1 if conv else 0)
+        if conv:
+            n_conv += 1
+            assert by_uid[u2][0] == 2 and np.array_equal(by_uid[u2][1], by_uid[uu][1])
+    assert len(u) == n + n_conv and 0.3 * n * p < n_conv < 2.0 * n * p
+
+
+def test_first_order_survival_is_exponential(orc):
+    """Over many steps of the log-spaced schedule the survivors of a
+    first-order channel are binomial with p = exp(-k t): the per-step
+    probabilities 1 - exp(-k dt) compose exactly."""
+    L, k = 3000.0, 2e-3
+    fo = [W.FirstOrder("A", 0, k, ())]
+    chem = orc.make_chem([1.0], [], first_order=fo)
+    n = 4000
+    rng = np.random.default_rng(3)
+    s = orc.Instance(L, 9, 0)
+    s.set_state(rng.uniform(-1400, 1400, size=(n, 3)), [0] * n, np.arange(n, dtype=np.uint64) + 1)
+    t = 0.0
+    for dt in np.geomspace(1e-2, 50.0, 60):
+        s.step(chem, float(dt))
+        t += float(dt)
+    surv = s.n
+    pk = math.exp(-k * t)
+    assert abs(surv - n * pk) <= 4.5 * math.sqrt(n * pk * (1 - pk)), (surv, n * pk)

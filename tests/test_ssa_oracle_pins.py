@@ -167,3 +167,15 @@ def test_autoionisation_holds_the_background():
     assert np.all(ens[:, :, 0] == ens[:, :, 1])
     m = ens[:, :, 0].mean()
     assert abs(m - n_eq) <= 0.02 * n_eq, (m, n_eq)
+
+
+def test_first_order_channel_is_binomial():
+    fo = [W.FirstOrder("A", 0, 2e-3, (1,))]
+    t = np.array([100.0, 700.0])
+    ens = S.ensemble([], 2, [30, 0], 1e-18, t, seed=17, n_real=3000, first_order=fo)
+    assert np.all(ens[:, :, 0] + ens[:, :, 1] == 30)
+    for k, tk in enumerate(t):
+        p = math.exp(-2e-3 * tk)
+        states = list(range(31))
+        pk = [math.comb(30, s) * p ** s * (1 - p) ** (30 - s) for s in states]
+        _check_hist(ens[:, k, 0], states, pk, len(ens))
