@@ -122,6 +122,29 @@ int gsbs_set_species(gsbs_ctx* ctx, int32_t n, const double* D);
  * 2R >= L for some cube (PBC 2). */
 int gsbs_set_reactions(gsbs_ctx* ctx, int32_t n, const gsbs_reaction* r);
 
+/* A first-order channel: a molecule of species a turns into its products at
+ * k_per_ns per ns (scavenging by a solute held at a fixed concentration,
+ * e.g. e_aq + O2 at k [O2]).  An extension of Table 1. */
+typedef struct {
+    int32_t a;
+    int32_t n_products; /* 0..2: 0 removes the molecule */
+    int32_t products[2];
+    double k_per_ns;
+} gsbs_first_order;
+
+/* Replace the first-order channels (at most one per species; 0 clears them).
+ * SBS: after each step's pair reactions, every molecule that took part in the
+ * step and is not one of its products converts with probability
+ * 1 - exp(-k dt), decided by the top 24 bits k24 of Philox word 0 at counter
+ * (uid, step, 3, 0): converts iff (2 k24 + 1) 2^-25 < p; product 1 keeps the
+ * molecule's place and uid, product 2 appears at the same point with uid
+ * = word 1 | 2^63.  Rate equations: k [a]; Gillespie runs: propensity k n_a,
+ * after the reactions and before the sources, in species order.  Fails with
+ * GSBS_EINVAL for a species outside the table, two channels of one species,
+ * a rate <= 0 or not finite, or more than two products; GSBS_ESTATE before
+ * gsbs_set_species. */
+int gsbs_set_first_order(gsbs_ctx* ctx, int32_t n, const gsbs_first_order* ch);
+
 /* A zero-order reaction: its products appear at rate_M_per_ns mol/L/ns
  * anywhere in the volume.  Extension of Table 1, which prints R9 as an
  * equilibrium: R9's reverse, the water autoionisation H2O -> H3O+ + OH- at
@@ -314,7 +337,8 @@ int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y
  * at the event rate k [a][b] (k [a]^2 / 2 when a == b: the table prints 2k for
  * self-recombinations, so that d[a]/dt = -k [a]^2, the paper's equation for the
  * OH recombination), k = 10 * k_in L/mol/ns; each event removes its reactants
- * (not b when keep_b) and adds its products; each zero-order source of
+ * (not b when keep_b) and adds its products; each first-order channel of
+ * gsbs_set_first_order runs at k [a], and each zero-order source of
  * gsbs_set_sources adds its rate to its products.  c0 and c1 are [n][n_species]
  * concentrations in mol/L (row-major; n_species must equal the table's
  * species count, else GSBS_EINVAL), dt_ns[n] the time of each solution;
@@ -343,8 +367,9 @@ int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, 
  * (k_r = 10 * k_in L/mol/ns, the printed constant: 2k for a
  * self-recombination), h_r = n_a n_b or n_a (n_a - 1) / 2 when a == b; each
  * event removes the reactants (not b when keep_b) and adds the products.  The
- * zero-order sources of gsbs_set_sources follow the reactions in the
- * propensity list with a_q = rate_q N_A V and add their products.
+ * first-order channels of gsbs_set_first_order (a = k n_a, species order) and
+ * then the zero-order sources of gsbs_set_sources (a_q = rate_q N_A V) follow
+ * the reactions in the propensity list.
  * Random numbers: Philox4x64-10, key (seed, 0x4753534153534131), counter
  * (stream0 + m, j / 2, 0, 0) for events j (even; words 0, 1) and j + 1
  * (words 2, 3); waiting time -ln(u1) / a_0, reaction = first r whose running

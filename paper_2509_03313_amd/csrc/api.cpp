@@ -153,6 +153,7 @@ struct gsbs_ctx {
     std::vector<double> D;
     std::vector<gsbs_reaction> rx;
     std::vector<gsbs_source> src;  // zero-order sources (homogeneous solvers)
+    std::vector<gsbs_first_order> fo;  // first-order channels, one per species at most
     std::vector<double> R;
     bool chem_ready = false;
     ChemDev chem_h{};
@@ -361,6 +362,11 @@ int build_chem(gsbs_ctx* c) {
         c->R[r] = Dab > 0 ? smol_radius(q.k_in, Dab) : 0.0;
     }
     h.reactive_mask = mask;
+    for (const gsbs_first_order& f : c->fo) {
+        h.fo_mask |= 1u << f.a;
+        h.fo_nprod[f.a] = f.n_products;
+        for (int k = 0; k < 2; ++k) h.fo_prod[f.a][k] = k < f.n_products ? f.products[k] : -1;
+    }
     h.n_species = c->ns;
     h.rounds = c->prm.rounds;
     h.contact_only = c->prm.contact_only;
@@ -398,6 +404,7 @@ double fill_physics(const gsbs_ctx* c, double L, uint64_t step, int idx, double 
     double rcmax = 0.0;
     if (!active) return 0.0;
     for (int s = 0; s < c->ns; ++s) S.sigma[s] = (float)std::sqrt(2.0 * c->D[s] * dt);
+    for (const gsbs_first_order& f : c->fo) S.fo_p[f.a] = -std::expm1(-f.k_per_ns * dt);
     for (size_t r = 0; r < c->rx.size(); ++r) {
         const gsbs_reaction& q = c->rx[r];
         const double Dab = c->D[q.a] + c->D[q.b];
@@ -639,6 +646,7 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
              int32_t grid, int32_t flags, hipEvent_t* span = nullptr, const InstStep* row0 = nullptr, int cfg0 = -1,
              int64_t nest0 = 0) {
     if (span) HIPCHK(hipEventRecord(span[0], c->st));
+    if (!c->fo.empty()) flags |= kStepFirstOrder;
     launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags,
                 c->profiling ? c->prof_ev : nullptr);
     HIPCHK(hipGetLastError());
@@ -916,6 +924,26 @@ int gsbs_set_sources(gsbs_ctx* c, int32_t n, const gsbs_source* src) {
             if (src[q].products[k] < 0 || src[q].products[k] >= c->ns) return fail(GSBS_EINVAL, "product species");
     }
     c->src.assign(src, src + n);
+    return GSBS_OK;
+}
+
+int gsbs_set_first_order(gsbs_ctx* c, int32_t n, const gsbs_first_order* f) {
+    if (!c || n < 0 || n > kMaxSpecies || (n > 0 && !f)) return fail(GSBS_EINVAL, "first-order channels: 0..16");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    uint32_t seen = 0;
+    for (int q = 0; q < n; ++q) {
+        if (f[q].a < 0 || f[q].a >= c->ns) return fail(GSBS_EINVAL, "first-order species");
+        if ((seen >> f[q].a) & 1u) return fail(GSBS_EINVAL, "one first-order channel per species");
+        seen |= 1u << f[q].a;
+        if (!(f[q].k_per_ns > 0.0) || !std::isfinite(f[q].k_per_ns))
+            return fail(GSBS_EINVAL, "first-order rate must be finite and > 0");
+        if (f[q].n_products < 0 || f[q].n_products > 2) return fail(GSBS_EINVAL, "0..2 first-order products");
+        for (int k = 0; k < f[q].n_products; ++k)
+            if (f[q].products[k] < 0 || f[q].products[k] >= c->ns) return fail(GSBS_EINVAL, "product species");
+    }
+    c->fo.assign(f, f + n);
+    std::sort(c->fo.begin(), c->fo.end(), [](const gsbs_first_order& x, const gsbs_first_order& y) { return x.a < y.a; });
+    if (c->chem_ready) CHK(build_chem(c));
     return GSBS_OK;
 }
 
@@ -1360,6 +1388,8 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
     if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
     if (n_species != c->ns) return fail(GSBS_EINVAL, "rate equations: n_species is not the table's");
     if (c->ns > kOdeMaxSpecies) return fail(GSBS_EINVAL, "the rate equations take at most 8 species");
+    if (c->rx.size() + c->fo.size() > (size_t)kMaxReactions)
+        return fail(GSBS_EINVAL, "the rate equations take at most 32 reactions and channels");
     if (n == 0) return GSBS_OK;
     OdeTable tb{};
     tb.ns = c->ns;
@@ -1373,6 +1403,14 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
         tb.nu[r][q.a] -= 1.0;
         if (!q.keep_b) tb.nu[r][q.b] -= 1.0;
         for (int k = 0; k < q.n_products; ++k) tb.nu[r][q.products[k]] += 1.0;
+    }
+    for (const gsbs_first_order& f : c->fo) {
+        const int r = tb.nr++;
+        tb.ra[r] = f.a;
+        tb.rb[r] = -1;
+        tb.kr[r] = f.k_per_ns;
+        tb.nu[r][f.a] -= 1.0;
+        for (int k = 0; k < f.n_products; ++k) tb.nu[r][f.products[k]] += 1.0;
     }
     for (const gsbs_source& q : c->src)
         for (int k = 0; k < q.n_products; ++k) tb.src[q.products[k]] += q.rate_M_per_ns;
@@ -1450,6 +1488,19 @@ int gsbs_ssa(gsbs_ctx* c, int32_t n, int32_t n_species, const int32_t* n0, const
         for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
         tb.dn[r] = d;
     }
+    tb.nfo = (int32_t)c->fo.size();
+    for (int q = 0; q < tb.nfo; ++q) {
+        // the oracle's order: channels by species
+        int nu[kOdeMaxSpecies] = {};
+        const gsbs_first_order& f = c->fo[(size_t)q];
+        nu[f.a] -= 1;
+        for (int k = 0; k < f.n_products; ++k) nu[f.products[k]] += 1;
+        uint64_t d = 0;
+        for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
+        tb.fo_a[q] = f.a;
+        tb.fo_k[q] = f.k_per_ns;
+        tb.dn[kSsaMaxReactions + q] = d;
+    }
     tb.nsrc = (int32_t)c->src.size();
     for (int q = 0; q < tb.nsrc; ++q) {
         int nu[kOdeMaxSpecies] = {};
@@ -1457,7 +1508,7 @@ int gsbs_ssa(gsbs_ctx* c, int32_t n, int32_t n_species, const int32_t* n0, const
         uint64_t d = 0;
         for (int s = 0; s < kOdeMaxSpecies; ++s) d |= (uint64_t)(uint8_t)(int8_t)nu[s] << (8 * s);
         tb.src_rate[q] = c->src[q].rate_M_per_ns;
-        tb.dn[kSsaMaxReactions + q] = d;
+        tb.dn[kSsaMaxReactions + kOdeMaxSpecies + q] = d;
     }
     const size_t nc = (size_t)n * (size_t)c->ns, no = (size_t)n * (size_t)n_rec * (size_t)c->ns;
     int32_t *d0 = nullptr, *dout = nullptr;

@@ -16,7 +16,8 @@ constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 // Chemistry tables (constant during a run).
 // Reaction table of the rate equations (passed by value to the integrator):
 // reaction r runs at the event rate kr[r] [a][b] (kr = k for a != b, k / 2 for
-// a == b; k in L/mol/ns) and changes species s by nu[r][s] per event.  The
+// a == b; k in L/mol/ns), or kr[r] [a] for a first-order channel (rb = -1, kr
+// per ns), and changes species s by nu[r][s] per event.  The
 // integrator keeps a mixture's state in registers: at most kOdeMaxSpecies.
 constexpr int kOdeMaxSpecies = 8;
 struct OdeTable {
@@ -33,11 +34,15 @@ struct OdeTable {
 // the signed byte s of dn[r] per event.
 constexpr int kSsaMaxReactions = 16;
 constexpr int kMaxSources = 4;
+// propensity slots: reactions, first-order channels, sources
+constexpr int kSsaSlots = kSsaMaxReactions + kOdeMaxSpecies + kMaxSources;
 struct SsaTable {
-    int32_t ns, nr, nsrc;
+    int32_t ns, nr, nfo, nsrc;
     int32_t ra[kSsaMaxReactions], rb[kSsaMaxReactions];
-    uint64_t dn[kSsaMaxReactions + kMaxSources];  // reactions, then sources
+    uint64_t dn[kSsaSlots];
     double k10[kSsaMaxReactions];
+    int32_t fo_a[kOdeMaxSpecies];                  // first-order channels: species, rate per ns
+    double fo_k[kOdeMaxSpecies];
     double src_rate[kMaxSources];                  // zero-order sources, mol/L/ns
 };
 
@@ -53,6 +58,11 @@ struct ChemDev {
     int32_t n_species;
     int32_t rounds;
     int32_t contact_only;
+    // first-order channels: species s -> fo_prod[s][0] (+ fo_prod[s][1]);
+    // removed when fo_nprod[s] == 0; bit s of fo_mask: s has a channel
+    uint32_t fo_mask;
+    int32_t fo_nprod[kMaxSpecies];
+    int32_t fo_prod[kMaxSpecies][2];
 };
 
 // Everything one instance needs for one step; rebuilt by the host per step.
@@ -89,6 +99,7 @@ struct alignas(16) InstStep {
     int32_t unit_off_sp[kMaxSpecies + 4];
     uint64_t step;                 // Philox step counter word
     uint64_t key0, key1;           // Philox key (seed, instance)
+    double fo_p[kMaxSpecies];      // first-order conversion probability 1 - exp(-k dt) per species
 };
 
 // Accepted (or, in debug logging, candidate) pair of sorted indices.
@@ -201,5 +212,6 @@ constexpr int32_t kStepBySpecies = 8;   // debug: force the species-bin search
 constexpr int32_t kStepWholeCells = 16;  // debug: force the whole-cell search
 constexpr int32_t kStepHasWhole = 32;    // some instance uses the whole-cell search this step
 constexpr int32_t kStepHasSpecies = 64;  // some instance uses the species-bin search this step
+constexpr int32_t kStepFirstOrder = 128; // the chemistry has first-order channels
 
 }  // namespace gsbs

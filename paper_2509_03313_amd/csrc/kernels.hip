@@ -1659,6 +1659,62 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
     }
 }
 
+// First-order channels (an extension: scavenging by a solute held at a fixed
+// concentration).  After the step's pair reactions every live molecule of
+// the sorted array (not this step's products, which sit at n_live and beyond)
+// whose species has a channel converts with probability p = 1 - exp(-k dt)
+// (FP64, from the host): the top 24 bits k24 of word 0 of the Philox block
+// (uid, step, 3, 0) decide, converting iff (2 k24 + 1) 2^-25 < p (exact in
+// FP64).  Product 1 takes the molecule's place and uid; product 2 is appended
+// at the same point with uid = word 1 | 2^63; no product removes it.
+__global__ __launch_bounds__(GSBS_BLOCK) void k_first_order(float4* __restrict__ pos, uint64_t* __restrict__ uid,
+                                                          DevCounters* __restrict__ ctr,
+                                                          const InstStep* __restrict__ P,
+                                                          const ChemDev* __restrict__ chem,
+                                                          long long* __restrict__ counts, int32_t cap) {
+    const int n = ctr->n_live;
+    const uint32_t mask = chem->fo_mask;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float4 p = pos[i];
+        const int meta = __float_as_int(p.w);
+        const int sp = meta & 0xFF;
+        if (sp == kDead || !((mask >> sp) & 1u)) continue;
+        const int inst = meta >> 8;
+        const InstStep& S = P[inst];
+        if (!S.active) continue;
+        uint64_t w[4];
+        const uint64_t u = uid[i];
+        philox(u, S.step, 3ull, 0ull, S.key0, S.key1, w);
+        if (!((double)(2u * (uint32_t)(w[0] >> 40) + 1u) * 0x1p-25 < S.fo_p[sp])) continue;
+        long long* cnt = counts + inst * kMaxSpecies;
+        atomicAdd((unsigned long long*)&cnt[sp], (unsigned long long)(-1ll));
+        const int np = chem->fo_nprod[sp];
+        if (np == 0) {
+            pos[i].w = __int_as_float((inst << 8) | kDead);
+            continue;
+        }
+        const int p0 = chem->fo_prod[sp][0];
+        pos[i].w = __int_as_float((inst << 8) | p0);
+        atomicAdd((unsigned long long*)&cnt[p0], 1ull);
+        if (np < 2) continue;
+        // append product 2: a slot below cap, else flag the overflow
+        int dst = __hip_atomic_load(&ctr->n_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (dst < cap) {
+            const int prev = atomicCAS(&ctr->n_in, dst, dst + 1);
+            if (prev == dst) break;
+            dst = prev;
+        }
+        if (dst >= cap) {
+            atomicOr(&ctr->err, kErrMolOverflow);
+            continue;
+        }
+        const int p1 = chem->fo_prod[sp][1];
+        pos[dst] = make_float4(p.x, p.y, p.z, __int_as_float((inst << 8) | p1));
+        uid[dst] = w[1] | 0x8000000000000000ull;
+        atomicAdd((unsigned long long*)&cnt[p1], 1ull);
+    }
+}
+
 // -------------------------------------------------------------- records ---
 __global__ void k_record(const long long* __restrict__ counts, long long* __restrict__ rec, int32_t max_rec,
                          RecordList list) {
@@ -1734,6 +1790,9 @@ void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const 
     hipLaunchKernelGGL(k_react, dim3(1), dim3(kReactBlock), 0, st, b.pos_out, b.uid_out, b.ctr, P, chem,
                        b.pairs, b.pair_cap, b.claim, b.mate, b.counts, b.msteps, n_inst, b.cap,
                        (flags & kStepSearchOnly) ? 1 : 0);
+    if ((flags & kStepFirstOrder) && !(flags & kStepSearchOnly))
+        hipLaunchKernelGGL(k_first_order, dim3(grid), dim3(GSBS_BLOCK), 0, st, b.pos_out, b.uid_out, b.ctr, P, chem,
+                           b.counts, b.cap);
     mark(5, 1);
 }
 

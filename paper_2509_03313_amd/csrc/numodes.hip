@@ -29,7 +29,7 @@ namespace {
 template <int S>
 __device__ __forceinline__ void gather2(const double* y, int a, int b, double& ya, double& yb) {
     ya = 0.0;
-    yb = 0.0;
+    yb = b < 0 ? 1.0 : 0.0;  // b < 0: first-order channel, rate kr [a]
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         ya = s == a ? y[s] : ya;
@@ -52,7 +52,8 @@ __device__ __forceinline__ void ode_rhs(const double* y, const OdeTable& tb, dou
 }
 
 // J[i][j] = d f_i / d y_j = sum_r nu[r][i] d rate_r / d y_j; the rate of r
-// depends on y_a and y_b only: kr y_b and kr y_a, or 2 kr y_a when a == b.
+// depends on y_a and y_b only: kr y_b and kr y_a, or 2 kr y_a when a == b, or
+// kr for a first-order channel (b < 0).
 template <int S>
 __device__ __forceinline__ void ode_jac(const double* y, const OdeTable& tb, double (*J)[S]) {
 #pragma unroll

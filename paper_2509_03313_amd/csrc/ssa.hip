@@ -15,8 +15,9 @@
 // of propensities exceeds u2 a_0 (the last one with a_r > 0 if rounding leaves
 // none).  The reaction choice is exact integer-derived FP64 arithmetic in a
 // fixed order, so the event sequence of a stream is reproducible bit for bit.
-// Zero-order sources (rate q in mol/L/ns) follow the reactions in the
-// propensity list with a_q = rate_q N_A V.
+// First-order channels (a = k n_s, in species order) and then zero-order
+// sources (a_q = rate_q N_A V, rate in mol/L/ns) follow the reactions in the
+// propensity list.
 #include "device_common.h"
 #include "engine.h"
 
@@ -31,7 +32,8 @@ __device__ __forceinline__ double u53(uint64_t w) {
     return ((double)(w >> 11) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-template <int S>
+// kExtra: the table has first-order channels or sources (more propensity slots)
+template <int S, bool kExtra>
 __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, const double* __restrict__ vol,
                                             const double* __restrict__ t_rec, int32_t n_rec,
                                             int32_t* __restrict__ out, long long* __restrict__ events, int32_t n,
@@ -46,7 +48,8 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
 #pragma unroll
     for (int s = 0; s < S; ++s) cnt_lds[s][lane] = s < ns ? n0[(size_t)m * ns + s] : 0;
     const double nav = kNA * vol[m];
-    constexpr int kA = kSsaMaxReactions + kMaxSources;  // reactions, then sources
+    constexpr int kA = kExtra ? kSsaSlots : kSsaMaxReactions;  // reactions, first-order channels, sources
+    constexpr int kF = kSsaMaxReactions, kQ = kSsaMaxReactions + kOdeMaxSpecies;
     double c[kSsaMaxReactions];
 #pragma unroll
     for (int r = 0; r < kSsaMaxReactions; ++r) c[r] = r < nr ? tb.k10[r] / nav : 0.0;
@@ -72,10 +75,17 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
                 a[r] = 0.0;
             }
         }
+        if (kExtra) {
 #pragma unroll
-        for (int q = 0; q < kMaxSources; ++q) {
-            a[kSsaMaxReactions + q] = q < tb.nsrc ? tb.src_rate[q] * nav : 0.0;
-            if (q < tb.nsrc) a0 += a[kSsaMaxReactions + q];
+            for (int q = 0; q < kOdeMaxSpecies; ++q) {
+                a[kF + q] = q < tb.nfo ? tb.fo_k[q] * (double)cnt_lds[q < tb.nfo ? tb.fo_a[q] : 0][lane] : 0.0;
+                if (q < tb.nfo) a0 += a[kF + q];
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxSources; ++q) {
+                a[kQ + q] = q < tb.nsrc ? tb.src_rate[q] * nav : 0.0;
+                if (q < tb.nsrc) a0 += a[kQ + q];
+            }
         }
         double t_next = __builtin_huge_val(), u2 = 0.0;
         if (a0 > 0.0) {
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         int mu = -1, last = -1;
 #pragma unroll
         for (int r = 0; r < kA; ++r) {
-            if (r < nr || (r >= kSsaMaxReactions && r - kSsaMaxReactions < tb.nsrc)) {
+            if (r < nr || (r >= kF && r < kQ && r - kF < tb.nfo) || (r >= kQ && r - kQ < tb.nsrc)) {
                 cum += a[r];
                 last = (mu < 0 && a[r] > 0.0) ? r : last;
                 mu = (mu < 0 && target < cum) ? r : mu;
@@ -113,7 +123,8 @@ __global__ __launch_bounds__(64) void k_ssa(const int32_t* __restrict__ n0, cons
         uint64_t d = 0;
 #pragma unroll
         for (int r = 0; r < kA; ++r)
-            if (r < nr || (r >= kSsaMaxReactions && r - kSsaMaxReactions < tb.nsrc)) d = r == mu ? tb.dn[r] : d;
+            if (r < nr || (r >= kF && r < kQ && r - kF < tb.nfo) || (r >= kQ && r - kQ < tb.nsrc))
+                d = r == mu ? tb.dn[r] : d;
 #pragma unroll
         for (int s = 0; s < S; ++s) cnt_lds[s][lane] += (int32_t)(int8_t)(uint8_t)(d >> (8 * s));
         t = t_next;
@@ -129,15 +140,18 @@ void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const doub
                 long long max_events) {
     if (n <= 0 || n_rec <= 0 || tb.ns > kOdeMaxSpecies || tb.nr > kSsaMaxReactions) return;
     const dim3 grid((n + 63) / 64), block(64);
-    if (tb.ns <= 4)
-        hipLaunchKernelGGL(k_ssa<4>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb, seed, stream0,
-                           max_events);
-    else if (tb.ns <= 7)
-        hipLaunchKernelGGL(k_ssa<7>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb, seed, stream0,
-                           max_events);
-    else
-        hipLaunchKernelGGL(k_ssa<kOdeMaxSpecies>, grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb,
-                           seed, stream0, max_events);
+    const bool extra = tb.nfo + tb.nsrc > 0;
+#define GSBS_SSA_LAUNCH(SL, EX)                                                                                   \
+    hipLaunchKernelGGL((k_ssa<SL, EX>), grid, block, 0, st, n0, vol, t_rec, n_rec, out, events, n, tb, seed, stream0, \
+                       max_events)
+    if (tb.ns <= 4) {
+        if (extra) GSBS_SSA_LAUNCH(4, true); else GSBS_SSA_LAUNCH(4, false);
+    } else if (tb.ns <= 7) {
+        if (extra) GSBS_SSA_LAUNCH(7, true); else GSBS_SSA_LAUNCH(7, false);
+    } else {
+        if (extra) GSBS_SSA_LAUNCH(kOdeMaxSpecies, true); else GSBS_SSA_LAUNCH(kOdeMaxSpecies, false);
+    }
+#undef GSBS_SSA_LAUNCH
 }
 
 }  // namespace gsbs

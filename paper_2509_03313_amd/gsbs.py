@@ -48,6 +48,10 @@ class gsbs_reaction(C.Structure):
                 ("products", C.c_int32 * 3), ("keep_b", C.c_int32)]
 
 
+class gsbs_first_order(C.Structure):
+    _fields_ = [("a", C.c_int32), ("n_products", C.c_int32), ("products", C.c_int32 * 2), ("k_per_ns", C.c_double)]
+
+
 class gsbs_source(C.Structure):
     _fields_ = [("rate_M_per_ns", C.c_double), ("n_products", C.c_int32), ("products", C.c_int32 * 3)]
 
@@ -101,6 +105,7 @@ _SIGS = {
     "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
     "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
     "gsbs_set_sources": [_vp, _i32, _vp],
+    "gsbs_set_first_order": [_vp, _i32, _vp],
     "gsbs_ssa": [_vp, _i32, _i32, _vp, _vp, _i32, _P(_d), _u64, _u64, _i64, _vp, _P(_i64), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
@@ -526,6 +531,19 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_set_first_order(ctx, channels):
+    """First-order channels: objects with a, k (per ns) and products (at most
+    two; see workload.FirstOrder)."""
+    arr = (gsbs_first_order * max(len(channels), 1))()
+    for q, f in enumerate(channels):
+        arr[q].a = int(f.a)
+        arr[q].k_per_ns = float(f.k)
+        arr[q].n_products = len(f.products)
+        for j, p in enumerate(f.products):
+            arr[q].products[j] = int(p)
+    _chk(_lib.gsbs_set_first_order(ctx, len(channels), C.cast(arr, _vp)))
 
 
 def gsbs_set_sources(ctx, sources):

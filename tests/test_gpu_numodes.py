@@ -172,3 +172,26 @@ def test_zero_order_sources(g):
         ref = N.integrate(c0[m], t[m], W.REACTIONS, sources=W.SOURCES_PH7)
         big = ref > 1e-13
         assert np.all(np.abs(c1[m] - ref)[big] <= 5e-5 * ref[big]), (m, c1[m], ref)
+
+
+def test_first_order_channels(g):
+    """Aerated water on the device against the oracle (first-order scavenging
+    by O2 and the superoxide reactions), plus the closed form of one channel."""
+    fo = [W.FirstOrder("A", 0, 3e-3, (1, 2))]
+    e = g.Engine(1000.0, 1, [1.0] * 3, [W.Reaction("X", 1, 2, 0.1, ())])
+    g.gsbs_set_first_order(e.ctx, fo)
+    c1, _ = g.gsbs_numodes(e.ctx, np.array([[2e-6, 0.0, 0.0]]), [300.0], rtol=1e-8)
+    e.close()
+    ref = N.integrate([2e-6, 0.0, 0.0], 300.0, [W.Reaction("X", 1, 2, 0.1, ())], first_order=fo)
+    assert np.allclose(c1[0], ref, rtol=2e-6, atol=1e-15)
+    e = g.Engine(1000.0, 1, W.D_CONFIG_O2, W.REACTIONS_O2)
+    g.gsbs_set_first_order(e.ctx, W.FIRST_ORDER_O2)
+    rng = np.random.default_rng(12)
+    c0 = 10.0 ** rng.uniform(-8, -6, size=(8, 8))
+    t = np.array([1e2, 1e4, 1e6, 1e8] * 2)
+    c1, _ = g.gsbs_numodes(e.ctx, c0, t, rtol=1e-7)
+    e.close()
+    for m in range(8):
+        ref = N.integrate(c0[m], t[m], W.REACTIONS_O2, first_order=W.FIRST_ORDER_O2)
+        big = ref > 1e-13
+        assert np.all(np.abs(c1[m] - ref)[big] <= 5e-5 * ref[big]), (m, c1[m], ref)

@@ -466,3 +466,56 @@ def test_full_size_first_steps(g, orc):
     assert Q == c0[W.H3O] - c0[W.E_AQ] - c0[W.OHM]
     assert Wr == c0[W.OH] + 2 * c0[W.H2O2] - c0[W.E_AQ] - c0[W.H] - 2 * c0[W.H2]
     e.close()
+
+
+def test_first_order_channels_match_oracle(g, orc):
+    """Aerated water (first-order scavenging of e_aq and H by O2, lumped
+    superoxide and its reactions): the GPU and the oracle take the same
+    first-order conversions (uid-keyed Philox decisions against the same FP64
+    probability) and the same pair reactions, step for step, until an FP32 /
+    FP64 accept flip of a pair."""
+    wl = W.single_pulse_small(4)
+    L = wl.L
+    inj = wl.injections[0]
+    n = len(inj.species)
+    uid = np.arange(n, dtype=np.uint64)
+    # scavenging 400x faster than in aerated water, so that many conversions
+    # fall within the compared steps (the first ~20 ps)
+    fo = [W.FirstOrder(f.name, f.a, 400.0 * f.k, f.products) for f in W.FIRST_ORDER_O2]
+    chem = orc.make_chem(W.D_CONFIG_O2, W.REACTIONS_O2, first_order=fo)
+    e = make_engine(g, L, 1000, D=W.D_CONFIG_O2, reactions=W.REACTIONS_O2)
+    g.gsbs_set_first_order(e.ctx, fo)
+    g.gsbs_debug_set_state(e.ctx, inj.xyz, inj.species, uid, step=0, next_uid=n)
+    o = orc.Instance(L, 1000, 0)
+    o.set_state(inj.xyz.astype(np.float64), inj.species.astype(np.int32), uid, step=0, next_uid=n)
+    o.set_log(2)
+    sched = orc.schedule(0.0, 200.0, [0.0], [], wl.dt0, wl.ratio, orc.dt_max(chem, L))
+    t = 0.0
+    for k, te in enumerate(sched[:1500]):
+        dt = te - t
+        t = te
+        g.gsbs_debug_step(e.ctx, dt, g.DEBUG_LOG_ALL)
+        o.step(chem, dt)
+        pg = g.gsbs_debug_get_pairs(e.ctx)
+        lo = o.log()
+        accg = {tuple(p) for p, f in zip(pg["uid"].tolist(), pg["flag"]) if f & 1}
+        acco = {tuple(p) for p, f in zip(lo["uid"].tolist(), lo["flag"]) if f & 1}
+        if accg != acco:
+            say("accept flip at step", k)
+            break
+        xg, sg, ug = g.gsbs_debug_get_state(e.ctx, 0)
+        xo, _, so, uo = o.state()
+        a, b = np.argsort(ug), np.argsort(uo)
+        assert np.array_equal(ug[a], uo[b]), k
+        assert np.array_equal(sg[a].astype(np.int32), so[b]), k
+        err = np.abs(minimg(xg[a].astype(np.float64) - xo[b], L))
+        assert err.max() <= 1e-5 * L, (k, err.max())
+    n_sup = int(np.sum(so == W.O2M))
+    n_two = int(np.sum(uo >= np.uint64(2 ** 63)))
+    say("steps compared", k + 1, "superoxide", n_sup, "second products", n_two)
+    assert k > 300 and n_sup > 20 and n_two > 3
+    # the device counts follow the conversions
+    _, sg, _ = g.gsbs_debug_get_state(e.ctx, 0)
+    cg = e.current_counts(0)
+    assert np.array_equal(cg, np.bincount(sg.astype(np.int64), minlength=len(cg))[:len(cg)])
+    e.close()

@@ -200,3 +200,29 @@ def test_sources_event_for_event(g):
     # the source took part: its events are in the compared sequences
     say("source events", fired)
     assert fired > 0
+
+
+def test_first_order_event_for_event(g):
+    """Aerated water with the pH 7 source: first-order channels, sources and
+    reactions, event for event against the oracle."""
+    n = 40
+    V = 1e-17
+    n0 = S.counts_from_conc([2e-6, 2e-6, 3e-7, 2e-6 + 1e-7, 1e-7, 1e-7, 1e-7, 0.0], V)
+    n0 = np.tile(n0.astype(np.int32), (n, 1))
+    t_rec = np.concatenate([[0.0], np.geomspace(1.0, 1e7, 20)])
+    e = g.Engine(1000.0, 1, W.D_CONFIG_O2, W.REACTIONS_O2)
+    g.gsbs_set_first_order(e.ctx, W.FIRST_ORDER_O2)
+    g.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
+    out, ev = g.gsbs_ssa(e.ctx, n0, np.full(n, V), t_rec, seed=37)
+    e.close()
+    fo_events = 0
+    for m in range(n):
+        ref, ne, (ev_t, ev_r) = S.ssa(W.REACTIONS_O2, 8, n0[m], V, t_rec, 37, m, log_events=1 << 22,
+                                      sources=W.SOURCES_PH7, first_order=W.FIRST_ORDER_O2)
+        assert ne >= 0
+        fo_events += int(np.sum((ev_r >= len(W.REACTIONS_O2)) & (ev_r < len(W.REACTIONS_O2) + 2)))
+        for k, tk in enumerate(t_rec):
+            if not np.array_equal(out[m, k], ref[k]):
+                assert np.any(np.abs(ev_t - tk) <= 1e-9 * tk), (m, k, out[m, k], ref[k])
+    say("first-order events", fo_events)
+    assert fo_events > 0
