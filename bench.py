@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--dose-rate-seeds", type=int, default=3, help="pulse trains per grid point")
     ap.add_argument("--ph7", action="store_true", help="dose-rate study in pH 7 water (background ions and "
                                                         "R9's reverse in the rate equations)")
+    ap.add_argument("--o2", action="store_true", help="dose-rate study in aerated water (O2 scavenging of e_aq "
+                                                      "and H, superoxide reactions)")
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
@@ -534,7 +536,7 @@ def dose_rate_bench(args):
 
     trains = DR.paper_trains(seeds=tuple(range(1, args.dose_rate_seeds + 1)))
     note(f"{len(trains)} pulse trains, {sum(t.n_pulses for t in trains)} pulses")
-    r = DR.run(trains, seed=args.seed, ph7=args.ph7)
+    r = DR.run(trains, seed=args.seed, ph7=args.ph7, o2=args.o2)
     note(f"wall {r['wall']:.1f} s, {r['steps']} steps, {r['molecule_steps']} molecule-steps, "
          f"{r['ode_steps']} rate-equation steps")
     grid = []
@@ -542,19 +544,20 @@ def dose_rate_bench(args):
         for rate in sorted({t.avg_rate for t in trains}):
             idx = [k for k, t in enumerate(trains) if t.pulse_rate == dp and t.avg_rate == rate]
             g = np.array([r["g_h2o2"][k] for k in idx])
+            gp = np.array([r["g_h2o2_post"][k] for k in idx])
             b = np.array([DR.build_up(trains[k], r["counts"][k]) for k in idx])
             grid.append(dict(pulse_rate_gy_s=dp, avg_rate_gy_s=rate, g_h2o2=round(float(g.mean()), 4),
                              g_h2o2_sem=round(float(g.std(ddof=1) / np.sqrt(len(g))) if len(g) > 1 else 0.0, 4),
-                             radical_build_up=round(float(b.mean()), 4)))
+                             g_h2o2_post=round(float(gp.mean()), 4), radical_build_up=round(float(b.mean()), 4)))
             note(f"Dp {dp:g} Gy/s  Dav {rate:>8g} Gy/s: G(H2O2) {g.mean():.4f} +- {grid[-1]['g_h2o2_sem']:.4f}"
-                 f"  radicals standing / per pulse {b.mean():.3f}")
+                 f"  post-irradiation {gp.mean():.4f}  radicals standing / per pulse {b.mean():.3f}")
     line = {
         "metric": "molecule-steps/s of the dose-rate grid (SBS + rate equations, batched pulse trains)",
         "value": round(r["molecule_steps"] / r["wall"], 1), "unit": "molecule-steps/s", "higher_is_better": True,
         "n_gpus": 1, "dtype": "f32 SBS, f64 rate equations", "data": "synthetic",
         "config": {"workload": f"{len(trains)} trains of 1 us pulses at 2e5 / 1e6 Gy/s to 20 Gy, average "
                                f"0.01-1e5 Gy/s, 2 um cube, hand-over 1 us after each pulse"
-                               + ("; pH 7 water" if args.ph7 else "")},
+                               + ("; pH 7 water" if args.ph7 else "") + ("; aerated" if args.o2 else "")},
         "wall_s": round(r["wall"], 2), "grid": grid,
     }
     print(json.dumps(line), flush=True)

@@ -27,6 +27,7 @@ NA = 6.02214076e23
 C_FLOOR = 1e-10
 TAU_SETTLE = 1000.0  # ns after a pulse's last batch before the rate equations take over
 GAP = 1.0            # ns of engine clock between the re-population and the next pulse
+T_POST = 1e11        # ns (100 s) of rate equations after the last record: the post-irradiation yield
 
 
 @dataclasses.dataclass
@@ -85,22 +86,32 @@ def paper_trains(seeds=(1, 2), avg_rates=(0.01, 1.0, 10.0, 100.0, 1e3, 1e4, 1e5)
 
 
 def run(trains: List[Train], L: float = 2000.0, seed: int = 1, numodes_rtol: float = 1e-6,
-        ph7: bool = False) -> dict:
+        ph7: bool = False, o2: bool = False) -> dict:
     """Run the trains as instances of one engine.  Returns, per train, the
     species counts, the H2O2 count and the deposited energy just before every
     pulse after the first and one period after the last, the H2O2 yield (slope
-    of count against energy, molecules per 100 eV) and the wall time of the
-    whole batch.
+    of count against energy, molecules per 100 eV), the post-irradiation yield
+    (the same slope of the H2O2 that each recorded mixture holds 100 s later,
+    by the rate equations: the paper's post-irradiation concentrations after
+    1, 2, ... pulses) and the wall time of the whole batch.
 
     ph7: pH 7 water (a chemistry extension): every cube starts with the
     1e-7 mol/L H3O+ / OH- background at uniform positions, and the rate
     equations carry R9's reverse (the water autoionisation) as a zero-order
     source.  The SBS stages (about 2 us per pulse) do not create ions; the
-    background's turnover time, 1 / (k9 sqrt(Kw)) ~ 90 us, is much longer."""
+    background's turnover time, 1 / (k9 sqrt(Kw)) ~ 90 us, is much longer.
+
+    o2: aerated water (the other extension): O2 at a fixed 2.5e-4 mol/L
+    scavenges e_aq and H by first-order channels, superoxide (species 7)
+    reacts with OH, e_aq and H."""
     import torch
     n = len(trains)
     V = L ** 3 * 1e-24
-    e = gsbs.Engine([L] * n, seed, W.D_CONFIG, W.REACTIONS)
+    if o2:
+        e = gsbs.Engine([L] * n, seed, W.D_CONFIG_O2, W.REACTIONS_O2)
+        gsbs.gsbs_set_first_order(e.ctx, W.FIRST_ORDER_O2)
+    else:
+        e = gsbs.Engine([L] * n, seed, W.D_CONFIG, W.REACTIONS)
     inj = [t.injections(L) for t in trains]
     if ph7:
         gsbs.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
@@ -148,15 +159,31 @@ def run(trains: List[Train], L: float = 2000.0, seed: int = 1, numodes_rtol: flo
             h2o2[i].append(int(cnt[W.H2O2]))
             counts[i].append(np.asarray(cnt, dtype=np.int64))
             edep[i].append(float(sum(j.edep_ev for j in inj[i] if j.t < nxt[i] - 1e-9)))
+    # post-irradiation: the rate equations carry every recorded mixture (the
+    # cube just before each later pulse, and one period after the last)
+    # T_POST further, radicals spent and slow superoxide dismutation done --
+    # the H2O2 an irradiation of that many pulses leaves behind
+    allc = np.concatenate([np.stack(counts[i]).astype(np.float64) for i in range(n)]) / (NA * V)
+    post, _ = gsbs.gsbs_numodes(e.ctx, allc, np.full(len(allc), T_POST), rtol=numodes_rtol)
+    post_h2o2, k0 = [], 0
+    for i in range(n):
+        post_h2o2.append(post[k0:k0 + len(counts[i]), W.H2O2] * NA * V)
+        k0 += len(counts[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = e.stats()
     e.close()
-    yields = []
+    def slope(x, y):
+        return float(np.polyfit(x, y, 1)[0]) if len(x) > 1 else float(y[0] / x[0])
+
+    yields, g_post = [], []
     for i in range(n):
-        x, y = np.array(edep[i]) / 100.0, np.array(h2o2[i], dtype=np.float64)
-        yields.append(float(np.polyfit(x, y, 1)[0]) if len(x) > 1 else float(y[0] / x[0]))
-    return dict(h2o2=h2o2, edep=edep, counts=[np.stack(c) for c in counts], g_h2o2=np.array(yields), wall=wall,
+        x = np.array(edep[i]) / 100.0
+        yields.append(slope(x, np.array(h2o2[i], dtype=np.float64)))
+        g_post.append(slope(x, post_h2o2[i]))
+    g_post = np.array(g_post)
+    return dict(h2o2=h2o2, edep=edep, counts=[np.stack(c) for c in counts], g_h2o2=np.array(yields),
+                g_h2o2_post=g_post, wall=wall,
                 steps=st["steps"],
                 molecule_steps=st["molecule_steps"], ode_steps=ode_steps)
 
@@ -165,11 +192,13 @@ RADICALS = (W.E_AQ, W.OH, W.H)
 
 
 def build_up(train: Train, counts: np.ndarray, L: float = 2000.0, last: int = 5) -> float:
-    """Radicals (e_aq, OH, H) standing at the next pulse start, over the
-    radicals one pulse injects, averaged over the last pulses of a train: ~0
-    when the mixture reaches its steady state between pulses (the paper's SDR
-    regime), growing with the average dose rate above the threshold (UHDR)."""
+    """Radicals (e_aq, OH, H, and superoxide when the chemistry has it)
+    standing at the next pulse start, over the radicals one pulse injects,
+    averaged over the last pulses of a train: ~0 when the mixture reaches its
+    steady state between pulses (the paper's SDR regime), growing with the
+    average dose rate above the threshold (UHDR)."""
     per_pulse = W.tracks_per_gray(L) * train.dose * L / W.SPUR_SPACING_NM * W.SPUR_MEAN_MOLECULES * \
         float(sum(W.SPUR_FRACTIONS[s] for s in RADICALS))
-    standing = counts[-last:, list(RADICALS)].sum(axis=1).mean()
+    cols = list(RADICALS) + ([W.O2M] if counts.shape[1] > W.O2M else [])
+    standing = counts[-last:, cols].sum(axis=1).mean()
     return float(standing / per_pulse)

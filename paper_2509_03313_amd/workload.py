@@ -99,8 +99,9 @@ SOURCES_PH7 = [Source("R9 reverse", 10.0 * 11.0 * KW_M2, (H3O, OHM))]  # 1e10 /M
 # pKa 4.8, lumped as O2- at pH 7: H + O2 -> HO2 -> O2- + H3O+).  Rate constants
 # (1e10 L/mol/s) from the compilation of Buxton, Greenstock, Helman and Ross,
 # J. Phys. Chem. Ref. Data 17 (1988) and Bielski et al., J. Phys. Chem. Ref.
-# Data 14 (1985); superoxide dismutation (~1e5-1e6 L/mol/s at pH 7) is left
-# out.  D(O2-) = 1.75 nm^2/ns.
+# Data 14 (1985); the superoxide dismutation at pH 7 (observed 2e5 L/mol/s,
+# entered like R1/R6/R8 as a self-recombination) gives H2O2 over seconds.
+# D(O2-) = 1.75 nm^2/ns.
 O2M = 7
 SPECIES_O2 = SPECIES + ["O2-"]
 D_CONFIG_O2 = D_CONFIG + [1.75]
@@ -109,6 +110,7 @@ REACTIONS_O2 = REACTIONS + [
     Reaction("O2- + OH", O2M, OH, 1.0, (OHM,)),
     Reaction("O2- + e_aq", O2M, E_AQ, 1.3, (H2O2, OHM, OHM)),
     Reaction("O2- + H", O2M, H, 2.0, (H2O2, OHM)),
+    Reaction("O2- + O2-", O2M, O2M, 2e-5, (H2O2, OHM, OHM)),
 ]
 FIRST_ORDER_O2 = [
     FirstOrder("e_aq + O2", E_AQ, 1.9e10 * O2_AERATED_M * 1e-9, (O2M,)),
