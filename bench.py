@@ -200,7 +200,7 @@ def surrogate_bench(args):
 
 def kernels_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "engine.h"):
+    for f in ("kernels.hip", "engine.h", "device_common.h"):
         h.update(open(os.path.join(ROOT, "paper_2509_03313_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

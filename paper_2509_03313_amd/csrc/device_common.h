@@ -58,6 +58,20 @@ __device__ __forceinline__ uint32_t wave_prev(uint32_t v, uint32_t first) {
 }
 
 // --------------------------------------------------------------- Philox ---
+// Full 128-bit product of a 64-bit constant and x from four 32 x 32 + 64
+// multiply-adds (v_mad_u64_u32), shared by the low and the high half:
+// a b = lo(p00) + 2^32 p10 + 2^64 (hi(p10) + hi(p01) + a1 b1).
+template <uint64_t A>
+__device__ __forceinline__ void mul128(uint64_t x, uint64_t& lo, uint64_t& hi) {
+    constexpr uint32_t a0 = (uint32_t)A, a1 = (uint32_t)(A >> 32);
+    const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+    const uint64_t p00 = (uint64_t)a0 * x0;
+    const uint64_t p01 = (uint64_t)a0 * x1 + (p00 >> 32);
+    const uint64_t p10 = (uint64_t)a1 * x0 + (uint32_t)p01;
+    lo = (p10 << 32) | (uint32_t)p00;
+    hi = (uint64_t)a1 * x1 + (p01 >> 32) + (p10 >> 32);
+}
+
 // Philox4x64-10 (Salmon et al., SC'11): multipliers 0xD2E7470EE14C6C93 and
 // 0xCA5A826395121157, Weyl increments 0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B.
 __device__ __forceinline__ void philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
@@ -68,10 +82,9 @@ __device__ __forceinline__ void philox(uint64_t c0, uint64_t c1, uint64_t c2, ui
             k0 += 0x9E3779B97F4A7C15ull;
             k1 += 0xBB67AE8584CAA73Bull;
         }
-        const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c0;
-        const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
-        const uint64_t lo1 = 0xCA5A826395121157ull * c2;
-        const uint64_t hi1 = __umul64hi(0xCA5A826395121157ull, c2);
+        uint64_t lo0, hi0, lo1, hi1;
+        mul128<0xD2E7470EE14C6C93ull>(c0, lo0, hi0);
+        mul128<0xCA5A826395121157ull>(c2, lo1, hi1);
         const uint64_t n0 = hi1 ^ c1 ^ k0;
         const uint64_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
