@@ -330,6 +330,27 @@ int gsbs_features(gsbs_ctx* ctx, int32_t inst, double dt_next_ns, double r_max_n
 int gsbs_repopulate(gsbs_ctx* ctx, int32_t inst, double t_new_ns, const float* y, int32_t y_is_device,
                     const float* mu_y, const float* sd_y, double c_floor_M, int32_t relative);
 
+/* ------------------------------------------------------- checkpoint --- */
+/* Checkpoint and resume: the whole state of a context between calls --
+ * chemistry, parameters, seed, every instance's time, step counter, next uid,
+ * deposited energy, record times and results, pending injections, and the
+ * molecule array with its counters.  Random numbers are counter-based (seed,
+ * instance, uid, step), so a run resumed from a checkpoint continues exactly
+ * as the uninterrupted run would (same steps, same outcomes), provided both
+ * stop at the same step ends.
+ *
+ * gsbs_save writes the checkpoint into buf (host, cap bytes) and its length
+ * into *size; with buf NULL it only reports the length.  Fails with
+ * GSBS_ECAPACITY when cap is too small, GSBS_ESTATE before the chemistry is
+ * set.  The format is private to this library version. */
+int gsbs_save(gsbs_ctx* ctx, void* buf, int64_t cap, int64_t* size);
+
+/* Restore a checkpoint of gsbs_save into ctx, which must have been created
+ * with the same number of instances and the same cube edges (its seed and
+ * chemistry are replaced).  Fails with GSBS_EINVAL for anything else or a
+ * truncated or inconsistent buffer (ctx unchanged up to the chemistry). */
+int gsbs_load(gsbs_ctx* ctx, const void* buf, int64_t size);
+
 /* ------------------------------------------------- rate equations --- */
 /* The homogeneous beam-off stage of the paper (its "NumODEs", Eq. 3-4): the
  * mass-action rate equations of the context's reaction table for n

@@ -1247,6 +1247,261 @@ int gsbs_sync(gsbs_ctx* c) {
     return GSBS_OK;
 }
 
+// ------------------------------------------------------------ checkpoint ---
+extern "C++" {
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x31504b4353425347ull;  // "GSBSCKP1"
+
+struct Writer {
+    std::vector<char> b;
+    template <typename T>
+    void put(const T& v) {
+        const char* p = reinterpret_cast<const char*>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+    }
+    void raw(const void* p, size_t n) {
+        const char* q = static_cast<const char*>(p);
+        b.insert(b.end(), q, q + n);
+    }
+    template <typename T>
+    void vec(const std::vector<T>& v) {
+        put<uint64_t>(v.size());
+        if (!v.empty()) raw(v.data(), sizeof(T) * v.size());
+    }
+};
+
+struct Reader {
+    const char* p;
+    size_t n, at = 0;
+    bool ok = true;
+    template <typename T>
+    T get() {
+        T v{};
+        if (at + sizeof(T) > n) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, p + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    void raw(void* q, size_t m) {
+        if (at + m > n) {
+            ok = false;
+            return;
+        }
+        std::memcpy(q, p + at, m);
+        at += m;
+    }
+    template <typename T>
+    std::vector<T> vec(size_t limit) {
+        const uint64_t m = get<uint64_t>();
+        std::vector<T> v;
+        if (!ok || m > limit || at + sizeof(T) * m > n) {
+            ok = false;
+            return v;
+        }
+        v.resize((size_t)m);
+        raw(v.data(), sizeof(T) * m);
+        return v;
+    }
+};
+
+}  // namespace
+}  // extern "C++"
+
+int gsbs_save(gsbs_ctx* c, void* buf, int64_t cap, int64_t* size) {
+    if (!c || !size || cap < 0 || (cap > 0 && !buf)) return fail(GSBS_EINVAL, "bad checkpoint arguments");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    HIPCHK(hipStreamSynchronize(c->st));
+    Writer w;
+    w.put(kCkptMagic);
+    w.put<int32_t>(c->n_inst);
+    w.put<uint64_t>(c->seed);
+    w.put(c->prm);
+    w.vec(c->D);
+    w.vec(c->rx);
+    w.vec(c->src);
+    w.vec(c->fo);
+    w.put<int64_t>(c->steps);
+    w.put<int64_t>(c->max_live);
+    w.vec(c->injected);
+    for (const InstHost& in : c->inst) {
+        w.put(in.L);
+        w.put(in.cap_hint);
+        w.put(in.t);
+        w.put(in.step);
+        w.put(in.next_uid);
+        w.put(in.edep);
+        w.put(in.n_est);
+        w.raw(in.sp_est, sizeof(in.sp_est));
+        w.put(in.dt_max);
+        w.vec(in.anchors);
+        w.vec(in.rec_t);
+        w.vec(in.rec_done);
+        w.vec(in.rec_edep);
+        w.put<uint64_t>(in.pending.size());
+        for (const Pending& q : in.pending) {
+            w.put(q.t);
+            w.put(q.n);
+            w.put(q.edep);
+            std::vector<float> xyz((size_t)q.n * 3);
+            std::vector<uint8_t> sp((size_t)q.n);
+            if (q.n > 0) {
+                HIPCHK(hipMemcpy(xyz.data(), q.d_xyz, sizeof(float) * xyz.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(sp.data(), q.d_sp, sp.size(), hipMemcpyDeviceToHost));
+            }
+            w.raw(xyz.data(), sizeof(float) * xyz.size());
+            w.raw(sp.data(), sp.size());
+        }
+    }
+    DevCounters h{};
+    HIPCHK(hipMemcpy(&h, c->ctr, sizeof(h), hipMemcpyDeviceToHost));
+    w.put(h);
+    const int32_t nin = h.n_in;
+    std::vector<float4> pos((size_t)std::max(nin, 0));
+    std::vector<uint64_t> uid((size_t)std::max(nin, 0));
+    if (nin > 0) {
+        HIPCHK(hipMemcpy(pos.data(), c->pos[c->cur], sizeof(float4) * nin, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(uid.data(), c->uid[c->cur], sizeof(uint64_t) * nin, hipMemcpyDeviceToHost));
+    }
+    w.vec(pos);
+    w.vec(uid);
+    std::vector<long long> cnt((size_t)c->n_inst * kMaxSpecies);
+    std::vector<unsigned long long> ms((size_t)c->n_inst);
+    HIPCHK(hipMemcpy(cnt.data(), c->counts, sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ms.data(), c->msteps, sizeof(unsigned long long) * ms.size(), hipMemcpyDeviceToHost));
+    w.vec(cnt);
+    w.vec(ms);
+    std::vector<long long> rec((size_t)c->n_inst * c->max_rec * kMaxSpecies);
+    if (!rec.empty())
+        HIPCHK(hipMemcpy(rec.data(), c->rec, sizeof(long long) * rec.size(), hipMemcpyDeviceToHost));
+    w.put<int32_t>(c->max_rec);
+    w.vec(rec);
+    *size = (int64_t)w.b.size();
+    if (!buf) return GSBS_OK;
+    if (cap < *size) return fail(GSBS_ECAPACITY, "checkpoint buffer too small");
+    std::memcpy(buf, w.b.data(), w.b.size());
+    return GSBS_OK;
+}
+
+int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
+    if (!c || !buf || size <= 0) return fail(GSBS_EINVAL, "bad checkpoint arguments");
+    Reader r{static_cast<const char*>(buf), (size_t)size};
+    if (r.get<uint64_t>() != kCkptMagic || !r.ok) return fail(GSBS_EINVAL, "not a checkpoint");
+    if (r.get<int32_t>() != c->n_inst) return fail(GSBS_EINVAL, "checkpoint of another number of instances");
+    const uint64_t seed = r.get<uint64_t>();
+    const gsbs_params prm = r.get<gsbs_params>();
+    const std::vector<double> D = r.vec<double>(kMaxSpecies);
+    const std::vector<gsbs_reaction> rx = r.vec<gsbs_reaction>(kMaxReactions);
+    const std::vector<gsbs_source> src = r.vec<gsbs_source>(kMaxSources);
+    const std::vector<gsbs_first_order> fo = r.vec<gsbs_first_order>(kMaxSpecies);
+    const int64_t steps = r.get<int64_t>(), max_live = r.get<int64_t>();
+    const std::vector<int64_t> injected = r.vec<int64_t>((size_t)c->n_inst);
+    if (!r.ok || D.empty() || injected.size() != (size_t)c->n_inst) return fail(GSBS_EINVAL, "truncated checkpoint");
+    std::vector<InstHost> inst((size_t)c->n_inst);
+    struct PendingHost {
+        double t, edep;
+        int64_t n;
+        std::vector<float> xyz;
+        std::vector<uint8_t> sp;
+    };
+    std::vector<std::vector<PendingHost>> pend((size_t)c->n_inst);
+    for (int i = 0; i < c->n_inst; ++i) {
+        InstHost& in = inst[(size_t)i];
+        in.L = r.get<double>();
+        in.cap_hint = r.get<int64_t>();
+        in.t = r.get<double>();
+        in.step = r.get<uint64_t>();
+        in.next_uid = r.get<uint64_t>();
+        in.edep = r.get<double>();
+        in.n_est = r.get<int64_t>();
+        r.raw(in.sp_est, sizeof(in.sp_est));
+        in.dt_max = r.get<double>();
+        in.anchors = r.vec<double>(1u << 30);
+        in.rec_t = r.vec<double>(1u << 30);
+        in.rec_done = r.vec<char>(1u << 30);
+        in.rec_edep = r.vec<double>(1u << 30);
+        const uint64_t np = r.get<uint64_t>();
+        if (!r.ok || np > (1u << 24)) return fail(GSBS_EINVAL, "truncated checkpoint");
+        if (in.L != c->inst[(size_t)i].L) return fail(GSBS_EINVAL, "checkpoint of another box");
+        for (uint64_t k = 0; k < np && r.ok; ++k) {
+            PendingHost q;
+            q.t = r.get<double>();
+            q.n = r.get<int64_t>();
+            q.edep = r.get<double>();
+            if (!r.ok || q.n < 0 || (size_t)q.n > r.n) return fail(GSBS_EINVAL, "truncated checkpoint");
+            q.xyz.resize((size_t)q.n * 3);
+            q.sp.resize((size_t)q.n);
+            r.raw(q.xyz.data(), sizeof(float) * q.xyz.size());
+            r.raw(q.sp.data(), q.sp.size());
+            pend[(size_t)i].push_back(std::move(q));
+        }
+    }
+    const DevCounters h = r.get<DevCounters>();
+    const std::vector<float4> pos = r.vec<float4>(1u << 31);
+    const std::vector<uint64_t> uid = r.vec<uint64_t>(1u << 31);
+    const std::vector<long long> cnt = r.vec<long long>((size_t)c->n_inst * kMaxSpecies);
+    const std::vector<unsigned long long> ms = r.vec<unsigned long long>((size_t)c->n_inst);
+    const int32_t max_rec = r.get<int32_t>();
+    const std::vector<long long> rec = r.vec<long long>(1u << 30);
+    if (!r.ok || r.at != r.n || pos.size() != uid.size() || (int64_t)pos.size() != (int64_t)h.n_in ||
+        cnt.size() != (size_t)c->n_inst * kMaxSpecies || ms.size() != (size_t)c->n_inst || max_rec < 0 ||
+        rec.size() != (size_t)c->n_inst * (size_t)max_rec * kMaxSpecies)
+        return fail(GSBS_EINVAL, "inconsistent checkpoint");
+    // chemistry and parameters through the setters (they validate and rebuild the tables)
+    CHK(gsbs_set_species(c, (int32_t)D.size(), D.data()));
+    CHK(gsbs_set_params(c, &prm));
+    CHK(gsbs_set_reactions(c, (int32_t)rx.size(), rx.data()));
+    CHK(gsbs_set_sources(c, (int32_t)src.size(), src.data()));
+    CHK(gsbs_set_first_order(c, (int32_t)fo.size(), fo.data()));
+    c->seed = seed;
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (auto& in : c->inst)
+        for (auto& q : in.pending) {
+            dfree(q.d_xyz);
+            dfree(q.d_sp);
+        }
+    int64_t need = (int64_t)pos.size();
+    for (int i = 0; i < c->n_inst; ++i)
+        for (const PendingHost& q : pend[(size_t)i]) need += q.n;
+    CHK(ensure_capacity(c, need + need / 2 + 1024));
+    for (int i = 0; i < c->n_inst; ++i) {
+        InstHost& in = c->inst[(size_t)i];
+        in = inst[(size_t)i];
+        for (const PendingHost& q : pend[(size_t)i]) {
+            Pending p{q.t, q.n, nullptr, nullptr, q.edep};
+            if (q.n > 0) {
+                CHK(dalloc(&p.d_xyz, (size_t)q.n * 3));
+                CHK(dalloc(&p.d_sp, (size_t)q.n));
+                HIPCHK(hipMemcpy(p.d_xyz, q.xyz.data(), sizeof(float) * q.xyz.size(), hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(p.d_sp, q.sp.data(), q.sp.size(), hipMemcpyHostToDevice));
+            }
+            in.pending.push_back(p);
+        }
+    }
+    if (max_rec > c->max_rec) {
+        long long* nr = nullptr;
+        CHK(dalloc(&nr, rec.size()));
+        dfree(c->rec);
+        c->rec = nr;
+    }
+    c->max_rec = max_rec;
+    if (!rec.empty()) HIPCHK(hipMemcpy(c->rec, rec.data(), sizeof(long long) * rec.size(), hipMemcpyHostToDevice));
+    if (!pos.empty()) {
+        HIPCHK(hipMemcpy(c->pos[c->cur], pos.data(), sizeof(float4) * pos.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->uid[c->cur], uid.data(), sizeof(uint64_t) * uid.size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(c->ctr, &h, sizeof(h), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->counts, cnt.data(), sizeof(long long) * cnt.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->msteps, ms.data(), sizeof(unsigned long long) * ms.size(), hipMemcpyHostToDevice));
+    c->steps = steps;
+    c->max_live = max_live;
+    c->injected = injected;
+    return GSBS_OK;
+}
+
 int gsbs_get_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
     if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
     const InstHost& in = c->inst[i];

@@ -106,6 +106,8 @@ _SIGS = {
     "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
     "gsbs_set_sources": [_vp, _i32, _vp],
     "gsbs_set_first_order": [_vp, _i32, _vp],
+    "gsbs_save": [_vp, _vp, _i64, _P(_i64)],
+    "gsbs_load": [_vp, _vp, _i64],
     "gsbs_ssa": [_vp, _i32, _i32, _vp, _vp, _i32, _P(_d), _u64, _u64, _i64, _vp, _P(_i64), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
     "gsbs_mlp_create": [_i32, _vp, _P(_vp)],
@@ -444,6 +446,16 @@ class Engine:
     def stats(self):
         return gsbs_get_stats(self.ctx)
 
+    def save(self) -> bytes:
+        return gsbs_save(self.ctx)
+
+    def load(self, blob: bytes, records=None):
+        """Restore a checkpoint; records: the per-instance record times the
+        saved engine had (kept on the Python side for counts())."""
+        gsbs_load(self.ctx, blob)
+        if records is not None:
+            self.records = [np.asarray(r, dtype=np.float64) for r in records]
+
     def radii(self):
         return gsbs_get_radii(self.ctx, self.nr)
 
@@ -531,6 +543,21 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_save(ctx) -> bytes:
+    """Checkpoint of the whole context state (see gsbs_load)."""
+    n = _i64()
+    _chk(_lib.gsbs_save(ctx, None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _chk(_lib.gsbs_save(ctx, C.cast(buf, _vp), n.value, C.byref(n)))
+    return buf.raw[:n.value]
+
+
+def gsbs_load(ctx, blob: bytes):
+    """Restore a checkpoint into a context with the same instances and edges."""
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _chk(_lib.gsbs_load(ctx, C.cast(buf, _vp), len(blob)))
 
 
 def gsbs_set_first_order(ctx, channels):

@@ -1,0 +1,98 @@
+"""Checkpoint and resume through the C ABI: a run saved between pulses and
+resumed in a fresh context continues exactly as the uninterrupted run
+(counter-based random numbers: same steps, same reactions, same counts)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_2509_03313_amd import workload as W  # noqa: E402
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the device"
+    from paper_2509_03313_amd import gsbs
+    return gsbs
+
+
+def _run_two(g, seed=77):
+    wls = [W.multi_pulse(5 + i, n_pulses=3, dose_per_pulse=1.0, L=2000.0, avg_rate_gy_s=1e4, n_batches=2,
+                         n_records=20) for i in range(2)]
+    e = g.Engine([w.L for w in wls], seed, W.D_CONFIG, W.REACTIONS)
+    for i, w in enumerate(wls):
+        e.load_workload(w, inst=i)
+    return e, wls
+
+
+def test_resume_continues_exactly(g):
+    e, wls = _run_two(g)
+    t1 = 150e3  # ns: after the second pulse's batches, before the third pulse
+    e.advance_to(t1)
+    blob = e.save()
+    say("checkpoint bytes", len(blob), "molecules", [e.n(i) for i in range(2)])
+    t_end = max(w.t_end for w in wls)
+    e.advance_to(t_end)
+    ca = [e.counts(i) for i in range(2)]
+    ga = [e.gvalues(i) for i in range(2)]
+    na = [e.current_counts(i) for i in range(2)]
+    sa = e.stats()
+    e.close()
+    f = g.Engine([w.L for w in wls], 12345, W.D_CONFIG, W.REACTIONS)
+    f.load(blob, records=[w.records for w in wls])
+    assert [f.time(i) for i in range(2)] == [t1, t1]
+    f.advance_to(t_end)
+    for i in range(2):
+        assert np.array_equal(f.counts(i), ca[i]), i
+        assert np.array_equal(f.gvalues(i), ga[i]), i
+        assert np.array_equal(f.current_counts(i), na[i]), i
+    assert f.stats()["reactions"] == sa["reactions"]
+    f.close()
+
+
+def test_checkpoint_keeps_chemistry_and_rejects_bad_input(g):
+    e = g.Engine([1000.0, 1000.0], 3, W.D_CONFIG_O2, W.REACTIONS_O2)
+    g.gsbs_set_first_order(e.ctx, W.FIRST_ORDER_O2)
+    g.gsbs_set_sources(e.ctx, W.SOURCES_PH7)
+    rng = np.random.default_rng(1)
+    e.inject(0, 0.0, rng.uniform(-400, 400, size=(500, 3)).astype(np.float32),
+             rng.integers(0, 8, size=500).astype(np.uint8))
+    e.advance_to(5.0)
+    blob = e.save()
+    c0 = 10.0 ** rng.uniform(-8, -6, size=(4, 8))
+    ref, _ = g.gsbs_numodes(e.ctx, c0, [1e3, 1e5, 1e7, 1e9])
+    e.close()
+    f = g.Engine([1000.0, 1000.0], 9, W.D_CONFIG, W.REACTIONS)  # other chemistry: replaced by the load
+    f.load(blob)
+    got, _ = g.gsbs_numodes(f.ctx, c0, [1e3, 1e5, 1e7, 1e9])
+    assert np.array_equal(got, ref)
+    assert f.n(0) > 0 and f.time(0) == 5.0
+    f.close()
+    with pytest.raises(g.GsbsError):  # another number of instances
+        h = g.Engine(1000.0, 3, W.D_CONFIG, W.REACTIONS)
+        try:
+            h.load(blob)
+        finally:
+            h.close()
+    with pytest.raises(g.GsbsError):  # other edges
+        h = g.Engine([1000.0, 1500.0], 3, W.D_CONFIG, W.REACTIONS)
+        try:
+            h.load(blob)
+        finally:
+            h.close()
+    h = g.Engine([1000.0, 1000.0], 3, W.D_CONFIG, W.REACTIONS)
+    for bad in (blob[: len(blob) // 2], b"\x00" * 64, blob + b"\x01"):
+        with pytest.raises(g.GsbsError):
+            h.load(bad)
+    h.close()
