@@ -519,3 +519,31 @@ def test_first_order_channels_match_oracle(g, orc):
     cg = e.current_counts(0)
     assert np.array_equal(cg, np.bincount(sg.astype(np.int64), minlength=len(cg))[:len(cg)])
     e.close()
+
+
+def test_first_order_only_batched_matches_oracle_exactly(g, orc):
+    """First-order channels alone decide in exact FP64 on both sides, so a
+    batched run of two instances with different end times (one idles while
+    the other steps) reproduces the oracle's record counts exactly for each
+    instance (Philox key (seed, instance))."""
+    fo = [W.FirstOrder("e", W.E_AQ, 0.05, (W.OHM,)), W.FirstOrder("H", W.H, 0.02, (W.H2, W.H3O)),
+          W.FirstOrder("OH", W.OH, 0.01, ())]
+    # one pair reaction whose species never occurs (H2O2 is neither injected nor
+    # produced here): the search runs but finds nothing to decide in FP32
+    idle = [W.Reaction("idle", W.H2O2, W.H2O2, 0.5, (W.H2,))]
+    wls = [W.single_pulse_small(6), W.single_pulse_small(7)]
+    ends = [40.0, 120.0]
+    seed = 4321
+    e = make_engine(g, [w.L for w in wls], seed, reactions=idle)
+    g.gsbs_set_first_order(e.ctx, fo)
+    for i, w in enumerate(wls):
+        e.load_workload(w, inst=i)
+    e.advance_to(np.array(ends))
+    chem = orc.make_chem(wls[0].D, idle, first_order=fo)
+    for i, w in enumerate(wls):
+        ref = orc.run(w, chem, inst=i, t_end=ends[i], philox_seed=seed)
+        got = e.counts(i)[:len(ref["counts"])]
+        say("instance", i, "records", len(ref["counts"]), "final", got[-1].tolist())
+        assert np.array_equal(got, ref["counts"]), i
+        assert got[-1][W.E_AQ] < ref["counts"][0][W.E_AQ]
+    e.close()
