@@ -9,7 +9,7 @@ change of the log concentrations at the next pulse; the instance is then
 re-populated homogeneously at those counts (gsbs_repopulate) and the next
 pulse is injected into it.  Plain SBS is the fallback whenever a held-out
 error table says the network's G(H2O2) error could exceed 1 %, and it is the
-judge of that error.
+reference that error is measured against.
 
 This module drives the library: it builds pulse plans from the synthetic track
 generator, runs the engine to make training samples (features at the switch
