@@ -67,7 +67,7 @@ def parse():
                     help="SBS + PBCs, Gillespie runs and the rate equations of one homogeneous mixture in "
                          "0.2, 0.5 and 1 um cubes")
     ap.add_argument("--ssa-realisations", type=int, default=4096, help="Gillespie runs per cube edge")
-    ap.add_argument("--ssa-throughput", type=int, default=131072, metavar="N",
+    ap.add_argument("--ssa-throughput", type=int, default=524288, metavar="N",
                     help="Gillespie runs of the 0.5 um volume-scaling cube timed for the event rate")
     ap.add_argument("--dose-rate", action="store_true",
                     help="the paper's dose-rate study: 1 us pulse trains at 2e5 and 1e6 Gy/s to 20 Gy, "
