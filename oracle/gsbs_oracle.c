@@ -28,6 +28,13 @@
  *     density p(r,t) of the supplement, with the sign of its erfc argument read
  *     as +(r-R)).
  *
+ *   - Sec. "Setup for verification of periodic boundary conditions" and the
+ *     discussion of its figure: the stochastic (Gillespie) reference for
+ *     homogeneous mixtures, orc_ssa (direct method).
+ *   - Extensions of Table 1 (the discussion asks for pH and oxygen
+ *     chemistry): zero-order sources in orc_ssa and first-order channels in
+ *     orc_step and orc_ssa.
+ *
  * Everything is FP64, except the two functions whose names end in _f32: they
  * emulate the single-precision cell binning and candidate test bit for bit so
  * that integer decisions taken in FP32 can be compared exactly.
