@@ -99,6 +99,7 @@ def lib():
                 "orc_cand_f32": (i64, [i64, P(f32), P(i32), f32, P(Chem), d, P(i64), i64]),
                 "orc_ssa": (i64, [P(Chem), d, P(i64), i32, P(d), u64, u64, i64, P(i64), P(d), P(i32), i64,
                                   i32, P(d), P(i32), P(i32)]),
+                "orc_spurs": (i64, [d, u64, u64, i32, d, d, d, i32, P(d), P(d), P(i32), i64]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -138,6 +139,21 @@ def make_chem(D, reactions, c_cut: float = 5.0, rounds: int = 4, contact_only: b
         for k, p in enumerate(f.products):
             c.fo_prod[f.a][k] = p
     return c
+
+
+# --------------------------------------------------------------- spurs ---
+def spurs(L, seed, stream, n_tracks, spacing, mean, sigma, frac):
+    """The counter-based spur model of orc_spurs: (xyz [n][3] float64, species int32)."""
+    frac = np.ascontiguousarray(frac, dtype=np.float64)
+    one = np.zeros(3)
+    onei = np.zeros(1, dtype=np.int32)
+    n = lib().orc_spurs(float(L), C.c_uint64(seed), C.c_uint64(stream), int(n_tracks), float(spacing), float(mean),
+                        float(sigma), len(frac), _p(frac, C.c_double), _p(one, C.c_double), _p(onei, C.c_int32), 0)
+    xyz = np.zeros((max(n, 1), 3))
+    sp = np.zeros(max(n, 1), dtype=np.int32)
+    lib().orc_spurs(float(L), C.c_uint64(seed), C.c_uint64(stream), int(n_tracks), float(spacing), float(mean),
+                    float(sigma), len(frac), _p(frac, C.c_double), _p(xyz, C.c_double), _p(sp, C.c_int32), int(n))
+    return xyz[:n], sp[:n]
 
 
 # ------------------------------------------------------------- scalars ---

@@ -974,3 +974,75 @@ int64_t orc_ssa(const orc_chem* c, double volume_L, const int64_t* n0, int32_t n
         ++j;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based spur model (input side: it stands in for the paper's       */
+/* physical and physico-chemical stages, which are out of scope).  A pulse   */
+/* of n_tracks straight tracks parallel to z through the cube; on each track */
+/* spur centres at exponential spacing, a Poisson number of molecules per    */
+/* spur, species drawn from fixed fractions, Gaussian offsets per axis.      */
+/* Philox4x64-10, key (seed, 0x53505552534D4F44), u = (top 53 bits + 1/2)    */
+/* 2^-53:                                                                   */
+/*   track k, block (stream, k, 0, 0): x = -L/2 + L u0, y = -L/2 + L u1;     */
+/*   spur j, block (stream, k, j + 1, 0): z_j = z_{j-1} - spacing ln u0      */
+/*     (z_{-1} = -L/2; the track ends at the first z_j >= L/2), molecule     */
+/*     count by inversion of the Poisson CDF at u1 (at most 64);            */
+/*   molecule m, block (stream, k, j + 1, 2m + 1): offsets                  */
+/*     sigma sqrt(-2 ln u0) (cos, sin)(2 pi u1) on x, y and                 */
+/*     sigma sqrt(-2 ln u2) cos(2 pi u3) on z; block (stream, k, j + 1,     */
+/*     2m + 2): species = first s with u0 < frac_0 + ... + frac_s (the last  */
+/*     species with a positive fraction otherwise).                          */
+/* Positions are wrapped into [-L/2, L/2).  Writes up to cap molecules in   */
+/* track, spur, molecule order and returns how many the pulse has.           */
+/* ------------------------------------------------------------------------ */
+int64_t orc_spurs(double L, uint64_t seed, uint64_t stream, int32_t n_tracks, double spacing, double mean,
+                  double sigma, int32_t ns, const double* frac, double* xyz, int32_t* sp, int64_t cap)
+{
+    const uint64_t key[2] = {seed, 0x53505552534D4F44ULL};
+    const double two_pi = 6.283185307179586476925286766559;
+    int last = 0;
+    for (int s = 0; s < ns; ++s) if (frac[s] > 0.0) last = s;
+    int64_t n = 0;
+    for (int32_t k = 0; k < n_tracks; ++k) {
+        uint64_t w[4];
+        uint64_t ctr[4] = {stream, (uint64_t)k, 0, 0};
+        orc_philox4x64_10(ctr, key, w);
+        const double x = -0.5 * L + L * orc_u53(w[0]), y = -0.5 * L + L * orc_u53(w[1]);
+        double z = -0.5 * L;
+        for (uint64_t j = 0; j < (1u << 20); ++j) {
+            uint64_t cj[4] = {stream, (uint64_t)k, j + 1, 0};
+            orc_philox4x64_10(cj, key, w);
+            z = z - spacing * log(orc_u53(w[0]));
+            if (z >= 0.5 * L) break;
+            const double u = orc_u53(w[1]);
+            int cnt = 0;
+            double p = exp(-mean), F = p;
+            while (u > F && cnt < 64) { ++cnt; p *= mean / cnt; F += p; }
+            for (int m = 0; m < cnt; ++m) {
+                uint64_t cm[4] = {stream, (uint64_t)k, j + 1, (uint64_t)(2 * m + 1)}, v[4];
+                orc_philox4x64_10(cm, key, v);
+                const double r1 = sigma * sqrt(-2.0 * log(orc_u53(v[0])));
+                const double a1 = two_pi * orc_u53(v[1]);
+                const double r2 = sigma * sqrt(-2.0 * log(orc_u53(v[2])));
+                const double a2 = two_pi * orc_u53(v[3]);
+                cm[3] = (uint64_t)(2 * m + 2);
+                orc_philox4x64_10(cm, key, v);
+                const double us = orc_u53(v[0]);
+                double cum = 0.0;
+                int s_pick = last;
+                for (int s = 0; s < ns; ++s) {
+                    cum += frac[s];
+                    if (us < cum) { s_pick = s; break; }
+                }
+                if (n < cap) {
+                    xyz[3 * n + 0] = orc_wrap(x + r1 * cos(a1), L);
+                    xyz[3 * n + 1] = orc_wrap(y + r1 * sin(a1), L);
+                    xyz[3 * n + 2] = orc_wrap(z + r2 * cos(a2), L);
+                    sp[n] = s_pick;
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}

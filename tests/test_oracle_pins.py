@@ -563,3 +563,61 @@ def test_first_order_survival_is_exponential(orc):
     surv = s.n
     pk = math.exp(-k * t)
     assert abs(surv - n * pk) <= 4.5 * math.sqrt(n * pk * (1 - pk)), (surv, n * pk)
+
+
+# ------------------------------------------------------ spur model (input) ---
+SPUR_KEY = 0x53505552534D4F44
+
+
+def _u53(w):
+    return ((int(w) >> 11) + 0.5) / 2 ** 53
+
+
+def test_spur_model_follows_its_counters(orc):
+    """Track origins and first spur positions from a numpy Philox: x, y =
+    -L/2 + L u, first spur z = -L/2 - spacing ln u; with sigma 0 every molecule
+    of a track sits on the track's line."""
+    L, seed, stream, spacing = 2000.0, 7, 3, 150.0
+    xyz, sp = orc.spurs(L, seed, stream, 6, spacing, 5.13, 0.0, W.SPUR_FRACTIONS)
+    for k in range(6):
+        w = _numpy_philox([stream, k, 0, 0], [seed, SPUR_KEY])
+        x0, y0 = -L / 2 + L * _u53(w[0]), -L / 2 + L * _u53(w[1])
+        on = np.isclose(xyz[:, 0], x0, atol=1e-9) & np.isclose(xyz[:, 1], y0, atol=1e-9)
+        assert on.sum() > 0
+        w1 = _numpy_philox([stream, k, 1, 0], [seed, SPUR_KEY])
+        z0 = -L / 2 - spacing * math.log(_u53(w1[0]))
+        if z0 < L / 2:
+            assert np.any(np.isclose(xyz[on, 2], z0, atol=1e-9))
+    assert np.all(xyz >= -L / 2) and np.all(xyz < L / 2)
+
+
+def test_spur_model_statistics(orc):
+    """Spurs form a Poisson process of rate 1/spacing along each track,
+    molecules per spur are Poisson(mean), species follow the fractions and the
+    offsets are normal with standard deviation sigma per axis."""
+    L, spacing, mean, sigma = 5000.0, 100.0, 5.13, 2.0
+    n_tr = 400
+    xyz, sp = orc.spurs(L, 11, 0, n_tr, spacing, mean, sigma, W.SPUR_FRACTIONS)
+    n = len(sp)
+    expect = n_tr * L / spacing * mean
+    # variance of a compound Poisson total: rate * E[N^2] = (L / spacing) n_tr (mean + mean^2)
+    sd = math.sqrt(n_tr * L / spacing * (mean + mean ** 2))
+    assert abs(n - expect) <= 5 * sd, (n, expect, sd)
+    frac = np.bincount(sp, minlength=7) / n
+    for s, f in enumerate(W.SPUR_FRACTIONS):
+        assert abs(frac[s] - f) <= 5 * math.sqrt(f * (1 - f) / n) + 1e-12, (s, frac[s], f)
+    # offsets: about one spur per track (spacing = the edge); few
+    # tracks (~70 nm apart) so that each molecule's nearest track line is its own
+    n_k = 200
+    xyz1, _ = orc.spurs(1000.0, 12, 1, n_k, 1000.0, 50.0, 3.0, W.SPUR_FRACTIONS)
+    orig = []
+    for k in range(n_k):
+        w = _numpy_philox([1, k, 0, 0], [12, SPUR_KEY])
+        orig.append((-500.0 + 1000.0 * _u53(w[0]), -500.0 + 1000.0 * _u53(w[1])))
+    orig = np.array(orig)
+    dd = xyz1[:, None, :2] - orig[None, :, :]
+    dd = (dd + 500.0) % 1000.0 - 500.0
+    k = np.argmin(np.sum(dd ** 2, axis=2), axis=1)
+    d = dd[np.arange(len(xyz1)), k]
+    assert len(d) > 3000
+    assert abs(d.std() - 3.0) < 0.1 and abs(d.mean()) < 0.1, (d.std(), d.mean())
