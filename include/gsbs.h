@@ -186,6 +186,39 @@ int gsbs_get_dt_max(gsbs_ctx* ctx, int32_t inst, double* dt);
 int gsbs_inject(gsbs_ctx* ctx, int32_t inst, double t_ns, int64_t n, const float* xyz,
                 const uint8_t* species, double edep_eV, int32_t device_ptrs);
 
+/* A pulse generated on the device from a counter-based spur model (the input
+ * side: it stands in for the paper's physical and physico-chemical stages).
+ * n_tracks straight tracks parallel to z through the cube; along each, spur
+ * centres at exponential spacing (mean spacing_nm), a Poisson number of
+ * molecules per spur (mean mol_per_spur, at most 30; at most 64 drawn), the
+ * species from frac[0..n_species-1] (>= 0, summing to 1), Gaussian offsets of
+ * sigma_nm per axis.  Draws: Philox4x64-10, key (the context seed,
+ * 0x53505552534D4F44), u = (top 53 bits + 1/2) 2^-53; track k: block
+ * (stream, k, 0, 0), x = -L/2 + L u0, y = -L/2 + L u1; spur j: block
+ * (stream, k, j+1, 0), z_j = z_{j-1} - spacing ln u0 from z = -L/2 until
+ * z_j >= L/2, count by inverting the Poisson CDF at u1; molecule m: block
+ * (stream, k, j+1, 2m+1) for the offsets sigma sqrt(-2 ln u0)(cos, sin)(2 pi
+ * u1) on x, y and sigma sqrt(-2 ln u2) cos(2 pi u3) on z, block
+ * (stream, k, j+1, 2m+2) for the species (first s with u0 below the running
+ * sum of the fractions).  FP64, wrapped into the cube, stored as FP32.  The
+ * molecules are queued like gsbs_inject's at t_ns, with deposited energy
+ * n_tracks * L * let_kev_per_um eV; *n_injected (may be NULL) receives their
+ * number.  Fails with GSBS_EINVAL for bad parameters, GSBS_ESTATE for a time
+ * before the instance's present or before the species are set. */
+typedef struct {
+    double t_ns;
+    int32_t n_tracks;
+    int32_t reserved;
+    double spacing_nm;
+    double mol_per_spur;
+    double sigma_nm;
+    double let_kev_per_um;
+    uint64_t stream;
+    double frac[16];
+} gsbs_pulse;
+
+int gsbs_inject_pulse(gsbs_ctx* ctx, int32_t inst, const gsbs_pulse* pulse, int64_t* n_injected);
+
 /* Record times of instance inst (ns, ascending); counts are taken at each
  * record time after that boundary's injection.  Replaces earlier records. */
 int gsbs_set_records(gsbs_ctx* ctx, int32_t inst, int32_t n, const double* t_ns);

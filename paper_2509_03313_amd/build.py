@@ -26,7 +26,7 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-SOURCES = (("kernels.hip", True), ("mlp.hip", True), ("surrogate.hip", True), ("numodes.hip", True), ("ssa.hip", True), ("api.cpp", False),
+SOURCES = (("kernels.hip", True), ("mlp.hip", True), ("surrogate.hip", True), ("numodes.hip", True), ("ssa.hip", True), ("spurs.hip", True), ("api.cpp", False),
            ("mlp_api.cpp", False))
 
 

@@ -972,6 +972,15 @@ int gsbs_get_dt_max(gsbs_ctx* c, int32_t i, double* dt) {
     return GSBS_OK;
 }
 
+// Queue an injection (its molecules already in device buffers it owns).
+static void queue_pending(InstHost& in, const Pending& p) {
+    in.pending.push_back(p);
+    std::stable_sort(in.pending.begin(), in.pending.end(), [](const Pending& x, const Pending& y) { return x.t < y.t; });
+    in.anchors.push_back(p.t);
+    std::sort(in.anchors.begin(), in.anchors.end());
+    in.anchors.erase(std::unique(in.anchors.begin(), in.anchors.end()), in.anchors.end());
+}
+
 int gsbs_inject(gsbs_ctx* c, int32_t i, double t, int64_t n, const float* xyz, const uint8_t* sp,
                 double edep, int32_t device_ptrs) {
     if (!c || i < 0 || i >= c->n_inst || n < 0 || (n > 0 && (!xyz || !sp)))
@@ -1001,11 +1010,88 @@ int gsbs_inject(gsbs_ctx* c, int32_t i, double t, int64_t n, const float* xyz, c
         HIPCHK(hipMemcpyAsync(p.d_sp, sp, (size_t)n, k, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
     }
-    in.pending.push_back(p);
-    std::stable_sort(in.pending.begin(), in.pending.end(), [](const Pending& x, const Pending& y) { return x.t < y.t; });
-    in.anchors.push_back(t);
-    std::sort(in.anchors.begin(), in.anchors.end());
-    in.anchors.erase(std::unique(in.anchors.begin(), in.anchors.end()), in.anchors.end());
+    queue_pending(in, p);
+    return GSBS_OK;
+}
+
+int gsbs_inject_pulse(gsbs_ctx* c, int32_t i, const gsbs_pulse* q, int64_t* n_injected) {
+    if (!c || !q || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad pulse");
+    if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
+    InstHost& in = c->inst[i];
+    if (!(q->t_ns >= in.t)) return fail(GSBS_ESTATE, "pulse before the instance's present time");
+    if (q->n_tracks < 0 || !(q->spacing_nm > 0.0) || !(q->mol_per_spur >= 0.0) || q->mol_per_spur > 30.0 ||
+        !(q->sigma_nm >= 0.0) || !(q->let_kev_per_um >= 0.0) || !std::isfinite(q->spacing_nm) ||
+        !std::isfinite(q->sigma_nm))
+        return fail(GSBS_EINVAL, "bad pulse parameters");
+    SpurParams P{};
+    double sum = 0.0;
+    for (int s = 0; s < c->ns; ++s) {
+        if (!(q->frac[s] >= 0.0)) return fail(GSBS_EINVAL, "negative species fraction");
+        sum += q->frac[s];
+        P.cum[s] = sum;
+        if (q->frac[s] > 0.0) P.last = s;
+    }
+    if (!(std::fabs(sum - 1.0) <= 1e-9)) return fail(GSBS_EINVAL, "species fractions must sum to 1");
+    P.L = in.L;
+    P.spacing = q->spacing_nm;
+    P.mean = q->mol_per_spur;
+    P.sigma = q->sigma_nm;
+    P.ns = c->ns;
+    P.n_tracks = q->n_tracks;
+    P.seed = c->seed;
+    P.stream = q->stream;
+    const int nt = q->n_tracks;
+    std::vector<int64_t> cnt((size_t)nt), off((size_t)nt);
+    int64_t total = 0;
+    int64_t* d_cnt = nullptr;
+    float* d_xyz = nullptr;
+    uint8_t* d_sp = nullptr;
+    struct Release {
+        int64_t** a;
+        float** x;
+        uint8_t** s;
+        bool keep = false;
+        ~Release() {
+            dfree(*a);
+            if (!keep) {
+                dfree(*x);
+                dfree(*s);
+            }
+        }
+    } release{&d_cnt, &d_xyz, &d_sp};
+    if (nt > 0) {
+        CHK(dalloc(&d_cnt, (size_t)nt));
+        launch_spur_count(c->st, P, d_cnt);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int64_t) * nt, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int k = 0; k < nt; ++k) {
+            off[(size_t)k] = total;
+            total += cnt[(size_t)k];
+        }
+    }
+    if (total > (int64_t)0x7FFFFFF0) return fail(GSBS_ECAPACITY, "pulse beyond 2^31 molecules");
+    int64_t pend_all = 0;
+    for (auto& qq : c->inst) {
+        int64_t pend = 0;
+        for (auto& pp : qq.pending) pend += pp.n;
+        pend_all += qq.n_est + pend;
+    }
+    pend_all += total;
+    CHK(ensure_capacity(c, pend_all + pend_all / 2 + 1024));
+    if (total > 0) {
+        CHK(dalloc(&d_xyz, (size_t)total * 3));
+        CHK(dalloc(&d_sp, (size_t)total));
+        HIPCHK(hipMemcpyAsync(d_cnt, off.data(), sizeof(int64_t) * nt, hipMemcpyHostToDevice, c->st));
+        launch_spur_emit(c->st, P, d_cnt, d_xyz, d_sp);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    // deposited energy: tracks of length L at the LET (keV/um x nm = eV)
+    Pending p{q->t_ns, total, d_xyz, d_sp, (double)nt * in.L * q->let_kev_per_um};
+    release.keep = true;
+    queue_pending(in, p);
+    if (n_injected) *n_injected = total;
     return GSBS_OK;
 }
 

@@ -46,6 +46,14 @@ struct SsaTable {
     double src_rate[kMaxSources];                  // zero-order sources, mol/L/ns
 };
 
+// Counter-based spur model of a pulse (device generator of gsbs_inject_pulse).
+struct SpurParams {
+    double L, spacing, mean, sigma;
+    double cum[kMaxSpecies];  // running sums of the species fractions
+    int32_t ns, last, n_tracks, pad;
+    uint64_t seed, stream;
+};
+
 struct ChemDev {
     int32_t rmap[kMaxSpecies][kMaxSpecies];  // reaction index of a species pair or -1
     float D[kMaxSpecies];                    // nm^2/ns
@@ -195,6 +203,8 @@ void launch_repop_counts(hipStream_t st, const float* y, const float* mu, const 
                          double vol_litre, uint64_t seed, int inst, uint64_t step, int relative,
                          const long long* counts, long long* out);
 // Rate equations of n mixtures (c0, c1: [n][tb.ns] mol/L, dt: [n] ns, device).
+void launch_spur_count(hipStream_t st, const SpurParams& P, int64_t* cnt);
+void launch_spur_emit(hipStream_t st, const SpurParams& P, const int64_t* off, float* xyz, uint8_t* sp);
 void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const double* t_rec, int32_t n_rec,
                 int32_t* out, long long* events, int32_t n, const SsaTable& tb, uint64_t seed, uint64_t stream0,
                 long long max_events);

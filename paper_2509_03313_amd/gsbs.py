@@ -48,6 +48,12 @@ class gsbs_reaction(C.Structure):
                 ("products", C.c_int32 * 3), ("keep_b", C.c_int32)]
 
 
+class gsbs_pulse(C.Structure):
+    _fields_ = [("t_ns", C.c_double), ("n_tracks", C.c_int32), ("reserved", C.c_int32),
+                ("spacing_nm", C.c_double), ("mol_per_spur", C.c_double), ("sigma_nm", C.c_double),
+                ("let_kev_per_um", C.c_double), ("stream", C.c_uint64), ("frac", C.c_double * 16)]
+
+
 class gsbs_first_order(C.Structure):
     _fields_ = [("a", C.c_int32), ("n_products", C.c_int32), ("products", C.c_int32 * 2), ("k_per_ns", C.c_double)]
 
@@ -107,6 +113,7 @@ _SIGS = {
     "gsbs_set_sources": [_vp, _i32, _vp],
     "gsbs_set_first_order": [_vp, _i32, _vp],
     "gsbs_save": [_vp, _vp, _i64, _P(_i64)],
+    "gsbs_inject_pulse": [_vp, _i32, _P(gsbs_pulse), _P(_i64)],
     "gsbs_load": [_vp, _vp, _i64],
     "gsbs_ssa": [_vp, _i32, _i32, _vp, _vp, _i32, _P(_d), _u64, _u64, _i64, _vp, _P(_i64), _i32],
     "gsbs_mlp_param_count": [_P(_i64)],
@@ -543,6 +550,25 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_inject_pulse(ctx, inst, t_ns, n_tracks, frac, stream=0, spacing_nm=100.0, mol_per_spur=5.13,
+                      sigma_nm=2.0, let_kev_per_um=0.8) -> int:
+    """A pulse generated on the device from the counter-based spur model;
+    returns the number of molecules queued."""
+    p = gsbs_pulse()
+    p.t_ns = float(t_ns)
+    p.n_tracks = int(n_tracks)
+    p.spacing_nm = float(spacing_nm)
+    p.mol_per_spur = float(mol_per_spur)
+    p.sigma_nm = float(sigma_nm)
+    p.let_kev_per_um = float(let_kev_per_um)
+    p.stream = int(stream)
+    for k, f in enumerate(frac):
+        p.frac[k] = float(f)
+    n = _i64()
+    _chk(_lib.gsbs_inject_pulse(ctx, int(inst), C.byref(p), C.byref(n)))
+    return n.value
 
 
 def gsbs_save(ctx) -> bytes:
