@@ -96,3 +96,57 @@ def test_checkpoint_keeps_chemistry_and_rejects_bad_input(g):
         with pytest.raises(g.GsbsError):
             h.load(bad)
     h.close()
+
+
+_CHILD = r'''
+import os, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+from paper_2509_03313_amd import gsbs, workload as W
+mode, path, out = sys.argv[1], sys.argv[2], sys.argv[3]
+wls = [W.multi_pulse(5 + i, n_pulses=3, dose_per_pulse=1.0, L=2000.0, avg_rate_gy_s=1e4, n_batches=2,
+                     n_records=20) for i in range(2)]
+e = gsbs.Engine([w.L for w in wls], 77, W.D_CONFIG, W.REACTIONS)
+if mode == "resume":
+    e.load(open(path, "rb").read(), records=[w.records for w in wls])
+else:
+    for i, w in enumerate(wls):
+        e.load_workload(w, inst=i)
+T = 100e3  # pulse period
+t_end = max(w.t_end for w in wls)
+if mode != "resume":
+    for k in (1, 2):  # checkpoint at every pulse start after the first
+        e.advance_to(k * T)
+        open(path + ".tmp", "wb").write(e.save())
+        os.replace(path + ".tmp", path)
+        if mode == "crash" and k == 2:
+            os._exit(3)  # the process dies after its last checkpoint
+e.advance_to(t_end)
+np.save(out, np.stack([e.counts(i) for i in range(2)]))
+e.close()
+'''
+
+
+def test_resume_after_a_crash(tmp_path):
+    """A run that dies after writing its checkpoint at the third pulse start is
+    finished by a new process from that file; the records equal those of a
+    run that checkpointed at the same times and never stopped."""
+    import subprocess
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need the device"
+    root = os.path.dirname(HERE)
+    script = tmp_path / "child.py"
+    script.write_text(_CHILD.format(root=root))
+    ck = str(tmp_path / "run.ckpt")
+
+    def child(*args):
+        return subprocess.run([sys.executable, str(script), *args], timeout=300).returncode
+
+    assert child("full", str(tmp_path / "full.ckpt"), str(tmp_path / "full.npy")) == 0
+    assert child("crash", ck, str(tmp_path / "never.npy")) == 3
+    assert not (tmp_path / "never.npy").exists() and os.path.exists(ck)
+    assert child("resume", ck, str(tmp_path / "resumed.npy")) == 0
+    full = np.load(tmp_path / "full.npy")
+    resumed = np.load(tmp_path / "resumed.npy")
+    say("records", full.shape, "final counts", full[0, -1].tolist())
+    assert np.array_equal(full, resumed)
