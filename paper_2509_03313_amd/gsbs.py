@@ -427,6 +427,10 @@ class Engine:
     def inject(self, inst, t, xyz, species, edep_ev=0.0):
         gsbs_inject(self.ctx, inst, t, xyz, species, edep_ev)
 
+    def inject_pulse(self, inst, t, n_tracks, frac, **kw) -> int:
+        """A pulse generated on the device (see gsbs_inject_pulse)."""
+        return gsbs_inject_pulse(self.ctx, inst, t, n_tracks, frac, **kw)
+
     def set_records(self, inst, times):
         self.records[inst] = np.asarray(times, dtype=np.float64)
         gsbs_set_records(self.ctx, inst, self.records[inst])
