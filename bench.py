@@ -362,9 +362,17 @@ def numodes_bench(args):
     e = gsbs.Engine(1000.0, 1, W.D_CONFIG, W.REACTIONS)
     gsbs.gsbs_numodes(e.ctx, c0[:64], dt[:64])  # warm
     torch.cuda.synchronize()
+    # HIP events on the engine's stream (torch's current stream) around the call:
+    # the launch plus the copy-back of the step counts
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     c1, steps = gsbs.gsbs_numodes(e.ctx, c0, dt, rtol=1e-6)
-    wall_ode = time.perf_counter() - t0
+    ev1.record()
+    ev1.synchronize()
+    wall_host = time.perf_counter() - t0
+    wall_ode = ev0.elapsed_time(ev1) / 1e3
+    note(f"event time {wall_ode * 1e3:.2f} ms, host time {wall_host * 1e3:.2f} ms")
     e.close()
     tot_steps = int(np.sum(steps))
     ach = ALG_FLOP_PER_ODE_STEP * tot_steps / wall_ode / 1e12
@@ -490,9 +498,15 @@ def volume_scaling_bench(args):
     vol = torch.full((n_r,), V, dtype=torch.float64, device="cuda")
     gsbs.gsbs_ssa(e.ctx, n0d[:64], vol[:64], rec, seed=args.seed)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record()
     _, ev = gsbs.gsbs_ssa(e.ctx, n0d, vol, rec, seed=args.seed + 2)
-    wall = time.perf_counter() - t0
+    e1.record()
+    e1.synchronize()
+    wall_host = time.perf_counter() - t0
+    wall = e0.elapsed_time(e1) / 1e3  # HIP events on the engine's stream: the launch and its copies
+    note(f"event time {wall * 1e3:.2f} ms, host time {wall_host * 1e3:.2f} ms")
     e.close()
     ssa_rate = ev.sum() / wall
     ach = ALG_FLOP_PER_SSA_EVENT * ssa_rate / 1e12
