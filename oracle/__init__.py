@@ -8,6 +8,7 @@ arXiv 2509.03313 each function follows.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -62,7 +63,44 @@ def lib():
         if _lib is None:
             if not os.path.exists(_LIB):
                 build(force=True)
-            L = C.CDLL(_LIB)
+            _lib = _bind(C.CDLL(_LIB))
+    return _lib
+
+
+def compile_variant(source: str, path: str) -> str:
+    """Compile C source text (a patched copy of gsbs_oracle.c) the way build()
+    compiles the oracle; tests use it to plant a mistake and check that a pin
+    catches it."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(source)
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", src,
+                    "-o", path, "-lm"], check=True)
+    return path
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+@contextlib.contextmanager
+def swapped(path: str):
+    """Every wrapper below calls the library at `path` inside the block."""
+    global _lib
+    old = lib()
+    with _lock:
+        _lib = _bind(C.CDLL(path))
+    try:
+        yield
+    finally:
+        with _lock:
+            _lib = old
+
+
+def _bind(L):
+    if True:
+        if True:
             d, i32, i64, u64, f32 = C.c_double, C.c_int32, C.c_int64, C.c_uint64, C.c_float
             P = C.POINTER
             vp = C.c_void_p
@@ -100,13 +138,13 @@ def lib():
                 "orc_ssa": (i64, [P(Chem), d, P(i64), i32, P(d), u64, u64, i64, P(i64), P(d), P(i32), i64,
                                   i32, P(d), P(i32), P(i32)]),
                 "orc_spurs": (i64, [d, u64, u64, i32, d, d, d, i32, P(d), P(d), P(i32), i64]),
+                "orc_match": (i64, [i64, i64, P(i64), P(i64), P(C.c_uint32), P(u64), i32, P(i64), P(i64)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
                 f.restype = res
                 f.argtypes = args
-            _lib = L
-    return _lib
+    return L
 
 
 # ------------------------------------------------------------ chemistry ---
@@ -154,6 +192,25 @@ def spurs(L, seed, stream, n_tracks, spacing, mean, sigma, frac):
     lib().orc_spurs(float(L), C.c_uint64(seed), C.c_uint64(stream), int(n_tracks), float(spacing), float(mean),
                     float(sigma), len(frac), _p(frac, C.c_double), _p(xyz, C.c_double), _p(sp, C.c_int32), int(n))
     return xyz[:n], sp[:n]
+
+
+def match(n, pairs, u24, uid, rounds=4):
+    """Single-partner matching of accepted pairs (orc_match): pairs [k][2]
+    molecule indices below n, u24[k] the pair uniforms' 24-bit integers, uid[n].
+    Returns (partner [n] with -1 for unmatched, matched pair indices in match
+    order, tie flag)."""
+    pr = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+    pi = np.ascontiguousarray(pr[:, 0])
+    pj = np.ascontiguousarray(pr[:, 1])
+    u = np.ascontiguousarray(u24, dtype=np.uint32)
+    ud = np.ascontiguousarray(uid, dtype=np.uint64)
+    partner = np.zeros(max(n, 1), dtype=np.int64)
+    order = np.zeros(max(len(pi), 1), dtype=np.int64)
+    r = lib().orc_match(int(n), len(pi), _p(pi, C.c_int64), _p(pj, C.c_int64), _p(u, C.c_uint32),
+                        _p(ud, C.c_uint64), int(rounds), _p(partner, C.c_int64), _p(order, C.c_int64))
+    tie = r < 0
+    m = -r - 1 if tie else r
+    return partner[:n], order[:m], bool(tie)
 
 
 # ------------------------------------------------------------- scalars ---

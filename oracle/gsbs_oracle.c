@@ -493,6 +493,57 @@ static uint64_t orc_key(uint32_t u24, uint64_t partner_uid)
     return ((uint64_t)u24 << 40) | (partner_uid & 0xFFFFFFFFFFULL);
 }
 
+/* Single-partner matching of one step's accepted pairs.  Reading (the
+ * paper's "reacts when within R" gives no rule for a molecule with several
+ * accepted partners): each molecule's best accepted partner is the one with
+ * the smallest key (pair uniform's 24-bit integer, then the partner's uid,
+ * orc_key); pairs whose two molecules are each other's best react; the same
+ * is repeated on the molecules still unmatched, over the pairs left, for at
+ * most `rounds` rounds.  Pair k joins molecules pi[k] and pj[k] (indices below
+ * n) with uniform u24[k]; uid[] holds the molecules' uids.  partner[m]
+ * receives m's partner or -1; order[] (may be NULL) the matched pair indices
+ * in the order they matched.  Returns the number of matched pairs, or
+ * -(that number) - 1 if some molecule was matched twice in one round, which
+ * needs two of its pairs with identical keys. */
+int64_t orc_match(int64_t n, int64_t n_pairs, const int64_t* pi, const int64_t* pj, const uint32_t* u24,
+                  const uint64_t* uid, int32_t rounds, int64_t* partner, int64_t* order)
+{
+    uint64_t* best = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    int64_t* got = order ? order : (int64_t*)malloc(sizeof(int64_t) * (n_pairs ? n_pairs : 1));
+    int64_t n_matched = 0;
+    int tie = 0;
+    for (int64_t i = 0; i < n; ++i) partner[i] = -1;
+    for (int round = 0; round < rounds; ++round) {
+        for (int64_t k = 0; k < n_pairs; ++k) {
+            best[pi[k]] = UINT64_MAX;
+            best[pj[k]] = UINT64_MAX;
+        }
+        for (int64_t k = 0; k < n_pairs; ++k) {
+            if (partner[pi[k]] >= 0 || partner[pj[k]] >= 0) continue;
+            uint64_t ki = orc_key(u24[k], uid[pj[k]]);
+            uint64_t kj = orc_key(u24[k], uid[pi[k]]);
+            if (ki < best[pi[k]]) best[pi[k]] = ki;
+            if (kj < best[pj[k]]) best[pj[k]] = kj;
+        }
+        int64_t first = n_matched;
+        for (int64_t k = 0; k < n_pairs; ++k) {
+            if (partner[pi[k]] >= 0 || partner[pj[k]] >= 0) continue;
+            if (best[pi[k]] == orc_key(u24[k], uid[pj[k]]) && best[pj[k]] == orc_key(u24[k], uid[pi[k]]))
+                got[n_matched++] = k;
+        }
+        for (int64_t m = first; m < n_matched; ++m) {
+            int64_t k = got[m];
+            if (partner[pi[k]] >= 0 || partner[pj[k]] >= 0) tie = 1;
+            partner[pi[k]] = pj[k];
+            partner[pj[k]] = pi[k];
+        }
+        if (n_matched == first) break;
+    }
+    free(best);
+    if (!order) free(got);
+    return tie ? -n_matched - 1 : n_matched;
+}
+
 /* One SBS step of length dt.  Returns the number of reactions, or -1 if two
  * pairs sharing a molecule carried identical matching keys (never expected). */
 int64_t orc_step(orc_inst* s, const orc_chem* c, double dt)
@@ -563,43 +614,17 @@ int64_t orc_step(orc_inst* s, const orc_chem* c, double dt)
         free(head); free(next); free(cidx);
     }
 
-    /* 3. Single-partner matching.  Reading: each molecule's best accepted
-     *    partner is the one with the smallest key (pair uniform, then partner
-     *    uid); mutual bests react; repeat on the still-unmatched molecules. */
+    /* 3. Single-partner matching (orc_match). */
     int64_t* partner = (int64_t*)malloc(sizeof(int64_t) * (n ? n : 1));
-    uint64_t* best = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
     int64_t* matched_pairs = (int64_t*)malloc(sizeof(int64_t) * (acc.n ? acc.n : 1));
-    int64_t n_matched = 0;
-    int tie = 0;
-    for (int64_t i = 0; i < n; ++i) partner[i] = -1;
-    for (int round = 0; round < c->rounds; ++round) {
-        for (int64_t k = 0; k < acc.n; ++k) {
-            best[acc.p[k].i] = UINT64_MAX;
-            best[acc.p[k].j] = UINT64_MAX;
-        }
-        for (int64_t k = 0; k < acc.n; ++k) {
-            orc_pair q = acc.p[k];
-            if (partner[q.i] >= 0 || partner[q.j] >= 0) continue;
-            uint64_t ki = orc_key(q.u24, s->uid[q.j]);
-            uint64_t kj = orc_key(q.u24, s->uid[q.i]);
-            if (ki < best[q.i]) best[q.i] = ki;
-            if (kj < best[q.j]) best[q.j] = kj;
-        }
-        int64_t first = n_matched;
-        for (int64_t k = 0; k < acc.n; ++k) {
-            orc_pair q = acc.p[k];
-            if (partner[q.i] >= 0 || partner[q.j] >= 0) continue;
-            if (best[q.i] == orc_key(q.u24, s->uid[q.j]) && best[q.j] == orc_key(q.u24, s->uid[q.i]))
-                matched_pairs[n_matched++] = k;
-        }
-        for (int64_t m = first; m < n_matched; ++m) {
-            orc_pair q = acc.p[matched_pairs[m]];
-            if (partner[q.i] >= 0 || partner[q.j] >= 0) tie = 1;
-            partner[q.i] = q.j;
-            partner[q.j] = q.i;
-        }
-        if (n_matched == first) break;
-    }
+    int64_t* mi = (int64_t*)malloc(sizeof(int64_t) * (acc.n ? acc.n : 1));
+    int64_t* mj = (int64_t*)malloc(sizeof(int64_t) * (acc.n ? acc.n : 1));
+    uint32_t* mu = (uint32_t*)malloc(sizeof(uint32_t) * (acc.n ? acc.n : 1));
+    for (int64_t k = 0; k < acc.n; ++k) { mi[k] = acc.p[k].i; mj[k] = acc.p[k].j; mu[k] = acc.p[k].u24; }
+    int64_t n_matched = orc_match(n, acc.n, mi, mj, mu, s->uid, c->rounds, partner, matched_pairs);
+    int tie = n_matched < 0;
+    if (tie) n_matched = -n_matched - 1;
+    free(mi); free(mj); free(mu);
 
     /* 4. Reactions (Table 1).  Reading: products sit at the D-weighted point
      *    x_a + D_a/(D_a+D_b) * minimg(x_b - x_a) (a = reactant with the lower
@@ -724,7 +749,7 @@ int64_t orc_step(orc_inst* s, const orc_chem* c, double dt)
     s->step++;
     s->t += dt;
     free(px); free(psp); free(puid); free(dead);
-    free(partner); free(best); free(matched_pairs); free(acc.p);
+    free(partner); free(matched_pairs); free(acc.p);
     return tie ? -1 : n_matched;
 }
 
