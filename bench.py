@@ -50,10 +50,22 @@ ALG_FLOP_PER_CANDIDATE = 20
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed benchmark steps (campaign: --chunk SBS steps each; single pulse: whole runs)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before (the autotuner explores in them)")
+    ap.add_argument("--chunk", type=int, default=1000, help="campaign: global SBS steps per benchmark step")
+    ap.add_argument("--search-split", type=int, default=0,
+                    help="species-bin search: partner-stream slices per box (0: chosen by the library)")
+    ap.add_argument("--step-graph", type=int, default=-1, help="1/0: HIP step graphs on/off (-1: library default)")
+    ap.add_argument("--live", choices=("dominant", "all"), default="all",
+                    help="campaign: time the warmup's dominant kernel or every step kernel with HIP events")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=80, help="SBS steps of the oracle sample (~13 s on one core)")
+    ap.add_argument("--instances", type=int, default=64, help="cubes of the batched campaign")
+    ap.add_argument("--budget", type=int, default=20000, help="SBS steps per campaign instance at most")
+    ap.add_argument("--single-pulse", action="store_true",
+                    help="one 1 Gy pulse in a 10 um cube, 1 ps -> 1 ms, instead of the batched campaign")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="SBS steps of the oracle sample (default 80 for the single pulse, 600 for the campaign)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -577,8 +589,203 @@ def dose_rate_bench(args):
     print(json.dumps(line), flush=True)
 
 
+# Algorithmic HBM bytes per molecule-step of the whole step: one read and one
+# write of the 32-byte molecule record to move and react it, and one read and
+# one write to regroup it by cell.  Neighbour reads of the pair search reuse
+# LDS and L2 and are not counted.
+STEP_BYTES = 128
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def _oracle_campaign_sample(args_tuple):
+    """The FP64 oracle on the first n_steps SBS steps of one campaign instance
+    (same batches, drawn by the oracle's copy of the spur model, same Philox
+    streams); returns (molecule-steps, seconds)."""
+    seed, i, n_steps, budget = args_tuple
+    import numpy as np
+
+    import oracle
+    from paper_2509_03313_amd import workload as W
+    x = W.campaign(seed)[i]
+    chem = oracle.make_chem(W.D_CONFIG, W.REACTIONS)
+    dm = oracle.dt_max(chem, x.L)
+    anchors = np.array([b[0] for b in x.batches])
+    events = np.unique(np.concatenate([x.records, anchors]))
+    sched = oracle.schedule(0.0, x.t_end, anchors, events, W.DT0_NS, W.RATIO, dm)[:n_steps]
+    s = oracle.Instance(x.L, 1000, i)
+    k_b = 0
+    t_prev = 0.0
+    ms = 0
+    t0 = time.perf_counter()
+    for te in sched:
+        while k_b < len(x.batches) and x.batches[k_b][0] <= t_prev:
+            t, n_tr, st = x.batches[k_b]
+            xyz, sp = oracle.spurs(x.L, 1000, st, n_tr, W.SPUR_SPACING_NM, W.SPUR_MEAN_MOLECULES, W.SPUR_SIGMA_NM,
+                                   W.SPUR_FRACTIONS)
+            s.inject(xyz, sp, n_tr * x.L * W.LET_KEV_PER_UM)
+            k_b += 1
+        ms += s.n
+        s.step(chem, te - t_prev)
+        t_prev = te
+    return ms, time.perf_counter() - t0
+
+
+def campaign_cpu_baseline(args):
+    """1-core and all-core FP64 oracle rates on the first --cpu-steps steps of
+    campaign instances (one process per instance)."""
+    import multiprocessing as mp
+    model, ncpu, avail = cpu_info()
+    cores = max(1, min(avail or 1, 16))
+    ms1, dt1 = _oracle_campaign_sample((args.seed, 0, args.cpu_steps, 0))
+    jobs = [(args.seed, i % 64, args.cpu_steps, 0) for i in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_campaign_sample, jobs)
+    wall = time.perf_counter() - t0
+    msa = sum(r[0] for r in res)
+    return dict(value=round(msa / wall, 1), unit="molecule-steps/s", cores=cores, kind="oracle",
+                cpu_model=model, nproc=ncpu, cores_available=avail,
+                one_core=dict(value=round(ms1 / dt1, 1), molecule_steps=int(ms1), seconds=round(dt1, 2)),
+                all_core=dict(value=round(msa / wall, 1), molecule_steps=int(msa), seconds=round(wall, 2),
+                              processes=cores),
+                sample=f"first {args.cpu_steps} SBS steps of campaign instances 0..{cores - 1} (one process each; "
+                       f"1-core figure: instance 0 alone), FP64 oracle, same batches and Philox streams")
+
+
+def campaign_bench(args):
+    """The batched campaign (64 cubes, edges 2-10 um, 0.1-2 Gy per pulse, 1-20
+    pulses at 1e6 Gy/s, average 0.01-1e5 Gy/s, 10 batches per pulse), every
+    instance to the end of its train or its 20000th SBS step.  One benchmark
+    step is --chunk global SBS steps of all instances (by default 1000, so that
+    20 steps run the whole campaign); warmup steps run the start of a separate
+    copy of the campaign with the grid autotuner exploring."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import campaign as CA
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import workload as W
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    insts = W.campaign(args.seed, args.instances)
+    note(f"{len(insts)} instances, budget {args.budget} SBS steps, {args.chunk} SBS steps per benchmark step")
+
+    def make(tune):
+        p = gsbs.gsbs_default_params()
+        p.autotune = 1 if tune else 0
+        p.search_split = args.search_split
+        if args.step_graph >= 0:
+            p.step_graph = args.step_graph
+        t = time.perf_counter()
+        su = CA.setup(insts, budget=args.budget, params=p)
+        torch.cuda.synchronize()
+        note(f"setup {time.perf_counter() - t:.1f} s: {su.molecules} molecules in {int(su.batches.sum())} batches, "
+             f"device bytes {gsbs.gsbs_get_device_bytes(su.engine.ctx) / 2**30:.2f} GiB")
+        return su
+
+    prof_w = None
+    if args.warmup:
+        su = make(True)
+        gsbs.gsbs_set_live_timing(su.engine.ctx, gsbs.KERNEL_SLOTS)
+        t = time.perf_counter()
+        for k in range(args.warmup):
+            su.engine.advance_to(su.targets_after((k + 1) * args.chunk))
+            note(f"warmup step {k + 1}/{args.warmup}: {time.perf_counter() - t:.2f} s")
+        torch.cuda.synchronize()
+        prof_w = gsbs.gsbs_get_profile(su.engine.ctx)
+        note(f"warmup {args.warmup} steps: {time.perf_counter() - t:.2f} s, stats {su.engine.stats()}, "
+             f"profile {prof_w}")
+        su.engine.close()
+    su = make(False)
+    bytes_state = gsbs.gsbs_get_device_bytes(su.engine.ctx)
+    live = gsbs.KERNEL_SLOTS if args.live == "all" else (
+        (max(prof_w, key=lambda q: prof_w[q][0]),) if prof_w else ("k_pairs",))
+    # HIP events around the timed kernels, on the engine's stream, inside the timed region
+    gsbs.gsbs_set_live_timing(su.engine.ctx, live)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        su.engine.advance_to(su.targets_after((k + 1) * args.chunk))
+        note(f"step {k + 1}/{args.steps}: {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = su.engine.stats()
+    prof = gsbs.gsbs_get_profile(su.engine.ctx)
+    n_sbs = int(min(args.steps * args.chunk, su.planned_steps.max()))
+    done = all(abs(su.engine.time(i) - su.targets[i]) <= 1e-9 * su.targets[i] for i in range(len(insts)))
+    g_h2o2 = [float(su.engine.gvalues(i)[-1][W.H2O2]) for i in range(len(insts))] if done else None
+    note(f"timed {args.steps} steps: {wall:.2f} s, stats {st}, profile {prof}")
+    su.engine.close()
+    value = st["molecule_steps"] / wall
+    timed = {q: v for q, v in prof.items() if v[1] > 0}
+    dom = max(timed, key=lambda q: timed[q][0])
+    tot_ms, launches, units = prof[dom][0], prof[dom][1], prof[dom][2]
+    ach = STEP_BYTES * units / (tot_ms / 1e3) / 1e9 if tot_ms > 0 else 0.0
+    roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 5),
+                traffic=None, kernel=dom, avg_launch_us=round(tot_ms * 1e3 / max(launches, 1), 3),
+                alg_bytes_per_unit=STEP_BYTES, unit_name="molecule-step of the instances the kernel searched",
+                units_per_launch=round(units / max(launches, 1), 1))
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        if t.get("kernels_hash") == kernels_hash() and t.get("workload") == "campaign" and dom in t.get(
+                "per_launch_bytes", {}):
+            roof["traffic"] = t["per_launch_bytes"][dom]
+    step_ach = value * STEP_BYTES / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = campaign_cpu_baseline(args)
+        note(f"cpu baseline: {cpu}")
+    line = {
+        "metric": "molecule-steps/s of SBS diffusion-reaction",
+        "value": round(value, 1), "unit": "molecule-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched campaign: {len(insts)} periodic cubes (edges 2-10 um, 0.1-2 Gy per pulse, "
+                               f"1-20 pulses of 1e6 Gy/s, average 0.01-1e5 Gy/s, 10 injection batches per pulse), "
+                               f"each to the end of its train or its {args.budget}th SBS step; one benchmark step = "
+                               f"{args.chunk} SBS steps of all cubes",
+                   "instances": len(insts), "step_budget": args.budget, "sbs_steps_per_step": args.chunk,
+                   "sbs_steps_timed": n_sbs, "molecules_injected": su.molecules, "max_live": st["max_live"],
+                   "device_state_bytes": int(bytes_state), "species": 7, "reactions": 9},
+        "ms_per_sbs_step": round(wall / max(n_sbs, 1) * 1e3, 4),
+        "roofline": roof,
+        "roofline_step": dict(bound="hbm", achieved=round(step_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(step_ach / HBM_PEAK_GBS, 5), alg_bytes_per_molecule_step=STEP_BYTES),
+        "cpu_baseline": cpu,
+        "live_timed_kernels": list(live),
+        "profile_ms": {q: round(v[0], 3) for q, v in timed.items()},
+        "profile_launches": {q: v[1] for q, v in timed.items()},
+        "profile_work": {q: v[2] for q, v in timed.items()},
+        "profile_candidates": {q: v[3] for q, v in timed.items() if v[3]},
+        "warmup_profile_ms": {q: round(v[0], 3) for q, v in prof_w.items()} if prof_w else None,
+        "reactions": st["reactions"], "pair_candidates": st["pair_candidates"],
+        "G_H2O2_end_mean": round(float(np.mean(g_h2o2)), 5) if g_h2o2 else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.cpu_steps is None:
+        args.cpu_steps = 80 if args.single_pulse else 600
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent instances would shard across GPUs without communication)", file=sys.stderr)
@@ -600,6 +807,9 @@ def main():
         return
     if args.dose_rate:
         dose_rate_bench(args)
+        return
+    if not args.single_pulse and not args.calibrate_copy:
+        campaign_bench(args)
         return
 
     if args.calibrate_copy:

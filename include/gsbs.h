@@ -225,11 +225,83 @@ int gsbs_set_records(gsbs_ctx* ctx, int32_t inst, int32_t n, const double* t_ns)
 
 /* ---------------------------------------------------------------- advance --- */
 
+#define GSBS_PLAIN 0      /* every interval by SBS steps */
+#define GSBS_SURROGATE 1  /* inter-pulse intervals by the network where its error estimate allows */
+
 /* Advance every instance i to t_target[i] (>= its current time) by SBS steps:
  * Brownian jump + PBC 1, cell binning, minimum-image candidate search, radial
  * Brownian-bridge contact probability, mutual-best single-partner matching,
- * products.  Returns after the device work has completed. */
-int gsbs_advance_to(gsbs_ctx* ctx, const double* t_target);
+ * products.  Returns after the device work has completed.
+ *
+ * mode GSBS_SURROGATE (after gsbs_set_surrogate) replaces the long
+ * homogeneous evolution between pulses (the paper's beam-off stage, Eq. 3-4)
+ * by the network where its held-out error estimate allows.  A hand-over
+ * point of an instance is settle_ns after one of its injections at a_k when
+ * its next injection a_(k+1) comes later than a_k + settle_ns + min_gap_ns;
+ * there the instance stops, its features are computed (gsbs_features with the
+ * configuration's mu, sd), and the interval [a_k + settle_ns, a_(k+1)] is
+ * handed to the network when
+ *   - the table entry of its bin (log10 of the interval length in ns, log10 of
+ *     the total concentration in mol/L) is at most tol (outside the table's
+ *     edges: never),
+ *   - every normalised feature lies within [lo - m (hi - lo) - 1e-3,
+ *     hi + m (hi - lo) + 1e-3], m = guard_margin, and
+ *   - with budget > 0, the entries of the intervals the instance has handed
+ *     over since gsbs_set_surrogate, this one included, sum to at most budget.
+ * A handed-over instance is re-populated at a_(k+1) from the network's output
+ * as the change of the log10 concentrations (gsbs_repopulate with relative = 1,
+ * mu_y, sd_y); else it continues by SBS steps.  While a surrogate is set,
+ * hand-over points are step ends in both modes, so that an advance in which
+ * the network takes no interval is the GSBS_PLAIN advance bit for bit.
+ * Fails with GSBS_ESTATE for GSBS_SURROGATE without a surrogate, GSBS_EINVAL
+ * for another mode. */
+int gsbs_advance_to(gsbs_ctx* ctx, const double* t_target, int32_t mode);
+
+typedef struct gsbs_mlp gsbs_mlp;
+
+/* Surrogate hand-over configuration (arrays are copied). */
+typedef struct {
+    double settle_ns;          /* hand-over this long after an injection (1000) */
+    double min_gap_ns;         /* shortest interval handed over (0) */
+    double tol;                /* largest table entry of an interval handed over (0.01) */
+    double budget;             /* > 0: largest sum of the entries handed over per instance */
+    double guard_margin;       /* fraction of the training span the features may exceed (0.1) */
+    double r_max_nm;           /* pair-correlation shells reach min(L/2, r_max_nm) (200) */
+    double c_floor_M;          /* added to concentrations before log10 (1e-10) */
+    int32_t n_ref_max;         /* references per species of the pair correlations (1024) */
+    int32_t n_dt, n_c;         /* table bins, 1..16 each */
+    int32_t reserved;
+    const float* mu;           /* [296] feature centres */
+    const float* sd;           /* [296] feature scales */
+    const float* lo;           /* [296] smallest normalised training feature (NULL: no guard) */
+    const float* hi;           /* [296] largest normalised training feature */
+    const float* mu_y;         /* [7] output centres (a calibration offset folded in) */
+    const float* sd_y;         /* [7] output scales */
+    const double* dt_edges;    /* [n_dt + 1] ascending, log10 ns */
+    const double* c_edges;     /* [n_c + 1] ascending, log10 mol/L */
+    const double* table;       /* [n_dt][n_c] held-out error estimate (relative H2O2 error) */
+} gsbs_surrogate;
+
+/* Set (cfg and net non-NULL) or clear (both NULL) the surrogate of the
+ * context: net is borrowed (it must outlive the context's advances and hold
+ * at least as many batch rows as the context has instances); every instance's
+ * spent budget and hand-over log restart.  The table needs the 7-species,
+ * 9-reaction chemistry of gsbs_features.  Fails with GSBS_EINVAL for
+ * non-positive scales, non-ascending edges or a bin count outside 1..16. */
+int gsbs_set_surrogate(gsbs_ctx* ctx, gsbs_mlp* net, const gsbs_surrogate* cfg);
+
+/* Hand-over points instance inst met in GSBS_SURROGATE advances since
+ * gsbs_set_surrogate (host arrays of capacity max_n, any may be NULL): the
+ * hand-over time, the next injection time, the table entry (+inf when the
+ * guard or the table's edges refused it) and whether the network took the
+ * interval; *n the count. */
+int gsbs_get_handover_log(gsbs_ctx* ctx, int32_t inst, int64_t max_n, double* t_switch, double* t_next,
+                          double* estimate, int32_t* taken, int64_t* n);
+
+/* Pair-correlation function of instance inst in its present state: out[r][k]
+ * for the 9 reactions and 32 shells, as defined for gsbs_features (features
+ * 7..294 unnormalised).  Synchronises. */
+int gsbs_pair_corr(gsbs_ctx* ctx, int32_t inst, double r_max_nm, int32_t n_ref_max, float* out);
 
 /* Block until all queued work on the context's stream has finished. */
 int gsbs_sync(gsbs_ctx* ctx);
@@ -267,6 +339,25 @@ int gsbs_get_tuning(int32_t max_k, int32_t* keys, int32_t* best, double* best_ms
  * context's stream (on = 1).  Profiling drains the stream after each step, so
  * it is for measurement passes, not for production runs. */
 int gsbs_set_profiling(gsbs_ctx* ctx, int32_t on);
+
+/* Live per-kernel timing: while kernel_mask != 0, gsbs_advance_to records a
+ * HIP event at every boundary between the kernels of each step (slots as
+ * named by gsbs_get_profile: 0 k_bin, 1 k_scan, 2 k_scatter, 3 k_pairs,
+ * 4 k_pairs_sp, 5 k_react with the first-order kernel), on the context's
+ * stream, without draining it: a chunk of steps' events are read once its
+ * last kernel has finished.  A slot's time runs from its boundary to the
+ * next.  Times and launches of the slots whose bit is set accumulate into
+ * gsbs_get_profile's totals, and its work units then come from device-side
+ * counters: molecule-steps of the stepped instances (k_bin, k_scatter,
+ * k_react), of the instances searched by whole cells (k_pairs) or species bins
+ * (k_pairs_sp), bins (k_scan).  Switching (also to 0) drains the stream and
+ * clears the totals.  Not combined with gsbs_set_profiling or step graphs.
+ * Fails with GSBS_EINVAL for mask bits above 5. */
+int gsbs_set_live_timing(gsbs_ctx* ctx, uint32_t kernel_mask);
+
+/* Device memory the context holds now, in bytes: molecule arrays at their
+ * capacity, search grid, pair list, records, queued injections. */
+int gsbs_get_device_bytes(gsbs_ctx* ctx, int64_t* bytes);
 
 /* Accumulated profile: for k < *n (at most max_k) the kernel name (NUL-padded
  * in names[k*32 .. k*32+31]), total milliseconds, number of launches, work
@@ -457,8 +548,6 @@ int gsbs_ssa(gsbs_ctx* ctx, int32_t n, int32_t n_species, const int32_t* n0, con
  * x / t / y arrays are device pointers, row-major [batch][width], read and
  * written in order on the stream given at creation; every call returns after
  * queueing its kernels unless it returns host data. */
-typedef struct gsbs_mlp gsbs_mlp;
-
 /* Number of parameters of the flat FP32 layout used by set/get: per layer the
  * weight matrix W[n_out][n_in] row-major, then the bias b[n_out]. */
 int gsbs_mlp_param_count(int64_t* n);

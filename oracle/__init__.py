@@ -139,6 +139,8 @@ def _bind(L):
                                   i32, P(d), P(i32), P(i32)]),
                 "orc_spurs": (i64, [d, u64, u64, i32, d, d, d, i32, P(d), P(d), P(i32), i64]),
                 "orc_match": (i64, [i64, i64, P(i64), P(i64), P(C.c_uint32), P(u64), i32, P(i64), P(i64)]),
+                "orc_accept_f32": (i64, [i64, P(f32), P(f32), P(i32), P(u64), f32, P(Chem), d, u64, u64, u64,
+                                         P(i64), P(d), P(C.c_uint32), i64, P(i64)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -211,6 +213,28 @@ def match(n, pairs, u24, uid, rounds=4):
     tie = r < 0
     m = -r - 1 if tie else r
     return partner[:n], order[:m], bool(tie)
+
+
+def accept_f32(xyz, xyz0, species, uid, L, chem, dt, step, seed, inst=0, max_pairs=50_000_000):
+    """One step's decisions on fixed FP32 end (xyz) and start (xyz0) positions:
+    (accepted pairs [k][2] of sorted indices, their P, u24, candidate count)."""
+    x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    x0 = np.ascontiguousarray(xyz0, dtype=np.float32).reshape(-1, 3)
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    u = np.ascontiguousarray(uid, dtype=np.uint64)
+    n = len(sp)
+    cap = 1 << 16
+    while True:
+        pr = np.zeros((cap, 2), dtype=np.int64)
+        P = np.zeros(cap)
+        u24 = np.zeros(cap, dtype=np.uint32)
+        nc = C.c_int64()
+        k = lib().orc_accept_f32(n, _p(x, C.c_float), _p(x0, C.c_float), _p(sp, C.c_int32), _p(u, C.c_uint64),
+                                 float(L), C.byref(chem), float(dt), int(step), int(seed), int(inst),
+                                 _p(pr, C.c_int64), _p(P, C.c_double), _p(u24, C.c_uint32), cap, C.byref(nc))
+        if k <= cap or cap >= max_pairs:
+            return pr[:min(k, cap)], P[:min(k, cap)], u24[:min(k, cap)], nc.value
+        cap = min(max_pairs, 2 * k)
 
 
 # ------------------------------------------------------------- scalars ---

@@ -882,6 +882,125 @@ int64_t orc_cand_f32(int64_t n, const float* xyz, const int32_t* sp, float L, co
     return cnt;
 }
 
+/* The FP32 candidate predicate of orc_cand_f32 for one pair (i < j). */
+static int orc_is_cand_f32(const float* xyz, int64_t i, int64_t j, float L, float rc2)
+{
+    const float halfL = 0.5f * L;
+    volatile float d[3];
+    for (int a = 0; a < 3; ++a) {
+        volatile float v = xyz[3 * j + a] - xyz[3 * i + a];
+        if (v >= halfL) v = v - L;
+        else if (v < -halfL) v = v + L;
+        d[a] = v;
+    }
+    volatile float sx = d[0] * d[0];
+    volatile float sy = d[1] * d[1];
+    volatile float sz = d[2] * d[2];
+    volatile float s2 = sx + sy;
+    volatile float d2 = s2 + sz;
+    return d2 < rc2;
+}
+
+/* One step's pair decisions on fixed FP32 positions, for inputs too large for
+ * the all-pairs loop: the candidates are the pairs orc_cand_f32 selects (the
+ * same FP32 predicate), found through a bucket grid of edge >= 1.001 x the
+ * largest cutoff (27 neighbouring buckets, periodic), or all pairs when fewer
+ * than 3 buckets fit; each candidate then gets the oracle's FP64 contact
+ * probability (orc_bridge on the minimum-image separations of the end
+ * positions xyz and the start positions xyz0) and its pair uniform (Philox at
+ * (lower uid, higher uid, step, 1), key (seed, inst)), accepted iff u < P.
+ * Writes up to max accepted pairs (sorted indices i < j, their P and u24);
+ * returns the number accepted and the number of candidates in *n_cand. */
+int64_t orc_accept_f32(int64_t n, const float* xyz, const float* xyz0, const int32_t* sp, const uint64_t* uid,
+                       float L, const orc_chem* c, double dt, uint64_t step, uint64_t seed, uint64_t inst,
+                       int64_t* pairs, double* P, uint32_t* u24, int64_t max, int64_t* n_cand)
+{
+    float rc2[ORC_MAX_REACT];
+    int32_t rmap[ORC_MAX_SPECIES][ORC_MAX_SPECIES];
+    orc_rc2_f32(c, dt, rc2);
+    for (int a = 0; a < ORC_MAX_SPECIES; ++a)
+        for (int b = 0; b < ORC_MAX_SPECIES; ++b) rmap[a][b] = -1;
+    double rcmax = 0.0, R[ORC_MAX_REACT], Dab[ORC_MAX_REACT];
+    for (int r = 0; r < c->nr; ++r) {
+        rmap[c->ra[r]][c->rb[r]] = r;
+        rmap[c->rb[r]][c->ra[r]] = r;
+        Dab[r] = c->D[c->ra[r]] + c->D[c->rb[r]];
+        R[r] = orc_radius(c->k_in[r], Dab[r]);
+        double rc = sqrt((double)rc2[r]);
+        if (rc > rcmax) rcmax = rc;
+    }
+    int64_t nc = (int64_t)floor((double)L / (1.001 * rcmax));
+    if (nc > 256) nc = 256;
+    const uint64_t key[2] = {seed, inst};
+    int64_t n_acc = 0, cand = 0;
+    /* candidate (i, j): evaluate and keep if accepted */
+#define ORC_PAIR(I, J)                                                                         \
+    do {                                                                                       \
+        int64_t i_ = (I), j_ = (J);                                                            \
+        int32_t rx = rmap[sp[i_]][sp[j_]];                                                     \
+        if (rx >= 0 && orc_is_cand_f32(xyz, i_, j_, L, rc2[rx])) {                             \
+            ++cand;                                                                            \
+            double d1[3], d0[3];                                                               \
+            for (int a = 0; a < 3; ++a) {                                                      \
+                d1[a] = orc_minimg((double)xyz[3 * j_ + a] - (double)xyz[3 * i_ + a], L);      \
+                d0[a] = orc_minimg((double)xyz0[3 * j_ + a] - (double)xyz0[3 * i_ + a], L);    \
+            }                                                                                  \
+            double r1 = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);                   \
+            double r0 = sqrt(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]);                   \
+            double p = c->contact_only ? ((r0 <= R[rx] || r1 <= R[rx]) ? 1.0 : 0.0)            \
+                                       : orc_bridge(r0, r1, R[rx], Dab[rx] * dt);              \
+            uint64_t lo = uid[i_] < uid[j_] ? uid[i_] : uid[j_];                               \
+            uint64_t hi = uid[i_] < uid[j_] ? uid[j_] : uid[i_];                               \
+            uint64_t ctr[4] = {lo, hi, step, 1}, w[4];                                         \
+            orc_philox4x64_10(ctr, key, w);                                                    \
+            if (orc_u24(w[0]) < p) {                                                           \
+                if (n_acc < max) {                                                             \
+                    pairs[2 * n_acc] = i_ < j_ ? i_ : j_;                                      \
+                    pairs[2 * n_acc + 1] = i_ < j_ ? j_ : i_;                                  \
+                    P[n_acc] = p;                                                              \
+                    u24[n_acc] = (uint32_t)(w[0] >> 40);                                       \
+                }                                                                              \
+                ++n_acc;                                                                       \
+            }                                                                                  \
+        }                                                                                      \
+    } while (0)
+    if (nc < 3) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) ORC_PAIR(i, j);
+    } else {
+        int64_t ncell = nc * nc * nc;
+        int64_t* head = (int64_t*)malloc(sizeof(int64_t) * ncell);
+        int64_t* next = (int64_t*)malloc(sizeof(int64_t) * (n ? n : 1));
+        int64_t* cid = (int64_t*)malloc(sizeof(int64_t) * 3 * (n ? n : 1));
+        for (int64_t k = 0; k < ncell; ++k) head[k] = -1;
+        for (int64_t i = n - 1; i >= 0; --i) {
+            int64_t q[3];
+            for (int a = 0; a < 3; ++a) {
+                int64_t k = (int64_t)floor(((double)xyz[3 * i + a] + 0.5 * (double)L) / (double)L * (double)nc);
+                q[a] = k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+                cid[3 * i + a] = q[a];
+            }
+            int64_t cell = (q[0] * nc + q[1]) * nc + q[2];
+            next[i] = head[cell];
+            head[cell] = i;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            for (int ox = -1; ox <= 1; ++ox)
+                for (int oy = -1; oy <= 1; ++oy)
+                    for (int oz = -1; oz <= 1; ++oz) {
+                        int64_t qx = (cid[3 * i] + ox + nc) % nc;
+                        int64_t qy = (cid[3 * i + 1] + oy + nc) % nc;
+                        int64_t qz = (cid[3 * i + 2] + oz + nc) % nc;
+                        for (int64_t j = head[(qx * nc + qy) * nc + qz]; j >= 0; j = next[j])
+                            if (j > i) ORC_PAIR(i, j);
+                    }
+        free(head); free(next); free(cid);
+    }
+#undef ORC_PAIR
+    *n_cand = cand;
+    return n_acc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Homogeneous stochastic kinetics: Gillespie's direct method (Gillespie,    */
 /* J. Phys. Chem. 81, 1977), the algorithm of the stochastic reference the   */

@@ -20,6 +20,7 @@
 
 #include "engine.h"
 #include "gsbs.h"
+#include "mlp.h"
 
 using namespace gsbs;
 
@@ -31,6 +32,8 @@ int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+const char* const kBroken = "the context's state was lost by a failed gsbs_load; load a checkpoint or destroy it";
 
 }  // namespace
 
@@ -47,6 +50,7 @@ namespace {
     } while (0)
 
 constexpr int kChunk = 64;  // global steps per uploaded parameter chunk
+constexpr int kFeatures = 7 + 9 * kSurBins + 1;  // surrogate input row
 
 // 1e10 L/mol/s expressed per pair in nm^3/ns: 1e10 * 1e24 nm^3 / (N_A * 1e9 ns)
 double rate_to_nm3_per_ns(double k_in) { return k_in * (1e25 / 6.02214076e23); }
@@ -81,6 +85,14 @@ struct InstHost {
     std::vector<char> rec_done;
     std::vector<double> rec_edep;
     double dt_max = 0;
+    // surrogate hand-overs: estimates spent, the last hand-over point handled, log
+    double sur_spent = 0;
+    double sur_done = -INFINITY;
+    struct Handover {
+        double t_switch, t_next, estimate;
+        int32_t taken;
+    };
+    std::vector<Handover> sur_log;
 };
 
 // The step schedule: lattice anchor + dt0 * ratio^j after every anchor up to the
@@ -198,6 +210,15 @@ struct gsbs_ctx {
     int64_t steps = 0;
     int64_t max_live = 0;
     bool tuning = true;
+    bool broken = false;  // a gsbs_load failed while replacing the state
+    // surrogate hand-over (gsbs_set_surrogate)
+    bool sur_on = false;
+    gsbs_mlp* sur_net = nullptr;
+    gsbs_surrogate sur_cfg{};
+    std::vector<float> sur_mu, sur_sd, sur_lo, sur_hi, sur_mu_y, sur_sd_y;
+    std::vector<double> sur_dt_edges, sur_c_edges, sur_table;
+    float* sur_x = nullptr;  // [n_inst][296] feature rows of the instances at a hand-over point
+    float* sur_y = nullptr;  // [n_inst][7] network outputs
     // profiling
     bool profiling = false;
     struct StepLog {
@@ -208,6 +229,16 @@ struct gsbs_ctx {
     };
     std::vector<StepLog> step_log;
     hipEvent_t prof_ev[2 * kStepKernels] = {};
+    // live timing: events around the masked kernels of every step, one pool per
+    // chunk buffer, read once the chunk's last kernel has finished (no drain)
+    uint32_t live_mask = 0;
+    std::vector<hipEvent_t> live_ev[2];
+    hipEvent_t live_done[2] = {nullptr, nullptr};
+    bool live_pending[2] = {false, false};
+    int live_nstep[2] = {0, 0};
+    int32_t live_flags[2][kChunk] = {};
+    DevCounters live_base{};  // device counters when live timing was switched on
+    int64_t live_bins = 0;    // bins scanned by the live-timed steps
     // executable graphs launched during the current advance (destroyed after its final sync)
     std::vector<hipGraphExec_t> graph_execs;
     // surrogate state buffers (allocated on first use)
@@ -260,7 +291,9 @@ int read_counters(gsbs_ctx* c, DevCounters* out) {
     return GSBS_OK;
 }
 
-// Grow the molecule arrays to hold at least `need` molecules.
+// Grow the molecule arrays to hold at least `need` molecules.  Every new
+// buffer is allocated before an old one is freed: on an allocation failure
+// the context keeps its state.
 int ensure_capacity(gsbs_ctx* c, int64_t need) {
     if (need <= c->cap) return GSBS_OK;
     int64_t nc = std::max<int64_t>({need, (int64_t)c->cap * 2, 4096});
@@ -271,17 +304,50 @@ int ensure_capacity(gsbs_ctx* c, int64_t need) {
         CHK(read_counters(c, &h));
         n_in = h.n_in;
     }
-    float4* np[2];
-    uint64_t* nu[2];
+    float4* np[2] = {nullptr, nullptr};
+    uint64_t* nu[2] = {nullptr, nullptr};
+    float4 *npos0 = nullptr, *nx0 = nullptr, *nxnew = nullptr;
+    uint2* ncr = nullptr;
+    unsigned long long* ncl = nullptr;
+    int32_t* nmate = nullptr;
+    PairRec* npairs = nullptr;
+    const uint32_t want_pairs = (uint32_t)std::max<int64_t>(1 << 16, nc);
+    int rc = GSBS_OK;
     for (int b = 0; b < 2; ++b) {
-        CHK(dalloc(&np[b], nc));
-        CHK(dalloc(&nu[b], nc));
+        if (rc == GSBS_OK) rc = dalloc(&np[b], nc);
+        if (rc == GSBS_OK) rc = dalloc(&nu[b], nc);
     }
-    if (n_in > 0) {
-        HIPCHK(hipMemcpyAsync(np[0], c->pos[c->cur], sizeof(float4) * n_in, hipMemcpyDeviceToDevice, c->st));
-        HIPCHK(hipMemcpyAsync(nu[0], c->uid[c->cur], sizeof(uint64_t) * n_in, hipMemcpyDeviceToDevice, c->st));
+    if (rc == GSBS_OK) rc = dalloc(&npos0, nc);
+    if (rc == GSBS_OK) rc = dalloc(&ncr, nc);
+    if (rc == GSBS_OK) rc = dalloc(&ncl, nc);
+    if (rc == GSBS_OK) rc = dalloc(&nmate, nc);
+    if (rc == GSBS_OK) rc = dalloc(&nx0, nc);
+    if (rc == GSBS_OK) rc = dalloc(&nxnew, nc);
+    if (rc == GSBS_OK && want_pairs > c->pair_cap) rc = dalloc(&npairs, want_pairs);
+    hipError_t e = hipSuccess;
+    if (rc == GSBS_OK && n_in > 0) {
+        e = hipMemcpyAsync(np[0], c->pos[c->cur], sizeof(float4) * n_in, hipMemcpyDeviceToDevice, c->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nu[0], c->uid[c->cur], sizeof(uint64_t) * n_in, hipMemcpyDeviceToDevice, c->st);
     }
-    HIPCHK(hipStreamSynchronize(c->st));
+    if (rc == GSBS_OK && e == hipSuccess) e = hipMemsetAsync(ncl, 0xFF, sizeof(unsigned long long) * nc, c->st);
+    if (rc == GSBS_OK && e == hipSuccess) e = hipMemsetAsync(nmate, 0xFF, sizeof(int32_t) * nc, c->st);
+    if (rc == GSBS_OK && e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (rc != GSBS_OK || e != hipSuccess) {
+        for (int b = 0; b < 2; ++b) {
+            dfree(np[b]);
+            dfree(nu[b]);
+        }
+        dfree(npos0);
+        dfree(ncr);
+        dfree(ncl);
+        dfree(nmate);
+        dfree(nx0);
+        dfree(nxnew);
+        dfree(npairs);
+        if (rc != GSBS_OK) return rc;
+        return fail(GSBS_EHIP, std::string("growing the molecule arrays: ") + hipGetErrorString(e));
+    }
     for (int b = 0; b < 2; ++b) {
         dfree(c->pos[b]);
         dfree(c->uid[b]);
@@ -295,22 +361,18 @@ int ensure_capacity(gsbs_ctx* c, int64_t need) {
     dfree(c->mate);
     dfree(c->x0_dbg);
     dfree(c->xnew);
-    CHK(dalloc(&c->pos0, nc));
-    CHK(dalloc(&c->cellrank, nc));
-    CHK(dalloc(&c->claim, nc));
-    CHK(dalloc(&c->mate, nc));
-    CHK(dalloc(&c->x0_dbg, nc));
-    CHK(dalloc(&c->xnew, nc));
-    HIPCHK(hipMemsetAsync(c->claim, 0xFF, sizeof(unsigned long long) * nc, c->st));
-    HIPCHK(hipMemsetAsync(c->mate, 0xFF, sizeof(int32_t) * nc, c->st));
+    c->pos0 = npos0;
+    c->cellrank = ncr;
+    c->claim = ncl;
+    c->mate = nmate;
+    c->x0_dbg = nx0;
+    c->xnew = nxnew;
     c->cap = (int32_t)nc;
-    uint32_t want_pairs = (uint32_t)std::max<int64_t>(1 << 16, nc);
-    if (want_pairs > c->pair_cap) {
+    if (npairs) {
         dfree(c->pairs);
-        CHK(dalloc(&c->pairs, want_pairs));
+        c->pairs = npairs;
         c->pair_cap = want_pairs;
     }
-    HIPCHK(hipStreamSynchronize(c->st));
     return GSBS_OK;
 }
 
@@ -438,6 +500,50 @@ constexpr GridCfg kCfgs[] = {
 };
 constexpr int kNumCfg = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 
+// A boxes of species s in the species-bin search grid of one instance.
+int64_t boxes_of(const InstStep& S, int s) {
+    const int kx = S.kdim_sp[s] & 0xFF, ky = (S.kdim_sp[s] >> 8) & 0xFF, kz = (S.kdim_sp[s] >> 16) & 0xFF;
+    const int64_t nc = S.nc;
+    return ((nc + kx - 1) / kx) * ((nc + ky - 1) / ky) * ((nc + kz - 1) / kz);
+}
+
+// Waves of the species-bin search resident on the device at once (its LDS
+// use allows three 4-wave blocks per compute unit).
+constexpr double kResidentWaves = 256.0 * 12.0;
+
+// Stream slices of the species-bin search for one step over all instances:
+// a box whose partner stream exceeds W = (the step's whole streamed work) /
+// (4 x resident waves) is cut into ceil(work / W) slices (at most 64, at
+// least 4 stages of 64 molecules each), so that no slice is longer than a
+// quarter of a resident wave's share and long streams do not leave the
+// device idle at the end of the launch.  Rewrites each row's work-item
+// offsets; inactive rows get none.
+void assign_splits(const gsbs_ctx* c, InstStep* rows, int n) {
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const InstStep& S = rows[i];
+        if (!S.active || !S.by_species) continue;
+        for (int s = 0; s < c->ns; ++s)
+            if (S.pm_dir[s]) total += (double)boxes_of(S, s) * (double)S.work_sp[s];
+    }
+    const double W = std::max(256.0, total / (4.0 * kResidentWaves));
+    for (int i = 0; i < n; ++i) {
+        InstStep& S = rows[i];
+        if (!S.by_species) continue;
+        int64_t off = 0;
+        for (int s = 0; s < c->ns; ++s) {
+            int64_t ns = 1;
+            if (S.work_sp[s] > W) ns = std::min<int64_t>(64, (int64_t)std::ceil((double)S.work_sp[s] / W));
+            ns = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)(S.work_sp[s] / 256.0)));
+            if (c->prm.search_split > 0) ns = c->prm.search_split;
+            S.nsplit_sp[s] = (int32_t)ns;
+            S.unit_off_sp[s] = (int32_t)off;
+            if (S.active && S.pm_dir[s]) off += boxes_of(S, s) * ns;
+        }
+        S.unit_off_sp[c->ns] = (int32_t)std::min<int64_t>(off, 0x7FFFFFF0);
+    }
+}
+
 // Grid of one instance for one configuration: nc cells per axis, no smaller
 // than (cutoff / reach) and at least `occ` molecules per cell on average.
 // Returns cells.
@@ -475,13 +581,11 @@ int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_
         }
         // A box of each species: kx*ky*kz cells chosen to minimise the partner
         // molecules streamed per A molecule (64 A molecules per wave pass, a fixed
-        // cost per pass); then the stream of every box is cut into nsplit slices so
-        // that the launch has enough waves
+        // cost per pass)
         const double ncell = (double)nc * nc * nc;
-        double units_total = 0.0, work_total = 0.0;
-        int64_t units_sp[kMaxSpecies] = {};
         for (int s = 0; s < c->ns; ++s) {
             S.kdim_sp[s] = 1 | (1 << 8) | (1 << 16);
+            S.work_sp[s] = 0.0f;
             if (!S.pm_dir[s]) continue;
             const double per_cell = (double)std::max<int64_t>(sp_est[s], 0) / ncell;
             double best = INFINITY, best_work = 0.0;
@@ -514,25 +618,15 @@ int32_t fill_grid(const gsbs_ctx* c, const int64_t* sp_est, double L, int64_t n_
                         S.kdim_sp[s] = kx | (ky << 8) | (kz << 16);
                     }
                 }
-            const int kx = S.kdim_sp[s] & 0xFF, ky = (S.kdim_sp[s] >> 8) & 0xFF, kz = (S.kdim_sp[s] >> 16) & 0xFF;
-            units_sp[s] = ((nc + kx - 1) / kx) * ((nc + ky - 1) / ky) * ((nc + kz - 1) / kz);
-            units_total += (double)units_sp[s];
-            work_total += (double)units_sp[s] * best_work;
+            S.work_sp[s] = (float)best_work;
         }
-        constexpr double kTargetItems = 8192.0;  // waves per launch that keep every SIMD busy
-        const double n_inst = (double)std::max<size_t>(c->inst.size(), 1);
-        int64_t nsplit = 1;
-        if (units_total > 0) {
-            const double want = std::ceil(kTargetItems / (units_total * n_inst));
-            const double room = std::floor(work_total / units_total / 256.0);  // >= 4 stages per slice
-            nsplit = (int64_t)std::max(1.0, std::min({want, room, 16.0}));
-        }
-        if (c->prm.search_split > 0) nsplit = c->prm.search_split;
-        S.nsplit = (int32_t)nsplit;
+        // one slice per box for now: assign_splits cuts the long streams once every
+        // instance of the step is planned
         int64_t off = 0;
         for (int s = 0; s < c->ns; ++s) {
+            S.nsplit_sp[s] = 1;
             S.unit_off_sp[s] = (int32_t)off;
-            off += units_sp[s] * nsplit;
+            off += S.pm_dir[s] ? boxes_of(S, s) : 0;
         }
         S.unit_off_sp[c->ns] = (int32_t)off;
     }
@@ -644,11 +738,13 @@ StepBuffers buffers(gsbs_ctx* c) {
 
 int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_inst, int32_t bins, int32_t units,
              int32_t grid, int32_t flags, hipEvent_t* span = nullptr, const InstStep* row0 = nullptr, int cfg0 = -1,
-             int64_t nest0 = 0) {
+             int64_t nest0 = 0, hipEvent_t* live = nullptr) {
     if (span) HIPCHK(hipEventRecord(span[0], c->st));
     if (!c->fo.empty()) flags |= kStepFirstOrder;
-    launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags,
-                c->profiling ? c->prof_ev : nullptr);
+    if (c->profiling)
+        launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags, c->prof_ev);
+    else
+        launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags, live, kEvChain);
     HIPCHK(hipGetLastError());
     if (span) HIPCHK(hipEventRecord(span[1], c->st));
     if (c->profiling) {
@@ -678,6 +774,27 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
             c->step_log.push_back({(int64_t)row0->step, (double)tot, row0->nc, row0->reach, row0->by_species, cfg0,
                                    nest0});
     }
+    return GSBS_OK;
+}
+
+// Kernel times of a finished chunk of live-timed steps (buffer b).
+int live_harvest(gsbs_ctx* c, int b) {
+    if (!c->live_pending[b]) return GSBS_OK;
+    HIPCHK(hipEventSynchronize(c->live_done[b]));
+    for (int k = 0; k < c->live_nstep[b]; ++k) {
+        const int32_t fl = c->live_flags[b][k];
+        for (int q = 0; q < kStepKernels; ++q) {
+            if (!((c->live_mask >> q) & 1u)) continue;
+            if ((q == 3 && !(fl & kStepHasWhole)) || (q == 4 && !(fl & kStepHasSpecies))) continue;
+            float ms = 0.f;
+            const hipEvent_t* e = &c->live_ev[b][(size_t)k * (kStepKernels + 1) + q];
+            HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+            c->prof_ms[q] += ms;
+            c->prof_n[q] += 1;
+        }
+    }
+    c->live_pending[b] = false;
+    c->live_nstep[b] = 0;
     return GSBS_OK;
 }
 
@@ -867,8 +984,15 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->sur_hist);
     dfree(c->sur_vec);
     dfree(c->sur_newc);
+    dfree(c->sur_x);
+    dfree(c->sur_y);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < 2; ++b) {
+        for (auto& e : c->live_ev[b])
+            if (e) (void)hipEventDestroy(e);
+        if (c->live_done[b]) (void)hipEventDestroy(c->live_done[b]);
+    }
     for (auto& e : c->tune_ev)
         if (e) (void)hipEventDestroy(e);
     for (int b = 0; b < 2; ++b) {
@@ -985,6 +1109,7 @@ int gsbs_inject(gsbs_ctx* c, int32_t i, double t, int64_t n, const float* xyz, c
                 double edep, int32_t device_ptrs) {
     if (!c || i < 0 || i >= c->n_inst || n < 0 || (n > 0 && (!xyz || !sp)))
         return fail(GSBS_EINVAL, "bad injection");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
     InstHost& in = c->inst[i];
     if (t < in.t) return fail(GSBS_ESTATE, "injection before the instance's present time");
@@ -1016,6 +1141,7 @@ int gsbs_inject(gsbs_ctx* c, int32_t i, double t, int64_t n, const float* xyz, c
 
 int gsbs_inject_pulse(gsbs_ctx* c, int32_t i, const gsbs_pulse* q, int64_t* n_injected) {
     if (!c || !q || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad pulse");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     if (c->ns == 0) return fail(GSBS_ESTATE, "set the species first");
     InstHost& in = c->inst[i];
     if (!(q->t_ns >= in.t)) return fail(GSBS_ESTATE, "pulse before the instance's present time");
@@ -1129,9 +1255,17 @@ int gsbs_set_records(gsbs_ctx* c, int32_t i, int32_t n, const double* t) {
     return GSBS_OK;
 }
 
-int gsbs_advance_to(gsbs_ctx* c, const double* target) {
-    if (!c || !target) return fail(GSBS_EINVAL, "null");
-    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+// Hand-over points of an instance: settle_ns after an injection a_k whose next
+// injection a_(k+1) comes later than a_k + settle_ns + min_gap_ns; (time, next).
+static void handover_points(const gsbs_ctx* c, const InstHost& in, std::vector<std::pair<double, double>>& out) {
+    out.clear();
+    if (!c->sur_on) return;
+    const double st = c->sur_cfg.settle_ns, gap = c->sur_cfg.min_gap_ns;
+    for (size_t k = 0; k + 1 < in.anchors.size(); ++k)
+        if (in.anchors[k + 1] - in.anchors[k] > st + gap) out.push_back({in.anchors[k] + st, in.anchors[k + 1]});
+}
+
+static int advance_plain(gsbs_ctx* c, const double* target) {
     for (int i = 0; i < c->n_inst; ++i)
         if (target[i] < c->inst[i].t) return fail(GSBS_ESTATE, "target time before the present");
     // schedules
@@ -1144,7 +1278,13 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
             if (r > in.t && r <= target[i]) ev.push_back(r);
         for (auto& p : in.pending)
             if (p.t > in.t && p.t <= target[i]) ev.push_back(p.t);
+        // with a surrogate set, hand-over points are step ends in both modes
+        std::vector<std::pair<double, double>> hp;
+        handover_points(c, in, hp);
+        for (auto& q : hp)
+            if (q.first > in.t && q.first <= target[i]) ev.push_back(q.first);
         std::sort(ev.begin(), ev.end());
+        ev.erase(std::unique(ev.begin(), ev.end()), ev.end());
         plan_steps(in.t, target[i], in.anchors.data(), (int)in.anchors.size(), ev.data(), (int)ev.size(),
                    c->prm.dt0_ns, c->prm.ratio, in.dt_max, sched[i]);
         G = std::max(G, sched[i].size());
@@ -1228,12 +1368,16 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
                 }
                 const int32_t cells = fill_grid(c, c->inst[i].sp_est, c->inst[i].L, nest[i], rcm[i], kCfgs[cfg], 0, row);
                 base += row.by_species ? cells * c->ns : cells;
-                row.unit_base = (int32_t)ubase;
-                ubase += units_of(row, c->ns);
                 if (active) fl |= row.by_species ? kStepHasSpecies : kStepHasWhole;
                 if (active)
                     for (auto& p : c->inst[i].pending)
                         if (p.t == sched[i][g]) nest[i] += p.n;
+            }
+            assign_splits(c, &hrow[(size_t)k * c->n_inst], c->n_inst);
+            for (int i = 0; i < c->n_inst; ++i) {
+                InstStep& row = hrow[(size_t)k * c->n_inst + i];
+                row.unit_base = (int32_t)std::min<int64_t>(ubase, 0x7FFFFFF0);
+                ubase += units_of(row, c->ns);
             }
             total_cells[k] = base;
             total_units[k] = (int32_t)std::min<int64_t>(ubase, 0x7FFFFFF0);
@@ -1252,7 +1396,13 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
         bool explore_chunk = false;
         for (int k = 0; k < nstep; ++k) explore_chunk = explore_chunk || tune_cfg[k] >= 0;
         // (the legacy null stream cannot be captured)
-        const bool use_graph = c->prm.step_graph && !c->profiling && !explore_chunk && c->st != nullptr;
+        const bool live = c->live_mask != 0 && !c->profiling;
+        const bool use_graph = c->prm.step_graph && !c->profiling && !live && !explore_chunk && c->st != nullptr;
+        if (live) {
+            CHK(live_harvest(c, b));
+            c->live_nstep[b] = nstep;
+            for (int k = 0; k < nstep; ++k) c->live_flags[b][k] = step_flags[k];
+        }
         bool capturing = false;
         auto flush_graph = [&]() -> int {
             if (!capturing) return GSBS_OK;
@@ -1277,7 +1427,9 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
             CHK(run_step(c, bf, c->d_chunk[b] + (size_t)k * c->n_inst, c->n_inst, total_cells[k], total_units[k],
                          grid_for(n_total),
                          step_flags[k], tune_cfg[k] >= 0 ? &c->tune_ev[2 * k] : nullptr,
-                         &hrow[(size_t)k * c->n_inst], step_cfg[k], step_nest[k]));
+                         &hrow[(size_t)k * c->n_inst], step_cfg[k], step_nest[k],
+                         live ? &c->live_ev[b][(size_t)k * (kStepKernels + 1)] : nullptr));
+            if (live) c->live_bins += total_cells[k];
             c->cur ^= 1;
             c->steps++;
             for (int i = 0; i < c->n_inst; ++i) {
@@ -1295,6 +1447,10 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
             }
         }
         CHK(flush_graph());
+        if (live) {
+            HIPCHK(hipEventRecord(c->live_done[b], c->st));
+            c->live_pending[b] = true;
+        }
         for (int i = 0; i < c->n_inst; ++i) c->inst[i].n_est = nest[i];
         {
             const int sl = c->cnt_slot;
@@ -1321,10 +1477,160 @@ int gsbs_advance_to(gsbs_ctx* c, const double* target) {
     }
     for (int i = 0; i < c->n_inst; ++i) c->inst[i].t = target[i];
     HIPCHK(hipStreamSynchronize(c->st));
+    for (int b = 0; b < 2; ++b) CHK(live_harvest(c, b));
     for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
     c->graph_execs.clear();
     CHK(check_device_errors(c));
     return refresh_estimates(c);
+}
+
+int gsbs_advance_to(gsbs_ctx* c, const double* target, int32_t mode) {
+    if (!c || !target) return fail(GSBS_EINVAL, "null");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    if (mode != GSBS_PLAIN && mode != GSBS_SURROGATE) return fail(GSBS_EINVAL, "mode: GSBS_PLAIN or GSBS_SURROGATE");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!(target[i] >= c->inst[i].t)) return fail(GSBS_ESTATE, "target time before the present");
+    if (mode == GSBS_PLAIN) return advance_plain(c, target);
+    if (!c->sur_on) return fail(GSBS_ESTATE, "GSBS_SURROGATE without a surrogate (gsbs_set_surrogate)");
+    const gsbs_surrogate& q = c->sur_cfg;
+    std::vector<double> stop((size_t)c->n_inst), next((size_t)c->n_inst);
+    std::vector<std::pair<double, double>> hp;
+    std::vector<int> at;
+    std::vector<float> xrow((size_t)c->n_inst * kFeatures);
+    for (;;) {
+        // every instance runs to its next hand-over point not handled yet, else to its target
+        at.clear();
+        for (int i = 0; i < c->n_inst; ++i) {
+            InstHost& in = c->inst[(size_t)i];
+            stop[(size_t)i] = target[i];
+            handover_points(c, in, hp);
+            for (auto& h : hp)
+                if (h.first >= in.t && h.first > in.sur_done && h.second <= target[i]) {
+                    stop[(size_t)i] = h.first;
+                    next[(size_t)i] = h.second;
+                    at.push_back(i);
+                    break;
+                }
+        }
+        CHK(advance_plain(c, stop.data()));
+        if (at.empty()) return GSBS_OK;
+        // features of the instances at their hand-over point, one row each, then the network
+        for (size_t k = 0; k < at.size(); ++k) {
+            const int i = at[k];
+            CHK(gsbs_features(c, i, next[(size_t)i] - stop[(size_t)i], q.r_max_nm, q.n_ref_max, q.c_floor_M,
+                              c->sur_mu.data(), c->sur_sd.data(), c->sur_x + k * kFeatures, 1));
+        }
+        HIPCHK(hipMemcpy(xrow.data(), c->sur_x, sizeof(float) * kFeatures * at.size(), hipMemcpyDeviceToHost));
+        CHK(mlp_forward_sync(c->sur_net, c->sur_x, (int)at.size(), c->sur_y));
+        for (size_t k = 0; k < at.size(); ++k) {
+            const int i = at[k];
+            InstHost& in = c->inst[(size_t)i];
+            const double t_sw = stop[(size_t)i], t_nx = next[(size_t)i];
+            // table entry of the interval's bin; +inf outside the edges or the inputs' range
+            double est = INFINITY;
+            std::vector<int64_t> cnt((size_t)c->ns);
+            CHK(gsbs_get_current_counts(c, i, cnt.data()));
+            double n_tot = 0;
+            for (int64_t v : cnt) n_tot += (double)v;
+            const double c_tot = n_tot / (6.02214076e23 * in.L * in.L * in.L * 1e-24);
+            const double ldt = std::log10(t_nx - t_sw), lc = std::log10(c_tot);
+            const auto& de = c->sur_dt_edges;
+            const auto& ce = c->sur_c_edges;
+            if (ldt >= de.front() && ldt <= de.back() && c_tot > 0 && lc >= ce.front() && lc <= ce.back()) {
+                int a = (int)(std::upper_bound(de.begin(), de.end(), ldt) - de.begin()) - 1;
+                int b = (int)(std::upper_bound(ce.begin(), ce.end(), lc) - ce.begin()) - 1;
+                a = std::min(std::max(a, 0), q.n_dt - 1);
+                b = std::min(std::max(b, 0), q.n_c - 1);
+                est = c->sur_table[(size_t)a * q.n_c + b];
+            }
+            if (!c->sur_lo.empty()) {
+                const float* x = &xrow[k * kFeatures];
+                for (int f = 0; f < kFeatures; ++f) {
+                    const double span = (double)c->sur_hi[f] - (double)c->sur_lo[f];
+                    const double m = q.guard_margin * span + 1e-3;
+                    if (!((double)x[f] >= (double)c->sur_lo[f] - m && (double)x[f] <= (double)c->sur_hi[f] + m))
+                        est = INFINITY;
+                }
+            }
+            const bool take = est <= q.tol && (q.budget <= 0 || in.sur_spent + est <= q.budget);
+            in.sur_done = t_sw;
+            in.sur_log.push_back({t_sw, t_nx, est, take ? 1 : 0});
+            if (take) {
+                in.sur_spent += est;
+                CHK(gsbs_repopulate(c, i, t_nx, c->sur_y + k * kMlpOut, 1, c->sur_mu_y.data(), c->sur_sd_y.data(),
+                                    q.c_floor_M, 1));
+            }
+        }
+    }
+}
+
+int gsbs_set_surrogate(gsbs_ctx* c, gsbs_mlp* net, const gsbs_surrogate* q) {
+    if (!c) return fail(GSBS_EINVAL, "null");
+    for (auto& in : c->inst) {
+        in.sur_spent = 0;
+        in.sur_done = -INFINITY;
+        in.sur_log.clear();
+    }
+    if (!net && !q) {
+        c->sur_on = false;
+        c->sur_net = nullptr;
+        return GSBS_OK;
+    }
+    if (!net || !q || !q->mu || !q->sd || !q->mu_y || !q->sd_y || !q->dt_edges || !q->c_edges || !q->table ||
+        (!q->lo) != (!q->hi))
+        return fail(GSBS_EINVAL, "surrogate: network, normalisation, edges and table are required");
+    if (q->n_dt < 1 || q->n_dt > 16 || q->n_c < 1 || q->n_c > 16 || !(q->settle_ns > 0) || !(q->min_gap_ns >= 0) ||
+        !(q->tol >= 0) || !(q->guard_margin >= 0) || !(q->r_max_nm > 0) || !(q->c_floor_M > 0) || q->n_ref_max < 1 ||
+        !std::isfinite(q->settle_ns) || !std::isfinite(q->budget))
+        return fail(GSBS_EINVAL, "surrogate: bad parameters");
+    if (!c->chem_ready || c->ns != 7 || c->rx.size() != 9)
+        return fail(GSBS_ESTATE, "surrogate: features are defined for 7 species and 9 reactions");
+    for (int f = 0; f < kFeatures; ++f)
+        if (!(q->sd[f] > 0) || !std::isfinite(q->mu[f])) return fail(GSBS_EINVAL, "surrogate: feature scales");
+    for (int k = 0; k < kMlpOut; ++k)
+        if (!(q->sd_y[k] > 0) || !std::isfinite(q->mu_y[k])) return fail(GSBS_EINVAL, "surrogate: output scales");
+    for (int k = 0; k < q->n_dt; ++k)
+        if (!(q->dt_edges[k + 1] > q->dt_edges[k])) return fail(GSBS_EINVAL, "surrogate: dt edges must ascend");
+    for (int k = 0; k < q->n_c; ++k)
+        if (!(q->c_edges[k + 1] > q->c_edges[k])) return fail(GSBS_EINVAL, "surrogate: concentration edges must ascend");
+    if (!c->sur_x) {
+        CHK(dalloc(&c->sur_x, (size_t)c->n_inst * kFeatures));
+        CHK(dalloc(&c->sur_y, (size_t)c->n_inst * kMlpOut));
+    }
+    c->sur_cfg = *q;
+    c->sur_mu.assign(q->mu, q->mu + kFeatures);
+    c->sur_sd.assign(q->sd, q->sd + kFeatures);
+    c->sur_lo.clear();
+    c->sur_hi.clear();
+    if (q->lo) {
+        c->sur_lo.assign(q->lo, q->lo + kFeatures);
+        c->sur_hi.assign(q->hi, q->hi + kFeatures);
+    }
+    c->sur_mu_y.assign(q->mu_y, q->mu_y + kMlpOut);
+    c->sur_sd_y.assign(q->sd_y, q->sd_y + kMlpOut);
+    c->sur_dt_edges.assign(q->dt_edges, q->dt_edges + q->n_dt + 1);
+    c->sur_c_edges.assign(q->c_edges, q->c_edges + q->n_c + 1);
+    c->sur_table.assign(q->table, q->table + (size_t)q->n_dt * q->n_c);
+    c->sur_cfg.mu = c->sur_cfg.sd = c->sur_cfg.lo = c->sur_cfg.hi = c->sur_cfg.mu_y = c->sur_cfg.sd_y = nullptr;
+    c->sur_cfg.dt_edges = c->sur_cfg.c_edges = c->sur_cfg.table = nullptr;
+    c->sur_net = net;
+    c->sur_on = true;
+    return GSBS_OK;
+}
+
+int gsbs_get_handover_log(gsbs_ctx* c, int32_t i, int64_t max_n, double* t_switch, double* t_next, double* estimate,
+                          int32_t* taken, int64_t* n) {
+    if (!c || !n || i < 0 || i >= c->n_inst || max_n < 0) return fail(GSBS_EINVAL, "bad arguments");
+    const auto& lg = c->inst[(size_t)i].sur_log;
+    for (int64_t k = 0; k < std::min<int64_t>(max_n, (int64_t)lg.size()); ++k) {
+        if (t_switch) t_switch[k] = lg[(size_t)k].t_switch;
+        if (t_next) t_next[k] = lg[(size_t)k].t_next;
+        if (estimate) estimate[k] = lg[(size_t)k].estimate;
+        if (taken) taken[k] = lg[(size_t)k].taken;
+    }
+    *n = (int64_t)lg.size();
+    return GSBS_OK;
 }
 
 int gsbs_sync(gsbs_ctx* c) {
@@ -1399,6 +1705,7 @@ struct Reader {
 
 int gsbs_save(gsbs_ctx* c, void* buf, int64_t cap, int64_t* size) {
     if (!c || !size || cap < 0 || (cap > 0 && !buf)) return fail(GSBS_EINVAL, "bad checkpoint arguments");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
     HIPCHK(hipStreamSynchronize(c->st));
     Writer w;
@@ -1472,11 +1779,27 @@ int gsbs_save(gsbs_ctx* c, void* buf, int64_t cap, int64_t* size) {
     return GSBS_OK;
 }
 
+// Molecule record of a checkpoint: finite position inside its cube, instance
+// field below n_inst, species below ns (or the removed flag).
+static bool valid_record(const float4& p, const std::vector<InstHost>& inst, int ns, int* out_inst, int* out_sp) {
+    int meta;
+    std::memcpy(&meta, &p.w, 4);
+    const int q = meta >> 8, sp = meta & 0xFF;
+    if (q < 0 || q >= (int)inst.size() || (sp >= ns && sp != kDead)) return false;
+    const float hL = 0.5f * (float)inst[(size_t)q].L;
+    for (float x : {p.x, p.y, p.z})
+        if (!(x >= -hL && x < hL)) return false;
+    *out_inst = q;
+    *out_sp = sp;
+    return true;
+}
+
 int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
     if (!c || !buf || size <= 0) return fail(GSBS_EINVAL, "bad checkpoint arguments");
     Reader r{static_cast<const char*>(buf), (size_t)size};
     if (r.get<uint64_t>() != kCkptMagic || !r.ok) return fail(GSBS_EINVAL, "not a checkpoint");
     if (r.get<int32_t>() != c->n_inst) return fail(GSBS_EINVAL, "checkpoint of another number of instances");
+    // 1. parse and check everything on the host; the context is not touched
     const uint64_t seed = r.get<uint64_t>();
     const gsbs_params prm = r.get<gsbs_params>();
     const std::vector<double> D = r.vec<double>(kMaxSpecies);
@@ -1486,6 +1809,7 @@ int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
     const int64_t steps = r.get<int64_t>(), max_live = r.get<int64_t>();
     const std::vector<int64_t> injected = r.vec<int64_t>((size_t)c->n_inst);
     if (!r.ok || D.empty() || injected.size() != (size_t)c->n_inst) return fail(GSBS_EINVAL, "truncated checkpoint");
+    const int ns = (int)D.size();
     std::vector<InstHost> inst((size_t)c->n_inst);
     struct PendingHost {
         double t, edep;
@@ -1512,16 +1836,30 @@ int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
         const uint64_t np = r.get<uint64_t>();
         if (!r.ok || np > (1u << 24)) return fail(GSBS_EINVAL, "truncated checkpoint");
         if (in.L != c->inst[(size_t)i].L) return fail(GSBS_EINVAL, "checkpoint of another box");
+        if (!std::isfinite(in.t) || in.t < 0 || !std::isfinite(in.edep) || in.rec_done.size() != in.rec_t.size() ||
+            in.rec_edep.size() != in.rec_t.size() || !std::is_sorted(in.anchors.begin(), in.anchors.end()))
+            return fail(GSBS_EINVAL, "inconsistent instance in the checkpoint");
+        for (size_t k = 1; k < in.rec_t.size(); ++k)
+            if (!(in.rec_t[k] > in.rec_t[k - 1])) return fail(GSBS_EINVAL, "record times must increase");
+        const float hL = 0.5f * (float)in.L;
         for (uint64_t k = 0; k < np && r.ok; ++k) {
             PendingHost q;
             q.t = r.get<double>();
             q.n = r.get<int64_t>();
             q.edep = r.get<double>();
             if (!r.ok || q.n < 0 || (size_t)q.n > r.n) return fail(GSBS_EINVAL, "truncated checkpoint");
+            if (!(q.t >= in.t) || !std::isfinite(q.t)) return fail(GSBS_EINVAL, "queued injection before the present");
             q.xyz.resize((size_t)q.n * 3);
             q.sp.resize((size_t)q.n);
             r.raw(q.xyz.data(), sizeof(float) * q.xyz.size());
             r.raw(q.sp.data(), q.sp.size());
+            for (int64_t m = 0; m < q.n && r.ok; ++m) {
+                if (q.sp[(size_t)m] >= ns) return fail(GSBS_EINVAL, "queued molecule of an unknown species");
+                for (int a = 0; a < 3; ++a) {
+                    const float x = q.xyz[(size_t)m * 3 + a];
+                    if (!(x >= -hL && x < hL)) return fail(GSBS_EINVAL, "queued molecule outside its cube");
+                }
+            }
             pend[(size_t)i].push_back(std::move(q));
         }
     }
@@ -1536,7 +1874,54 @@ int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
         cnt.size() != (size_t)c->n_inst * kMaxSpecies || ms.size() != (size_t)c->n_inst || max_rec < 0 ||
         rec.size() != (size_t)c->n_inst * (size_t)max_rec * kMaxSpecies)
         return fail(GSBS_EINVAL, "inconsistent checkpoint");
-    // chemistry and parameters through the setters (they validate and rebuild the tables)
+    if (h.err != 0 || h.n_live < 0 || h.n_live > h.n_in) return fail(GSBS_EINVAL, "checkpoint of a failed context");
+    // every record holds a known species of a known instance inside its cube, and
+    // the species counts are those of the live records
+    std::vector<long long> tally((size_t)c->n_inst * kMaxSpecies, 0);
+    for (const float4& p : pos) {
+        int q = 0, sp = 0;
+        if (!valid_record(p, inst, ns, &q, &sp)) return fail(GSBS_EINVAL, "checkpoint record out of range");
+        if (sp != kDead) tally[(size_t)q * kMaxSpecies + sp]++;
+    }
+    if (tally != cnt) return fail(GSBS_EINVAL, "checkpoint counts differ from its molecules");
+    for (size_t i = 0; i < (size_t)c->n_inst; ++i)
+        for (size_t k = 0; k < inst[i].rec_t.size() && k < (size_t)max_rec; ++k)
+            for (int sp = 0; sp < kMaxSpecies; ++sp)
+                if (rec[(i * (size_t)max_rec + k) * kMaxSpecies + sp] < -1)
+                    return fail(GSBS_EINVAL, "checkpoint records out of range");
+    // 2. device buffers of the new state, before anything of the old one is freed
+    int64_t need = (int64_t)pos.size();
+    for (int i = 0; i < c->n_inst; ++i)
+        for (const PendingHost& q : pend[(size_t)i]) need += q.n;
+    std::vector<std::vector<Pending>> npend((size_t)c->n_inst);
+    long long* nrec = nullptr;
+    auto release_new = [&]() {
+        for (auto& v : npend)
+            for (auto& p : v) {
+                dfree(p.d_xyz);
+                dfree(p.d_sp);
+            }
+        dfree(nrec);
+    };
+    int rc = GSBS_OK;
+    for (int i = 0; i < c->n_inst && rc == GSBS_OK; ++i)
+        for (const PendingHost& q : pend[(size_t)i]) {
+            Pending p{q.t, q.n, nullptr, nullptr, q.edep};
+            if (q.n > 0 && ((rc = dalloc(&p.d_xyz, (size_t)q.n * 3)) != GSBS_OK ||
+                            (rc = dalloc(&p.d_sp, (size_t)q.n)) != GSBS_OK)) {
+                npend[(size_t)i].push_back(p);
+                break;
+            }
+            npend[(size_t)i].push_back(p);
+        }
+    if (rc == GSBS_OK && max_rec > c->max_rec) rc = dalloc(&nrec, rec.size());
+    if (rc == GSBS_OK) rc = ensure_capacity(c, need + need / 2 + 1024);  // keeps the old molecules if it fails
+    if (rc != GSBS_OK) {
+        release_new();
+        return rc;
+    }
+    // 3. apply; a failure from here on leaves the context unusable until a load succeeds
+    c->broken = true;
     CHK(gsbs_set_species(c, (int32_t)D.size(), D.data()));
     CHK(gsbs_set_params(c, &prm));
     CHK(gsbs_set_reactions(c, (int32_t)rx.size(), rx.data()));
@@ -1544,34 +1929,29 @@ int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
     CHK(gsbs_set_first_order(c, (int32_t)fo.size(), fo.data()));
     c->seed = seed;
     HIPCHK(hipStreamSynchronize(c->st));
+    for (int i = 0; i < c->n_inst; ++i) {
+        for (size_t k = 0; k < pend[(size_t)i].size(); ++k) {
+            const PendingHost& q = pend[(size_t)i][k];
+            const Pending& p = npend[(size_t)i][k];
+            if (q.n > 0) {
+                HIPCHK(hipMemcpy(p.d_xyz, q.xyz.data(), sizeof(float) * q.xyz.size(), hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(p.d_sp, q.sp.data(), q.sp.size(), hipMemcpyHostToDevice));
+            }
+        }
+    }
     for (auto& in : c->inst)
         for (auto& q : in.pending) {
             dfree(q.d_xyz);
             dfree(q.d_sp);
         }
-    int64_t need = (int64_t)pos.size();
-    for (int i = 0; i < c->n_inst; ++i)
-        for (const PendingHost& q : pend[(size_t)i]) need += q.n;
-    CHK(ensure_capacity(c, need + need / 2 + 1024));
     for (int i = 0; i < c->n_inst; ++i) {
         InstHost& in = c->inst[(size_t)i];
         in = inst[(size_t)i];
-        for (const PendingHost& q : pend[(size_t)i]) {
-            Pending p{q.t, q.n, nullptr, nullptr, q.edep};
-            if (q.n > 0) {
-                CHK(dalloc(&p.d_xyz, (size_t)q.n * 3));
-                CHK(dalloc(&p.d_sp, (size_t)q.n));
-                HIPCHK(hipMemcpy(p.d_xyz, q.xyz.data(), sizeof(float) * q.xyz.size(), hipMemcpyHostToDevice));
-                HIPCHK(hipMemcpy(p.d_sp, q.sp.data(), q.sp.size(), hipMemcpyHostToDevice));
-            }
-            in.pending.push_back(p);
-        }
+        in.pending = npend[(size_t)i];
     }
-    if (max_rec > c->max_rec) {
-        long long* nr = nullptr;
-        CHK(dalloc(&nr, rec.size()));
+    if (nrec) {
         dfree(c->rec);
-        c->rec = nr;
+        c->rec = nrec;
     }
     c->max_rec = max_rec;
     if (!rec.empty()) HIPCHK(hipMemcpy(c->rec, rec.data(), sizeof(long long) * rec.size(), hipMemcpyHostToDevice));
@@ -1585,11 +1965,13 @@ int gsbs_load(gsbs_ctx* c, const void* buf, int64_t size) {
     c->steps = steps;
     c->max_live = max_live;
     c->injected = injected;
+    c->broken = false;
     return GSBS_OK;
 }
 
 int gsbs_get_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
     if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     const InstHost& in = c->inst[i];
     if (in.rec_t.empty()) return GSBS_OK;
     std::vector<long long> buf((size_t)c->max_rec * kMaxSpecies);
@@ -1617,6 +1999,7 @@ int gsbs_get_gvalues(gsbs_ctx* c, int32_t i, double* out) {
 
 int gsbs_get_current_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
     if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     std::vector<long long> buf(kMaxSpecies);
     HIPCHK(hipMemcpyAsync(buf.data(), c->counts + (size_t)i * kMaxSpecies, sizeof(long long) * kMaxSpecies,
                           hipMemcpyDeviceToHost, c->st));
@@ -1627,8 +2010,6 @@ int gsbs_get_current_counts(gsbs_ctx* c, int32_t i, int64_t* out) {
 
 // ------------------------------------------------------------ surrogate ---
 namespace {
-
-constexpr int kFeatures = 7 + 9 * kSurBins + 1;
 
 // Reference subsample, pair-correlation shell counts and shell volumes of
 // instance i (device), for the current state.
@@ -1693,6 +2074,7 @@ int sur_pair_counts(gsbs_ctx* c, int i, double r_max, int n_ref_max, std::vector
 int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, int32_t n_ref_max, double c_floor_M,
                   const float* mu, const float* sd, float* out, int32_t out_is_device) {
     if (!c || !out || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad instance");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     if (!c->chem_ready || c->ns != 7 || c->rx.size() != 9)
         return fail(GSBS_ESTATE, "features are defined for 7 species and 9 reactions");
     if (!(dt_next_ns > 0) || !(r_max_nm > 0) || n_ref_max < 1 || !(c_floor_M > 0))
@@ -1722,17 +2104,16 @@ int gsbs_features(gsbs_ctx* c, int32_t i, double dt_next_ns, double r_max_nm, in
     return check_device_errors(c);
 }
 
-int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
-                 double rtol, int32_t* steps, int32_t on_device) {
-    if (!c || n < 0 || (n > 0 && (!c0 || !dt_ns || !c1)) || !(rtol > 0.0) || rtol > 0.1)
-        return fail(GSBS_EINVAL, "bad rate-equation arguments");
-    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
-    if (n_species != c->ns) return fail(GSBS_EINVAL, "rate equations: n_species is not the table's");
-    if (c->ns > kOdeMaxSpecies) return fail(GSBS_EINVAL, "the rate equations take at most 8 species");
-    if (c->rx.size() + c->fo.size() > (size_t)kMaxReactions)
-        return fail(GSBS_EINVAL, "the rate equations take at most 32 reactions and channels");
-    if (n == 0) return GSBS_OK;
-    OdeTable tb{};
+int gsbs_pair_corr(gsbs_ctx* c, int32_t i, double r_max_nm, int32_t n_ref_max, float* out) {
+    if (!c || !out) return fail(GSBS_EINVAL, "null");
+    std::vector<float> row(kFeatures);
+    CHK(gsbs_features(c, i, 1.0, r_max_nm, n_ref_max, 1e-10, nullptr, nullptr, row.data(), 0));
+    std::copy(row.begin() + 7, row.begin() + 7 + 9 * kSurBins, out);
+    return GSBS_OK;
+}
+
+// Reaction table of the rate equations (see gsbs_numodes).
+static void build_ode_table(const gsbs_ctx* c, OdeTable& tb) {
     tb.ns = c->ns;
     tb.nr = (int32_t)c->rx.size();
     for (int r = 0; r < tb.nr; ++r) {
@@ -1755,6 +2136,27 @@ int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, co
     }
     for (const gsbs_source& q : c->src)
         for (int k = 0; k < q.n_products; ++k) tb.src[q.products[k]] += q.rate_M_per_ns;
+}
+
+// Checks shared by the two rate-equation entry points.
+static int numodes_args(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns,
+                        double* c1, double rtol) {
+    if (!c || n < 0 || (n > 0 && (!c0 || !dt_ns || !c1)) || !(rtol > 0.0) || rtol > 0.1)
+        return fail(GSBS_EINVAL, "bad rate-equation arguments");
+    if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
+    if (n_species != c->ns) return fail(GSBS_EINVAL, "rate equations: n_species is not the table's");
+    if (c->ns > kOdeMaxSpecies) return fail(GSBS_EINVAL, "the rate equations take at most 8 species");
+    if (c->rx.size() + c->fo.size() > (size_t)kMaxReactions)
+        return fail(GSBS_EINVAL, "the rate equations take at most 32 reactions and channels");
+    return GSBS_OK;
+}
+
+int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
+                 double rtol, int32_t* steps, int32_t on_device) {
+    CHK(numodes_args(c, n, n_species, c0, dt_ns, c1, rtol));
+    if (n == 0) return GSBS_OK;
+    OdeTable tb{};
+    build_ode_table(c, tb);
     const size_t nc = (size_t)n * (size_t)c->ns;
     double *d0 = nullptr, *dd = nullptr, *d1 = nullptr;
     int32_t* dsteps = nullptr;
@@ -1899,6 +2301,7 @@ int gsbs_ssa(gsbs_ctx* c, int32_t n, int32_t n_species, const int32_t* n0, const
 int gsbs_repopulate(gsbs_ctx* c, int32_t i, double t_new, const float* y, int32_t y_is_device, const float* mu_y,
                     const float* sd_y, double c_floor_M, int32_t relative) {
     if (!c || !y || !mu_y || !sd_y || i < 0 || i >= c->n_inst) return fail(GSBS_EINVAL, "bad arguments");
+    if (c->broken) return fail(GSBS_ESTATE, kBroken);
     if (!c->chem_ready) return fail(GSBS_ESTATE, "set species and reactions first");
     InstHost& in = c->inst[i];
     if (!(t_new >= in.t)) return fail(GSBS_ESTATE, "re-population before the instance's present time");
@@ -1978,6 +2381,23 @@ int gsbs_get_stats(gsbs_ctx* c, gsbs_stats* out) {
     return GSBS_OK;
 }
 
+int gsbs_get_device_bytes(gsbs_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return fail(GSBS_EINVAL, "null");
+    int64_t b = 0;
+    const int64_t cap = c->cap;
+    b += 2 * cap * (int64_t)(sizeof(float4) + sizeof(uint64_t));                       // pos, uid (ping-pong)
+    b += cap * (int64_t)(sizeof(float4) + sizeof(uint2) + sizeof(unsigned long long) + sizeof(int32_t) +
+                         2 * sizeof(float4));                                           // pos0, cellrank, claim, mate, x0, xnew
+    b += (int64_t)(c->cell_cap + 1) * 2 * (int64_t)sizeof(uint32_t) +
+         (int64_t)(c->cell_cap / 4096 + 2) * (int64_t)sizeof(unsigned long long);       // cells, scan status
+    b += (int64_t)c->pair_cap * (int64_t)sizeof(PairRec);
+    b += (int64_t)c->n_inst * c->max_rec * kMaxSpecies * (int64_t)sizeof(long long);
+    for (const auto& in : c->inst)
+        for (const auto& p : in.pending) b += p.n * (int64_t)(3 * sizeof(float) + 1);
+    *bytes = b;
+    return GSBS_OK;
+}
+
 int gsbs_set_profiling(gsbs_ctx* c, int32_t on) {
     if (!c) return fail(GSBS_EINVAL, "null");
     if (on && !c->prof_ev[0])
@@ -2048,9 +2468,46 @@ int gsbs_get_step_log(gsbs_ctx* c, int64_t max_n, int64_t* step, double* ms, int
     return GSBS_OK;
 }
 
+int gsbs_set_live_timing(gsbs_ctx* c, uint32_t kernel_mask) {
+    if (!c || (kernel_mask >> kStepKernels) != 0u) return fail(GSBS_EINVAL, "kernel mask: bits 0..5");
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int b = 0; b < 2; ++b) CHK(live_harvest(c, b));
+    if (kernel_mask && c->live_ev[0].empty()) {
+        for (int b = 0; b < 2; ++b) {
+            c->live_ev[b].assign((size_t)kChunk * (kStepKernels + 1), nullptr);
+            for (auto& e : c->live_ev[b]) HIPCHK(hipEventCreate(&e));
+            HIPCHK(hipEventCreateWithFlags(&c->live_done[b], hipEventDisableTiming));
+        }
+    }
+    c->live_mask = kernel_mask;
+    c->live_bins = 0;
+    for (int k = 0; k < kStepKernels; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+        c->prof_work[k] = 0;
+        c->prof_cnd[k] = 0;
+    }
+    return read_counters(c, &c->live_base);
+}
+
 int gsbs_get_profile(gsbs_ctx* c, int32_t max_k, char* names, double* total_ms, int64_t* launches, int64_t* work,
                      int64_t* candidates, int32_t* n) {
     if (!c || !n) return fail(GSBS_EINVAL, "null");
+    if (c->live_mask && !c->profiling) {
+        // work units of the live-timed steps from the device's cumulative counters
+        DevCounters h{};
+        CHK(read_counters(c, &h));
+        const int64_t all = (int64_t)(h.msteps_mode[0] + h.msteps_mode[1]) -
+                            (int64_t)(c->live_base.msteps_mode[0] + c->live_base.msteps_mode[1]);
+        const int64_t whole = (int64_t)(h.msteps_mode[0] - c->live_base.msteps_mode[0]);
+        const int64_t sp = (int64_t)(h.msteps_mode[1] - c->live_base.msteps_mode[1]);
+        const int64_t csp = (int64_t)(h.cand_sp - c->live_base.cand_sp);
+        const int64_t call = (int64_t)(h.cand - c->live_base.cand);
+        for (int k = 0; k < kStepKernels; ++k) {
+            c->prof_work[k] = k == 1 ? c->live_bins : (k == 3 ? whole : (k == 4 ? sp : all));
+            c->prof_cnd[k] = k == 3 ? call - csp : (k == 4 ? csp : 0);
+        }
+    }
     for (int k = 0; k < std::min(max_k, kStepKernels); ++k) {
         if (names) {
             std::memset(names + 32 * k, 0, 32);
@@ -2186,6 +2643,7 @@ int gsbs_debug_step(gsbs_ctx* c, double dt, int32_t flags, const float* xyz0, in
     if (flags & kStepWholeCells) gc.by_species = 0;
     S[0].bin_base = 0;
     const int32_t ncell = fill_grid(c, in.sp_est, in.L, in.n_est, rcmax, gc, nc_force, S[0]);
+    assign_splits(c, S, 1);
     S[0].unit_base = 0;
     const int32_t units = (int32_t)units_of(S[0], c->ns);
     const int32_t cells = S[0].by_species ? ncell * c->ns : ncell;

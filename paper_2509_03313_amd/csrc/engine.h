@@ -96,7 +96,7 @@ struct alignas(16) InstStep {
     int32_t active;                // 1: this instance takes a step now
     int32_t by_species;            // 1: search partner-species bins, 0: whole cells
     int32_t unit_base;             // species-bin search: first global work item of this instance
-    int32_t nsplit;                // species-bin search: work items (stream slices) per A box
+    int32_t pad1;
     int32_t pad0;
     // species-bin search: partner species searched from each species (the more
     // abundant side of every pair), A-box size in cells of each species
@@ -105,6 +105,10 @@ struct alignas(16) InstStep {
     uint32_t pm_dir[kMaxSpecies];
     int32_t kdim_sp[kMaxSpecies];
     int32_t unit_off_sp[kMaxSpecies + 4];
+    // species-bin search: work items (stream slices) per A box of each species,
+    // and (host planning only) the partner molecules a box of that species streams
+    int32_t nsplit_sp[kMaxSpecies];
+    float work_sp[kMaxSpecies];
     uint64_t step;                 // Philox step counter word
     uint64_t key0, key1;           // Philox key (seed, instance)
     double fo_p[kMaxSpecies];      // first-order conversion probability 1 - exp(-k dt) per species
@@ -127,7 +131,11 @@ struct DevCounters {
     uint32_t err;              // bit0 molecule overflow, bit1 pair overflow, bit2 key tie
     unsigned long long cand;   // candidate pairs tested (cumulative)
     unsigned long long reactions;
-    unsigned long long pad[4];
+    // molecule-steps of the instances stepped with the whole-cell / species-bin
+    // search (cumulative), and the species-bin search's share of cand
+    unsigned long long msteps_mode[2];
+    unsigned long long cand_sp;
+    unsigned long long pad;
 };
 
 constexpr uint32_t kErrMolOverflow = 1u;
@@ -171,9 +179,12 @@ void launch_inject(hipStream_t st, float4* pos, uint64_t* uid, long long* counts
 // Kernels of one step, in launch order; ev (optional) holds 2 events per kernel.
 constexpr int kStepKernels = 6;
 extern const char* const kStepKernelNames[kStepKernels];
+// ev_mask: bit k set records the two events of kernel slot k (ev[2k], ev[2k+1]);
+// with kEvChain set, ev[0 .. kStepKernels] mark the boundaries between the slots.
+constexpr uint32_t kEvChain = 0x80000000u;
 void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const ChemDev* chem,
                  int32_t n_inst, int32_t total_bins, int32_t total_units, int32_t n_species, int32_t grid,
-                 int32_t flags, hipEvent_t* ev = nullptr);
+                 int32_t flags, hipEvent_t* ev = nullptr, uint32_t ev_mask = 0xFFFFFFFFu);
 // bins up to which k_bin counts in an LDS histogram (larger grids use global atomics)
 constexpr int32_t kLdsBins = 12288;
 void launch_record(hipStream_t st, const long long* counts, long long* rec, int32_t max_rec,
@@ -210,6 +221,7 @@ void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const doub
                 long long max_events);
 void launch_numodes(hipStream_t st, const double* c0, const double* dt, double* c1, int32_t* steps, int32_t n,
                     const OdeTable& tb, double rtol, double atol, int32_t max_steps);
+
 void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,
                   int n_new, int inst, uint64_t uid_base, uint64_t seed, uint64_t step, float L, int cap,
                   long long* counts, int grid);

@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
         while (si + 1 < ns && S.unit_off_sp[si + 1] <= lu) ++si;
         const uint32_t pm = S.pm_dir[si];
         if (pm == 0u) continue;
-        const int nc = S.nc, nsplit = S.nsplit;
+        const int nc = S.nc, nsplit = S.nsplit_sp[si];
         const int kx = S.kdim_sp[si] & 0xFF, ky = (S.kdim_sp[si] >> 8) & 0xFF, kz = (S.kdim_sp[si] >> 16) & 0xFF;
         const int nbx = (nc + kx - 1) / kx, nby = (nc + ky - 1) / ky, nbz = (nc + kz - 1) / kz;
         const int r = lu - S.unit_off_sp[si];
@@ -1407,7 +1407,10 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
     if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
     __syncthreads();
-    if (threadIdx.x == 0 && s_cand) atomicAdd(&ctr->cand, s_cand);
+    if (threadIdx.x == 0 && s_cand) {
+        atomicAdd(&ctr->cand, s_cand);
+        atomicAdd(&ctr->cand_sp, s_cand);
+    }
 }
 
 // --------------------------------------------------------------- react ---
@@ -1517,12 +1520,16 @@ __global__ __launch_bounds__(kReactBlock) void k_react(float4* __restrict__ pos,
     __shared__ int ht_mate[kReactHash];
     const int tid = threadIdx.x;
     // molecule-steps of the instances that stepped (counts before this step's reactions)
+    unsigned long long mm[2] = {0ull, 0ull};
     for (int t = tid; t < n_inst; t += kReactBlock) {
         if (!P[t].active) continue;
         long long s = 0;
         for (int k = 0; k < chem->n_species; ++k) s += counts[t * kMaxSpecies + k];
         msteps[t] += (unsigned long long)s;
+        mm[P[t].by_species ? 1 : 0] += (unsigned long long)s;
     }
+    if (mm[0]) atomicAdd(&ctr->msteps_mode[0], mm[0]);
+    if (mm[1]) atomicAdd(&ctr->msteps_mode[1], mm[1]);
     const uint32_t np_raw = ctr->n_pairs;
     const int np = (int)(np_raw < pair_cap ? np_raw : pair_cap);
     const int n_live = ctr->n_live;
@@ -1741,12 +1748,21 @@ const char* const kStepKernelNames[kStepKernels] = {"k_bin", "k_scan", "k_scatte
 
 void launch_step(hipStream_t st, const StepBuffers& b, const InstStep* P, const ChemDev* chem,
                  int32_t n_inst, int32_t total_bins, int32_t total_units, int32_t ns, int32_t grid, int32_t flags,
-                 hipEvent_t* ev) {
+                 hipEvent_t* ev, uint32_t ev_mask) {
     const int fixed = (flags & kStepFixed) ? 1 : 0;
     const int nb = (total_bins + kScanTile - 1) / kScanTile;
-    // every kernel slot gets its two events, also when the kernel is not launched
+    // every kernel slot in the mask gets its two events, also when the kernel is not
+    // launched; with kEvChain, ev[k] marks the start of slot k and ev[kStepKernels]
+    // the end of the last one (one event per boundary)
+    const bool chain = (ev_mask & kEvChain) != 0u;
     auto mark = [&](int slot, int end) {
-        if (ev) (void)hipEventRecord(ev[2 * slot + end], st);
+        if (!ev) return;
+        if (chain) {
+            if (end == 0) (void)hipEventRecord(ev[slot], st);
+            else if (slot == kStepKernels - 1) (void)hipEventRecord(ev[kStepKernels], st);
+            return;
+        }
+        if ((ev_mask >> slot) & 1u) (void)hipEventRecord(ev[2 * slot + end], st);
     };
     mark(0, 0);
     if (total_bins <= kLdsBins) {

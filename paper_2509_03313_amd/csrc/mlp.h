@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct gsbs_mlp;
+
 namespace gsbs {
 
 // Architecture: 296 inputs, four hidden layers of 256 (GELU), 7 outputs.
@@ -26,5 +28,8 @@ void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db);
 void mlp_adam(hipStream_t st, float* w, float* m1, float* m2, const float* grad, int64_t n, int rows, int cols,
               float lr, float beta1, float beta2, float eps, float c1, float c2, uint16_t* wb, uint16_t* wbt);
 void mlp_cast(hipStream_t st, const float* w, int64_t n, int rows, int cols, uint16_t* wb, uint16_t* wbt);
+
+// Forward pass of x[batch][296] (device) into y[batch][7] (device), synchronised.
+int mlp_forward_sync(gsbs_mlp* m, const float* x, int batch, float* y);
 
 }  // namespace gsbs

@@ -222,6 +222,14 @@ int gsbs_mlp_forward(gsbs_mlp* m, const float* x, int32_t batch, float* y) {
     return forward(m, x, batch, y);
 }
 
+// Forward pass for the surrogate hand-over of gsbs_advance_to: x, y device
+// arrays; returns once y is written.
+extern "C++" int gsbs::mlp_forward_sync(gsbs_mlp* m, const float* x, int batch, float* y) {
+    MCHK(gsbs_mlp_forward(m, x, batch, y));
+    MHIP(hipStreamSynchronize(m->st));
+    return GSBS_OK;
+}
+
 int gsbs_mlp_get_activation(gsbs_mlp* m, int32_t layer, int32_t batch, float* out) {
     if (!m || !out) return set_error(GSBS_EINVAL, "null");
     if (layer < 0 || layer >= kMlpLayers || batch < 1 || batch > m->max_batch)

@@ -88,7 +88,10 @@ _SIGS = {
     "gsbs_get_dt_max": [_vp, _i32, _P(_d)],
     "gsbs_inject": [_vp, _i32, _d, _i64, _vp, _vp, _d, _i32],
     "gsbs_set_records": [_vp, _i32, _i32, _P(_d)],
-    "gsbs_advance_to": [_vp, _P(_d)],
+    "gsbs_advance_to": [_vp, _P(_d), _i32],
+    "gsbs_set_surrogate": [_vp, _vp, _vp],
+    "gsbs_get_handover_log": [_vp, _i32, _i64, _P(_d), _P(_d), _P(_d), _P(_i32), _P(_i64)],
+    "gsbs_pair_corr": [_vp, _i32, _d, _i32, _P(C.c_float)],
     "gsbs_sync": [_vp],
     "gsbs_get_counts": [_vp, _i32, _P(_i64)],
     "gsbs_get_gvalues": [_vp, _i32, _P(_d)],
@@ -99,6 +102,8 @@ _SIGS = {
     "gsbs_get_step_log": [_vp, _i64, _P(_i64), _P(_d), _P(_i32), _P(_i64), _P(_i64)],
     "gsbs_get_tuning": [_i32, _P(_i32), _P(_i32), _P(_d), _P(_i32)],
     "gsbs_set_profiling": [_vp, _i32],
+    "gsbs_set_live_timing": [_vp, C.c_uint32],
+    "gsbs_get_device_bytes": [_vp, _P(_i64)],
     "gsbs_get_profile": [_vp, _i32, C.c_char_p, _P(_d), _P(_i64), _P(_i64), _P(_i64), _P(_i32)],
     "gsbs_plan_schedule": [_d, _d, _i32, _P(_d), _i32, _P(_d), _d, _d, _d, _P(_d), _i64, _P(_i64)],
     "gsbs_debug_get_state": [_vp, _i32, _i64, _P(C.c_float), _P(C.c_uint8), _P(_u64), _P(_i64)],
@@ -226,9 +231,65 @@ def gsbs_set_records(ctx, inst, times):
     _chk(_lib.gsbs_set_records(ctx, inst, len(t), _ptr(t, _d)))
 
 
-def gsbs_advance_to(ctx, targets):
+GSBS_PLAIN, GSBS_SURROGATE = 0, 1
+
+
+def gsbs_advance_to(ctx, targets, mode=GSBS_PLAIN):
     t = np.ascontiguousarray(targets, dtype=np.float64)
-    _chk(_lib.gsbs_advance_to(ctx, _ptr(t, _d)))
+    _chk(_lib.gsbs_advance_to(ctx, _ptr(t, _d), int(mode)))
+
+
+class gsbs_surrogate(C.Structure):
+    _fields_ = [("settle_ns", C.c_double), ("min_gap_ns", C.c_double), ("tol", C.c_double), ("budget", C.c_double),
+                ("guard_margin", C.c_double), ("r_max_nm", C.c_double), ("c_floor_M", C.c_double),
+                ("n_ref_max", C.c_int32), ("n_dt", C.c_int32), ("n_c", C.c_int32), ("reserved", C.c_int32),
+                ("mu", _vp), ("sd", _vp), ("lo", _vp), ("hi", _vp), ("mu_y", _vp), ("sd_y", _vp),
+                ("dt_edges", _vp), ("c_edges", _vp), ("table", _vp)]
+
+
+def gsbs_set_surrogate(ctx, net_handle, mu=None, sd=None, mu_y=None, sd_y=None, dt_edges=None, c_edges=None,
+                       table=None, lo=None, hi=None, settle_ns=1000.0, min_gap_ns=0.0, tol=0.01, budget=0.0,
+                       guard_margin=0.1, r_max_nm=200.0, c_floor_M=1e-10, n_ref_max=1024):
+    """Set (net_handle not None) or clear the surrogate hand-over of a context
+    (see gsbs_surrogate in gsbs.h).  Arrays are host arrays, copied."""
+    if net_handle is None:
+        _chk(_lib.gsbs_set_surrogate(ctx, None, None))
+        return
+    keep = []
+
+    def arr(a, t):
+        if a is None:
+            return None
+        v = np.ascontiguousarray(a, dtype=t)
+        keep.append(v)
+        return v.ctypes.data_as(_vp)
+
+    tb = np.ascontiguousarray(table, dtype=np.float64)
+    q = gsbs_surrogate(settle_ns, min_gap_ns, tol, budget, guard_margin, r_max_nm, c_floor_M, n_ref_max,
+                       tb.shape[0], tb.shape[1], 0, arr(mu, np.float32), arr(sd, np.float32), arr(lo, np.float32),
+                       arr(hi, np.float32), arr(mu_y, np.float32), arr(sd_y, np.float32), arr(dt_edges, np.float64),
+                       arr(c_edges, np.float64), arr(tb, np.float64))
+    _chk(_lib.gsbs_set_surrogate(ctx, net_handle, C.byref(q)))
+
+
+def gsbs_get_handover_log(ctx, inst):
+    """Hand-over points of an instance: dict of arrays t_switch, t_next, estimate, taken."""
+    n = _i64()
+    _chk(_lib.gsbs_get_handover_log(ctx, inst, 0, None, None, None, None, C.byref(n)))
+    m = max(n.value, 1)
+    ts, tn, es = np.zeros(m), np.zeros(m), np.zeros(m)
+    tk = np.zeros(m, dtype=np.int32)
+    _chk(_lib.gsbs_get_handover_log(ctx, inst, m, _ptr(ts, _d), _ptr(tn, _d), _ptr(es, _d), _ptr(tk, _i32),
+                                    C.byref(n)))
+    k = n.value
+    return dict(t_switch=ts[:k], t_next=tn[:k], estimate=es[:k], taken=tk[:k].astype(bool))
+
+
+def gsbs_pair_corr(ctx, inst, r_max_nm=200.0, n_ref_max=1024):
+    """Pair-correlation function [9][32] of instance inst (see gsbs_features)."""
+    out = np.zeros((9, 32), dtype=np.float32)
+    _chk(_lib.gsbs_pair_corr(ctx, inst, float(r_max_nm), int(n_ref_max), _ptr(out, C.c_float)))
+    return out
 
 
 def gsbs_sync(ctx):
@@ -301,6 +362,23 @@ def gsbs_get_tuning():
 
 def gsbs_set_profiling(ctx, on: bool):
     _chk(_lib.gsbs_set_profiling(ctx, 1 if on else 0))
+
+
+KERNEL_SLOTS = ("k_bin", "k_scan", "k_scatter", "k_pairs", "k_pairs_sp", "k_react")
+
+
+def gsbs_set_live_timing(ctx, kernels=()):
+    """Live per-kernel timing of the named kernels (see KERNEL_SLOTS); () turns it off."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << KERNEL_SLOTS.index(k)
+    _chk(_lib.gsbs_set_live_timing(ctx, mask))
+
+
+def gsbs_get_device_bytes(ctx) -> int:
+    v = _i64()
+    _chk(_lib.gsbs_get_device_bytes(ctx, C.byref(v)))
+    return v.value
 
 
 def gsbs_get_profile(ctx):
@@ -435,9 +513,9 @@ class Engine:
         self.records[inst] = np.asarray(times, dtype=np.float64)
         gsbs_set_records(self.ctx, inst, self.records[inst])
 
-    def advance_to(self, t):
+    def advance_to(self, t, mode=GSBS_PLAIN):
         tt = np.full(self.n_inst, float(t)) if np.ndim(t) == 0 else np.asarray(t, dtype=np.float64)
-        gsbs_advance_to(self.ctx, tt)
+        gsbs_advance_to(self.ctx, tt, mode)
 
     def counts(self, inst=0):
         return gsbs_get_counts(self.ctx, inst, len(self.records[inst]), self.ns)

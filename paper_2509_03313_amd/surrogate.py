@@ -63,9 +63,19 @@ class PulsePlan:
         return p * self.period
 
     def switch(self, p: int) -> float:
-        return self.start(p) + self.width + TAU_SETTLE
+        """Hand-over time after pulse p: the settle time after its last
+        injection (the library's rule, gsbs_advance_to)."""
+        self.injections()
+        return self._last.get(p, self.start(p)) + TAU_SETTLE
 
     def injections(self) -> List[W.Injection]:
+        if hasattr(self, "_inj"):
+            return self._inj
+        self._inj = self._make_injections()
+        return self._inj
+
+    def _make_injections(self) -> List[W.Injection]:
+        self._last = {}  # pulse -> time of its last injection
         rng = np.random.default_rng([self.seed, 7])
         n_tr = int(round(W.tracks_per_gray(self.L) * self.dose))
         out = []
@@ -79,6 +89,7 @@ class PulsePlan:
                 pos, sp = W.tracks_z(rng, self.L, k)
                 out.append(W.Injection(self.start(p) + b * self.width / self.n_batches, W._into_box(pos, self.L), sp,
                                        k * self.L * W.LET_KEV_PER_UM))
+                self._last[p] = out[-1].t
         return out
 
     def edep_until(self, t: float, inj: List[W.Injection]) -> float:
@@ -310,77 +321,85 @@ class Surrogate:
 
 
 # ------------------------------------------------------------ multi-pulse run ---
+def set_on(e: gsbs.Engine, surrogate: "Surrogate", tol: float = 0.01, budget: Optional[float] = None):
+    """Hand the surrogate to the library (gsbs_set_surrogate): normalisation
+    (calibration folded into the output centres), training range, error table."""
+    gsbs.gsbs_set_surrogate(e.ctx, surrogate.net.h, mu=surrogate.mu, sd=surrogate.sd, mu_y=surrogate.mu_out(),
+                            sd_y=surrogate.sd_y, dt_edges=surrogate.dt_edges, c_edges=surrogate.c_edges,
+                            table=surrogate.table, lo=surrogate.lo, hi=surrogate.hi, settle_ns=TAU_SETTLE, tol=tol,
+                            budget=budget or 0.0, r_max_nm=R_MAX, c_floor_M=C_FLOOR, n_ref_max=N_REF)
+
+
 def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01,
         budget: Optional[float] = None, numodes_rtol: Optional[float] = None) -> dict:
     """Plain (surrogate None) or hybrid multi-pulse run of one cube.  Returns
     the H2O2 count and G(H2O2) at every pulse start after the first and at the
     end, the wall time and the number of intervals the network took.
 
+    With a surrogate the whole run is one gsbs_advance_to in GSBS_SURROGATE
+    mode: the library stops each interval's hand-over point, applies the
+    error table, the input-range guard and the budget, and runs the network
+    and the re-population (see gsbs.h).  Records at the hand-over points and
+    at the pulse starts make those step ends in the plain run too, so both
+    runs follow the same trajectory up to the first interval the network takes.
+
     With numodes_rtol (and no surrogate) every interval goes to the rate
     equations instead (the paper's SBS + NumODEs alternation): the counts at
     the switch time become concentrations, gsbs_numodes carries them to the
-    next pulse start and the cube is re-populated homogeneously.
-
-    An interval goes to the network when its held-out error estimate is at most
-    tol.  With a budget, the estimates of the intervals the network takes are
-    also summed over the run and must stay within it: errors of consecutive
-    intervals add up in the state (H2O2 is long-lived), so the per-interval
-    rule alone does not bound the error of the run."""
+    next pulse start and the cube is re-populated homogeneously."""
     import torch
     inj = plan.injections()
     e = _engine(plan.L, seed)
     for j in inj:
         e.inject(0, j.t, j.xyz, j.species, j.edep_ev)
-    times, n_h2o2, g_h2o2, used, at_switch = [], [], [], [], []
+    n = plan.n_pulses
+    t_sw = [plan.switch(p) for p in range(n - 1)]
+    t_nx = [plan.start(p + 1) for p in range(n)]
+    rec = np.unique(np.array(t_sw + t_nx))
+    e.set_records(0, rec)
+    used = np.zeros(n, dtype=bool)
     spent = 0.0
-    row = torch.empty((1, gsbs.N_FEATURES), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for p in range(plan.n_pulses):
-        t_next = plan.start(p + 1)
-        took = False
-        if p + 1 < plan.n_pulses:
-            # both modes stop at the switch time, so that a plain and a hybrid run
-            # follow the same trajectory up to the first interval the network takes
-            ts = plan.switch(p)
-            e.advance_to(ts)
-            at_switch.append(e.current_counts(0))
-            if surrogate is None and numodes_rtol is not None:
-                conc = at_switch[-1].astype(np.float64) / (NA * plan.L ** 3 * 1e-24)
-                c1, _ = gsbs.gsbs_numodes(e.ctx, conc[None, :], [t_next - ts], rtol=numodes_rtol)
+    if surrogate is not None:
+        set_on(e, surrogate, tol, budget)
+        e.advance_to(t_nx[-1], gsbs.GSBS_SURROGATE)
+        lg = gsbs.gsbs_get_handover_log(e.ctx, 0)
+        for ts, tk, est in zip(lg["t_switch"], lg["taken"], lg["estimate"]):
+            p = int(np.argmin(np.abs(np.array(t_sw) - ts)))
+            used[p] = bool(tk)
+            spent += float(est) if tk else 0.0
+    elif numodes_rtol is not None:
+        for p in range(n):
+            if p + 1 < n:
+                e.advance_to(t_sw[p])
+                now = e.current_counts(0)
+                conc = now.astype(np.float64) / (NA * plan.L ** 3 * 1e-24)
+                c1, _ = gsbs.gsbs_numodes(e.ctx, conc[None, :], [t_nx[p] - t_sw[p]], rtol=numodes_rtol)
                 y = np.log10(np.maximum(c1[0], 0.0) + C_FLOOR).astype(np.float32)
-                gsbs.gsbs_repopulate(e.ctx, 0, t_next, y, np.zeros(len(y), np.float32),
+                gsbs.gsbs_repopulate(e.ctx, 0, t_nx[p], y, np.zeros(len(y), np.float32),
                                      np.ones(len(y), np.float32), C_FLOOR, relative=False)
-                took = True
-            if surrogate is not None:
-                gsbs.gsbs_features(e.ctx, 0, t_next - ts, R_MAX, N_REF, C_FLOOR, surrogate.mu, surrogate.sd,
-                                   out=row[0])
-                c_tot = float(np.sum(at_switch[-1])) / (NA * plan.L ** 3 * 1e-24)
-                x_norm = row[0].cpu().numpy()
-                err = surrogate.interval_error(math.log10(t_next - ts), c_tot, x_norm)
-                if err <= tol and (budget is None or spent + err <= budget):
-                    spent += err
-                    y = surrogate.net.forward(row)
-                    gsbs.gsbs_repopulate(e.ctx, 0, t_next, y[0], surrogate.mu_out(), surrogate.sd_y, C_FLOOR,
-                                         relative=True)
-                    took = True
-        if not took:
-            e.advance_to(t_next)
-        used.append(took)
-        cnt = e.current_counts(0)
-        if not took:  # a plain step that ends at t_next has also injected the molecules due then
-            for j in inj:
-                if j.t == t_next:
-                    cnt = cnt - np.bincount(j.species, minlength=len(cnt))[:len(cnt)]
-        ed = plan.edep_until(t_next - 1e-9, inj)
-        times.append(t_next)
-        n_h2o2.append(int(cnt[H2O2]))
-        g_h2o2.append(cnt[H2O2] / (ed / 100.0))
+                used[p] = True
+            else:
+                e.advance_to(t_nx[p])
+        e.advance_to(t_nx[-1])  # takes the records at the last pulse start
+    else:
+        e.advance_to(t_nx[-1])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    counts = e.counts(0)
+    at_switch = np.array([counts[int(np.searchsorted(rec, t))] for t in t_sw])
+    n_h2o2, g_h2o2 = [], []
+    for t in t_nx:
+        cnt = counts[int(np.searchsorted(rec, t))].copy()
+        for j in inj:  # the record at a pulse start follows that start's injection
+            if j.t == t:
+                cnt -= np.bincount(j.species, minlength=len(cnt))[:len(cnt)]
+        ed = plan.edep_until(t - 1e-9, inj)
+        n_h2o2.append(int(cnt[H2O2]))
+        g_h2o2.append(cnt[H2O2] / (ed / 100.0))
     st = e.stats()
     e.close()
-    return dict(t=np.array(times), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
-                intervals_by_network=int(sum(used)), used=np.array(used), counts_at_switch=np.array(at_switch),
-                error_estimate_spent=spent,
-                steps=st["steps"], molecule_steps=st["molecule_steps"])
+    return dict(t=np.array(t_nx), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
+                intervals_by_network=int(used.sum()), used=used, counts_at_switch=at_switch,
+                error_estimate_spent=spent, steps=st["steps"], molecule_steps=st["molecule_steps"])

@@ -367,3 +367,54 @@ def batched_first_pulses(seed: int, n_instances: int = 64):
         pos, sp = tracks_z(rng, L, n_tr)
         out.append((L, Injection(0.0, _into_box(pos, L), sp, n_tr * L * LET_KEV_PER_UM)))
     return out
+
+
+# Batched campaign: every instance of batched_instances with its whole pulse
+# train, each pulse split into n_batches injection batches of z-parallel
+# tracks drawn on the device by the counter-based spur model
+# (gsbs_inject_pulse).  Only times and track counts are drawn here.
+CAMPAIGN_STEP_BUDGET = 20000
+CAMPAIGN_PULSE_RATE_GY_S = 1e6
+
+
+@dataclasses.dataclass
+class CampaignInstance:
+    L: float                  # nm
+    dose_per_pulse: float     # Gy
+    n_pulses: int
+    avg_rate: float           # Gy/s
+    width: float              # ns, pulse width = dose / pulse rate
+    period: float             # ns, dose / average rate
+    batches: list             # [(t_ns, n_tracks, stream)], in time order
+    records: np.ndarray       # ns
+    t_end: float              # ns: one period after the last pulse starts
+
+
+def campaign(seed: int, n_instances: int = 64, n_batches: int = 10, n_records: int = 20,
+             pulse_rate_gy_s: float = CAMPAIGN_PULSE_RATE_GY_S) -> List[CampaignInstance]:
+    """Instances of batched_instances(seed) as pulse trains: rectangular pulses
+    of width Dp / Ddot_p every Dp / Ddot_av, track arrivals uniform in the
+    pulse and grouped into n_batches equal sub-intervals (each injected at its
+    start), records at n_records log-spaced times after every pulse start.
+    Spur-model streams are (instance << 32) | (pulse * n_batches + batch)."""
+    out = []
+    for i, p in enumerate(batched_instances(seed, n_instances)):
+        rng = np.random.default_rng([p["seed"], 6])
+        L = p["L"]
+        W = p["dose_per_pulse"] / pulse_rate_gy_s * 1e9
+        T = p["dose_per_pulse"] / p["avg_rate"] * 1e9
+        n_tr = int(round(tracks_per_gray(L) * p["dose_per_pulse"]))
+        batches, records = [], [0.0]
+        for q in range(p["n_pulses"]):
+            tp = q * T
+            arrive = rng.uniform(0.0, W, size=n_tr)
+            b = np.minimum((arrive / W * n_batches).astype(int), n_batches - 1)
+            cnt = np.bincount(b, minlength=n_batches)
+            for k in range(n_batches):
+                if cnt[k]:
+                    batches.append((tp + k * W / n_batches, int(cnt[k]), (i << 32) | (q * n_batches + k)))
+            records.extend(tp + log_times(DT0_NS, T, n_records))
+        t_end = (p["n_pulses"] - 1) * T + T
+        out.append(CampaignInstance(L, p["dose_per_pulse"], p["n_pulses"], p["avg_rate"], W, T, batches,
+                                    np.unique(np.asarray(records)), t_end))
+    return out

@@ -98,6 +98,62 @@ def test_checkpoint_keeps_chemistry_and_rejects_bad_input(g):
     h.close()
 
 
+def test_corrupt_checkpoints_are_rejected_and_leave_the_context_intact(g):
+    """A checkpoint whose molecule records or queued molecules are out of range
+    (species byte, instance field, position, counts that differ from the
+    molecules) fails with EINVAL before the context is touched: the context
+    still runs as before."""
+    L = 1000.0
+    rng = np.random.default_rng(5)
+    n = 300
+    xyz = rng.uniform(-400, 400, size=(n, 3)).astype(np.float32)
+    sp = rng.integers(0, 7, size=n).astype(np.uint8)
+    e = g.Engine(L, 3, W.D_CONFIG, W.REACTIONS)
+    g.gsbs_debug_set_state(e.ctx, xyz, sp, np.arange(n, dtype=np.uint64) + 1000, step=4, next_uid=5000)
+    q_xyz = rng.uniform(-400, 400, size=(40, 3)).astype(np.float32)
+    q_sp = rng.integers(0, 7, size=40).astype(np.uint8)
+    e.inject(0, 10.0, q_xyz, q_sp, 100.0)
+    e.set_records(0, [0.0, 5.0, 20.0])
+    blob = e.save()
+    e.close()
+    rec = lambda k: xyz[k].tobytes() + np.int32(int(sp[k])).tobytes()  # noqa: E731
+    at = blob.find(rec(7))
+    assert at > 0 and blob.find(rec(7), at + 1) < 0
+    q_at = blob.find(q_xyz.tobytes())
+    assert q_at > 0
+
+    def patch(off, data):
+        return blob[:off] + data + blob[off + len(data):]
+
+    meta = at + 12
+    bad = {
+        "species byte": patch(meta, bytes([40])),
+        "instance field": patch(meta + 1, bytes([3])),
+        "NaN position": patch(at, np.float32(np.nan).tobytes()),
+        "position outside": patch(at, np.float32(L / 2).tobytes()),
+        "counts differ": patch(meta, bytes([(int(sp[7]) + 1) % 7])),
+        "queued species": patch(q_at + q_xyz.nbytes, bytes([9])),
+        "queued position": patch(q_at, np.float32(-L).tobytes()),
+    }
+    h = g.Engine(L, 3, W.D_CONFIG, W.REACTIONS)
+    h.load(blob, records=[[0.0, 5.0, 20.0]])
+    h.advance_to(2.0)
+    for name, b in bad.items():
+        with pytest.raises(g.GsbsError) as ex:
+            h.load(b)
+        assert ex.value.code == -1, (name, str(ex.value))
+    assert h.time(0) == 2.0  # still the state before the failed loads
+    h.advance_to(20.0)
+    got = h.counts(0)
+    h.close()
+    ref = g.Engine(L, 3, W.D_CONFIG, W.REACTIONS)
+    ref.load(blob, records=[[0.0, 5.0, 20.0]])
+    ref.advance_to(2.0)
+    ref.advance_to(20.0)
+    assert np.array_equal(got, ref.counts(0))
+    ref.close()
+
+
 _CHILD = r'''
 import os, sys
 import numpy as np

@@ -455,6 +455,14 @@ def test_full_size_first_steps(g, orc):
         say("step", k, "accepted gpu", len(accg), "oracle", len(acco))
         assert len(accg ^ acco) <= max(2, len(acco) // 1000)
         assert len(acco) > 0
+        # every difference is a near-tie: the pair uniform lies within the FP32
+        # rounding of P (the bridge exponent of an evaluated pair is at most 18)
+        pg_of = {tuple(p): (P, u) for p, P, u in zip(pg["uid"].tolist(), pg["P"], pg["u24"])}
+        po_of = {tuple(p): (P, u) for p, P, u in zip(lo["uid"].tolist(), lo["P"], lo["u24"])}
+        for pair in accg ^ acco:
+            P, u24 = pg_of[pair] if pair in accg else po_of[pair]
+            u = (int(u24) + 0.5) * 2.0 ** -24
+            assert abs(u - float(P)) <= 2e-6 + 2e-5 * 19 * float(P), (pair, u, P)
     e.close()
     e = make_engine(g, wl.L, 2024)
     e.load_workload(wl)
@@ -547,3 +555,61 @@ def test_first_order_only_batched_matches_oracle_exactly(g, orc):
         assert np.array_equal(got, ref["counts"]), i
         assert got[-1][W.E_AQ] < ref["counts"][0][W.E_AQ]
     e.close()
+
+
+def _straddles(orc, x1, x0, sp, uid, L, dt, step, seed, pairs):
+    """Pairs (uid, uid) whose uniform lies within the FP32 rounding of the
+    oracle's P (the accept decision may go either way between FP32 and FP64)."""
+    idx = {int(u): k for k, u in enumerate(uid)}
+    ok = []
+    for a, b in pairs:
+        i, j = idx[a], idx[b]
+        r = [q for q in W.REACTIONS if {q.a, q.b} == {int(sp[i]), int(sp[j])}][0]
+        Dab = W.D_CONFIG[r.a] + W.D_CONFIG[r.b]
+        R = orc.radius(r.k_in, Dab)
+        r1 = np.linalg.norm(minimg(x1[j].astype(np.float64) - x1[i], L))
+        r0 = np.linalg.norm(minimg(x0[j].astype(np.float64) - x0[i], L))
+        P = orc.bridge(r0, r1, R, Dab * dt)
+        aexp = max((r0 - R) * (r1 - R) / (Dab * dt), 0.0)
+        u = ((int(orc.philox([min(a, b), max(a, b), step, 1], [seed, 0])[0]) >> 40) + 0.5) * 2.0 ** -24
+        ok.append(abs(u - P) <= 2e-6 + 2e-5 * (1 + aexp) * P)
+    return ok
+
+
+@pytest.mark.parametrize("dt", [500.0, 2000.0])
+def test_full_size_late_regime_species_bin_search(g, orc, dt):
+    """A late-regime state of the 10 um cube at full size: 150 000 molecules
+    of the spur-model mixture spread through the cube, one step of 0.5 or 2 us
+    on fixed positions through the production species-bin search (candidates
+    not logged, the library's own box shape and stream split, fused screening
+    and the bridge-exponent filter).  The candidate count equals the oracle's
+    FP32 count, and the accepted pairs equal the oracle's except pairs whose
+    uniform lies within the FP32 rounding of P."""
+    L, n, step, seed = 10000.0, 150000, 9, 31
+    rng = np.random.default_rng(int(dt))
+    x0 = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    sp = rng.choice(7, size=n, p=W.SPUR_FRACTIONS).astype(np.uint8)
+    sig = np.sqrt(2.0 * np.array(W.D_CONFIG)[sp] * dt)[:, None]
+    x1 = ((x0 + rng.normal(size=(n, 3)) * sig + L / 2) % L - L / 2).astype(np.float32)
+    x0 = x0.astype(np.float32)
+    uid = rng.permutation(np.arange(n, dtype=np.uint64) * 5 + 11)
+    say("late regime full size", dt, n)
+    e = make_engine(g, L, seed)
+    g.gsbs_debug_set_state(e.ctx, x1, sp, uid, step=step)
+    c0 = e.stats()["pair_candidates"]
+    g.gsbs_debug_step(e.ctx, dt, g.DEBUG_FIXED | g.DEBUG_SEARCH_ONLY | MODES["species"], xyz0=x0)
+    ncand = e.stats()["pair_candidates"] - c0
+    pr = g.gsbs_debug_get_pairs(e.ctx)
+    e.close()
+    acc_g = {tuple(p) for p, f in zip(pr["uid"].tolist(), pr["flag"]) if f & 1}
+    chem = orc.make_chem(W.D_CONFIG, W.REACTIONS)
+    say("oracle decisions")
+    pairs, P, u24, ncand_o = orc.accept_f32(x1, x0, sp, uid, L, chem, dt, step, seed, 0)
+    acc_o = {(int(min(uid[i], uid[j])), int(max(uid[i], uid[j]))) for i, j in pairs.tolist()}
+    diff = acc_g ^ acc_o
+    say("candidates gpu", ncand, "oracle", ncand_o, "accepted gpu", len(acc_g), "oracle", len(acc_o),
+        "differ", len(diff))
+    assert ncand == ncand_o and ncand > 10 ** 6
+    assert len(acc_o) > 100
+    assert len(diff) <= max(3, len(acc_o) // 1000)
+    assert all(_straddles(orc, x1, x0, sp, uid, L, dt, step, seed, sorted(diff)))

@@ -226,3 +226,58 @@ def test_first_order_event_for_event(g):
                 assert np.any(np.abs(ev_t - tk) <= 1e-9 * tk), (m, k, out[m, k], ref[k])
     say("first-order events", fo_events)
     assert fo_events > 0
+
+
+def test_sbs_pbc_volume_scaling(g):
+    """The paper's PBC verification on the device: the volume-scaling mixture
+    in 0.2, 0.5 and 1 um cubes, all on the same step times (the 0.2 um cube's
+    step cap), gives the same concentrations at every record within 4.5
+    standard errors of the cube-to-cube scatter (plus 1e-3 of the value: the
+    initial counts are rounded per cube); from 1 us on each edge stays within
+    25 % of the mean of Gillespie runs in the same volume (the paper reports
+    SBS + PBCs up to 20 % from its Gillespie reference: diffusion-controlled
+    rates that homogeneous kinetics leave out)."""
+    t_end = 1e4
+    rec = np.concatenate([[0.0], W.log_times(1e-3, t_end, 30)])
+    rec[-1] = t_end
+    e = g.Engine(200.0, 1, W.D_CONFIG, W.REACTIONS)
+    cap = e.dt_max()
+    e.close()
+    cubes = {200.0: 64, 500.0: 8, 1000.0: 4}
+    per, ssa = {}, {}
+    for L, k in cubes.items():
+        say("volume scaling SBS", L, k)
+        p = g.gsbs_default_params()
+        p.dt_max_ns = cap
+        e = g.Engine([L] * k, 7, W.D_CONFIG, W.REACTIONS, params=p)
+        for i in range(k):
+            wl = W.volume_scaling(5000 + 100 * i + int(L), L, t_end=t_end)
+            e.inject(i, 0.0, wl.injections[0].xyz, wl.injections[0].species)
+            e.set_records(i, rec)
+        e.advance_to(t_end)
+        per[L] = np.stack([e.counts(i) for i in range(k)]).astype(np.float64) / (L / 1000.0) ** 3
+        e.close()
+        V = L ** 3 * 1e-24
+        e = g.Engine(L, 1, W.D_CONFIG, W.REACTIONS)
+        n_r = 1024
+        out, _ = g.gsbs_ssa(e.ctx, np.tile(W.volume_scaling_counts(L).astype(np.int32), (n_r, 1)), np.full(n_r, V),
+                            rec, seed=41)
+        e.close()
+        ssa[L] = out.mean(axis=0) / (L / 1000.0) ** 3
+    ref = per[200.0]
+    for L in (500.0, 1000.0):
+        a, b = ref, per[L]
+        d = np.abs(a.mean(axis=0) - b.mean(axis=0))
+        se = np.sqrt(a.var(axis=0, ddof=1) / len(a) + b.var(axis=0, ddof=1) / len(b))
+        lim = 4.5 * se + 1e-3 * a.mean(axis=0)
+        use = b.mean(axis=0) * (L / 1000.0) ** 3 >= 20
+        z = (d / np.maximum(se, 1e-9))[use]
+        say("edge", L, "vs 0.2 um: largest |diff| / SE", float(z.max()))
+        assert np.all(d[use] <= lim[use])
+    late = rec >= 1e3
+    for L in cubes:
+        m = per[L].mean(axis=0)
+        ok = late[:, None] & (ssa[L] * (L / 1000.0) ** 3 >= 50)
+        r = m[ok] / ssa[L][ok]
+        say("edge", L, "SBS / Gillespie after 1 us", float(r.min()), float(r.max()))
+        assert np.all((r > 0.75) & (r < 1.33))

@@ -158,3 +158,87 @@ def test_surrogate_pipeline(g):
     hyb_b = SU.run(plan, s, tol=1.0, budget=0.01)
     say("budgeted hybrid", hyb_b["intervals_by_network"], hyb_b["error_estimate_spent"])
     assert hyb_b["intervals_by_network"] == 1 and abs(hyb_b["error_estimate_spent"] - 0.006) < 1e-12
+
+
+def _two_cube_engine(g, SU):
+    plans = [SU.PulsePlan(1000.0, 40 + i, 3, 1.0, 1e6, 1000.0) for i in range(2)]
+    e = g.Engine([p.L for p in plans], 17, W.D_CONFIG, W.REACTIONS)
+    for i, p in enumerate(plans):
+        for j in p.injections():
+            e.inject(i, j.t, j.xyz, j.species, j.edep_ev)
+        e.set_records(i, np.unique(np.concatenate([W.log_times(1e-3, 3e6, 40), [p.switch(0), p.start(1)]])))
+    return e, plans
+
+
+def _net(g, SU):
+    s = SU.Surrogate(16)
+    s.init_weights(5)
+    s.mu = np.zeros(296, np.float32)
+    s.sd = np.ones(296, np.float32)
+    s.mu_y = np.zeros(7, np.float32)
+    s.sd_y = np.full(7, 0.01, np.float32)
+    s.dt_edges = np.array([3.0, 6.0, 9.0])
+    s.c_edges = np.array([-12.0, -6.0, 0.0])
+    return s
+
+
+def test_surrogate_mode_declining_every_interval_is_plain_bit_for_bit(g):
+    """gsbs_advance_to(GSBS_SURROGATE) with a table of +inf takes no interval:
+    records, final counts and stats equal the GSBS_PLAIN advance (hand-over
+    points are step ends in both modes while a surrogate is set)."""
+    from paper_2509_03313_amd import surrogate as SU
+    s = _net(g, SU)
+    s.table = np.full((2, 2), np.inf)
+    out = []
+    for mode in (g.GSBS_PLAIN, g.GSBS_SURROGATE):
+        e, plans = _two_cube_engine(g, SU)
+        SU.set_on(e, s)
+        e.advance_to(3e6, mode)
+        out.append(([e.counts(i) for i in range(2)], [e.current_counts(i) for i in range(2)], e.stats(),
+                     [g.gsbs_get_handover_log(e.ctx, i) for i in range(2)]))
+        e.close()
+    (ca, na, sa, _), (cb, nb, sb, lb) = out
+    for i in range(2):
+        assert np.array_equal(ca[i], cb[i]) and np.array_equal(na[i], nb[i])
+        assert len(lb[i]["taken"]) == 2 and not lb[i]["taken"].any() and np.all(np.isinf(lb[i]["estimate"]))
+    assert sa == sb
+    say("declined hand-overs:", lb[0]["t_switch"].tolist(), "steps", sb["steps"])
+
+
+def test_surrogate_mode_zero_table_hands_every_interval_over(g):
+    """A zero table with no input-range guard hands every inter-pulse interval
+    to the network: both cubes are re-populated at each next pulse start,
+    records inside the handed-over intervals stay empty, and fewer SBS steps
+    run; gsbs_pair_corr gives the features' pair-correlation block."""
+    from paper_2509_03313_amd import surrogate as SU
+    s = _net(g, SU)
+    s.table = np.zeros((2, 2))
+    s.lo = s.hi = None
+    e, plans = _two_cube_engine(g, SU)
+    e.advance_to(plans[0].switch(0) - 1.0)
+    pc = g.gsbs_pair_corr(e.ctx, 0, 150.0, 512)
+    feat = g.gsbs_features(e.ctx, 0, 1.0, r_max=150.0, n_ref_max=512)
+    assert pc.shape == (9, 32) and np.array_equal(pc.ravel(), feat[7:7 + 288])
+    SU.set_on(e, s)
+    e.advance_to(3e6, g.GSBS_SURROGATE)
+    for i in range(2):
+        lg = g.gsbs_get_handover_log(e.ctx, i)
+        assert lg["taken"].all() and len(lg["taken"]) == 2, lg
+        assert np.allclose(lg["t_next"], [plans[i].start(1), plans[i].start(2)])
+        c = e.counts(i)
+        r = e.records[i]
+        inside = (r > plans[i].switch(0)) & (r < plans[i].start(1))
+        assert inside.any() and np.all(c[inside] == -1)
+        assert np.all(c[~inside] >= 0)
+    steps_sur = e.stats()["steps"]
+    e.close()
+    e, _ = _two_cube_engine(g, SU)
+    e.advance_to(3e6)
+    assert steps_sur < e.stats()["steps"]
+    e.close()
+    with pytest.raises(g.GsbsError):  # no surrogate set
+        e, _ = _two_cube_engine(g, SU)
+        try:
+            e.advance_to(10.0, g.GSBS_SURROGATE)
+        finally:
+            e.close()

@@ -284,3 +284,37 @@ def test_volume_scaling_pin_catches_a_missing_wrap(orc, tmp_path):
                      "s->x[3 * i + a] = s->x[3 * i + a] + sigma * z[a];"))
     d, se, use = _vs_z(path)
     assert not np.all(d[use] <= 4.5 * se[use] + 1e-9)
+
+
+# ------------------------------------------- full-size decisions (bucket grid) ---
+@pytest.mark.parametrize("L,n,dt", [(400.0, 2500, 3.0), (600.0, 3000, 40.0), (1000.0, 4000, 60.0),
+                                    (400.0, 2500, 40.0)])
+def test_accept_f32_equals_all_pairs(orc, L, n, dt):
+    """orc_accept_f32 (bucket grid, for full-size inputs) selects exactly the
+    candidates of the all-pairs orc_cand_f32, and accepts exactly those whose
+    pair uniform (Philox at (lower uid, higher uid, step, 1)) falls below the
+    oracle's contact probability of their FP64 separations."""
+    rng = np.random.default_rng(int(L + dt))
+    x0 = rng.uniform(-L / 2, L / 2, size=(n, 3))
+    m = (n // 30) * 10
+    x0[:m] = rng.uniform(-L / 2, L / 2, size=(n // 30, 3)).repeat(10, axis=0) + rng.normal(0, 2.0, size=(m, 3))
+    x0 = ((x0 + L / 2) % L - L / 2).astype(np.float32)
+    x1 = ((x0 + rng.normal(0, math.sqrt(2 * 5 * dt), size=(n, 3)) + L / 2) % L - L / 2).astype(np.float32)
+    sp = rng.integers(0, 7, size=n).astype(np.int32)
+    uid = rng.permutation(np.arange(n, dtype=np.uint64) * 7 + 3)
+    chem = orc.make_chem(W.D_CONFIG, W.REACTIONS)
+    ref = orc.cand_f32(x1, sp, L, chem, dt)
+    pr, P, u24, ncand = orc.accept_f32(x1, x0, sp, uid, L, chem, dt, 6, 21, 2)
+    assert ncand == len(ref) and ncand > 100
+    acc = set()
+    for i, j in ref.tolist():
+        r = W.REACTIONS[[k for k, q in enumerate(W.REACTIONS) if {q.a, q.b} == {sp[i], sp[j]}][0]]
+        Dab = W.D_CONFIG[r.a] + W.D_CONFIG[r.b]
+        d1 = [orc.minimg(float(x1[j, a]) - float(x1[i, a]), L) for a in range(3)]
+        d0 = [orc.minimg(float(x0[j, a]) - float(x0[i, a]), L) for a in range(3)]
+        p = orc.bridge(math.sqrt(sum(v * v for v in d0)), math.sqrt(sum(v * v for v in d1)), orc.radius(r.k_in, Dab),
+                       Dab * dt)
+        lo, hi = sorted((int(uid[i]), int(uid[j])))
+        if ((int(orc.philox([lo, hi, 6, 1], [21, 2])[0]) >> 40) + 0.5) * 2.0 ** -24 < p:
+            acc.add((min(i, j), max(i, j)))
+    assert set(map(tuple, pr.tolist())) == acc and len(acc) > 0

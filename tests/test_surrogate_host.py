@@ -15,7 +15,8 @@ def test_pulse_plan_times_and_energy():
     from paper_2509_03313_amd import workload as W
     pl = SU.PulsePlan(2000.0, 3, 4, 1.0, 1e6, 1e3, n_batches=2)
     assert pl.width == 1000.0 and pl.period == 1e6
-    assert pl.start(2) == 2e6 and pl.switch(1) == 1e6 + 1000.0 + SU.TAU_SETTLE
+    # hand-over: the settle time after the pulse's last injection (batch 2 at +500 ns)
+    assert pl.start(2) == 2e6 and pl.switch(1) == 1e6 + 500.0 + SU.TAU_SETTLE
     inj = pl.injections()
     assert sorted({j.t for j in inj}) == [p * 1e6 + b * 500.0 for p in range(4) for b in range(2)]
     # energy per pulse: tracks x L x LET, tracks from Eq. 5 at 1 Gy
@@ -24,7 +25,7 @@ def test_pulse_plan_times_and_energy():
     assert abs(e_pulse - n_tr * 2000.0 * W.LET_KEV_PER_UM) < 1e-6
     assert pl.edep_until(1e6 - 1e-9, inj) == e_pulse
     # the same plan gives the same molecules
-    inj2 = pl.injections()
+    inj2 = SU.PulsePlan(2000.0, 3, 4, 1.0, 1e6, 1e3, n_batches=2).injections()
     assert all(np.array_equal(a.xyz, b.xyz) and np.array_equal(a.species, b.species) for a, b in zip(inj, inj2))
 
 
