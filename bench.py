@@ -92,10 +92,16 @@ def parse():
     ap.add_argument("--surrogate", action="store_true",
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
-    ap.add_argument("--sur-train-L", type=float, default=2000.0, help="cube edge (nm) of the training runs")
-    ap.add_argument("--sur-plans", type=int, default=256, help="training runs (12 pulses each)")
-    ap.add_argument("--sur-held", type=int, default=16, help="held-out runs (12 pulses each) for the error table")
-    ap.add_argument("--sur-rates", type=str, default="1000,100", help="average dose rates (Gy/s) of the 20-pulse runs")
+    ap.add_argument("--sur-train-L", type=float, default=5000.0, help="cube edge (nm) of the training runs")
+    ap.add_argument("--sur-plans", type=int, default=3456, help="training runs")
+    ap.add_argument("--sur-pulses", type=int, default=4, help="pulses per training and held-out run")
+    ap.add_argument("--sur-held", type=int, default=64, help="held-out runs for the error table")
+    ap.add_argument("--sur-rate-range", type=str, default="1,3000", help="average dose rates (Gy/s) of the "
+                                                                          "training runs, log-uniform")
+    ap.add_argument("--sur-cap", type=float, default=5e7, help="training intervals are simulated at most this long "
+                                                              "(ns) after the hand-over")
+    ap.add_argument("--sur-rates", type=str, default="1,10,100,1000",
+                    help="average dose rates (Gy/s) of the 20-pulse runs")
     ap.add_argument("--sur-save", type=str, default="", help="path prefix to save the model, held-out set and runs")
     return ap.parse_args()
 
@@ -112,22 +118,26 @@ def surrogate_bench(args):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    rates, doses = (80.0, 3000.0), (0.7, 1.3)
-    plans = SU.random_plans(args.seed + 1, args.sur_plans, L=args.sur_train_L, n_pulses=12, rates=rates, doses=doses)
+    rates = tuple(float(r) for r in args.sur_rate_range.split(","))
+    doses = (0.7, 1.3)
+    plans = SU.random_plans(args.seed + 1, args.sur_plans, L=args.sur_train_L, n_pulses=args.sur_pulses,
+                            rates=rates, doses=doses)
     train = {}
-    for b0 in range(0, len(plans), 64):
-        d = SU.generate(plans[b0:b0 + 64], seed=1000 + b0)
+    for b0 in range(0, len(plans), 128):
+        d = SU.generate(plans[b0:b0 + 128], seed=1000 + b0, t_cap=args.sur_cap)
         for k, v in d.items():
             train[k] = np.concatenate([train[k], v]) if k in train else v
         note(f"training samples {len(train['X'])} after {time.perf_counter() - t0:.1f} s")
     # held-out runs in the large cube: its count noise (~0.5 % of the H2O2 made per pulse)
     # is small enough for the 1 % table to mean something
-    held_plans = SU.random_plans(args.seed + 2, args.sur_held, L=args.sur_L, n_pulses=12, rates=rates, doses=doses)
+    held_plans = SU.random_plans(args.seed + 2, args.sur_held, L=args.sur_L, n_pulses=args.sur_pulses, rates=rates,
+                                 doses=doses)
     held = {}
-    for b0 in range(0, len(held_plans), 8):
-        d = SU.generate(held_plans[b0:b0 + 8], seed=2000 + b0, log=note)
+    for b0 in range(0, len(held_plans), 32):
+        d = SU.generate(held_plans[b0:b0 + 32], seed=2000 + b0, t_cap=args.sur_cap)
         for k, v in d.items():
             held[k] = np.concatenate([held[k], v]) if k in held else v
+        note(f"held-out samples {len(held['X'])} after {time.perf_counter() - t0:.1f} s")
     note(f"held-out samples {len(held['X'])} after {time.perf_counter() - t0:.1f} s")
     t_gen = time.perf_counter() - t0
     n, n_held = len(train["X"]), len(held["X"])
@@ -142,7 +152,7 @@ def surrogate_bench(args):
         c = SU.Surrogate(1024)
         c.init_weights(args.seed)
         hist = c.fit(train, epochs=60, batch=64, lr=5e-4, log=note, g_weight=gw)
-        e = c.build_table(pick, n_dt=2, n_c=2)
+        e = c.build_table(pick, n_dt=3, n_c=2)
         cands[gw] = (float(np.quantile(e, 0.95)), float(np.median(e)), c, hist)
         note(f"pair-correlation weight {gw:g}: held-out relative H2O2 error median {np.median(e):.4f}, "
              f"p95 {np.quantile(e, 0.95):.4f}")
@@ -154,7 +164,7 @@ def surrogate_bench(args):
     # then measures the calibrated network
     bias = s.calibrate(pick)
     note(f"calibration: mean log10 residual per species {np.round(bias, 5).tolist()}")
-    err = s.build_table(tab, n_dt=2, n_c=2)
+    err = s.build_table(tab, n_dt=3, n_c=2)
     if args.sur_save:
         s.save(args.sur_save + "_model.npz")
         np.savez(args.sur_save + "_held.npz", **held)
@@ -198,6 +208,8 @@ def surrogate_bench(args):
         "dtype": "f32 SBS, bf16 network with f32 accumulation", "data": "synthetic",
         "config": {"workload": f"20 pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate 1e6 Gy/s, "
                                f"2 batches per pulse", "train_runs": len(plans), "train_L_nm": args.sur_train_L,
+                   "train_pulses_per_run": args.sur_pulses, "train_avg_rates_gy_s": list(rates),
+                   "train_interval_cap_ns": args.sur_cap,
                    "samples": int(n), "held_out_runs": len(held_plans), "held_out": int(n_held)},
         "train": {"generate_s": round(t_gen, 1), "train_s": round(t_train, 2), "final_loss": round(hist[-1], 6),
                   "pair_correlation_weight": gw_best,
@@ -667,6 +679,42 @@ def campaign_cpu_baseline(args):
                        f"1-core figure: instance 0 alone), FP64 oracle, same batches and Philox streams")
 
 
+def small_config_us_per_step(runs=5):
+    """The 1e4-molecule single pulse in a 1 um cube (2000 steps, 1 ps -> 1 us),
+    launch-bound: microseconds per SBS step with the step kernels launched one
+    by one and with each chunk of steps replayed as a HIP graph."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import workload as W
+    wl = W.single_pulse_small(1000)
+    stream = torch.cuda.Stream()  # capturable (not the null stream), default priority
+    out = {}
+    for graph in (0, 1):
+        p = gsbs.gsbs_default_params()
+        p.step_graph = graph
+        p.autotune = 0
+        times = []
+        for k in range(runs + 1):
+            e = gsbs.Engine(wl.L, 1000, wl.D, wl.reactions, params=p, stream=ctypes.c_void_p(stream.cuda_stream))
+            e.load_workload(wl)
+            stream.synchronize()
+            t = time.perf_counter()
+            e.advance_to(wl.t_end)
+            stream.synchronize()
+            dt = time.perf_counter() - t
+            n = e.stats()["steps"]
+            e.close()
+            if k:
+                times.append(dt / n * 1e6)
+        out["graph" if graph else "eager"] = round(float(np.median(times)), 2)
+    out["steps"] = int(n)
+    return out
+
+
 def campaign_bench(args):
     """The batched campaign (64 cubes, edges 2-10 um, 0.1-2 Gy per pulse, 1-20
     pulses at 1e6 Gy/s, average 0.01-1e5 Gy/s, 10 batches per pulse), every
@@ -749,6 +797,8 @@ def campaign_bench(args):
                 "per_launch_bytes", {}):
             roof["traffic"] = t["per_launch_bytes"][dom]
     step_ach = value * STEP_BYTES / 1e9
+    small = small_config_us_per_step()
+    note(f"1 um single pulse, us per SBS step: {small}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = campaign_cpu_baseline(args)
@@ -770,6 +820,7 @@ def campaign_bench(args):
         "roofline_step": dict(bound="hbm", achieved=round(step_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                               frac=round(step_ach / HBM_PEAK_GBS, 5), alg_bytes_per_molecule_step=STEP_BYTES),
         "cpu_baseline": cpu,
+        "small_config_us_per_sbs_step": small,
         "live_timed_kernels": list(live),
         "profile_ms": {q: round(v[0], 3) for q, v in timed.items()},
         "profile_launches": {q: v[1] for q, v in timed.items()},

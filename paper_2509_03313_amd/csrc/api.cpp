@@ -240,7 +240,16 @@ struct gsbs_ctx {
     DevCounters live_base{};  // device counters when live timing was switched on
     int64_t live_bins = 0;    // bins scanned by the live-timed steps
     // executable graphs launched during the current advance (destroyed after its final sync)
-    std::vector<hipGraphExec_t> graph_execs;
+    // executable step graphs kept for reuse: a captured chunk whose launches have
+    // the shape of a cached one updates it (hipGraphExecUpdate) instead of
+    // instantiating a new one; each entry's event marks the end of its last launch
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        hipEvent_t done;
+        uint64_t uses;
+    };
+    std::vector<GraphEntry> graph_cache;
+    int64_t graph_instantiated = 0, graph_updated = 0;
     // surrogate state buffers (allocated on first use)
     int32_t sur_cap = 0;
     int32_t* sur_ref_idx = nullptr;
@@ -975,7 +984,10 @@ int gsbs_destroy(gsbs_ctx* c) {
     dfree(c->ctr);
     dfree(c->rec);
     dfree(c->chem_d);
-    for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
+    for (auto& ge : c->graph_cache) {
+        (void)hipGraphExecDestroy(ge.exec);
+        (void)hipEventDestroy(ge.done);
+    }
     dfree(c->sur_ref_idx);
     dfree(c->sur_ref_cnt);
     dfree(c->sur_pair_ab);
@@ -1409,12 +1421,45 @@ static int advance_plain(gsbs_ctx* c, const double* target) {
             capturing = false;
             hipGraph_t gr = nullptr;
             HIPCHK(hipStreamEndCapture(c->st, &gr));
-            hipGraphExec_t ex = nullptr;
-            const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            // reuse an idle cached executable graph of the same shape, else
+            // instantiate one and keep it (two of one shape then alternate)
+            gsbs_ctx::GraphEntry* use = nullptr;
+            for (auto& ge : c->graph_cache) {
+                if (hipEventQuery(ge.done) != hipSuccess) continue;  // still running: leave it
+                hipGraphNode_t err_node = nullptr;
+                hipGraphExecUpdateResult res{};
+                if (hipGraphExecUpdate(ge.exec, gr, &err_node, &res) == hipSuccess) {
+                    use = &ge;
+                    c->graph_updated++;
+                    break;
+                }
+                (void)hipGetLastError();  // a failed update leaves an error to clear
+            }
+            if (!use) {
+                hipGraphExec_t ex = nullptr;
+                const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                if (ei != hipSuccess) {
+                    (void)hipGraphDestroy(gr);
+                    return fail(GSBS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+                }
+                hipEvent_t ev = nullptr;
+                HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                if (c->graph_cache.size() >= 8) {  // keep the most recently used shapes
+                    auto old = std::min_element(c->graph_cache.begin(), c->graph_cache.end(),
+                                                [](const gsbs_ctx::GraphEntry& a, const gsbs_ctx::GraphEntry& b) { return a.uses < b.uses; });
+                    HIPCHK(hipEventSynchronize(old->done));
+                    (void)hipGraphExecDestroy(old->exec);
+                    (void)hipEventDestroy(old->done);
+                    c->graph_cache.erase(old);
+                }
+                c->graph_cache.push_back({ex, ev, 0});
+                use = &c->graph_cache.back();
+                c->graph_instantiated++;
+            }
             (void)hipGraphDestroy(gr);
-            if (ei != hipSuccess) return fail(GSBS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-            c->graph_execs.push_back(ex);
-            HIPCHK(hipGraphLaunch(ex, c->st));
+            use->uses = (uint64_t)c->steps;
+            HIPCHK(hipGraphLaunch(use->exec, c->st));
+            HIPCHK(hipEventRecord(use->done, c->st));
             return GSBS_OK;
         };
         for (int k = 0; k < nstep; ++k) {
@@ -1478,8 +1523,7 @@ static int advance_plain(gsbs_ctx* c, const double* target) {
     for (int i = 0; i < c->n_inst; ++i) c->inst[i].t = target[i];
     HIPCHK(hipStreamSynchronize(c->st));
     for (int b = 0; b < 2; ++b) CHK(live_harvest(c, b));
-    for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
-    c->graph_execs.clear();
+
     CHK(check_device_errors(c));
     return refresh_estimates(c);
 }

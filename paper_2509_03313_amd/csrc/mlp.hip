@@ -1,10 +1,10 @@
 // mlp.hip -- gfx950 kernels of the inter-pulse surrogate: a 296-256-256-256-256-7
 // perceptron with erf-GELU hidden layers, BF16 weights and activations and FP32
-// accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), its backward pass
+// accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), its backward pass
 // and an Adam update on FP32 master weights.
 //
 // Every matrix product has the form C[M x N] = A[M x K] * B[N x K]^T with both
-// operands K-contiguous in BF16 and M, N, K multiples of 16 (zero padded), so
+// operands K-contiguous in BF16 and M, N, K multiples of 32 (zero padded), so
 // one kernel serves the forward product (X W^T), the input gradient
 // (dZ (W^T)^T) and the weight gradient (dZ^T (X^T)^T): the producers also
 // write the transposed copies the products need.
@@ -12,7 +12,7 @@
 
 namespace gsbs {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpBlock = 256;
@@ -36,29 +36,64 @@ __device__ __forceinline__ float gelu_grad(float z) {
     return cdf + z * pdf;
 }
 
-// C = A B^T: one wave per 16 x 16 tile of C, K in steps of 16.  Lane l feeds
-// row l%16 of the A tile and row l%16 of the B tile (k = 4*(l/16) .. +3) and
-// receives C[4*(l/16) + i][l%16], i = 0..3.
+// C = A B^T on the matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16).  A
+// block of 4 waves computes a 64 x 64 tile of C, each wave a 32 x 32 quarter
+// as 2 x 2 MFMA tiles.  Per K step of 32 the block stages A[64][32] and
+// B[64][32] in LDS -- one 16-byte global load per thread and operand, rows
+// padded by 16 bytes against bank conflicts -- and each wave reads its
+// fragments from there: lane l feeds row l%16 of an A tile and of a B tile
+// with the 8 values k = 8 (l/16) .. +7 and receives C[4 (l/16) + i][l%16],
+// i = 0..3, of each tile.  M, N, K are multiples of 32 (zero padded); rows
+// beyond M or N of a partial tile load zeros and store nothing.
+constexpr int kGemmTile = 64;
+constexpr int kGemmK = 32;
+constexpr int kGemmPad = 8;  // BF16 values of row padding in LDS
+
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restrict__ A, int32_t lda,
                                                      const uint16_t* __restrict__ B, int32_t ldb,
                                                      float* __restrict__ C, int32_t ldc, int32_t M, int32_t N,
                                                      int32_t K) {
-    const int tiles_n = N >> 4;
-    const int t = blockIdx.x * (kMlpBlock / 64) + (threadIdx.x >> 6);
-    if (t >= (M >> 4) * tiles_n) return;
-    const int tm = t / tiles_n, tn = t % tiles_n;
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const uint16_t* pa = A + (size_t)(tm * 16 + r) * lda + 4 * g;
-    const uint16_t* pb = B + (size_t)(tn * 16 + r) * ldb + 4 * g;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + k0);
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(pb + k0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    __shared__ __align__(16) uint16_t sa[kGemmTile][kGemmK + kGemmPad];
+    __shared__ __align__(16) uint16_t sb[kGemmTile][kGemmK + kGemmPad];
+    const int bm = blockIdx.y * kGemmTile, bn = blockIdx.x * kGemmTile;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int lr = t >> 2, lq = (t & 3) * 8;  // loader: row and 8-value chunk of the K slice
+    const bool va = bm + lr < M, vb = bn + lr < N;
+    const uint16_t* pa = A + (size_t)(bm + lr) * lda + lq;
+    const uint16_t* pb = B + (size_t)(bn + lr) * ldb + lq;
+    const int r = lane & 15, g = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+        const uint4 ra = va ? *reinterpret_cast<const uint4*>(pa + k0) : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 rb = vb ? *reinterpret_cast<const uint4*>(pb + k0) : make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();  // the previous slice has been read
+        *reinterpret_cast<uint4*>(&sa[lr][lq]) = ra;
+        *reinterpret_cast<uint4*>(&sb[lr][lq]) = rb;
+        __syncthreads();
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fa[i] = *reinterpret_cast<const bf16x8*>(&sa[wm + 16 * i + r][g]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(&sb[wn + 16 * j + r][g]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) C[(size_t)(tm * 16 + 4 * g + i) * ldc + tn * 16 + r] = acc[i];
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = bm + wm + 16 * i + 4 * (lane >> 4) + e, col = bn + wn + 16 * j + r;
+                if (row < M && col < N) C[(size_t)row * ldc + col] = acc[i][j][e];
+            }
 }
 
 // Input features (FP32, rows of n_in) -> BF16 activations X [Mp x Kp] and X^T
@@ -180,8 +215,8 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kMlpBlock 
 
 void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
                  int N, int K) {
-    const int tiles = (M / 16) * (N / 16);
-    hipLaunchKernelGGL(k_gemm_nt, dim3((tiles + 3) / 4), dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+    const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
 }
 void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp) {
     hipLaunchKernelGGL(k_mlp_input, dim3(blocks_for((int64_t)Mp * Kp)), dim3(kMlpBlock), 0, st, x, B, n_in, X, XT,

@@ -21,17 +21,18 @@ namespace {
         if (e_ != hipSuccess) return set_error(GSBS_EHIP, (std::string(#x) + ": " + hipGetErrorString(e_)).c_str()); \
     } while (0)
 
-constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
+// every matrix dimension of the products is a multiple of 32 (the K step of the MFMA)
+constexpr int pad32(int v) { return (v + 31) / 32 * 32; }
 
 // Padded layer shapes: K inputs (valid kv), N outputs (valid nv).
 struct Shape {
     int K, N, kv, nv;
 };
-constexpr Shape kShape[kMlpLayers] = {{pad16(kMlpIn), kMlpHidden, kMlpIn, kMlpHidden},
+constexpr Shape kShape[kMlpLayers] = {{pad32(kMlpIn), kMlpHidden, kMlpIn, kMlpHidden},
                                       {kMlpHidden, kMlpHidden, kMlpHidden, kMlpHidden},
                                       {kMlpHidden, kMlpHidden, kMlpHidden, kMlpHidden},
                                       {kMlpHidden, kMlpHidden, kMlpHidden, kMlpHidden},
-                                      {kMlpHidden, pad16(kMlpOut), kMlpHidden, kMlpOut}};
+                                      {kMlpHidden, pad32(kMlpOut), kMlpHidden, kMlpOut}};
 
 template <typename T>
 int zalloc(T** p, size_t n, hipStream_t st) {
@@ -113,7 +114,7 @@ int copy_params(gsbs_mlp* m, float* const* dev_w, float* const* dev_b, const flo
 }
 
 int forward(gsbs_mlp* m, const float* x, int B, float* y) {
-    const int Mp = pad16(B);
+    const int Mp = pad32(B);
     mlp_input(m->st, x, B, kMlpIn, m->act[0], m->actT[0], Mp, kShape[0].K);
     for (int l = 0; l < kMlpLayers; ++l) {
         const Shape& s = kShape[l];
@@ -147,7 +148,7 @@ int gsbs_mlp_create(int32_t max_batch, void* stream, gsbs_mlp** out) {
     gsbs_mlp* m = new gsbs_mlp();
     m->st = (hipStream_t)stream;
     m->max_batch = max_batch;
-    m->Mp_max = pad16(max_batch);
+    m->Mp_max = pad32(max_batch);
     const int Mp = m->Mp_max;
     int r = GSBS_OK;
     for (int l = 0; l < kMlpLayers && r == GSBS_OK; ++l) {
@@ -235,7 +236,7 @@ int gsbs_mlp_get_activation(gsbs_mlp* m, int32_t layer, int32_t batch, float* ou
     if (layer < 0 || layer >= kMlpLayers || batch < 1 || batch > m->max_batch)
         return set_error(GSBS_EINVAL, "layer or batch out of range");
     const Shape& s = kShape[layer];
-    std::vector<uint16_t> h((size_t)pad16(batch) * s.K);
+    std::vector<uint16_t> h((size_t)pad32(batch) * s.K);
     MHIP(hipMemcpyAsync(h.data(), m->act[layer], h.size() * 2, hipMemcpyDeviceToHost, m->st));
     MHIP(hipStreamSynchronize(m->st));
     for (int r = 0; r < batch; ++r)
@@ -251,7 +252,7 @@ int gsbs_mlp_get_activation(gsbs_mlp* m, int32_t layer, int32_t batch, float* ou
 int gsbs_mlp_backward(gsbs_mlp* m, const float* x, const float* t, int32_t batch, float* loss) {
     MCHK(check(m, x, batch));
     if (!t) return set_error(GSBS_EINVAL, "null");
-    const int B = batch, Mp = pad16(batch);
+    const int B = batch, Mp = pad32(batch);
     MCHK(forward(m, x, B, m->Y));
     MHIP(hipMemsetAsync(m->loss, 0, 4, m->st));
     const Shape& so = kShape[kMlpLayers - 1];

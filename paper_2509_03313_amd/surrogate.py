@@ -107,10 +107,17 @@ def _engine(Ls, seed, capacity=0):
 
 
 # ------------------------------------------------------------- training data ---
-def generate(plans: List[PulsePlan], seed: int, log=None) -> dict:
+def generate(plans: List[PulsePlan], seed: int, log=None, t_cap: Optional[float] = None) -> dict:
     """Run every plan with plain SBS as one batched context (one instance per
     plan) and collect, for every pulse but the last, the raw features at the
-    switch time and the log concentrations there and at the next pulse."""
+    switch time and the log concentrations there and at the next pulse.
+
+    With t_cap (ns), an interval longer than t_cap after the switch time is
+    simulated only to switch + t_cap: by then the radicals have recombined and
+    the homogeneous mixture of inert products and a few ions no longer changes
+    within the count noise, so its state there is the target, and the cube is
+    carried to the next pulse start unchanged (re-populated at the same
+    counts)."""
     n = len(plans)
     e = _engine([pl.L for pl in plans], seed)
     inj = [pl.injections() for pl in plans]
@@ -122,7 +129,10 @@ def generate(plans: List[PulsePlan], seed: int, log=None) -> dict:
         ev = []
         for p in range(pl.n_pulses - 1):
             ev.append((pl.switch(p), "switch", p))
-            ev.append((pl.start(p + 1), "next", p))
+            if t_cap is not None and pl.start(p + 1) - pl.switch(p) > t_cap:
+                ev.append((pl.switch(p) + t_cap, "capped", p))
+            else:
+                ev.append((pl.start(p + 1), "next", p))
         events.append(ev)
     pos = [0] * n
     X, Y0, Y1, meta = [], [], [], []
@@ -151,6 +161,10 @@ def generate(plans: List[PulsePlan], seed: int, log=None) -> dict:
                 Y0.append(y0)
                 Y1.append(log_conc(e.current_counts(i) - fresh, pl.L))
                 meta.append((math.log10(dt), math.log10(pl.avg_rate), float(np.sum(10.0 ** y0))))
+                if kind == "capped":  # carried unchanged to the next pulse start
+                    z = np.zeros(7, np.float32)
+                    gsbs.gsbs_repopulate(e.ctx, i, pl.start(p + 1), z, z, np.ones(7, np.float32), C_FLOOR,
+                                         relative=True)
             pos[i] += 1
         if log:
             log(f"generate: {sum(pos)}/{sum(len(v) for v in events)} events, {time.perf_counter() - t0:.1f} s")

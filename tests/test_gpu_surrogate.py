@@ -201,7 +201,9 @@ def test_surrogate_mode_declining_every_interval_is_plain_bit_for_bit(g):
     for i in range(2):
         assert np.array_equal(ca[i], cb[i]) and np.array_equal(na[i], nb[i])
         assert len(lb[i]["taken"]) == 2 and not lb[i]["taken"].any() and np.all(np.isinf(lb[i]["estimate"]))
-    assert sa == sb
+    # max_live is sampled at synchronisation points, which the hand-over stops add
+    keys = ("steps", "molecule_steps", "reactions", "pair_candidates")
+    assert {k: sa[k] for k in keys} == {k: sb[k] for k in keys}
     say("declined hand-overs:", lb[0]["t_switch"].tolist(), "steps", sb["steps"])
 
 
@@ -227,7 +229,9 @@ def test_surrogate_mode_zero_table_hands_every_interval_over(g):
         assert np.allclose(lg["t_next"], [plans[i].start(1), plans[i].start(2)])
         c = e.counts(i)
         r = e.records[i]
-        inside = (r > plans[i].switch(0)) & (r < plans[i].start(1))
+        inside = np.zeros(len(r), dtype=bool)
+        for ts, tn in zip(lg["t_switch"], lg["t_next"]):
+            inside |= (r > ts) & (r < tn)
         assert inside.any() and np.all(c[inside] == -1)
         assert np.all(c[~inside] >= 0)
     steps_sur = e.stats()["steps"]
