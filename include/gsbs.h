@@ -501,6 +501,20 @@ int gsbs_load(gsbs_ctx* ctx, const void* buf, int64_t size);
 int gsbs_numodes(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
                  double rtol, int32_t* steps, int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * computation of gsbs_numodes on device arrays only, with no allocation.
+ * c0, dt_ns, c1 are device pointers (as gsbs_numodes with on_device = 1);
+ * steps (host, n entries, required) receives the accepted steps.  The step
+ * counts are staged in a file-scope device array of the library (1048576
+ * int32 = 4 MiB per GPU, held until the process ends), so n is at most
+ * 1048576 (else GSBS_EINVAL); every call on one GPU uses that GPU's array,
+ * so calls that overlap on one GPU race (serialise them, e.g. on one
+ * stream).  Call with the context's device current.  Returns after c1 and
+ * steps are written; errors as gsbs_numodes. */
+int gsbs_numodes_noalloc(gsbs_ctx* ctx, int32_t n, int32_t n_species, const double* c0, const double* dt_ns,
+                         double* c1, double rtol, int32_t* steps);
+
 /* --------------------------------------------- stochastic kinetics --- */
 /* Homogeneous stochastic kinetics of the context's reaction table in n
  * independent well-mixed volumes: Gillespie's direct method (Gillespie 1977),

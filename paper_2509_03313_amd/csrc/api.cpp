@@ -2195,6 +2195,25 @@ static int numodes_args(gsbs_ctx* c, int32_t n, int32_t n_species, const double*
     return GSBS_OK;
 }
 
+int gsbs_numodes_noalloc(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns,
+                         double* c1, double rtol, int32_t* steps) {
+    CHK(numodes_args(c, n, n_species, c0, dt_ns, c1, rtol));
+    if (n > 0 && !steps) return fail(GSBS_EINVAL, "steps: a host array of n entries is required");
+    if (n > kNoAllocMaxMixtures) return fail(GSBS_EINVAL, "gsbs_numodes_noalloc: at most 1048576 mixtures per call");
+    if (n == 0) return GSBS_OK;
+    OdeTable tb{};
+    build_ode_table(c, tb);
+    int32_t* sc = nullptr;
+    CHK(numodes_scratch(&sc));
+    launch_numodes(c->st, c0, dt_ns, c1, sc, n, tb, rtol, 1e-10 * rtol, 200000);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(steps, sc, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int32_t m = 0; m < n; ++m)
+        if (steps[m] < 0) return fail(GSBS_ESTATE, "rate equations: step limit reached");
+    return GSBS_OK;
+}
+
 int gsbs_numodes(gsbs_ctx* c, int32_t n, int32_t n_species, const double* c0, const double* dt_ns, double* c1,
                  double rtol, int32_t* steps, int32_t on_device) {
     CHK(numodes_args(c, n, n_species, c0, dt_ns, c1, rtol));

@@ -221,7 +221,10 @@ void launch_ssa(hipStream_t st, const int32_t* n0, const double* vol, const doub
                 long long max_events);
 void launch_numodes(hipStream_t st, const double* c0, const double* dt, double* c1, int32_t* steps, int32_t n,
                     const OdeTable& tb, double rtol, double atol, int32_t max_steps);
-
+// Mixtures of one gsbs_numodes_noalloc call at most, and the device address of
+// its step-count array on the current device (numodes.hip).
+constexpr int32_t kNoAllocMaxMixtures = 1 << 20;
+int numodes_scratch(int32_t** out);
 void launch_repop(hipStream_t st, float4* pos, uint64_t* uid, DevCounters* ctr, const long long* newc, int ns,
                   int n_new, int inst, uint64_t uid_base, uint64_t seed, uint64_t step, float L, int cap,
                   long long* counts, int grid);

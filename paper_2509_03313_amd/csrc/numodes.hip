@@ -18,7 +18,11 @@
 // (a == b; the table prints 2k for self-recombinations), k_r in L/mol/ns;
 // d[X]/dt = sum_r nu_rX rate_r with nu_rX the net change of X per event
 // (products minus reactants).  The stage matrix is factored in registers.
+#include <mutex>
+#include <string>
+
 #include "engine.h"
+#include "gsbs.h"
 
 namespace gsbs {
 
@@ -267,6 +271,35 @@ __global__ __launch_bounds__(64) void k_numodes(const double* __restrict__ c0, c
 }
 
 }  // namespace
+
+// Step counts of gsbs_numodes_noalloc: a file-scope device array instead of an
+// allocation (each GPU the library runs on holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: the
+// per-device address from hipGetSymbolAddress, taken once per device, is
+// what the launches and copies use.
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxMixtures];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int numodes_scratch(int32_t** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return set_error(GSBS_EHIP, "no current HIP device for the rate-equation scratch array");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(GSBS_EHIP, (std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)).c_str());
+        g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GSBS_OK;
+}
 
 void launch_numodes(hipStream_t st, const double* c0, const double* dt, double* c1, int32_t* steps, int32_t n,
                     const OdeTable& tb, double rtol, double atol, int32_t max_steps) {

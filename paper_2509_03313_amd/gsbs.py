@@ -115,6 +115,7 @@ _SIGS = {
     "gsbs_features": [_vp, _i32, _d, _d, _i32, _d, _vp, _vp, _vp, _i32],
     "gsbs_repopulate": [_vp, _i32, _d, _vp, _i32, _vp, _vp, _d, _i32],
     "gsbs_numodes": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32), _i32],
+    "gsbs_numodes_noalloc": [_vp, _i32, _i32, _vp, _vp, _vp, _d, _P(_i32)],
     "gsbs_set_sources": [_vp, _i32, _vp],
     "gsbs_set_first_order": [_vp, _i32, _vp],
     "gsbs_save": [_vp, _vp, _i64, _P(_i64)],
@@ -632,6 +633,20 @@ def gsbs_numodes(ctx, c0, dt_ns, rtol=1e-6):
     _chk(_lib.gsbs_numodes(ctx, n, ns, c0h.ctypes.data_as(_vp), dth.ctypes.data_as(_vp), c1.ctypes.data_as(_vp),
                            float(rtol), _ptr(steps, _i32), 0))
     return c1, steps[:n]
+
+
+def gsbs_numodes_noalloc(ctx, c0, dt_ns, c1, rtol=1e-6):
+    """gsbs_numodes on device tensors without any allocation in the library:
+    c0, c1 [n][n_species] and dt_ns [n] contiguous float64 device tensors (c1
+    written in place).  Returns the accepted steps (host)."""
+    n, ns = int(c0.shape[0]), int(c0.shape[1])
+    for t, shape in ((c0, (n, ns)), (c1, (n, ns)), (dt_ns, (n,))):
+        if tuple(t.shape) != shape or str(t.dtype) != "torch.float64" or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("c0, c1: [n][n_species], dt_ns: [n]; contiguous float64 device tensors")
+    steps = np.zeros(max(n, 1), dtype=np.int32)
+    _chk(_lib.gsbs_numodes_noalloc(ctx, n, ns, C.c_void_p(c0.data_ptr()), C.c_void_p(dt_ns.data_ptr()),
+                                   C.c_void_p(c1.data_ptr()), float(rtol), _ptr(steps, _i32)))
+    return steps[:n]
 
 
 def gsbs_inject_pulse(ctx, inst, t_ns, n_tracks, frac, stream=0, spacing_nm=100.0, mol_per_spur=5.13,
