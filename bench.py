@@ -103,6 +103,10 @@ def parse():
     ap.add_argument("--sur-rates", type=str, default="1,10,100,1000",
                     help="average dose rates (Gy/s) of the 20-pulse runs")
     ap.add_argument("--sur-save", type=str, default="", help="path prefix to save the model, held-out set and runs")
+    ap.add_argument("--sur-data", type=str, default="",
+                    help="npz of the training and held-out samples: read if it exists, else written after generating")
+    ap.add_argument("--sur-generate-only", action="store_true", help="stop after generating (and saving) the samples")
+    ap.add_argument("--sur-batch", type=int, default=512, help="training runs stepped together in one context")
     return ap.parse_args()
 
 
@@ -122,24 +126,36 @@ def surrogate_bench(args):
     doses = (0.7, 1.3)
     plans = SU.random_plans(args.seed + 1, args.sur_plans, L=args.sur_train_L, n_pulses=args.sur_pulses,
                             rates=rates, doses=doses)
-    train = {}
-    for b0 in range(0, len(plans), 128):
-        d = SU.generate(plans[b0:b0 + 128], seed=1000 + b0, t_cap=args.sur_cap)
-        for k, v in d.items():
-            train[k] = np.concatenate([train[k], v]) if k in train else v
-        note(f"training samples {len(train['X'])} after {time.perf_counter() - t0:.1f} s")
     # held-out runs in the large cube: its count noise (~0.5 % of the H2O2 made per pulse)
     # is small enough for the 1 % table to mean something
     held_plans = SU.random_plans(args.seed + 2, args.sur_held, L=args.sur_L, n_pulses=args.sur_pulses, rates=rates,
                                  doses=doses)
-    held = {}
-    for b0 in range(0, len(held_plans), 32):
-        d = SU.generate(held_plans[b0:b0 + 32], seed=2000 + b0, t_cap=args.sur_cap)
-        for k, v in d.items():
-            held[k] = np.concatenate([held[k], v]) if k in held else v
-        note(f"held-out samples {len(held['X'])} after {time.perf_counter() - t0:.1f} s")
-    note(f"held-out samples {len(held['X'])} after {time.perf_counter() - t0:.1f} s")
+    sets = None
+    if args.sur_data and os.path.exists(args.sur_data):
+        z = np.load(args.sur_data)
+        sets = {"train": {k[6:]: z[k] for k in z.files if k.startswith("train_")},
+                "held": {k[5:]: z[k] for k in z.files if k.startswith("held_")}}
+        if len(sets["train"]["X"]) != (args.sur_pulses - 1) * len(plans) or \
+                len(sets["held"]["X"]) != (args.sur_pulses - 1) * len(held_plans):
+            raise SystemExit(f"{args.sur_data} was generated with other --sur-plans/--sur-held/--sur-pulses")
+        note(f"training and held-out samples read from {args.sur_data}")
+    if sets is None:
+        sets = {"train": {}, "held": {}}
+        for name, pl_all, bsz, seed0 in (("train", plans, args.sur_batch, 1000), ("held", held_plans, 32, 2000)):
+            dst = sets[name]
+            for b0 in range(0, len(pl_all), bsz):
+                d = SU.generate(pl_all[b0:b0 + bsz], seed=seed0 + b0, t_cap=args.sur_cap)
+                for k, v in d.items():
+                    dst[k] = np.concatenate([dst[k], v]) if k in dst else v
+                note(f"{name} samples {len(dst['X'])} after {time.perf_counter() - t0:.1f} s")
+        if args.sur_data:
+            np.savez(args.sur_data, **{"train_" + k: v for k, v in sets["train"].items()},
+                     **{"held_" + k: v for k, v in sets["held"].items()})
+    train, held = sets["train"], sets["held"]
     t_gen = time.perf_counter() - t0
+    if args.sur_generate_only:
+        note(f"generated {len(train['X'])} training and {len(held['X'])} held-out samples in {t_gen:.1f} s")
+        return
     n, n_held = len(train["X"]), len(held["X"])
     # two candidates, with and without the pair-correlation inputs; one half of the
     # held-out samples picks the candidate, the other half fills its error table

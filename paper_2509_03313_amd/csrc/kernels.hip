@@ -27,13 +27,19 @@ namespace gsbs {
 
 #define GSBS_BLOCK 256
 
-// ln(u) for u = (k + 1/2) 2^-24, k = top 24 bits of w.  Both branches feed an
-// exactly representable FP32 argument: 2k+1 < 2^24 below the midpoint, and
-// 1 - u = (2^25 - 2k - 1) 2^-25 above it (log1p keeps it accurate near u = 1).
+// ln(u) for u = (k + 1/2) 2^-24, k = top 24 bits of w, to a few FP32 ulps
+// relative.  Below the midpoint u = (2k+1) 2^-25 is exact in FP32.  Above it u
+// needs 25 bits, but 1 - u = (2^25 - 2k - 1) 2^-25 is exact; u is split as
+// w + d with w = fl(1 - (1 - u)) and d = (1 - w) - (1 - u), both differences
+// exact (Sterbenz; |d| <= 2^-25), and ln(u) = ln(w) + ln(1 + d/w), where
+// ln(1 + d/w) = d/w to within 2^-51.  One logf per value, no log1pf.
 __device__ __forceinline__ float ln_u24(uint64_t w) {
     const uint32_t k = (uint32_t)(w >> 40);
-    if (k < (1u << 23)) return logf((float)(2u * k + 1u) * 0x1p-25f);
-    return log1pf(-(float)((1u << 25) - 2u * k - 1u) * 0x1p-25f);
+    const bool lower = k < (1u << 23);
+    const float v = (float)((1u << 25) - 2u * k - 1u) * 0x1p-25f;  // 1 - u (exact above the midpoint)
+    const float wu = lower ? (float)(2u * k + 1u) * 0x1p-25f : __fsub_rn(1.0f, v);
+    const float d = lower ? 0.0f : __fsub_rn(__fsub_rn(1.0f, wu), v);
+    return __fadd_rn(logf(wu), __fmul_rn(d, __builtin_amdgcn_rcpf(wu)));
 }
 
 // sin and cos of 2 pi u, u = (k + 1/2) 2^-24: 2 pi u = pi x with x = (2k+1) 2^-24;
@@ -55,8 +61,9 @@ __device__ __forceinline__ float3 jump(float4 p, uint64_t uid, const InstStep& S
     if (!S.active) return x;
     uint64_t w[4];
     philox(uid, S.step, 0ull, 0ull, S.key0, S.key1, w);
-    const float ra = sqrtf(-2.0f * ln_u24(w[0]));
-    const float rb = sqrtf(-2.0f * ln_u24(w[2]));
+    // the hardware root (1 ulp): -2 ln u >= 6e-8, no denormal argument
+    const float ra = __builtin_amdgcn_sqrtf(-2.0f * ln_u24(w[0]));
+    const float rb = __builtin_amdgcn_sqrtf(-2.0f * ln_u24(w[2]));
     float s1, c1, s3, c3;
     sincos_2pi_u24(w[1], &s1, &c1);
     sincos_2pi_u24(w[3], &s3, &c3);
