@@ -93,16 +93,23 @@ def parse():
                     help="the second metric: 20-pulse wall time with the inter-pulse network vs plain SBS")
     ap.add_argument("--sur-L", type=float, default=10000.0, help="cube edge (nm) of the held-out and 20-pulse runs")
     ap.add_argument("--sur-train-L", type=float, default=5000.0, help="cube edge (nm) of the training runs")
-    ap.add_argument("--sur-plans", type=int, default=3456, help="training runs")
-    ap.add_argument("--sur-pulses", type=int, default=4, help="pulses per training and held-out run")
-    ap.add_argument("--sur-held", type=int, default=64, help="held-out runs for the error table")
+    ap.add_argument("--sur-plans", type=str, default="3456,384", help="training runs, one count per set")
+    ap.add_argument("--sur-pulses", type=str, default="4,10", help="pulses per training and held-out run, one per set")
+    ap.add_argument("--sur-held", type=str, default="96,32", help="held-out runs for the error table, one per set")
+    ap.add_argument("--mlp", action="store_true", help="throughput of the surrogate network's kernels")
+    ap.add_argument("--mlp-batches", type=str, default="1024,16384,131072", help="--mlp: batch sizes")
+    ap.add_argument("--mlp-iters", type=int, default=50, help="--mlp: timed iterations per batch size")
+    ap.add_argument("--sur-eval-pulses", type=int, default=10, help="pulses of the plain / hybrid comparison runs")
     ap.add_argument("--sur-rate-range", type=str, default="1,3000", help="average dose rates (Gy/s) of the "
                                                                           "training runs, log-uniform")
     ap.add_argument("--sur-cap", type=float, default=5e7, help="training intervals are simulated at most this long "
                                                               "(ns) after the hand-over")
-    ap.add_argument("--sur-rates", type=str, default="1,10,100,1000",
+    ap.add_argument("--sur-rates", type=str, default="1000,100,10,1",
                     help="average dose rates (Gy/s) of the 20-pulse runs")
     ap.add_argument("--sur-save", type=str, default="", help="path prefix to save the model, held-out set and runs")
+    ap.add_argument("--sur-lean", action="store_true",
+                    help="no warm-up and no budget run; the hybrid run first (for long intervals)")
+    ap.add_argument("--sur-load", type=str, default="", help="saved network (Surrogate.save): skip generating and training")
     ap.add_argument("--sur-data", type=str, default="",
                     help="npz of the training and held-out samples: read if it exists, else written after generating")
     ap.add_argument("--sur-generate-only", action="store_true", help="stop after generating (and saving) the samples")
@@ -112,7 +119,8 @@ def parse():
 
 def surrogate_bench(args):
     """Train the inter-pulse network on SBS runs of the engine itself, then run
-    20 pulses of 1 Gy with and without it on the same pulses and seeds."""
+    --sur-eval-pulses pulses of 1 Gy with and without it on the same pulses and
+    seeds."""
     import numpy as np
     import torch
 
@@ -121,80 +129,112 @@ def surrogate_bench(args):
     def note(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
-    t0 = time.perf_counter()
-    rates = tuple(float(r) for r in args.sur_rate_range.split(","))
-    doses = (0.7, 1.3)
-    plans = SU.random_plans(args.seed + 1, args.sur_plans, L=args.sur_train_L, n_pulses=args.sur_pulses,
-                            rates=rates, doses=doses)
-    # held-out runs in the large cube: its count noise (~0.5 % of the H2O2 made per pulse)
-    # is small enough for the 1 % table to mean something
-    held_plans = SU.random_plans(args.seed + 2, args.sur_held, L=args.sur_L, n_pulses=args.sur_pulses, rates=rates,
-                                 doses=doses)
-    sets = None
-    if args.sur_data and os.path.exists(args.sur_data):
-        z = np.load(args.sur_data)
-        sets = {"train": {k[6:]: z[k] for k in z.files if k.startswith("train_")},
-                "held": {k[5:]: z[k] for k in z.files if k.startswith("held_")}}
-        if len(sets["train"]["X"]) != (args.sur_pulses - 1) * len(plans) or \
-                len(sets["held"]["X"]) != (args.sur_pulses - 1) * len(held_plans):
-            raise SystemExit(f"{args.sur_data} was generated with other --sur-plans/--sur-held/--sur-pulses")
-        note(f"training and held-out samples read from {args.sur_data}")
-    if sets is None:
+    if args.sur_load:
+        s = SU.Surrogate(1024)
+        s.load(args.sur_load)
+        note(f"network, normalisation and table read from {args.sur_load}")
+        line_train = {"model": os.path.basename(args.sur_load)}
+    else:
+        t0 = time.perf_counter()
+        rates = tuple(float(r) for r in args.sur_rate_range.split(","))
+        doses = (0.7, 1.3)
+        ints = lambda v: [int(x) for x in str(v).split(",") if x]  # noqa: E731
+        pulses, n_plans, held_runs = ints(args.sur_pulses), ints(args.sur_plans), ints(args.sur_held)
+        if not (len(pulses) == len(n_plans) == len(held_runs)):
+            raise SystemExit("--sur-pulses, --sur-plans and --sur-held take lists of one length")
+        # sets of training runs in the small cube and held-out runs in the large one (its
+        # count noise, ~0.5 % of the H2O2 made per pulse, is small enough for the 1 % table
+        # to mean something), one per pulse count
+        jobs = []
+        for k, (npl, nh, npu) in enumerate(zip(n_plans, held_runs, pulses)):
+            jobs.append(("train", SU.random_plans(args.seed + 1 + 10 * k, npl, L=args.sur_train_L, n_pulses=npu,
+                                                  rates=rates, doses=doses), args.sur_batch, 1000 + 100000 * k, k, npu))
+            jobs.append(("held", SU.random_plans(args.seed + 2 + 10 * k, nh, L=args.sur_L, n_pulses=npu, rates=rates,
+                                                 doses=doses), 32, 2000 + 100000 * k, k, npu))
+        n_train_runs = sum(n_plans)
         sets = {"train": {}, "held": {}}
-        for name, pl_all, bsz, seed0 in (("train", plans, args.sur_batch, 1000), ("held", held_plans, 32, 2000)):
+        for name, pl_all, bsz, seed0, k, npu in jobs:
             dst = sets[name]
             for b0 in range(0, len(pl_all), bsz):
-                d = SU.generate(pl_all[b0:b0 + bsz], seed=seed0 + b0, t_cap=args.sur_cap)
-                for k, v in d.items():
-                    dst[k] = np.concatenate([dst[k], v]) if k in dst else v
+                # with --sur-data every batch is kept in a file of its own, so that a
+                # generation split over several runs resumes where it stopped
+                tag = f"{name}{b0}_{bsz}" + (f"_s{k}p{npu}" if k else "")
+                part = f"{args.sur_data}.{tag}.npz" if args.sur_data else ""
+                if part and os.path.exists(part):
+                    z = np.load(part)
+                    d = {q: z[q] for q in z.files}
+                else:
+                    d = SU.generate(pl_all[b0:b0 + bsz], seed=seed0 + b0, t_cap=args.sur_cap, log=note)
+                    if part:
+                        np.savez(part, **d)
+                for q, v in d.items():
+                    dst[q] = np.concatenate([dst[q], v]) if q in dst else v
                 note(f"{name} samples {len(dst['X'])} after {time.perf_counter() - t0:.1f} s")
+        train, held = sets["train"], sets["held"]
+        t_gen = time.perf_counter() - t0
         if args.sur_data:
-            np.savez(args.sur_data, **{"train_" + k: v for k, v in sets["train"].items()},
-                     **{"held_" + k: v for k, v in sets["held"].items()})
-    train, held = sets["train"], sets["held"]
-    t_gen = time.perf_counter() - t0
-    if args.sur_generate_only:
-        note(f"generated {len(train['X'])} training and {len(held['X'])} held-out samples in {t_gen:.1f} s")
-        return
-    n, n_held = len(train["X"]), len(held["X"])
-    # two candidates, with and without the pair-correlation inputs; one half of the
-    # held-out samples picks the candidate, the other half fills its error table
-    hperm = np.random.default_rng(args.seed + 3).permutation(n_held)
-    sub = lambda d, k: {key: v[k] for key, v in d.items()}  # noqa: E731
-    pick, tab = sub(held, hperm[: n_held // 2]), sub(held, hperm[n_held // 2:])
-    t1 = time.perf_counter()
-    cands = {}
-    for gw in (1.0, 0.0):
-        c = SU.Surrogate(1024)
-        c.init_weights(args.seed)
-        hist = c.fit(train, epochs=60, batch=64, lr=5e-4, log=note, g_weight=gw)
-        e = c.build_table(pick, n_dt=3, n_c=2)
-        cands[gw] = (float(np.quantile(e, 0.95)), float(np.median(e)), c, hist)
-        note(f"pair-correlation weight {gw:g}: held-out relative H2O2 error median {np.median(e):.4f}, "
-             f"p95 {np.quantile(e, 0.95):.4f}")
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
-    gw_best = min(cands, key=lambda k: cands[k][0])
-    s, hist = cands[gw_best][2], cands[gw_best][3]
-    # the half that picked the candidate also gives its mean residual; the table half
-    # then measures the calibrated network
-    bias = s.calibrate(pick)
-    note(f"calibration: mean log10 residual per species {np.round(bias, 5).tolist()}")
-    err = s.build_table(tab, n_dt=3, n_c=2)
-    if args.sur_save:
-        s.save(args.sur_save + "_model.npz")
-        np.savez(args.sur_save + "_held.npz", **held)
-    note(f"chosen weight {gw_best:g}; table half: median {np.median(err):.4f}, p95 {np.quantile(err, 0.95):.4f}; "
-         f"table {np.round(s.table, 4).tolist()} over log10 dt edges {np.round(s.dt_edges, 2).tolist()}, "
-         f"log10 C_tot edges {np.round(s.c_edges, 2).tolist()}")
+            np.savez(args.sur_data, **{"train_" + q: v for q, v in train.items()},
+                     **{"held_" + q: v for q, v in held.items()})
+        if args.sur_generate_only:
+            note(f"generated {len(train['X'])} training and {len(held['X'])} held-out samples in {t_gen:.1f} s")
+            return
+        n, n_held = len(train["X"]), len(held["X"])
+        # two candidates, with and without the pair-correlation inputs; one half of the
+        # held-out samples picks the candidate, the other half fills its error table
+        hperm = np.random.default_rng(args.seed + 3).permutation(n_held)
+        sub = lambda d, k: {key: v[k] for key, v in d.items()}  # noqa: E731
+        pick, tab = sub(held, hperm[: n_held // 2]), sub(held, hperm[n_held // 2:])
+        t1 = time.perf_counter()
+        cands = {}
+        for gw in (1.0, 0.0):
+            c = SU.Surrogate(1024)
+            c.init_weights(args.seed)
+            hist = c.fit(train, epochs=60, batch=64, lr=5e-4, log=note, g_weight=gw)
+            e = c.build_table(pick, n_dt=3, n_c=2)
+            cands[gw] = (float(np.quantile(e, 0.95)), float(np.median(e)), c, hist)
+            note(f"pair-correlation weight {gw:g}: held-out relative H2O2 error median {np.median(e):.4f}, "
+                 f"p95 {np.quantile(e, 0.95):.4f}")
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        gw_best = min(cands, key=lambda k: cands[k][0])
+        s, hist = cands[gw_best][2], cands[gw_best][3]
+        # the half that picked the candidate also gives its mean residual; the table half
+        # then measures the calibrated network
+        bias = s.calibrate(pick)
+        note(f"calibration: mean log10 residual per species {np.round(bias, 5).tolist()}")
+        err = s.build_table(tab, n_dt=3, n_c=2)
+        if args.sur_save:
+            s.save(args.sur_save + "_model.npz")
+            np.savez(args.sur_save + "_held.npz", **held)
+        note(f"chosen weight {gw_best:g}; table half: median {np.median(err):.4f}, p95 {np.quantile(err, 0.95):.4f}; "
+             f"table {np.round(s.table, 4).tolist()} over log10 dt edges {np.round(s.dt_edges, 2).tolist()}, "
+             f"log10 C_tot edges {np.round(s.c_edges, 2).tolist()}")
+        line_train = {
+            "config": {"train_runs": n_plans, "train_L_nm": args.sur_train_L, "train_pulses_per_run": pulses,
+                       "train_avg_rates_gy_s": list(rates), "train_interval_cap_ns": args.sur_cap, "samples": int(n),
+                       "held_out_runs": held_runs, "held_out": int(n_held)},
+            "generate_s": round(t_gen, 1), "train_s": round(t_train, 2), "final_loss": round(hist[-1], 6),
+            "pair_correlation_weight": gw_best, "calibration_log10_bias": [round(float(b), 6) for b in bias],
+            "held_out_h2o2_rel_err_p95_by_weight": {str(k): round(v[0], 5) for k, v in cands.items()},
+            "held_out_h2o2_rel_err_median": round(float(np.median(err)), 5),
+            "held_out_h2o2_rel_err_p95": round(float(np.quantile(err, 0.95)), 5)}
+    note(f"table {np.round(s.table, 4).tolist()}")
     runs = []
     for rate in [float(r) for r in args.sur_rates.split(",") if r]:
-        plan = SU.PulsePlan(args.sur_L, args.seed + 77, 20, 1.0, 1e6, rate)
-        SU.run(SU.PulsePlan(args.sur_L, 5, 2, 1.0, 1e6, rate), None)  # warm the grid tuner
-        plain = SU.run(plan, None)
-        hyb = SU.run(plan, s)
-        # the same with the run's summed error estimate held within the 1 % bar
-        hyb_b = SU.run(plan, s, budget=0.01)
+        plan = SU.PulsePlan(args.sur_L, args.seed + 77, args.sur_eval_pulses, 1.0, 1e6, rate)
+        if args.sur_lean:
+            # long intervals: the hybrid run goes first and warms the grid tuner for the
+            # plain run (its own time includes the exploration); no budget run
+            hyb = SU.run(plan, s, log=note)
+            plain = SU.run(plan, None, log=note)
+            hyb_b = hyb
+        else:
+            note(f"rate {rate:g}: warming the grid tuner")
+            SU.run(SU.PulsePlan(args.sur_L, 5, 2, 1.0, 1e6, rate), None, log=note)
+            plain = SU.run(plan, None, log=note)
+            hyb = SU.run(plan, s, log=note)
+            # the same with the run's summed error estimate held within the 1 % bar
+            hyb_b = SU.run(plan, s, budget=0.01, log=note)
         rel = np.abs(hyb["g_h2o2"] - plain["g_h2o2"]) / plain["g_h2o2"]
         rel_b = np.abs(hyb_b["g_h2o2"] - plain["g_h2o2"]) / plain["g_h2o2"]
         note(f"network intervals {np.nonzero(hyb['used'])[0].tolist()}; H2O2 at pulse starts plain "
@@ -203,8 +243,8 @@ def surrogate_bench(args):
             np.savez(args.sur_save + f"_runs_{rate:g}.npz", **{"plain_" + k: v for k, v in plain.items()},
                      **{"hyb_" + k: v for k, v in hyb.items()})
         note(f"rate {rate:g}: plain {plain['wall']:.2f} s, hybrid {hyb['wall']:.2f} s, network intervals "
-             f"{hyb['intervals_by_network']}/19, max |dG(H2O2)|/G {rel.max():.4f}, end {rel[-1]:.4f}; "
-             f"with the 1 % budget {hyb_b['wall']:.2f} s, {hyb_b['intervals_by_network']}/19 intervals, "
+             f"{hyb['intervals_by_network']}/{args.sur_eval_pulses - 1}, max |dG(H2O2)|/G {rel.max():.4f}, end {rel[-1]:.4f}; "
+             f"with the 1 % budget {hyb_b['wall']:.2f} s, {hyb_b['intervals_by_network']}/{args.sur_eval_pulses - 1} intervals, "
              f"max {rel_b.max():.4f}")
         runs.append(dict(avg_rate_gy_s=rate, wall_plain_s=round(plain["wall"], 3), wall_hybrid_s=round(hyb["wall"], 3),
                          speedup=round(plain["wall"] / hyb["wall"], 3), intervals_by_network=hyb["intervals_by_network"],
@@ -218,21 +258,16 @@ def surrogate_bench(args):
                                           error_estimate_spent=round(hyb_b["error_estimate_spent"], 5),
                                           max_rel_dG_h2o2=round(float(rel_b.max()), 5),
                                           end_rel_dG_h2o2=round(float(rel_b[-1]), 5))))
+        if args.sur_save:  # each rate as it ends
+            with open(args.sur_save + "_runs.jsonl", "a") as f:
+                f.write(json.dumps(runs[-1]) + "\n")
     line = {
-        "metric": "20-pulse wall time, plain SBS / SBS with the inter-pulse network",
+        "metric": f"{args.sur_eval_pulses}-pulse wall time, plain SBS / SBS with the inter-pulse network",
         "value": runs[0]["speedup"] if runs else None, "unit": "x", "higher_is_better": True, "n_gpus": 1,
         "dtype": "f32 SBS, bf16 network with f32 accumulation", "data": "synthetic",
-        "config": {"workload": f"20 pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate 1e6 Gy/s, "
-                               f"2 batches per pulse", "train_runs": len(plans), "train_L_nm": args.sur_train_L,
-                   "train_pulses_per_run": args.sur_pulses, "train_avg_rates_gy_s": list(rates),
-                   "train_interval_cap_ns": args.sur_cap,
-                   "samples": int(n), "held_out_runs": len(held_plans), "held_out": int(n_held)},
-        "train": {"generate_s": round(t_gen, 1), "train_s": round(t_train, 2), "final_loss": round(hist[-1], 6),
-                  "pair_correlation_weight": gw_best,
-                  "calibration_log10_bias": [round(float(b), 6) for b in bias],
-                  "held_out_h2o2_rel_err_p95_by_weight": {str(k): round(v[0], 5) for k, v in cands.items()},
-                  "held_out_h2o2_rel_err_median": round(float(np.median(err)), 5),
-                  "held_out_h2o2_rel_err_p95": round(float(np.quantile(err, 0.95)), 5)},
+        "config": {"workload": f"{args.sur_eval_pulses} pulses x 1 Gy, {args.sur_L:g} nm periodic cube, pulse rate "
+                               f"1e6 Gy/s, 2 batches per pulse"},
+        "train": line_train,
         "runs": runs,
     }
     print(json.dumps(line), flush=True)
@@ -849,6 +884,64 @@ def campaign_bench(args):
     print(json.dumps(line), flush=True)
 
 
+# Algorithmic FLOPs of the perceptron per sample (unpadded layer sizes): the
+# forward products, and a training step's forward, input-gradient (all but the
+# first layer) and weight-gradient products.
+MLP_FWD_FLOP = 2 * (296 * 256 + 3 * 256 * 256 + 256 * 7)
+MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP - 2 * 296 * 256
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_bench(args):
+    """Throughput of the surrogate network's kernels (BF16 MFMA, FP32
+    accumulation): forward passes and training steps on a batch of random
+    inputs, timed with HIP events on the network's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+
+    def note(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    out = {}
+    for B in [int(b) for b in args.mlp_batches.split(",") if b]:
+        net = gsbs.Mlp(B)
+        rng = np.random.default_rng(args.seed)
+        net.set_weights((rng.standard_normal(net.n) * 0.05).astype(np.float32))
+        x = torch.from_numpy(rng.standard_normal((B, gsbs.MLP_IN)).astype(np.float32)).cuda()
+        t = torch.from_numpy(rng.standard_normal((B, gsbs.MLP_OUT)).astype(np.float32)).cuda()
+        y = torch.empty((B, gsbs.MLP_OUT), dtype=torch.float32, device="cuda")
+        res = {}
+        for name, fn, flop in (("forward", lambda: net.forward(x, y), MLP_FWD_FLOP),
+                               ("train_step", lambda: net.train_step(x, t, 1e-6), MLP_TRAIN_FLOP)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.mlp_iters):
+                fn()
+            e1.record()
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3 / args.mlp_iters
+            tf = flop * B / sec / 1e12
+            res[name] = dict(us=round(sec * 1e6, 2), tflops=round(tf, 2), frac_bf16_peak=round(tf / BF16_PEAK_TFLOPS, 5))
+            note(f"batch {B} {name}: {sec * 1e6:.1f} us, {tf:.2f} TFLOP/s ({100 * tf / BF16_PEAK_TFLOPS:.2f} % of bf16 peak)")
+        out[B] = res
+        net.close()
+    big = max(out)
+    line = {"metric": "surrogate network forward throughput", "value": round(big / (out[big]["forward"]["us"] / 1e6), 1),
+            "unit": "samples/s", "higher_is_better": True, "n_gpus": 1, "dtype": "bf16 (fp32 accumulation)",
+            "data": "synthetic", "config": {"workload": "296-256-256-256-256-7 perceptron, erf-GELU",
+                                             "flop_per_sample_forward": MLP_FWD_FLOP,
+                                             "flop_per_sample_train_step": MLP_TRAIN_FLOP},
+            "roofline": {"bound": "mfma", "achieved": out[big]["forward"]["tflops"], "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": out[big]["forward"]["frac_bf16_peak"], "traffic": None},
+            "batches": {str(b): r for b, r in out.items()}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.cpu_steps is None:
@@ -862,6 +955,9 @@ def main():
 
     if args.surrogate:
         surrogate_bench(args)
+        return
+    if args.mlp:
+        mlp_bench(args)
         return
     if args.batched:
         batched_bench(args)

@@ -568,6 +568,9 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     __shared__ float4 wpos_all[GSBS_BLOCK / 64][kWin];
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
     __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 7) | (needs Eq. 2 << 6) | lane
+    __shared__ int2 qinfo_all[GSBS_BLOCK / 64][kNbrQ];  // queued item: first partner, inclusive end of its tests
+    __shared__ int2 oinfo_all[GSBS_BLOCK / 64][64];     // own-cell tests of a lane: inclusive end, run (packed)
+    __shared__ int4 cq_all[GSBS_BLOCK / 64][128];       // candidates: i, j, bits of d2, (instance << 6) | reaction
     __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
     __shared__ float hs_f[5 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, 1/h, cull2_all[]
     __shared__ int hs_i[4];                            // home instance: nc, reach, bin_base, searched here
@@ -583,7 +586,38 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     float4* wpos = wpos_all[threadIdx.x >> 6];
     uint32_t* wbin = wbin_all[threadIdx.x >> 6];
     unsigned long long* nq = nq_all[threadIdx.x >> 6];
+    int2* qinfo = qinfo_all[threadIdx.x >> 6];
+    int2* oinfo = oinfo_all[threadIdx.x >> 6];
+    int4* cq = cq_all[threadIdx.x >> 6];
+    int cqn = 0;  // wave-uniform length of the candidate queue
     unsigned long long ncand = 0;
+    // Candidates of the balanced walks are queued and evaluated 64 at a time, one
+    // per lane (start separation, bridge probability, Philox pair uniform), so
+    // that the evaluation does not run once per candidate with the other lanes
+    // idle.  Every lane of the wave calls these.
+    auto cand_flush = [&](bool all) {
+        while (cqn >= 64 || (all && cqn > 0)) {
+            wave_sync_lds();
+            const int take = cqn < 64 ? cqn : 64;
+            const int rest = cqn - take;
+            int4 e = make_int4(0, 0, 0, 0), r = make_int4(0, 0, 0, 0);
+            if (lane < take) e = cq[lane];
+            if (lane < rest) r = cq[64 + lane];
+            wave_sync_lds();
+            if (lane < rest) cq[lane] = r;
+            cqn = rest;
+            if (lane < take)
+                eval_candidate_call(e.x, e.y, __int_as_float(e.z), pos0, uid, P[e.w >> 6], e.w & 63, contact_only,
+                                    log_all, ctr, pairs, pair_cap);
+        }
+    };
+    auto cand_push = [&](bool c, int ci, int cj, float d2, int inst_c, int rx) {
+        const unsigned long long m = __ballot(c);
+        if (m == 0ull) return;
+        if (c) cq[cqn + (int)__popcll(m & ((1ull << lane) - 1ull))] = make_int4(ci, cj, __float_as_int(d2), (inst_c << 6) | rx);
+        cqn += (int)__popcll(m);
+        if (cqn >= 64) cand_flush(false);
+    };
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const int i0 = base + (threadIdx.x & ~63);
         const int i = i0 + lane;
@@ -679,43 +713,89 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
             const int kc = run_beg + (q >= run_lanes ? q - run_lanes : q);
             return t >= ncyc ? 64 + (t - ncyc) : kc;
         };
-        if (act) {
-            // the largest cutoff of the species screens each partner before its own
-            // cutoff is looked up
-            if (inst == home) {
-                const float* rcrow = rc2s + si * kMaxSpecies;
-                // Partners four at a time (their LDS reads in flight together).  Two
-                // molecules of one cell are less than a cell width apart, below L/2
-                // once an edge holds 3 cells: Eq. 2 then changes nothing and is skipped.
-                auto own_loop = [&](auto plain_tag) {
+        // Own-cell pairs of the home instance's molecules, spread evenly over the
+        // wave: lane o owns nown(o) tests (its cyclic partners in its run, then the
+        // run's members at window positions 64 ..); the wave's T tests are cut into
+        // 64 contiguous chunks, one per lane, and each chunk is walked test by test,
+        // the owner changing where its range ends.  The largest cutoff of the
+        // owner's species screens each partner before its own cutoff is looked up.
+        // Two molecules of one cell are less than a cell width apart, below L/2
+        // once an edge holds 3 cells: Eq. 2 then changes nothing and is skipped.
+        {
+            const int mown = (act && inst == home) ? nown : 0;
+            const int oincl = (int)wave_incl_scan((uint32_t)mown);
+            const int T = wave_last(oincl);
+            if (T > 0) {
+                wave_sync_lds();
+                oinfo[lane] = make_int2(oincl, run_beg | (run_lanes << 6) | (ncyc << 13) | (mown << 19));
+                wave_sync_lds();
+                auto own_walk = [&](auto plain_tag) {
                     constexpr bool kPlain = decltype(plain_tag)::value;
-                    for (int t0 = 0; t0 < nown; t0 += 4) {
-                        float4 pj[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) pj[u] = wpos[own_partner(min(t0 + u, nown - 1))];
-                        float d2[4];
-                        uint32_t pass = 0u;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            d2[u] = kPlain ? sep2(pj[u], pi) : end_d2(pj[u], pi, sL, sHL);
-                            if (t0 + u < nown && d2[u] < cmax) pass |= 1u << u;
+                    const int c0 = (T * lane) >> 6, c1 = (T * (lane + 1)) >> 6;
+                    const int iters = (T + 63) >> 6;  // the longest chunk
+                    int o = 0, t = 0, rb = 0, rl = 1, ncy = 0, mo = 0, so = 0;
+                    int2 oi = make_int2(0, 0);
+                    float4 po = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float cm = 0.0f;
+                    auto load_owner = [&]() {
+                        rb = oi.y & 63;
+                        rl = (oi.y >> 6) & 127;
+                        ncy = (oi.y >> 13) & 63;
+                        mo = oi.y >> 19;
+                        po = wpos[o];
+                        so = __float_as_int(po.w) & (kMaxSpecies - 1);
+                        cm = hs_f[5 + so];
+                    };
+                    if (c0 < c1) {
+                        int lo = 0, hi = 63;  // the first lane whose range ends after c0
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (oinfo[mid].x > c0) hi = mid;
+                            else lo = mid + 1;
                         }
-                        while (pass) {  // rare: the partner is read again
-                            const int u = __ffs(pass) - 1;
-                            pass &= pass - 1u;
-                            const float dd = u == 0 ? d2[0] : (u == 1 ? d2[1] : (u == 2 ? d2[2] : d2[3]));
-                            const int k = own_partner(t0 + u);
-                            const int sj = __float_as_int(wpos[k].w) & 0xFF;
-                            if (!(dd < rcrow[sj])) continue;
-                            ++ncand;
-                            eval_candidate_call(i, i0 + k, dd, pos0, uid, S, row[sj], contact_only, log_all, ctr,
-                                                pairs, pair_cap);
+                        o = lo;
+                        oi = oinfo[o];
+                        t = c0 - (oi.x - (oi.y >> 19));
+                        load_owner();
+                    }
+                    for (int it = 0; it < iters; ++it) {
+                        bool cnd = false;
+                        int cj = 0, crx = 0;
+                        float cd2 = 0.0f;
+                        if (c0 + it < c1) {
+                            if (t == mo) {  // next lane with tests
+                                do {
+                                    ++o;
+                                    oi = oinfo[o];
+                                } while ((oi.y >> 19) == 0 && o < 63);
+                                load_owner();
+                                t = 0;
+                            }
+                            const int q = (o - rb) + 1 + t;
+                            const int k = t >= ncy ? 64 + (t - ncy) : rb + (q >= rl ? q - rl : q);
+                            const float4 pk = wpos[k];
+                            const float d2 = kPlain ? sep2(pk, po) : end_d2(pk, po, hs_f[0], hs_f[1]);
+                            if (d2 < cm) {  // rare
+                                const int sj = __float_as_int(pk.w) & 0xFF;
+                                if (d2 < rc2s[so * kMaxSpecies + sj]) {
+                                    ++ncand;
+                                    cnd = true;
+                                    cj = i0 + k;
+                                    cd2 = d2;
+                                    crx = rmap[so * kMaxSpecies + sj];
+                                }
+                            }
+                            ++t;
                         }
+                        cand_push(cnd, i0 + o, cj, cd2, home, crx);
                     }
                 };
-                if (sNc >= 3) own_loop(std::true_type{});
-                else own_loop(std::false_type{});
-            } else {
+                if (hs_i[0] >= 3) own_walk(std::true_type{});
+                else own_walk(std::false_type{});
+            }
+        }
+        if (act) {
+            if (inst != home) {  // a block straddling two instances: per-lane loop
                 for (int t = 0; t < nown; ++t) {
                     const int k = own_partner(t);
                     const float4 pj = wpos[k];
@@ -762,36 +842,115 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
         const int nitem = act ? nxr * nyr * nzr : 0;
         const int witem = wave_max_i(nitem);
         int qn = 0;
+        // The queued (molecule, cell) items, scanned with the work spread evenly
+        // over the wave: item e holds the tests of its molecule against every
+        // molecule of its cell; the tests of all items are cut into 64 contiguous
+        // chunks, one per lane, walked four at a time (their loads in flight
+        // together), the item changing where its range ends.  Eq. 2 is applied
+        // when some item needs it (a wrapped cell, or a grid too small for
+        // neighbour cells to stay within L/2): elsewhere it is the identity.
         auto drain = [&]() {
             wave_sync_lds();
+            int carry = 0;
+            bool eq2 = false;
             for (int e0 = 0; e0 < qn; e0 += 64) {
                 const bool has = e0 + lane < qn;
                 const unsigned long long it = has ? nq[e0 + lane] : 0ull;
-                // Eq. 2 only where some item of the pass needs it (a wrapped cell, or a
-                // grid too small for neighbour cells to stay within L/2)
-                const bool eq2 = __ballot(has && ((it >> 6) & 1ull)) != 0ull;
+                int j0 = 0, cnt = 0;
                 if (has) {
-                    const int ml = (int)(it & 63ull);
                     const int b = (int)(it >> 7);
-                    const float4 pm = wpos[ml];
-                    const int mm = __float_as_int(pm.w);
-                    const int sm = mm & (kMaxSpecies - 1);
-                    const InstStep& Sm = P[mm >> 8];
-                    float cm, Lm, hLm;
-                    if ((mm >> 8) == home) {
-                        cm = hs_f[5 + sm], Lm = hs_f[0], hLm = hs_f[1];
-                    } else {
-                        cm = Sm.cull2_all[sm], Lm = Sm.L, hLm = Sm.halfL;
-                    }
-                    if (eq2)
-                        scan_run<true>(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid,
-                                       Sm, rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
-                                       ncand);
-                    else
-                        scan_run<false>(i0 + ml, pm, (int)start[b], (int)start[b + 1], cm, Lm, hLm, pos, pos0, uid,
-                                        Sm, rmap + sm * kMaxSpecies, contact_only, log_all, ctr, pairs, pair_cap,
-                                        ncand);
+                    j0 = (int)start[b];
+                    cnt = (int)start[b + 1] - j0;
                 }
+                eq2 = eq2 || __ballot(has && ((it >> 6) & 1ull)) != 0ull;
+                const int inc = (int)wave_incl_scan((uint32_t)cnt) + carry;
+                if (has) qinfo[e0 + lane] = make_int2(j0, inc);
+                carry = wave_last(inc);
+            }
+            const int T = carry;
+            wave_sync_lds();
+            auto walk = [&](auto eq2_tag) {
+                constexpr bool kEq2 = decltype(eq2_tag)::value;
+                const int c0 = (int)(((long long)T * lane) >> 6), c1 = (int)(((long long)T * (lane + 1)) >> 6);
+                const int iters = ((T + 63) / 64 + 1) / 2;  // pairs of tests in the longest chunk
+                int e = 0, ebeg = 0, t = 0;
+                int2 qi = make_int2(0, 0);
+                if (c0 < c1) {
+                    int lo = 0, hi = qn - 1;  // the first item whose range ends after c0
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (qinfo[mid].y > c0) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    e = lo;
+                    qi = qinfo[e];
+                    ebeg = e ? qinfo[e - 1].y : 0;  // first test of item e
+                    t = c0 - ebeg;
+                }
+                int ecur = -1;  // item whose molecule data are loaded
+                float4 pm = make_float4(0.f, 0.f, 0.f, 0.f);
+                float cm = 0.0f, Lm = 0.0f, hLm = 0.0f;
+                int im = 0, rowo = 0, ml = 0;
+                for (int it = 0; it < iters; ++it) {
+                    const int g0 = c0 + 2 * it;
+                    int eu[2], ju[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        eu[u] = -1;
+                        ju[u] = 0;
+                        if (g0 + u < c1) {
+                            while (ebeg + t >= qi.y) {  // next item with tests
+                                ebeg = qi.y;
+                                ++e;
+                                qi = qinfo[e];
+                                t = 0;
+                            }
+                            eu[u] = e;
+                            ju[u] = qi.x + t;
+                            ++t;
+                        }
+                    }
+                    float4 pj[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) pj[u] = eu[u] >= 0 ? pos[ju[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        bool cnd = false;
+                        int crx = 0;
+                        float cd2 = 0.0f;
+                        if (eu[u] >= 0) {
+                            if (eu[u] != ecur) {
+                                ecur = eu[u];
+                                ml = (int)(nq[ecur] & 63ull);
+                                pm = wpos[ml];
+                                const int mm = __float_as_int(pm.w);
+                                const int sm = mm & (kMaxSpecies - 1);
+                                im = mm >> 8;
+                                rowo = sm * kMaxSpecies;
+                                if (im == home) {
+                                    cm = hs_f[5 + sm], Lm = hs_f[0], hLm = hs_f[1];
+                                } else {
+                                    cm = P[im].cull2_all[sm], Lm = P[im].L, hLm = P[im].halfL;
+                                }
+                            }
+                            const float d2 = kEq2 ? end_d2(pj[u], pm, Lm, hLm) : sep2(pj[u], pm);
+                            if (d2 < cm) {  // rare
+                                const int rx = rmap[rowo + (__float_as_int(pj[u].w) & 0xFF)];
+                                if (rx >= 0 && d2 < P[im].rc2[rx]) {
+                                    ++ncand;
+                                    cnd = true;
+                                    crx = rx;
+                                    cd2 = d2;
+                                }
+                            }
+                        }
+                        cand_push(cnd, i0 + ml, ju[u], cd2, im, crx);
+                    }
+                }
+            };
+            if (T > 0) {
+                if (eq2) walk(std::true_type{});
+                else walk(std::false_type{});
             }
             wave_sync_lds();
             qn = 0;
@@ -826,10 +985,11 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
                         ((unsigned long long)(uint32_t)(sBase + c2) << 7) |
                         ((wrapped || !near_ok) ? 64ull : 0ull) | (unsigned long long)lane;
                 qn += __popcll(bal);
-                if (qn > kNbrQ - 64) drain();
             }
+            // one call site of the drain: when the queue is nearly full, and after the last item
+            if (qn > kNbrQ - 64 || (it + 1 == witem && qn > 0)) drain();
         }
-        if (qn > 0) drain();
+        cand_flush(true);  // the window and its wave's tables are reused by the next iteration
     }
     for (int d = 32; d >= 1; d >>= 1) ncand += __shfl_xor(ncand, d, 64);
     if (lane == 0 && ncand) atomicAdd(&s_cand, ncand);
@@ -1154,13 +1314,21 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
     int qn = 0;  // wave-uniform queue length
     unsigned long long ncand = 0;
     const InstStep* Sq = nullptr;
+    // first work item of each instance, one per lane (up to 64 instances)
+    const int ub_lane = lane < n_inst ? P[lane].unit_base : 0x7FFFFFFF;
     for (int u = blockIdx.x * waves + (threadIdx.x >> 6); u < total_units; u += gridDim.x * waves) {
-        // instance owning work item u (instances own consecutive ranges)
-        int lo_i = 0, hi_i = n_inst - 1;
-        while (lo_i < hi_i) {
-            const int mid = (lo_i + hi_i + 1) >> 1;
-            if (P[mid].unit_base <= u) lo_i = mid;
-            else hi_i = mid - 1;
+        // instance owning work item u (instances own consecutive ranges, in order):
+        // the last one whose first item is at most u
+        int lo_i = 0;
+        if (n_inst <= 64) {
+            lo_i = __popcll(__ballot(ub_lane <= u)) - 1;
+        } else {
+            int hi_i = n_inst - 1;
+            while (lo_i < hi_i) {
+                const int mid = (lo_i + hi_i + 1) >> 1;
+                if (P[mid].unit_base <= u) lo_i = mid;
+                else hi_i = mid - 1;
+            }
         }
         const InstStep& S = P[lo_i];
         if (!S.active || !S.by_species) continue;

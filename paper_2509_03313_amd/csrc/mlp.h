@@ -15,8 +15,10 @@ constexpr int kMlpHidden = 256;
 constexpr int kMlpOut = 7;
 constexpr int kMlpLayers = 5;
 
+// C = A B^T; work (work_elems floats, may be null) holds the partial products
+// when the reduction is split.
 void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
-                 int N, int K);
+                 int N, int K, float* work, size_t work_elems);
 void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp);
 void mlp_epilogue(hipStream_t st, const float* C, const float* bias, int B, int Mp, int Np, int n_valid, int hidden,
                   float* Z, uint16_t* A, uint16_t* AT, float* Y);
@@ -24,7 +26,8 @@ void mlp_loss(hipStream_t st, const float* Y, const float* T, int B, int n_out, 
               uint16_t* dZb, uint16_t* dZT, float* loss);
 void mlp_act_grad(hipStream_t st, const float* dA, const float* Z, int B, int Mp, int Np, int n_valid, float* dZ,
                   uint16_t* dZb, uint16_t* dZT);
-void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db);
+// Column sums of dZ; work holds ceil(Mp / 512) x Np partial sums.
+void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db, float* work);
 void mlp_adam(hipStream_t st, float* w, float* m1, float* m2, const float* grad, int64_t n, int rows, int cols,
               float lr, float beta1, float beta2, float eps, float c1, float c2, uint16_t* wb, uint16_t* wbt);
 void mlp_cast(hipStream_t st, const float* w, int64_t n, int rows, int cols, uint16_t* wb, uint16_t* wbt);

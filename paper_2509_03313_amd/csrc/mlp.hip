@@ -8,6 +8,8 @@
 // one kernel serves the forward product (X W^T), the input gradient
 // (dZ (W^T)^T) and the weight gradient (dZ^T (X^T)^T): the producers also
 // write the transposed copies the products need.
+#include <algorithm>
+
 #include "mlp.h"
 
 namespace gsbs {
@@ -44,7 +46,9 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // fragments from there: lane l feeds row l%16 of an A tile and of a B tile
 // with the 8 values k = 8 (l/16) .. +7 and receives C[4 (l/16) + i][l%16],
 // i = 0..3, of each tile.  M, N, K are multiples of 32 (zero padded); rows
-// beyond M or N of a partial tile load zeros and store nothing.
+// beyond M or N of a partial tile load zeros and store nothing.  With a split
+// of the reduction (blockIdx.z > 0 possible) block z sums k in [z kc, z kc + kc)
+// and writes its partial product to C + z M ldc; k_sum_splits adds them up.
 constexpr int kGemmTile = 64;
 constexpr int kGemmK = 32;
 constexpr int kGemmPad = 8;  // BF16 values of row padding in LDS
@@ -52,10 +56,12 @@ constexpr int kGemmPad = 8;  // BF16 values of row padding in LDS
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restrict__ A, int32_t lda,
                                                      const uint16_t* __restrict__ B, int32_t ldb,
                                                      float* __restrict__ C, int32_t ldc, int32_t M, int32_t N,
-                                                     int32_t K) {
+                                                     int32_t K, int32_t kc) {
     __shared__ __align__(16) uint16_t sa[kGemmTile][kGemmK + kGemmPad];
     __shared__ __align__(16) uint16_t sb[kGemmTile][kGemmK + kGemmPad];
     const int bm = blockIdx.y * kGemmTile, bn = blockIdx.x * kGemmTile;
+    const int kbeg = blockIdx.z * kc, kend = min(K, kbeg + kc);
+    C += (size_t)blockIdx.z * M * ldc;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lr = t >> 2, lq = (t & 3) * 8;  // loader: row and 8-value chunk of the K slice
@@ -68,7 +74,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restric
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    for (int k0 = kbeg; k0 < kend; k0 += kGemmK) {
         const uint4 ra = va ? *reinterpret_cast<const uint4*>(pa + k0) : make_uint4(0u, 0u, 0u, 0u);
         const uint4 rb = vb ? *reinterpret_cast<const uint4*>(pb + k0) : make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();  // the previous slice has been read
@@ -96,8 +102,20 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restric
             }
 }
 
-// Input features (FP32, rows of n_in) -> BF16 activations X [Mp x Kp] and X^T
-// [Kp x Mp], zero padded.
+// Sum of ns partial products work[z][M][ldc] into C[M][ldc] (columns < N),
+// in a fixed order.
+__global__ void k_sum_splits(const float* __restrict__ work, int32_t ns, int32_t M, int32_t N, int32_t ldc,
+                             float* __restrict__ C) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    const int r = (int)(e / N), c = (int)(e % N);
+    float s = 0.0f;
+    for (int z = 0; z < ns; ++z) s += work[((size_t)z * M + r) * ldc + c];
+    C[(size_t)r * ldc + c] = s;
+}
+
+// Input features (FP32, rows of n_in) -> BF16 activations X [Mp x Kp] and,
+// unless XT is null, X^T [Kp x Mp], zero padded.
 __global__ void k_mlp_input(const float* __restrict__ x, int32_t B, int32_t n_in, uint16_t* __restrict__ X,
                             uint16_t* __restrict__ XT, int32_t Mp, int32_t Kp) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,7 +124,7 @@ __global__ void k_mlp_input(const float* __restrict__ x, int32_t B, int32_t n_in
     const float v = (m < B && k < n_in) ? x[(size_t)m * n_in + k] : 0.0f;
     const uint16_t h = to_bf16(v);
     X[e] = h;
-    XT[(size_t)k * Mp + m] = h;
+    if (XT) XT[(size_t)k * Mp + m] = h;
 }
 
 // Z = C + bias; hidden layers: A = BF16(GELU(Z)) and its transpose (rows >= B
@@ -119,11 +137,11 @@ __global__ void k_mlp_epilogue(const float* __restrict__ C, const float* __restr
     const int m = (int)(e / Np), n = (int)(e % Np);
     const bool valid = m < B && n < n_valid;
     const float z = valid ? C[e] + bias[n] : 0.0f;
-    if (hidden) {
-        Z[e] = z;
+    if (hidden) {  // Z and AT are kept for a backward pass only
+        if (Z) Z[e] = z;
         const uint16_t h = to_bf16(valid ? gelu(z) : 0.0f);
         A[e] = h;
-        AT[(size_t)n * Mp + m] = h;
+        if (AT) AT[(size_t)n * Mp + m] = h;
     } else if (valid) {
         Y[(size_t)m * n_valid + n] = z;
     }
@@ -169,12 +187,21 @@ __global__ void k_mlp_act_grad(const float* __restrict__ dA, const float* __rest
 }
 
 // Bias gradient: column sums of dZ over the batch (one thread per column).
-__global__ void k_mlp_colsum(const float* __restrict__ dZ, int32_t Mp, int32_t Np, float* __restrict__ db) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= Np) return;
+// Column sums of dZ [Mp][Np] over a chunk of rows per blockIdx.y: 64 columns
+// per block, 4 rows at a time; the partial sums go to part[chunk][Np].
+constexpr int kColRows = 512;
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_colsum(const float* __restrict__ dZ, int32_t Mp, int32_t Np,
+                                                         float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kColRows, r1 = min(Mp, r0 + kColRows);
     float s = 0.0f;
-    for (int m = 0; m < Mp; ++m) s += dZ[(size_t)m * Np + n];
-    db[n] = s;
+    if (c < Np)
+        for (int r = r0 + q; r < r1; r += 4) s += dZ[(size_t)r * Np + c];
+    red[q][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (q == 0 && c < Np) part[(size_t)blockIdx.y * Np + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                             (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 // Adam on one parameter block; the BF16 copy (and its transpose for weight
@@ -214,9 +241,25 @@ __global__ void k_mlp_cast(const float* __restrict__ w, int64_t n, int32_t rows,
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kMlpBlock - 1) / kMlpBlock); }
 
 void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
-                 int N, int K) {
-    const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+                 int N, int K, float* work, size_t work_elems) {
+    const int tiles = ((N + kGemmTile - 1) / kGemmTile) * ((M + kGemmTile - 1) / kGemmTile);
+    // few output tiles over a long reduction (the weight gradients, K = batch):
+    // split K so that the launch fills the device, partial products in work
+    int ns = 1;
+    if (work && tiles < 256 && K >= 1024) {
+        ns = std::min(std::min(64, K / 512), std::max(1, 512 / tiles));
+        ns = (int)std::min<size_t>((size_t)ns, work_elems / ((size_t)M * ldc));
+        ns = std::max(ns, 1);
+    }
+    const int kc = ns > 1 ? ((K + ns - 1) / ns + kGemmK - 1) / kGemmK * kGemmK : K;
+    ns = (K + kc - 1) / kc;
+    const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, ns);
+    if (ns == 1) {
+        hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K, K);
+        return;
+    }
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, work, ldc, M, N, K, kc);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N)), dim3(kMlpBlock), 0, st, work, ns, M, N, ldc, C);
 }
 void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp) {
     hipLaunchKernelGGL(k_mlp_input, dim3(blocks_for((int64_t)Mp * Kp)), dim3(kMlpBlock), 0, st, x, B, n_in, X, XT,
@@ -237,8 +280,10 @@ void mlp_act_grad(hipStream_t st, const float* dA, const float* Z, int B, int Mp
     hipLaunchKernelGGL(k_mlp_act_grad, dim3(blocks_for((int64_t)Mp * Np)), dim3(kMlpBlock), 0, st, dA, Z, B, Mp, Np,
                        n_valid, dZ, dZb, dZT);
 }
-void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db) {
-    hipLaunchKernelGGL(k_mlp_colsum, dim3(blocks_for(Np)), dim3(kMlpBlock), 0, st, dZ, Mp, Np, db);
+void mlp_colsum(hipStream_t st, const float* dZ, int Mp, int Np, float* db, float* work) {
+    const int chunks = (Mp + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(k_mlp_colsum, dim3((Np + 63) / 64, chunks), dim3(kMlpBlock), 0, st, dZ, Mp, Np, work);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(Np)), dim3(kMlpBlock), 0, st, work, chunks, 1, Np, Np, db);
 }
 void mlp_adam(hipStream_t st, float* w, float* m1, float* m2, const float* grad, int64_t n, int rows, int cols,
               float lr, float beta1, float beta2, float eps, float c1, float c2, uint16_t* wb, uint16_t* wbt) {

@@ -2,6 +2,7 @@
 // gsbs_mlp_*): device buffers, forward pass, backward pass, Adam.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -71,6 +72,9 @@ struct gsbs_mlp {
     uint16_t *act[kMlpLayers] = {}, *actT[kMlpLayers] = {};
     float* Z[kMlpLayers] = {};
     float *C = nullptr, *Y = nullptr, *dZ = nullptr, *dA = nullptr, *loss = nullptr;
+    // partial products of split reductions (weight gradients, bias gradients)
+    float* work = nullptr;
+    size_t work_elems = 0;
     uint16_t *dZb = nullptr, *dZT = nullptr;
     std::vector<void*> owned;
 };
@@ -113,15 +117,17 @@ int copy_params(gsbs_mlp* m, float* const* dev_w, float* const* dev_b, const flo
     return GSBS_OK;
 }
 
-int forward(gsbs_mlp* m, const float* x, int B, float* y) {
+// train: also keep what the backward pass reads (pre-activations, transposed
+// activations).
+int forward(gsbs_mlp* m, const float* x, int B, float* y, bool train) {
     const int Mp = pad32(B);
-    mlp_input(m->st, x, B, kMlpIn, m->act[0], m->actT[0], Mp, kShape[0].K);
+    mlp_input(m->st, x, B, kMlpIn, m->act[0], train ? m->actT[0] : nullptr, Mp, kShape[0].K);
     for (int l = 0; l < kMlpLayers; ++l) {
         const Shape& s = kShape[l];
-        mlp_gemm_nt(m->st, m->act[l], s.K, m->wb[l], s.K, m->C, s.N, Mp, s.N, s.K);
+        mlp_gemm_nt(m->st, m->act[l], s.K, m->wb[l], s.K, m->C, s.N, Mp, s.N, s.K, nullptr, 0);
         const bool hidden = l + 1 < kMlpLayers;
-        mlp_epilogue(m->st, m->C, m->b[l], B, Mp, s.N, s.nv, hidden ? 1 : 0, m->Z[l], hidden ? m->act[l + 1] : nullptr,
-                     hidden ? m->actT[l + 1] : nullptr, y);
+        mlp_epilogue(m->st, m->C, m->b[l], B, Mp, s.N, s.nv, hidden ? 1 : 0, train ? m->Z[l] : nullptr,
+                     hidden ? m->act[l + 1] : nullptr, (hidden && train) ? m->actT[l + 1] : nullptr, y);
     }
     MHIP(hipGetLastError());
     return GSBS_OK;
@@ -168,6 +174,11 @@ int gsbs_mlp_create(int32_t max_batch, void* stream, gsbs_mlp** out) {
          (r = own(m, &m->dA, wide)) || (r = own(m, &m->loss, 1)) || (r = own(m, &m->dZb, wide)) ||
          (r = own(m, &m->dZT, wide)))) {
     }
+    // split reductions: at most 64 slices (and Mp / 512) of the largest weight
+    // gradient, and the column-sum chunks
+    const size_t slices = std::min<size_t>(64, (size_t)Mp / 512 + 1);
+    m->work_elems = std::max(slices * (size_t)kMlpHidden * kShape[0].K, ((size_t)Mp / 512 + 1) * kShape[0].K);
+    if (r == GSBS_OK) r = own(m, &m->work, m->work_elems);
     if (r == GSBS_OK && hipStreamSynchronize(m->st) != hipSuccess) r = set_error(GSBS_EHIP, "stream");
     if (r != GSBS_OK) {
         for (void* p : m->owned) (void)hipFree(p);
@@ -220,7 +231,7 @@ int gsbs_mlp_get_grads(gsbs_mlp* m, float* g, int64_t n) {
 int gsbs_mlp_forward(gsbs_mlp* m, const float* x, int32_t batch, float* y) {
     MCHK(check(m, x, batch));
     if (!y) return set_error(GSBS_EINVAL, "null");
-    return forward(m, x, batch, y);
+    return forward(m, x, batch, y, false);
 }
 
 // Forward pass for the surrogate hand-over of gsbs_advance_to: x, y device
@@ -253,18 +264,18 @@ int gsbs_mlp_backward(gsbs_mlp* m, const float* x, const float* t, int32_t batch
     MCHK(check(m, x, batch));
     if (!t) return set_error(GSBS_EINVAL, "null");
     const int B = batch, Mp = pad32(batch);
-    MCHK(forward(m, x, B, m->Y));
+    MCHK(forward(m, x, B, m->Y, true));
     MHIP(hipMemsetAsync(m->loss, 0, 4, m->st));
     const Shape& so = kShape[kMlpLayers - 1];
     mlp_loss(m->st, m->Y, t, B, kMlpOut, Mp, so.N, m->dZ, m->dZb, m->dZT, m->loss);
     for (int l = kMlpLayers - 1; l >= 0; --l) {
         const Shape& s = kShape[l];
         // dW = dZ^T X, db = column sums of dZ
-        mlp_gemm_nt(m->st, m->dZT, Mp, m->actT[l], Mp, m->gw[l], s.K, s.N, s.K, Mp);
-        mlp_colsum(m->st, m->dZ, Mp, s.N, m->gb[l]);
+        mlp_gemm_nt(m->st, m->dZT, Mp, m->actT[l], Mp, m->gw[l], s.K, s.N, s.K, Mp, m->work, m->work_elems);
+        mlp_colsum(m->st, m->dZ, Mp, s.N, m->gb[l], m->work);
         if (l == 0) break;
         // dA = dZ W, then dZ of the layer below through GELU'
-        mlp_gemm_nt(m->st, m->dZb, s.N, m->wbt[l], s.N, m->dA, s.K, Mp, s.K, s.N);
+        mlp_gemm_nt(m->st, m->dZb, s.N, m->wbt[l], s.N, m->dA, s.K, Mp, s.K, s.N, nullptr, 0);
         mlp_act_grad(m->st, m->dA, m->Z[l - 1], B, Mp, s.K, kShape[l - 1].nv, m->dZ, m->dZb, m->dZT);
     }
     MHIP(hipGetLastError());

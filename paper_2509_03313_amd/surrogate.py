@@ -345,7 +345,7 @@ def set_on(e: gsbs.Engine, surrogate: "Surrogate", tol: float = 0.01, budget: Op
 
 
 def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, tol: float = 0.01,
-        budget: Optional[float] = None, numodes_rtol: Optional[float] = None) -> dict:
+        budget: Optional[float] = None, numodes_rtol: Optional[float] = None, log=None) -> dict:
     """Plain (surrogate None) or hybrid multi-pulse run of one cube.  Returns
     the H2O2 count and G(H2O2) at every pulse start after the first and at the
     end, the wall time and the number of intervals the network took.
@@ -377,7 +377,11 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     t0 = time.perf_counter()
     if surrogate is not None:
         set_on(e, surrogate, tol, budget)
-        e.advance_to(t_nx[-1], gsbs.GSBS_SURROGATE)
+        # pulse by pulse (the hand-over points of each interval lie inside one call)
+        for p in range(n):
+            e.advance_to(t_nx[p], gsbs.GSBS_SURROGATE)
+            if log:
+                log(f"hybrid run: pulse {p + 1}/{n} started, {time.perf_counter() - t0:.1f} s")
         lg = gsbs.gsbs_get_handover_log(e.ctx, 0)
         for ts, tk, est in zip(lg["t_switch"], lg["taken"], lg["estimate"]):
             p = int(np.argmin(np.abs(np.array(t_sw) - ts)))
@@ -398,7 +402,10 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
                 e.advance_to(t_nx[p])
         e.advance_to(t_nx[-1])  # takes the records at the last pulse start
     else:
-        e.advance_to(t_nx[-1])
+        for p in range(n):
+            e.advance_to(t_nx[p])
+            if log:
+                log(f"plain run: pulse {p + 1}/{n} started, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     counts = e.counts(0)
