@@ -569,7 +569,6 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     __shared__ uint32_t wbin_all[GSBS_BLOCK / 64][kWin];
     __shared__ unsigned long long nq_all[GSBS_BLOCK / 64][kNbrQ];  // (global bin << 7) | (needs Eq. 2 << 6) | lane
     __shared__ int2 qinfo_all[GSBS_BLOCK / 64][kNbrQ];  // queued item: first partner, inclusive end of its tests
-    __shared__ int2 oinfo_all[GSBS_BLOCK / 64][64];     // own-cell tests of a lane: inclusive end, run (packed)
     __shared__ int4 cq_all[GSBS_BLOCK / 64][128];       // candidates: i, j, bits of d2, (instance << 6) | reaction
     __shared__ float rc2s[kMaxSpecies * kMaxSpecies];  // squared cutoffs of the home instance, -1: no reaction
     __shared__ float hs_f[5 + kMaxSpecies];            // home instance: L, L/2, h, cull_eps, 1/h, cull2_all[]
@@ -587,7 +586,6 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
     uint32_t* wbin = wbin_all[threadIdx.x >> 6];
     unsigned long long* nq = nq_all[threadIdx.x >> 6];
     int2* qinfo = qinfo_all[threadIdx.x >> 6];
-    int2* oinfo = oinfo_all[threadIdx.x >> 6];
     int4* cq = cq_all[threadIdx.x >> 6];
     int cqn = 0;  // wave-uniform length of the candidate queue
     unsigned long long ncand = 0;
@@ -713,85 +711,48 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
             const int kc = run_beg + (q >= run_lanes ? q - run_lanes : q);
             return t >= ncyc ? 64 + (t - ncyc) : kc;
         };
-        // Own-cell pairs of the home instance's molecules, spread evenly over the
-        // wave: lane o owns nown(o) tests (its cyclic partners in its run, then the
-        // run's members at window positions 64 ..); the wave's T tests are cut into
-        // 64 contiguous chunks, one per lane, and each chunk is walked test by test,
-        // the owner changing where its range ends.  The largest cutoff of the
-        // owner's species screens each partner before its own cutoff is looked up.
-        // Two molecules of one cell are less than a cell width apart, below L/2
-        // once an edge holds 3 cells: Eq. 2 then changes nothing and is skipped.
+        // Own-cell pairs of the home instance's molecules: each lane takes its
+        // nown cyclic partners in its run (then the run's members at window
+        // positions 64 ..), four at a time with their LDS reads in flight
+        // together, in a loop as long as the wave's longest list; candidates go
+        // to the wave's queue.  The largest cutoff of the owner's species screens
+        // each partner before its own cutoff is looked up.  Two molecules of one
+        // cell are less than a cell width apart, below L/2 once an edge holds 3
+        // cells: Eq. 2 then changes nothing and is skipped.
         {
             const int mown = (act && inst == home) ? nown : 0;
-            const int oincl = (int)wave_incl_scan((uint32_t)mown);
-            const int T = wave_last(oincl);
-            if (T > 0) {
-                wave_sync_lds();
-                oinfo[lane] = make_int2(oincl, run_beg | (run_lanes << 6) | (ncyc << 13) | (mown << 19));
-                wave_sync_lds();
-                auto own_walk = [&](auto plain_tag) {
+            const int wmax = wave_max_i(mown);
+            if (wmax > 0) {
+                const float* rcrow = rc2s + (si & (kMaxSpecies - 1)) * kMaxSpecies;
+                auto own_loop = [&](auto plain_tag) {
                     constexpr bool kPlain = decltype(plain_tag)::value;
-                    const int c0 = (T * lane) >> 6, c1 = (T * (lane + 1)) >> 6;
-                    const int iters = (T + 63) >> 6;  // the longest chunk
-                    int o = 0, t = 0, rb = 0, rl = 1, ncy = 0, mo = 0, so = 0;
-                    int2 oi = make_int2(0, 0);
-                    float4 po = make_float4(0.f, 0.f, 0.f, 0.f);
-                    float cm = 0.0f;
-                    auto load_owner = [&]() {
-                        rb = oi.y & 63;
-                        rl = (oi.y >> 6) & 127;
-                        ncy = (oi.y >> 13) & 63;
-                        mo = oi.y >> 19;
-                        po = wpos[o];
-                        so = __float_as_int(po.w) & (kMaxSpecies - 1);
-                        cm = hs_f[5 + so];
-                    };
-                    if (c0 < c1) {
-                        int lo = 0, hi = 63;  // the first lane whose range ends after c0
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (oinfo[mid].x > c0) hi = mid;
-                            else lo = mid + 1;
+                    for (int t0 = 0; t0 < wmax; t0 += 4) {
+                        float4 pj[4];
+                        int kk[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            kk[u] = own_partner(min(t0 + u, max(mown - 1, 0)));
+                            pj[u] = wpos[kk[u]];
                         }
-                        o = lo;
-                        oi = oinfo[o];
-                        t = c0 - (oi.x - (oi.y >> 19));
-                        load_owner();
-                    }
-                    for (int it = 0; it < iters; ++it) {
-                        bool cnd = false;
-                        int cj = 0, crx = 0;
-                        float cd2 = 0.0f;
-                        if (c0 + it < c1) {
-                            if (t == mo) {  // next lane with tests
-                                do {
-                                    ++o;
-                                    oi = oinfo[o];
-                                } while ((oi.y >> 19) == 0 && o < 63);
-                                load_owner();
-                                t = 0;
-                            }
-                            const int q = (o - rb) + 1 + t;
-                            const int k = t >= ncy ? 64 + (t - ncy) : rb + (q >= rl ? q - rl : q);
-                            const float4 pk = wpos[k];
-                            const float d2 = kPlain ? sep2(pk, po) : end_d2(pk, po, hs_f[0], hs_f[1]);
-                            if (d2 < cm) {  // rare
-                                const int sj = __float_as_int(pk.w) & 0xFF;
-                                if (d2 < rc2s[so * kMaxSpecies + sj]) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float d2 = kPlain ? sep2(pj[u], pi) : end_d2(pj[u], pi, sL, sHL);
+                            bool cnd = false;
+                            int crx = 0;
+                            if (t0 + u < mown && d2 < cmax) {  // rare
+                                const int sj = __float_as_int(pj[u].w) & 0xFF;
+                                if (d2 < rcrow[sj]) {
                                     ++ncand;
                                     cnd = true;
-                                    cj = i0 + k;
-                                    cd2 = d2;
-                                    crx = rmap[so * kMaxSpecies + sj];
+                                    crx = row[sj];
                                 }
                             }
-                            ++t;
+                            cand_push(cnd, i, i0 + kk[u], d2, home, crx);
                         }
-                        cand_push(cnd, i0 + o, cj, cd2, home, crx);
                     }
                 };
-                if (hs_i[0] >= 3) own_walk(std::true_type{});
-                else own_walk(std::false_type{});
+                if (hs_i[0] >= 3) own_loop(std::true_type{});
+                else own_loop(std::false_type{});
             }
         }
         if (act) {
