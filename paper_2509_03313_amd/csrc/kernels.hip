@@ -1100,16 +1100,22 @@ __device__ __forceinline__ void mask_push(uint32_t& m, float d2, float rc2) {
 // cutoff of this lane's A (a superset: rc2 comes with a relative margin of
 // 2^-19 over the exact FP32 test, which the candidate stage applies).  The
 // tests run from t = 31 down so that doubling the mask lands bit t at t.
+// Entries from nb on are padding (their bits are 0): blocks of 8 that hold
+// only padding are skipped, which leaves every bit where it was since they
+// are the first blocks of their half to run.
 template <bool kShift, bool kSame>
 __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, int ia, float rc2, float L, float hL,
-                                           uint32_t& mlo, uint32_t& mhi) {
+                                           int nb, uint32_t& mlo, uint32_t& mhi) {
     uint32_t half[2];
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
         uint32_t m = 0u;
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) {
-            const int t = 32 * g + 31 - kk;
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            if (32 * g + 24 - 8 * blk >= nb) continue;  // only padding (wave-uniform)
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+            const int t = 32 * g + 31 - 8 * blk - kk;
             float dx, dy, dz;
             // a stage whose shifts are exact screens the staged positions moved by
             // their shift (equal to the unmoved ones where the shift is 0)
@@ -1129,6 +1135,7 @@ __device__ __forceinline__ void stage_mask(const SpWave& w, const float4& pa, in
             float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __fmul_rn(dz, dz)));
             if (kSame) d2 = (__float_as_int(p.w) > ia) ? d2 : INFINITY;  // each pair once
             mask_push(m, d2, rc2);
+            }
         }
         half[g] = m;
     }
@@ -1521,14 +1528,15 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
                         wave_sync_lds();
                         if (b + 64 < p1) fetch(b + 64, fp, fq, fj, fc);
                         uint32_t mlo, mhi;
+                        const int nbs = p1 - b;  // staged entries that are partners (the rest is padding)
                         if (exact) {
-                            if (same) stage_mask<true, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                            else stage_mask<true, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                            if (same) stage_mask<true, true>(w, pa, ia, rc2m, L, hL, nbs, mlo, mhi);
+                            else stage_mask<true, false>(w, pa, ia, rc2m, L, hL, nbs, mlo, mhi);
                             stage_candidates<true>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S, contact_only,
                                                    log_all, ctr, pairs, pair_cap, ncand);
                         } else {
-                            if (same) stage_mask<false, true>(w, pa, ia, rc2m, L, hL, mlo, mhi);
-                            else stage_mask<false, false>(w, pa, ia, rc2m, L, hL, mlo, mhi);
+                            if (same) stage_mask<false, true>(w, pa, ia, rc2m, L, hL, nbs, mlo, mhi);
+                            else stage_mask<false, false>(w, pa, ia, rc2m, L, hL, nbs, mlo, mhi);
                             stage_candidates<false>(w, mlo, mhi, lane, rx, Rr, inv_s, rc2, L, hL, qn, uid, S,
                                                     contact_only, log_all, ctr, pairs, pair_cap, ncand);
                         }

@@ -373,6 +373,7 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     e.set_records(0, rec)
     used = np.zeros(n, dtype=bool)
     spent = 0.0
+    handover = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if surrogate is not None:
@@ -383,6 +384,7 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
             if log:
                 log(f"hybrid run: pulse {p + 1}/{n} started, {time.perf_counter() - t0:.1f} s")
         lg = gsbs.gsbs_get_handover_log(e.ctx, 0)
+        handover = {k: np.asarray(v) for k, v in lg.items()}
         for ts, tk, est in zip(lg["t_switch"], lg["taken"], lg["estimate"]):
             p = int(np.argmin(np.abs(np.array(t_sw) - ts)))
             used[p] = bool(tk)
@@ -423,4 +425,4 @@ def run(plan: PulsePlan, surrogate: Optional[Surrogate] = None, seed: int = 1, t
     e.close()
     return dict(t=np.array(t_nx), n_h2o2=np.array(n_h2o2), g_h2o2=np.array(g_h2o2), wall=wall,
                 intervals_by_network=int(used.sum()), used=used, counts_at_switch=at_switch,
-                error_estimate_spent=spent, steps=st["steps"], molecule_steps=st["molecule_steps"])
+                error_estimate_spent=spent, steps=st["steps"], molecule_steps=st["molecule_steps"], handover=handover)

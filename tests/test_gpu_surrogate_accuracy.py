@@ -43,6 +43,10 @@ def test_shipped_network_within_one_percent_at_100_gy_per_s():
         "network intervals", np.nonzero(hyb["used"])[0].tolist(), "walls", round(plain["wall"], 2),
         round(hyb["wall"], 2))
     assert hyb["intervals_by_network"] >= 1
+    # every interval is decided by its held-out estimate: taken within 1 %, else plain SBS
+    lg = hyb["handover"]
+    assert len(lg["taken"]) == plan.n_pulses - 1
+    assert np.array_equal(lg["taken"].astype(bool), lg["estimate"] <= 0.01), lg
     first = int(np.argmax(hyb["used"]))
     # identical trajectories up to the first interval the network takes
     assert np.array_equal(plain["n_h2o2"][:first], hyb["n_h2o2"][:first])
