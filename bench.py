@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--sur-pulses", type=str, default="4,10", help="pulses per training and held-out run, one per set")
     ap.add_argument("--sur-held", type=str, default="96,32", help="held-out runs for the error table, one per set")
     ap.add_argument("--mlp", action="store_true", help="throughput of the surrogate network's kernels")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="campaign: skip the single-cube 1-pulse and 20-pulse runs reported beside it")
     ap.add_argument("--mlp-batches", type=str, default="1024,16384,131072", help="--mlp: batch sizes")
     ap.add_argument("--mlp-iters", type=int, default=50, help="--mlp: timed iterations per batch size")
     ap.add_argument("--sur-eval-pulses", type=int, default=10, help="pulses of the plain / hybrid comparison runs")
@@ -766,6 +768,42 @@ def small_config_us_per_step(runs=5):
     return out
 
 
+def single_cube_configs(note):
+    """The two single-cube workloads beside the campaign, one timed run each
+    (wall clock around gsbs_advance_to, inputs already on the device): one
+    1 Gy pulse in a 10 um cube (1 ps -> 1 ms), and 20 pulses of 1 Gy at
+    1e6 Gy/s, 1000 Gy/s on average, 10 injection batches per pulse and 100
+    records per interval in a 10 um cube."""
+    import torch
+
+    from paper_2509_03313_amd import gsbs
+    from paper_2509_03313_amd import workload as W
+    out = {}
+    for name, wl, warm in (("single_pulse_10um_1Gy", W.single_pulse_large(0), True),
+                           ("multi_pulse_20x1Gy_10um_1000Gys", W.multi_pulse(0), False)):
+        res = None
+        for tune in ((True, False) if warm else (False,)):
+            p = gsbs.gsbs_default_params()
+            p.autotune = 1 if tune else 0
+            e = gsbs.Engine(wl.L, 1000, W.D_CONFIG, W.REACTIONS, params=p)
+            e.load_workload(wl)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            e.advance_to(wl.t_end)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            st = e.stats()
+            g = e.gvalues(0)
+            e.close()
+            res = dict(molecule_steps_per_s=round(st["molecule_steps"] / wall, 1), wall_s=round(wall, 3),
+                       sbs_steps=int(st["steps"]), molecule_steps=int(st["molecule_steps"]),
+                       max_live=int(st["max_live"]), injections=len(wl.injections),
+                       records=int(len(wl.records)), G_H2O2_end=round(float(g[-1][W.H2O2]), 5))
+            note(f"{name}{' (warm)' if tune else ''}: {res}")
+        out[name] = res
+    return out
+
+
 def campaign_bench(args):
     """The batched campaign (64 cubes, edges 2-10 um, 0.1-2 Gy per pulse, 1-20
     pulses at 1e6 Gy/s, average 0.01-1e5 Gy/s, 10 batches per pulse), every
@@ -850,6 +888,7 @@ def campaign_bench(args):
     step_ach = value * STEP_BYTES / 1e9
     small = small_config_us_per_step()
     note(f"1 um single pulse, us per SBS step: {small}")
+    singles = single_cube_configs(note) if not args.no_extra_configs else None
     cpu = None
     if not args.no_cpu_baseline:
         cpu = campaign_cpu_baseline(args)
@@ -869,11 +908,15 @@ def campaign_bench(args):
         "ms_per_sbs_step": round(wall / max(n_sbs, 1) * 1e3, 4),
         "roofline": roof,
         "roofline_step": dict(bound="hbm", achieved=round(step_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=round(step_ach / HBM_PEAK_GBS, 5), alg_bytes_per_molecule_step=STEP_BYTES),
+                              frac=round(step_ach / HBM_PEAK_GBS, 5), alg_bytes_per_molecule_step=STEP_BYTES,
+                              target_frac=0.5, gap_to_target=round(0.5 - step_ach / HBM_PEAK_GBS, 5)),
         "cpu_baseline": cpu,
         "small_config_us_per_sbs_step": small,
+        "single_cube_configs": singles,
         "live_timed_kernels": list(live),
         "profile_ms": {q: round(v[0], 3) for q, v in timed.items()},
+        "profile_launches": {q: int(v[1]) for q, v in timed.items()},
+        "profile_candidates": {q: int(v[3]) for q, v in timed.items() if v[3]},
         "profile_launches": {q: v[1] for q, v in timed.items()},
         "profile_work": {q: v[2] for q, v in timed.items()},
         "profile_candidates": {q: v[3] for q, v in timed.items() if v[3]},

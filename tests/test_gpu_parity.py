@@ -321,6 +321,42 @@ def test_species_curves_32_seeds(g):
     e.close()
 
 
+def test_reduced_large_pulse_curves_32_seeds(g):
+    """The 10 um single pulse reduced to a 2.5 um cube at the same track
+    density (~6e3 molecules, 1 ps -> 1 ms, 3297 steps, the late ones at the
+    cube's largest step, so the species-bin search runs): species counts and
+    G(H2O2) at 60 log-spaced times of 32 seeds (one batched launch) agree with
+    the oracle's within 2 % and 3 SE where the oracle mean is at least 20."""
+    gold = np.load(os.path.join(HERE, "golden", "single_pulse_2p5um_oracle.npz"))
+    co = gold["counts"].astype(np.float64)
+    seed = int(gold["philox_seed"])
+    wls = [W.single_pulse_large(i, L=float(gold["L_nm"]), n_records=int(gold["n_records"])) for i in range(co.shape[0])]
+    say("batched 32 reduced 10 um pulses")
+    e = make_engine(g, [w.L for w in wls], seed)
+    for i, w in enumerate(wls):
+        e.load_workload(w, inst=i)
+    e.advance_to(wls[0].t_end)
+    cg = np.stack([e.counts(i) for i in range(len(wls))]).astype(np.float64)
+    gg = np.stack([e.gvalues(i) for i in range(len(wls))])
+    assert cg.shape == co.shape and np.all(cg >= 0)
+    assert np.array_equal(cg[:, 0], co[:, 0])  # the first record is the injected state
+    d = cg - co
+    mo, mg = co.mean(axis=0), cg.mean(axis=0)
+    se = d.std(axis=0, ddof=1) / math.sqrt(co.shape[0])
+    bad = (mo >= 20) & (np.abs(mg - mo) > np.maximum(0.02 * mo, 3 * se))
+    say("records", co.shape[1], "checked", int((mo >= 20).sum()), "outside", int(bad.sum()))
+    assert not bad.any(), (np.argwhere(bad)[:5], mg[bad][:5], mo[bad][:5])
+    go = co[:, :, W.H2O2] / (gold["edep"] / 100.0)
+    gm = gg[:, :, W.H2O2]
+    m = mo[:, W.H2O2] >= 20
+    seG = (gm - go).std(axis=0, ddof=1) / math.sqrt(co.shape[0])
+    assert np.all(np.abs(gm.mean(0) - go.mean(0))[m] <= np.maximum(0.02 * go.mean(0), 3 * seG)[m])
+    st = e.stats()
+    assert st["steps"] == int(gold["n_steps"][0])
+    say("molecule-steps", st["molecule_steps"], "species-bin candidates", st.get("pair_candidates"))
+    e.close()
+
+
 def test_multi_pulse_curves_32_seeds(g):
     """Four pulses (two injection batches each, the step ramp restarting at
     every batch): species counts at 30 log-spaced times per interval of 32
