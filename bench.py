@@ -115,7 +115,8 @@ def parse():
     ap.add_argument("--sur-data", type=str, default="",
                     help="npz of the training and held-out samples: read if it exists, else written after generating")
     ap.add_argument("--sur-generate-only", action="store_true", help="stop after generating (and saving) the samples")
-    ap.add_argument("--sur-batch", type=int, default=512, help="training runs stepped together in one context")
+    ap.add_argument("--sur-batch", type=str, default="512",
+                    help="training runs stepped together in one context, one per set (the last repeats)")
     return ap.parse_args()
 
 
@@ -142,6 +143,8 @@ def surrogate_bench(args):
         doses = (0.7, 1.3)
         ints = lambda v: [int(x) for x in str(v).split(",") if x]  # noqa: E731
         pulses, n_plans, held_runs = ints(args.sur_pulses), ints(args.sur_plans), ints(args.sur_held)
+        bsz_list = ints(args.sur_batch)
+        bsz_of = lambda k: bsz_list[min(k, len(bsz_list) - 1)]  # noqa: E731
         if not (len(pulses) == len(n_plans) == len(held_runs)):
             raise SystemExit("--sur-pulses, --sur-plans and --sur-held take lists of one length")
         # sets of training runs in the small cube and held-out runs in the large one (its
@@ -150,7 +153,7 @@ def surrogate_bench(args):
         jobs = []
         for k, (npl, nh, npu) in enumerate(zip(n_plans, held_runs, pulses)):
             jobs.append(("train", SU.random_plans(args.seed + 1 + 10 * k, npl, L=args.sur_train_L, n_pulses=npu,
-                                                  rates=rates, doses=doses), args.sur_batch, 1000 + 100000 * k, k, npu))
+                                                  rates=rates, doses=doses), bsz_of(k), 1000 + 100000 * k, k, npu))
             jobs.append(("held", SU.random_plans(args.seed + 2 + 10 * k, nh, L=args.sur_L, n_pulses=npu, rates=rates,
                                                  doses=doses), 32, 2000 + 100000 * k, k, npu))
         n_train_runs = sum(n_plans)
