@@ -20,8 +20,11 @@ constexpr int kMlpLayers = 5;
 void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc, int M,
                  int N, int K, float* work, size_t work_elems);
 void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp);
-void mlp_epilogue(hipStream_t st, const float* C, const float* bias, int B, int Mp, int Np, int n_valid, int hidden,
-                  float* Z, uint16_t* A, uint16_t* AT, float* Y);
+// One forward layer: X W^T with the layer epilogue fused into the product's
+// store (Z = XW^T + bias; hidden: A = BF16(GELU(Z)), Z and AT when not null;
+// output: Y = Z as FP32 B x n_valid).
+void mlp_gemm_layer(hipStream_t st, const uint16_t* A, const uint16_t* W, int Mp, int Np, int Kp, const float* bias,
+                    int B, int n_valid, int hidden, float* Z, uint16_t* Aout, uint16_t* AT, float* Y);
 void mlp_loss(hipStream_t st, const float* Y, const float* T, int B, int n_out, int Mp, int Np, float* dZ,
               uint16_t* dZb, uint16_t* dZT, float* loss);
 void mlp_act_grad(hipStream_t st, const float* dA, const float* Z, int B, int Mp, int Np, int n_valid, float* dZ,

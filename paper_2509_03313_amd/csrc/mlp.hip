@@ -53,10 +53,37 @@ constexpr int kGemmTile = 64;
 constexpr int kGemmK = 32;
 constexpr int kGemmPad = 8;  // BF16 values of row padding in LDS
 
+// Layer epilogue applied to the product as it leaves the registers (forward
+// pass; bias null: plain store of C): Z = C + bias; hidden layers A = BF16(GELU(Z))
+// (Z and the transpose AT kept only when not null), rows >= B and columns
+// >= n_valid 0; output layer Y = Z (FP32, B x n_valid).
+struct MlpEpi {
+    const float* bias;
+    float* Z;
+    uint16_t* A;
+    uint16_t* AT;
+    float* Y;
+    int32_t B, n_valid, hidden, Mp;
+};
+
+__device__ __forceinline__ void epi_store(const MlpEpi& q, int row, int col, int Np, float v) {
+    const bool valid = row < q.B && col < q.n_valid;
+    const float z = valid ? v + q.bias[col] : 0.0f;
+    const size_t e = (size_t)row * Np + col;
+    if (q.hidden) {
+        if (q.Z) q.Z[e] = z;
+        const uint16_t h = to_bf16(valid ? gelu(z) : 0.0f);
+        q.A[e] = h;
+        if (q.AT) q.AT[(size_t)col * q.Mp + row] = h;
+    } else if (valid) {
+        q.Y[(size_t)row * q.n_valid + col] = z;
+    }
+}
+
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restrict__ A, int32_t lda,
                                                      const uint16_t* __restrict__ B, int32_t ldb,
                                                      float* __restrict__ C, int32_t ldc, int32_t M, int32_t N,
-                                                     int32_t K, int32_t kc) {
+                                                     int32_t K, int32_t kc, MlpEpi epi) {
     __shared__ __align__(16) uint16_t sa[kGemmTile][kGemmK + kGemmPad];
     __shared__ __align__(16) uint16_t sb[kGemmTile][kGemmK + kGemmPad];
     const int bm = blockIdx.y * kGemmTile, bn = blockIdx.x * kGemmTile;
@@ -98,7 +125,10 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_nt(const uint16_t* __restric
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = bm + wm + 16 * i + 4 * (lane >> 4) + e, col = bn + wn + 16 * j + r;
-                if (row < M && col < N) C[(size_t)row * ldc + col] = acc[i][j][e];
+                if (row < M && col < N) {
+                    if (epi.bias) epi_store(epi, row, col, ldc, acc[i][j][e]);
+                    else C[(size_t)row * ldc + col] = acc[i][j][e];
+                }
             }
 }
 
@@ -125,26 +155,6 @@ __global__ void k_mlp_input(const float* __restrict__ x, int32_t B, int32_t n_in
     const uint16_t h = to_bf16(v);
     X[e] = h;
     if (XT) XT[(size_t)k * Mp + m] = h;
-}
-
-// Z = C + bias; hidden layers: A = BF16(GELU(Z)) and its transpose (rows >= B
-// and columns >= n_valid stay 0); output layer: Y = Z (FP32, B x n_valid).
-__global__ void k_mlp_epilogue(const float* __restrict__ C, const float* __restrict__ bias, int32_t B,
-                               int32_t Mp, int32_t Np, int32_t n_valid, int32_t hidden, float* __restrict__ Z,
-                               uint16_t* __restrict__ A, uint16_t* __restrict__ AT, float* __restrict__ Y) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)Mp * Np) return;
-    const int m = (int)(e / Np), n = (int)(e % Np);
-    const bool valid = m < B && n < n_valid;
-    const float z = valid ? C[e] + bias[n] : 0.0f;
-    if (hidden) {  // Z and AT are kept for a backward pass only
-        if (Z) Z[e] = z;
-        const uint16_t h = to_bf16(valid ? gelu(z) : 0.0f);
-        A[e] = h;
-        if (AT) AT[(size_t)n * Mp + m] = h;
-    } else if (valid) {
-        Y[(size_t)m * n_valid + n] = z;
-    }
 }
 
 // Mean squared error over the B x n_out outputs and its gradient dY =
@@ -254,21 +264,23 @@ void mlp_gemm_nt(hipStream_t st, const uint16_t* A, int lda, const uint16_t* B, 
     const int kc = ns > 1 ? ((K + ns - 1) / ns + kGemmK - 1) / kGemmK * kGemmK : K;
     ns = (K + kc - 1) / kc;
     const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, ns);
+    const MlpEpi none{};
     if (ns == 1) {
-        hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K, K);
+        hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, C, ldc, M, N, K, K, none);
         return;
     }
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, work, ldc, M, N, K, kc);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, lda, B, ldb, work, ldc, M, N, K, kc, none);
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((int64_t)M * N)), dim3(kMlpBlock), 0, st, work, ns, M, N, ldc, C);
+}
+void mlp_gemm_layer(hipStream_t st, const uint16_t* A, const uint16_t* W, int Mp, int Np, int Kp, const float* bias,
+                    int B, int n_valid, int hidden, float* Z, uint16_t* Aout, uint16_t* AT, float* Y) {
+    const dim3 grid((Np + kGemmTile - 1) / kGemmTile, (Mp + kGemmTile - 1) / kGemmTile, 1);
+    const MlpEpi epi{bias, Z, Aout, AT, Y, B, n_valid, hidden, Mp};
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kMlpBlock), 0, st, A, Kp, W, Kp, (float*)nullptr, Np, Mp, Np, Kp, Kp, epi);
 }
 void mlp_input(hipStream_t st, const float* x, int B, int n_in, uint16_t* X, uint16_t* XT, int Mp, int Kp) {
     hipLaunchKernelGGL(k_mlp_input, dim3(blocks_for((int64_t)Mp * Kp)), dim3(kMlpBlock), 0, st, x, B, n_in, X, XT,
                        Mp, Kp);
-}
-void mlp_epilogue(hipStream_t st, const float* C, const float* bias, int B, int Mp, int Np, int n_valid, int hidden,
-                  float* Z, uint16_t* A, uint16_t* AT, float* Y) {
-    hipLaunchKernelGGL(k_mlp_epilogue, dim3(blocks_for((int64_t)Mp * Np)), dim3(kMlpBlock), 0, st, C, bias, B, Mp,
-                       Np, n_valid, hidden, Z, A, AT, Y);
 }
 void mlp_loss(hipStream_t st, const float* Y, const float* T, int B, int n_out, int Mp, int Np, float* dZ,
               uint16_t* dZb, uint16_t* dZT, float* loss) {

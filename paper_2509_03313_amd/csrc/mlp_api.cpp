@@ -71,7 +71,7 @@ struct gsbs_mlp {
     // activations entering layer l (BF16 and transpose), hidden pre-activations
     uint16_t *act[kMlpLayers] = {}, *actT[kMlpLayers] = {};
     float* Z[kMlpLayers] = {};
-    float *C = nullptr, *Y = nullptr, *dZ = nullptr, *dA = nullptr, *loss = nullptr;
+    float *Y = nullptr, *dZ = nullptr, *dA = nullptr, *loss = nullptr;
     // partial products of split reductions (weight gradients, bias gradients)
     float* work = nullptr;
     size_t work_elems = 0;
@@ -124,10 +124,10 @@ int forward(gsbs_mlp* m, const float* x, int B, float* y, bool train) {
     mlp_input(m->st, x, B, kMlpIn, m->act[0], train ? m->actT[0] : nullptr, Mp, kShape[0].K);
     for (int l = 0; l < kMlpLayers; ++l) {
         const Shape& s = kShape[l];
-        mlp_gemm_nt(m->st, m->act[l], s.K, m->wb[l], s.K, m->C, s.N, Mp, s.N, s.K, nullptr, 0);
         const bool hidden = l + 1 < kMlpLayers;
-        mlp_epilogue(m->st, m->C, m->b[l], B, Mp, s.N, s.nv, hidden ? 1 : 0, train ? m->Z[l] : nullptr,
-                     hidden ? m->act[l + 1] : nullptr, (hidden && train) ? m->actT[l + 1] : nullptr, y);
+        mlp_gemm_layer(m->st, m->act[l], m->wb[l], Mp, s.N, s.K, m->b[l], B, s.nv, hidden ? 1 : 0,
+                       train ? m->Z[l] : nullptr, hidden ? m->act[l + 1] : nullptr,
+                       (hidden && train) ? m->actT[l + 1] : nullptr, y);
     }
     MHIP(hipGetLastError());
     return GSBS_OK;
@@ -170,7 +170,7 @@ int gsbs_mlp_create(int32_t max_batch, void* stream, gsbs_mlp** out) {
     }
     const size_t wide = (size_t)Mp * kShape[0].K;
     if (r == GSBS_OK &&
-        ((r = own(m, &m->C, wide)) || (r = own(m, &m->Y, (size_t)Mp * kMlpOut)) || (r = own(m, &m->dZ, wide)) ||
+        ((r = own(m, &m->Y, (size_t)Mp * kMlpOut)) || (r = own(m, &m->dZ, wide)) ||
          (r = own(m, &m->dA, wide)) || (r = own(m, &m->loss, 1)) || (r = own(m, &m->dZb, wide)) ||
          (r = own(m, &m->dZT, wide)))) {
     }
