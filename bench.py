@@ -309,7 +309,22 @@ def cpu_baseline(wl, n_steps):
                        f"({ms} molecule-steps, {dt:.1f} s, 1 thread)")
 
 
-def roofline_of(prof, kernel=None, traffic_file=None):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of a kernel on a workload, from the scaled
+    FETCH_SIZE + WRITE_SIZE counters in profiles/traffic.json; None when the
+    file has no such entry or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernels_hash") != kernels_hash():
+        return None
+    return t.get("workloads", {}).get(workload, {}).get("per_launch_bytes", {}).get(kernel)
+
+
+def roofline_of(prof, kernel=None, workload=None):
     """Roofline object of one kernel of a profile (by default the one with the
     most time): HBM for the streaming kernels, FP32 vector for the species-bin
     search."""
@@ -331,10 +346,8 @@ def roofline_of(prof, kernel=None, traffic_file=None):
     else:
         r = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                  kernel=dom, avg_launch_us=round(avg_s * 1e6, 3))
-    if traffic_file and os.path.exists(traffic_file):
-        t = json.load(open(traffic_file))
-        if t.get("kernels_hash") == kernels_hash() and dom in t.get("per_launch_bytes", {}):
-            r["traffic"] = t["per_launch_bytes"][dom]
+    if workload:
+        r["traffic"] = measured_traffic(workload, dom)
     return r
 
 
@@ -882,12 +895,7 @@ def campaign_bench(args):
                 traffic=None, kernel=dom, avg_launch_us=round(tot_ms * 1e3 / max(launches, 1), 3),
                 alg_bytes_per_unit=STEP_BYTES, unit_name="molecule-step of the instances the kernel searched",
                 units_per_launch=round(units / max(launches, 1), 1))
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        t = json.load(open(tf))
-        if t.get("kernels_hash") == kernels_hash() and t.get("workload") == "campaign" and dom in t.get(
-                "per_launch_bytes", {}):
-            roof["traffic"] = t["per_launch_bytes"][dom]
+    roof["traffic"] = measured_traffic("campaign", dom)
     step_ach = value * STEP_BYTES / 1e9
     small = small_config_us_per_step()
     note(f"1 um single pulse, us per SBS step: {small}")
@@ -1089,7 +1097,7 @@ def main():
         pst = e.stats()
         note(f"profile: {prof}")
         e.close()
-        roofline = roofline_of(prof, traffic_file=os.path.join(ROOT, "profiles", "traffic.json"))
+        roofline = roofline_of(prof, workload="single_pulse_10um")
 
     cpu = None
     if not args.no_cpu_baseline:

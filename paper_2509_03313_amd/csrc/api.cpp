@@ -750,8 +750,9 @@ int run_step(gsbs_ctx* c, const StepBuffers& bf, const InstStep* P, int32_t n_in
              int64_t nest0 = 0, hipEvent_t* live = nullptr) {
     if (span) HIPCHK(hipEventRecord(span[0], c->st));
     if (!c->fo.empty()) flags |= kStepFirstOrder;
-    if (c->profiling)
-        launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags, c->prof_ev);
+    if (c->profiling)  // two events per kernel slot (the mask names the six slots, not the chained form)
+        launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags, c->prof_ev,
+                    (1u << kStepKernels) - 1u);
     else
         launch_step(c->st, bf, P, c->chem_d, n_inst, bins, units, c->ns, grid, flags, live, kEvChain);
     HIPCHK(hipGetLastError());

@@ -357,6 +357,28 @@ def test_reduced_large_pulse_curves_32_seeds(g):
     e.close()
 
 
+def test_profiling_mode_times_every_kernel(g):
+    """gsbs_set_profiling: every step's kernels get their own pair of HIP
+    events (synchronised per step); the profile reports a positive time for
+    every kernel that ran, and the run's counts equal an unprofiled run's."""
+    wl = W.single_pulse_small(3)
+    out = []
+    for prof in (False, True):
+        e = make_engine(g, wl.L, 1000)
+        e.load_workload(wl)
+        if prof:
+            g.gsbs_set_profiling(e.ctx, True)
+        e.advance_to(wl.t_end)
+        out.append((e.counts(0), g.gsbs_get_profile(e.ctx) if prof else None, e.stats()["steps"]))
+        e.close()
+    (c0, _, n0), (c1, pr, n1) = out
+    assert np.array_equal(c0, c1) and n0 == n1
+    say("profile", {k: (round(v[0], 3), v[1]) for k, v in pr.items()})
+    for k in ("k_bin", "k_scan", "k_scatter", "k_react"):
+        assert pr[k][1] == n1 and pr[k][0] > 0.0, (k, pr[k])
+    assert pr["k_pairs"][1] + pr["k_pairs_sp"][1] >= n1
+
+
 def test_multi_pulse_curves_32_seeds(g):
     """Four pulses (two injection batches each, the step ramp restarting at
     every batch): species counts at 30 log-spaced times per interval of 32
