@@ -985,7 +985,7 @@ __global__ __launch_bounds__(GSBS_BLOCK, 4) void k_pairs(const float4* __restric
 // A pair of one species is tested from the molecule with the lower sorted index.
 
 constexpr int kSegCap = 128;   // segments of 64 rows (at most two z-runs per row)
-constexpr int kListCap = 1024;  // candidates compacted per pass (16 per lane)
+constexpr int kListCap = 256;  // candidates compacted per pass (4 per lane)
 constexpr int kLaneQuota = kListCap / 64;
 constexpr float kFar = 3.0e38f;
 
@@ -1004,7 +1004,6 @@ struct SpWave {
     uint16_t list[kListCap];
     int4 qe[128];    // queued for evaluation: i, j, rx, bits of r0^2
     float qr[128];   // queued r1^2
-    int32_t rbeg[65], roff[65];
 };
 
 // Contact probability, pair uniform and acceptance of one pair.
@@ -1334,24 +1333,24 @@ __global__ __launch_bounds__(GSBS_BLOCK) void k_pairs_sp(const float4* __restric
         const int inclA = (int)wave_incl_scan((uint32_t)cntA);
         const int nA = wave_last(inclA);
         if (nA == 0) continue;
-        wave_sync_lds();
-        if (lane < nrowsA) {
-            w.rbeg[lane] = begA;
-            w.roff[lane] = inclA - cntA;
-        }
-        if (lane == 0) w.roff[nrowsA] = nA;
-        wave_sync_lds();
+        // first A index of each row, one row per lane (non-decreasing; past the rows: never reached)
+        const int exclA = lane < nrowsA ? inclA - cntA : 0x7FFFFFFF;
         const float h = S.h, eps = S.cull_eps, L = S.L, hL = S.halfL, inv_h = S.inv_h;
         const int* rrow = rmap + si * kMaxSpecies;
-        int rsearch = 0;  // A row of this lane's molecule (monotone over chunks)
         for (int ab = 0; ab < nA; ab += 64) {
             const int k = ab + lane;
             const bool va = k < nA;
-            int ia = -1;
-            if (va) {
-                while (rsearch + 1 < nrowsA && w.roff[rsearch + 1] <= k) ++rsearch;
-                ia = w.rbeg[rsearch] + (k - w.roff[rsearch]);
+            // row of this lane's molecule: the last row whose first index is at most k
+            // (rows read from the lanes that hold them; every lane takes part)
+            int row = 0;
+#pragma unroll
+            for (int st = 32; st >= 1; st >>= 1) {
+                const int nx = row + st;
+                const int ex = __shfl(exclA, nx < 64 ? nx : 63, 64);
+                if (nx < 64 && ex <= k) row = nx;
             }
+            const int rb0 = __shfl(begA, row, 64), rx0 = __shfl(exclA, row, 64);
+            const int ia = va ? rb0 + (k - rx0) : -1;
             float4 pa = make_float4(kFar, kFar, kFar, __int_as_float(-1));
             float4 qa = make_float4(0.f, 0.f, 0.f, 0.f);
             if (va) {
