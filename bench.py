@@ -324,6 +324,18 @@ def measured_traffic(workload, kernel):
     return t.get("workloads", {}).get(workload, {}).get("per_launch_bytes", {}).get(kernel)
 
 
+def add_traffic(r, workload):
+    """Counter bytes per launch of the roofline's kernel, and the HBM rate they
+    give over its measured mean launch time (with its fraction of peak)."""
+    t = measured_traffic(workload, r["kernel"])
+    r["traffic"] = t
+    if t and r.get("avg_launch_us"):
+        gbs = t / (r["avg_launch_us"] * 1e-6) / 1e9
+        r["traffic_gbs"] = round(gbs, 1)
+        r["traffic_frac"] = round(gbs / HBM_PEAK_GBS, 5)
+    return r
+
+
 def roofline_of(prof, kernel=None, workload=None):
     """Roofline object of one kernel of a profile (by default the one with the
     most time): HBM for the streaming kernels, FP32 vector for the species-bin
@@ -347,7 +359,7 @@ def roofline_of(prof, kernel=None, workload=None):
         r = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                  kernel=dom, avg_launch_us=round(avg_s * 1e6, 3))
     if workload:
-        r["traffic"] = measured_traffic(workload, dom)
+        add_traffic(r, workload)
     return r
 
 
@@ -895,7 +907,7 @@ def campaign_bench(args):
                 traffic=None, kernel=dom, avg_launch_us=round(tot_ms * 1e3 / max(launches, 1), 3),
                 alg_bytes_per_unit=STEP_BYTES, unit_name="molecule-step of the instances the kernel searched",
                 units_per_launch=round(units / max(launches, 1), 1))
-    roof["traffic"] = measured_traffic("campaign", dom)
+    add_traffic(roof, "campaign")
     step_ach = value * STEP_BYTES / 1e9
     small = small_config_us_per_step()
     note(f"1 um single pulse, us per SBS step: {small}")
