@@ -517,8 +517,8 @@ int64_t boxes_of(const InstStep& S, int s) {
 }
 
 // Waves of the species-bin search resident on the device at once (its LDS
-// use allows three 4-wave blocks per compute unit).
-constexpr double kResidentWaves = 256.0 * 12.0;
+// and register use allow four 4-wave blocks per compute unit).
+constexpr double kResidentWaves = 256.0 * 16.0;
 
 // Stream slices of the species-bin search for one step over all instances:
 // a box whose partner stream exceeds W = (the step's whole streamed work) /
