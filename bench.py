@@ -1124,6 +1124,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "ms_per_run": round(wall / args.steps * 1e3, 3),  # one benchmark step is one whole run
+        "ms_per_sbs_step": round(wall / (args.steps * max(sbs_steps, 1)) * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
